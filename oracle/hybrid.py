@@ -1,0 +1,195 @@
+"""The paper's hybrid Fourier/direct-space algorithm, step by step, in FP64.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Library FFTs (numpy)
+serve as steps; nothing is blocked, fused or reordered.
+
+Steps, in the paper's order (Sect. 4.1 and the artifact suppression of
+Sect. 4.3):
+
+(a) real FFT of every input ring, ``A_j(m) = sum_k x_jk exp(-2 pi i m k / N_j)``;
+    the phase shift of eq. "fftrot" turns it into the spectrum of the ring in
+    absolute longitude, ``A_j(m) exp(-i m phi0_j)``; the artifact-suppressed
+    mode duplicates (periodically extends) it past the ring's own Nyquist
+    frequency instead of zero-padding it.
+(b) for every output ring i and input ring j in the support, the kernel row
+    ``g(nu) = w_j K(theta(i, j, nu))`` sampled on a longitude grid centred on
+    the output ring (the paper's kernel grid, 4 nside points per ring), and its
+    FFT ``K_ij(m)``.  Equatorial ring pairs with equal ring lengths do not use
+    the phase shift: the kernel is sampled at the true pixel offsets, i.e. at
+    longitudes shifted by ``phi0_i - phi0_j`` (Sect. 4.3), which makes them
+    exact.  In absolute longitude this is the grid ``2 pi (d + s/2) / L`` with
+    s = 1 when the two rings are offset by an odd multiple of pi / L.
+(c) ``B_i(m) = sum_j K_ij(m) A~_j(m)`` (the theta-direction summation).
+(d) reverse phase shift, fold the super-Nyquist modes onto the ring's own
+    modes (Sect. 4.3), inverse real FFT of length N_i.
+(e) optionally, the first and last ring (8 pixels on HEALPix) recomputed by
+    the direct sum (Sect. 4.2).
+
+Readings taken where the paper is silent (each listed in the design doc):
+
+* Oversampling ``p``: pairs that involve a polar ring sample the kernel on
+  ``p L`` points (``p = 1`` is the paper's grid) and keep modes up to
+  ``p L / 2``; equatorial equal-length pairs always use ``p = 1`` (exact).
+* The Nyquist mode of each pair's grid is split symmetrically (half weight),
+  so every pair contributes the real trigonometric interpolant of its kernel
+  row, evaluated at the true pixel offsets.
+* The 1 / (p L) normalisation of the kernel FFT is applied per pair.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import SUPPORT_TOL, direct, kernel, rings, basis
+
+
+def _ring_distance(th_i, th_j, nu):
+    """Angle between (th_i, 0) and (th_j, nu), from 3-D unit vectors."""
+    ax, az = np.sin(th_i), np.cos(th_i)
+    bx, by, bz = np.sin(th_j) * np.cos(nu), np.sin(th_j) * np.sin(nu), np.cos(th_j)
+    cx = -az * by
+    cy = az * bx - ax * bz
+    cz = ax * by
+    return np.arctan2(np.sqrt(cx * cx + cy * cy + cz * cz), ax * bx + az * bz)
+
+
+def _grid_length(grid):
+    return 4 * grid.nside if grid.kind == "healpix" else grid.nphi
+
+
+def pair_plan(grid, radius, oversample):
+    """For each output ring i: list of (j, p, s) -- input ring, oversampling
+    factor and half-shift flag of the kernel grid."""
+    th, ph0, w, n, st = rings(grid)
+    L = _grid_length(grid)
+    out = []
+    for i in range(len(th)):
+        lst = []
+        for j in range(len(th)):
+            if abs(th[j] - th[i]) > radius + 1e-6:
+                continue
+            e = (ph0[i] - ph0[j]) * L / np.pi
+            aligned = n[i] == L and n[j] == L and abs(e - round(e)) < 1e-9
+            p = 1 if aligned else int(oversample)
+            s = int(round(e) * p) % 2 if aligned else 0
+            lst.append((j, p, s))
+        out.append(lst)
+    return out
+
+
+def _extended_spectrum(a, phi0, nring, mmax):
+    """Physical-longitude spectrum A_j(m mod N_j) exp(-i m phi0), m = 0..mmax."""
+    m = np.arange(mmax + 1)
+    r = m % nring
+    lower = r <= nring // 2
+    base = np.where(lower, a[np.minimum(r, nring // 2)], np.conj(a[np.minimum(nring - r, nring // 2)]))
+    return base * np.exp(-1j * m * phi0)
+
+
+def _kernel_row_spectrum(profile, radius, th_i, th_j, w_j, p, s, L, values=None):
+    """K_ij(m), m = 0..pL/2, with the 1/(pL) normalisation and the half-weight
+    Nyquist mode.  ``values`` optionally replaces K by another radial function
+    (used for the knot basis)."""
+    nn = p * L
+    nu = 2.0 * np.pi * (np.arange(nn) + 0.5 * s) / nn
+    t = _ring_distance(th_i, th_j, nu)
+    g = w_j * (kernel(profile, radius, t) if values is None else values(t))
+    m = np.arange(nn // 2 + 1)
+    kf = np.fft.fft(g)[: nn // 2 + 1] * np.exp(-1j * np.pi * m * s / nn)
+    kf = kf.real / nn
+    kf[nn // 2] *= 0.5
+    return kf
+
+
+def _fold_inverse(bm, phi0, nring):
+    """Reverse phase shift, alias every mode onto m mod N, inverse real FFT."""
+    m = np.arange(bm.size)
+    bp = bm * np.exp(1j * m * phi0)
+    half = nring // 2
+    g = np.zeros(half + 1, complex)
+    r = m % nring
+    pos = r <= half
+    np.add.at(g, r[pos], bp[pos])
+    rn = (nring - r) % nring
+    neg = (m > 0) & (rn <= half)
+    np.add.at(g, rn[neg], np.conj(bp[neg]))
+    return np.fft.irfft(g, nring) * nring
+
+
+def _hybrid_core(grid, profile, radius, x, oversample, values=None):
+    th, ph0, w, n, st = rings(grid)
+    L = _grid_length(grid)
+    x = np.asarray(x, dtype=np.float64)
+    spec = [np.fft.rfft(x[st[j]: st[j] + n[j]]) for j in range(len(th))]      # step (a)
+    plan = pair_plan(grid, radius, oversample)
+    y = np.empty(grid.npix)
+    for i, pairs in enumerate(plan):
+        mmax = max(p * L // 2 for (_, p, _) in pairs)
+        b = np.zeros(mmax + 1, complex)
+        for (j, p, s) in pairs:
+            kf = _kernel_row_spectrum(profile, radius, th[i], th[j], w[j], p, s, L, values)  # (b)
+            b[: kf.size] += kf * _extended_spectrum(spec[j], ph0[j], n[j], kf.size - 1)     # (c)
+        y[st[i]: st[i] + n[i]] = _fold_inverse(b, ph0[i], n[i])                             # (d)
+    return y
+
+
+def _pole_pixels(grid):
+    if grid.kind != "healpix":
+        return np.zeros(0, np.int64)
+    npix = grid.npix
+    return np.array([0, 1, 2, 3, npix - 4, npix - 3, npix - 2, npix - 1], np.int64)
+
+
+def hybrid(grid, profile, radius, x, oversample=2, fix_poles=True):
+    """The method's output map (FP64).  ``fix_poles`` recomputes the first and
+    last HEALPix ring by the direct sum (step (e))."""
+    y = _hybrid_core(grid, profile, radius, x, oversample)
+    idx = _pole_pixels(grid)
+    if fix_poles and idx.size:
+        y[idx] = direct(grid, profile, radius, x, idx=idx)
+    return y
+
+
+def hybrid_adjoint(grid, profile, radius, r, oversample=2, fix_poles=True):
+    """Transpose of ``hybrid`` as a linear map of x.  Ring pairs use symmetric
+    kernel grids, so the transpose of the ring pipeline is
+    ``w * pipeline(r / w)``; the direct-sum rows of step (e) transpose into
+    direct-sum columns."""
+    th, ph0, w, n, st = rings(grid)
+    wpix = np.repeat(w, n)
+    r = np.asarray(r, dtype=np.float64).copy()
+    idx = _pole_pixels(grid)
+    rfix = np.zeros(grid.npix)
+    if fix_poles and idx.size:
+        rfix[idx] = r[idx]
+        r[idx] = 0.0
+    out = wpix * _hybrid_core(grid, profile, radius, r / wpix, oversample)
+    if fix_poles and idx.size:
+        from . import adjoint
+        out += adjoint(grid, profile, radius, rfix)
+    return out
+
+
+def hybrid_knot_grad(grid, profile, radius, x, r, oversample=2, fix_poles=True):
+    """Gradient of 1/2 |hybrid(x) - t|^2 with respect to the spline knots,
+    given r = hybrid(x) - t: the method is linear in the kernel, so
+    g_k = <r, hybrid_k(x)> with hybrid_k the method run with kernel phi_k."""
+    nk = len(profile.knots)
+    g = np.empty(nk)
+    idx = _pole_pixels(grid)
+    r = np.asarray(r, dtype=np.float64)
+    for k in range(nk):
+        yk = _hybrid_core(grid, profile, radius, x, oversample,
+                          values=lambda t, k=k: basis(profile, radius, t)[:, k])
+        if fix_poles and idx.size:
+            from . import knot_grad
+            rr = r.copy()
+            rr[idx] = 0.0
+            g[k] = float(np.dot(rr, yk))
+        else:
+            g[k] = float(np.dot(r, yk))
+    if fix_poles and idx.size:
+        from . import knot_grad
+        rr = np.zeros_like(r)
+        rr[idx] = r[idx]
+        g += knot_grad(grid, profile, radius, x, rr)
+    return g

@@ -1,0 +1,189 @@
+/*
+ * arkcos.h -- C ABI of the MI355X (gfx950) implementation of the hybrid
+ * Fourier/direct-space convolution of an isolatitude-ring sphere map with a
+ * compact radial kernel (Elsner & Wandelt 2011, "ARKCoS").
+ *
+ * The operation (paper Sect. 2, eq. "def", discretised as in Sect. 3.1,
+ * eq. "direct", with pixel areas w_q as quadrature weights):
+ *
+ *     y_p = sum_{q : theta_pq <= R} K(theta_pq) x_q w_q
+ *
+ * computed by the hybrid algorithm of Sect. 4.1 with the artifact suppression
+ * of Sect. 4.3:
+ *   (a) a real FFT of every input ring, phase-shifted to absolute longitude
+ *       (eq. "fftrot") and periodically extended past the ring's Nyquist mode;
+ *   (b) for every output ring i and input ring j inside the support, the
+ *       azimuthal Fourier coefficients K_ij(m) of the kernel sampled at the
+ *       angular distance theta(i, j, dphi) (eq. "kernel_angle"; the distance
+ *       is evaluated in FP64 haversine form);
+ *   (c) B_i(m) = sum_j K_ij(m) A_j(m);
+ *   (d) reverse phase shift, aliasing of super-Nyquist modes onto the ring's
+ *       own modes, inverse real FFT per output ring; on HEALPix the 8 pixels
+ *       of the first and last ring are then recomputed by the direct sum
+ *       (Sect. 4.2).
+ * Equatorial HEALPix rings of equal length are paired without the phase
+ * shift, with the kernel sampled at the true pixel offsets (Sect. 4.3); this
+ * makes them exact.  Pairs involving a polar ring sample the kernel on
+ * `oversample * 4 nside` longitudes instead of 4 nside.
+ *
+ * Conventions shared by every entry point:
+ *   - Maps are device buffers in RING order: HEALPix with npix = 12 nside^2,
+ *     or ECP with npix = n_theta * n_phi (ring-major, theta_i = (i+1/2) pi /
+ *     n_theta, phi_k = 2 pi k / n_phi).  The element type is the plan's dtype
+ *     (float or double).  The caller owns every map, workspace and gradient
+ *     buffer.
+ *   - A plan owns only read-only device tables created by arkcos_plan on the
+ *     device that is current at that call; every later call must run with the
+ *     same device current.
+ *   - Calls taking a stream only enqueue work on it and never synchronise the
+ *     host; they allocate nothing.  Two calls that may overlap in time need
+ *     separate workspaces.
+ *   - Errors are returned as status codes; no call aborts or throws.  Host-side
+ *     argument checks run before any work is enqueued; a non-OK status means
+ *     nothing was enqueued.  arkcos_last_error() gives a message for the
+ *     calling thread.
+ */
+#ifndef ARKCOS_H
+#define ARKCOS_H
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct arkcos_plan_s* arkcos_plan_t;
+typedef struct arkcos_batch_s* arkcos_batch_t;
+
+typedef enum {
+  ARKCOS_OK = 0,
+  ARKCOS_ERR_INVALID_VALUE = 1, /* bad argument: null pointer, size, aliasing */
+  ARKCOS_ERR_NOT_SUPPORTED = 2, /* valid but outside what the library handles */
+  ARKCOS_ERR_OUT_OF_MEMORY = 3, /* device allocation failed (plan creation) */
+  ARKCOS_ERR_DEVICE = 4,        /* a HIP runtime call or launch failed */
+  ARKCOS_ERR_INTERNAL = 5
+} arkcos_status_t;
+
+typedef enum { ARKCOS_F32 = 0, ARKCOS_F64 = 1 } arkcos_dtype_t;
+
+/* Pixelisation (paper Sect. 4.1 for HEALPix; any isolatitude-ring grid with
+ * equal ring lengths works as ECP). */
+typedef struct {
+  int32_t kind;     /* 0 = ECP, 1 = HEALPix (RING order) */
+  int64_t nside;    /* HEALPix: 1 .. 8192 */
+  int64_t n_theta;  /* ECP: number of rings */
+  int64_t n_phi;    /* ECP: pixels per ring, even */
+} arkcos_geometry_t;
+
+/* Radial kernel profile K(theta), truncated at the support radius (Sect. 4). */
+typedef struct {
+  int32_t kind;             /* 0 = Gaussian exp(-theta^2 / 2 sigma^2), sigma = FWHM / sqrt(8 ln 2);
+                               1 = clamped cubic spline through knot values at
+                                   theta_k = k theta_max / (n_knots - 1), zero beyond theta_max */
+  double fwhm_rad;          /* Gaussian */
+  int32_t n_knots;          /* spline: 3 .. 64 */
+  double theta_max_rad;     /* spline */
+  const double* knot_values;/* spline: host array of n_knots values, copied by arkcos_plan */
+} arkcos_profile_t;
+
+typedef struct {
+  int32_t oversample;       /* kernel grid refinement p for pairs involving a polar
+                               ring: 1, 2, 4, 8 or 16; 0 = choose from the kernel's
+                               width (p = next power of two >= 4.3 pixel / FWHM) */
+  int32_t kgen;             /* how K_ij(m) is produced per call: 0 = automatic
+                               (recurrence from the kernel samples for narrow pairs,
+                               precomputed table for wide ones), 1 = recurrence for
+                               every pair, 2 = precomputed table for every pair */
+  int32_t fix_pole_pixels;  /* HEALPix: recompute the 8 pixels of the first and last
+                               ring by the direct sum (default 1) */
+  double band_tol;          /* modes with |K_ij(m)| below band_tol times the largest
+                               kernel-row magnitude are dropped; < 0 = default
+                               (1e-9 for F32, 0 for F64) */
+} arkcos_options_t;
+
+/* Summary of a plan (sizes, chosen parameters), for callers and tooling. */
+typedef struct {
+  int64_t npix, nrings, n_pairs, n_table_pairs;
+  int64_t spectrum_modes;   /* complex coefficients held for the input rings */
+  int64_t output_modes;     /* complex coefficients accumulated for the output rings */
+  int64_t pair_modes;       /* sum over ring pairs of the modes accumulated */
+  int64_t taps;             /* kernel samples held for the recurrence */
+  int64_t table_entries;    /* precomputed K_ij(m) values */
+  int32_t oversample, dtype, n_knots;
+  int32_t reserved;
+  size_t workspace_bytes, plan_bytes;
+} arkcos_plan_info_t;
+
+/* Fill *opts with the defaults (oversample 0, kgen 0, fix_pole_pixels 1,
+ * band_tol -1). */
+void arkcos_default_options(arkcos_options_t* opts);
+
+/* Build a plan on the current device: ring and pair tables, the FP64 kernel
+ * samples of every ring pair (step b), bands and optional K_ij(m) tables.
+ * support_radius_rad: R in (0, pi).  opts may be NULL (defaults).  Blocks the
+ * host until the device tables are ready.  *out is set only on success. */
+arkcos_status_t arkcos_plan(const arkcos_geometry_t* geom, const arkcos_profile_t* profile,
+                            double support_radius_rad, arkcos_dtype_t dtype,
+                            const arkcos_options_t* opts, arkcos_plan_t* out);
+
+arkcos_status_t arkcos_plan_destroy(arkcos_plan_t plan);
+arkcos_status_t arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info_t* info);
+
+/* Bytes of device workspace a convolve / adjoint / kernel_grad call needs
+ * (256-byte aligned base required). */
+arkcos_status_t arkcos_workspace_size(arkcos_plan_t plan, size_t* bytes);
+
+/* y = C x (steps a-d).  x, y: device, npix elements of the plan's dtype; they
+ * must not overlap.  ws: device workspace of arkcos_workspace_size bytes.  On
+ * return of the enqueued work the workspace holds the extended spectra of x,
+ * which arkcos_kernel_grad can reuse. */
+arkcos_status_t arkcos_convolve(arkcos_plan_t plan, const void* x, void* y, void* ws,
+                                hipStream_t stream);
+
+/* xbar = C^T r, the exact transpose of arkcos_convolve as a linear map: the
+ * same ring pipeline with the roles of the ring pairs swapped, K_ji and the
+ * pixel weights, i.e. xbar = w * C(r / w); the direct-sum pole rows transpose
+ * into direct-sum columns.  On HEALPix (equal weights) the ring part equals
+ * the forward map. */
+arkcos_status_t arkcos_convolve_adjoint(arkcos_plan_t plan, const void* r, void* xbar, void* ws,
+                                        hipStream_t stream);
+
+/* Gradient of L = 1/2 |C x - t|^2 with respect to the spline knot values,
+ * given r = C x - t:  g_k = <r, (dC/dc_k) x>, a per-ring-pair Fourier-space
+ * correlation of the spectra of r and x reduced over modes and kernel samples
+ * in FP64.  grad: device, n_knots doubles, overwritten.  Spline plans only.
+ * flags bit 0: the workspace still holds the spectra of x from the last
+ * arkcos_convolve(x) on it (skips their recomputation). */
+arkcos_status_t arkcos_kernel_grad(arkcos_plan_t plan, const void* x, const void* r,
+                                   double* grad, void* ws, uint32_t flags, hipStream_t stream);
+
+/* Replace the spline knot values (host array of n_knots doubles) and rebuild
+ * the kernel samples and tables in place.  Blocks the host; must not overlap
+ * with any call using the plan. */
+arkcos_status_t arkcos_set_knots(arkcos_plan_t plan, const double* knot_values);
+
+/* ---- batched form: many maps of uneven size, each with its own plan ---- */
+
+/* Group n plans (same dtype) into one batch: a work queue of (map, output
+ * ring, mode tile) items ordered heaviest first, with tile sizes chosen per
+ * plan by the autotuner.  The plans must outlive the batch. */
+arkcos_status_t arkcos_batch_plan(int32_t n, const arkcos_plan_t* plans, arkcos_batch_t* out);
+arkcos_status_t arkcos_batch_workspace_size(arkcos_batch_t batch, size_t* bytes);
+/* Forward (adjoint = 0) or transpose (adjoint = 1) of every map.  x, y: host
+ * arrays of n device pointers.  One persistent launch performs step (c) for
+ * all maps; the call makes no host synchronisation and no allocation, so it
+ * can be captured in a hipGraph. */
+arkcos_status_t arkcos_batch_convolve(arkcos_batch_t batch, const void* const* x, void* const* y,
+                                      int32_t adjoint, void* ws, hipStream_t stream);
+arkcos_status_t arkcos_batch_destroy(arkcos_batch_t batch);
+
+const char* arkcos_status_string(arkcos_status_t status);
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* arkcos_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARKCOS_H */

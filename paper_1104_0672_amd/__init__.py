@@ -1,0 +1,6 @@
+"""MI355X-native hybrid Fourier/direct-space convolution on the sphere.
+
+The compute path lives in libarkcos.so (HIP for gfx950, C ABI in
+include/arkcos.h); this package only binds it for PyTorch users.
+"""
+from .arkcos import ArkcosError, Plan, load_library  # noqa: F401

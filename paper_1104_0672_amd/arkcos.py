@@ -1,0 +1,234 @@
+"""ctypes binding of libarkcos.so (the C ABI in include/arkcos.h).
+
+Argument marshalling only: every step of the convolution runs in the HIP
+library.  PyTorch supplies device memory and the current stream.  If the
+library is missing the import-time loader raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libarkcos.so")
+
+F32, F64 = 0, 1
+ECP, HEALPIX = 0, 1
+GAUSSIAN, SPLINE = 0, 1
+
+
+class ArkcosError(RuntimeError):
+    pass
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nside", ctypes.c_int64), ("n_theta", ctypes.c_int64),
+                ("n_phi", ctypes.c_int64)]
+
+
+class ProfileC(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("fwhm_rad", ctypes.c_double), ("n_knots", ctypes.c_int32),
+                ("theta_max_rad", ctypes.c_double), ("knot_values", ctypes.POINTER(ctypes.c_double))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("oversample", ctypes.c_int32), ("kgen", ctypes.c_int32),
+                ("fix_pole_pixels", ctypes.c_int32), ("band_tol", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("npix", ctypes.c_int64), ("nrings", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+                ("n_table_pairs", ctypes.c_int64), ("spectrum_modes", ctypes.c_int64),
+                ("output_modes", ctypes.c_int64), ("pair_modes", ctypes.c_int64),
+                ("taps", ctypes.c_int64), ("table_entries", ctypes.c_int64),
+                ("oversample", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n_knots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t),
+                ("plan_bytes", ctypes.c_size_t)]
+
+
+EXPORTED = ["arkcos_default_options", "arkcos_plan", "arkcos_plan_destroy", "arkcos_plan_get_info",
+            "arkcos_workspace_size", "arkcos_convolve", "arkcos_convolve_adjoint", "arkcos_kernel_grad",
+            "arkcos_set_knots", "arkcos_batch_plan", "arkcos_batch_workspace_size",
+            "arkcos_batch_convolve", "arkcos_batch_destroy", "arkcos_status_string", "arkcos_last_error"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libarkcos.so and declare its signatures.  Raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ArkcosError(f"{path} not found: build it with `python -m paper_1104_0672_amd.build` "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, st, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int32, ctypes.c_double
+    lib.arkcos_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.arkcos_default_options.restype = None
+    lib.arkcos_plan.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(ProfileC), dbl, i32,
+                                ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    lib.arkcos_plan_destroy.argtypes = [vp]
+    lib.arkcos_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.arkcos_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.arkcos_convolve.argtypes = [vp, vp, vp, vp, vp]
+    lib.arkcos_convolve_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    lib.arkcos_kernel_grad.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint32, vp]
+    lib.arkcos_set_knots.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.arkcos_batch_plan.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.arkcos_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.arkcos_batch_convolve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, vp]
+    lib.arkcos_batch_destroy.argtypes = [vp]
+    lib.arkcos_status_string.argtypes = [st]
+    lib.arkcos_status_string.restype = ctypes.c_char_p
+    lib.arkcos_last_error.argtypes = []
+    lib.arkcos_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        f = getattr(lib, name)
+        if f.restype is ctypes.c_int or name in ("arkcos_plan", "arkcos_plan_destroy"):
+            f.restype = st
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        lib = load_library()
+        raise ArkcosError(f"{what}: {lib.arkcos_status_string(status).decode()} "
+                          f"({lib.arkcos_last_error().decode()})")
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A convolution plan: geometry, kernel profile, support radius, dtype.
+
+    Maps are 1-D torch tensors on the plan's device with npix elements
+    (RING order) of the plan's dtype.
+    """
+
+    def __init__(self, grid: str, radius: float, *, nside: int = 0, ntheta: int = 0, nphi: int = 0,
+                 fwhm: float = 0.0, knots: Optional[Sequence[float]] = None, theta_max: float = 0.0,
+                 dtype: str = "f32", oversample: int = 0, kgen: int = 0, fix_pole_pixels: bool = True,
+                 band_tol: float = -1.0):
+        lib = load_library()
+        self._lib = lib
+        self.handle = ctypes.c_void_p()
+        geom = Geometry(HEALPIX if grid == "healpix" else ECP, nside, ntheta, nphi)
+        self._knots = None
+        if knots is not None:
+            self._knots = (ctypes.c_double * len(knots))(*[float(v) for v in knots])
+            prof = ProfileC(SPLINE, 0.0, len(knots), float(theta_max),
+                            ctypes.cast(self._knots, ctypes.POINTER(ctypes.c_double)))
+        else:
+            prof = ProfileC(GAUSSIAN, float(fwhm), 0, 0.0, None)
+        opts = Options(int(oversample), int(kgen), int(bool(fix_pole_pixels)), float(band_tol))
+        self.dtype = torch.float32 if dtype == "f32" else torch.float64
+        self.grid = grid
+        _check(lib.arkcos_plan(ctypes.byref(geom), ctypes.byref(prof), float(radius),
+                               F32 if dtype == "f32" else F64, ctypes.byref(opts),
+                               ctypes.byref(self.handle)), "arkcos_plan")
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        info = PlanInfo()
+        _check(lib.arkcos_plan_get_info(self.handle, ctypes.byref(info)), "arkcos_plan_get_info")
+        self.info = info
+        self.npix = int(info.npix)
+        self.n_knots = int(info.n_knots)
+        self._ws = None
+
+    @classmethod
+    def from_workload(cls, w, **kw) -> "Plan":
+        g, p = w.grid, w.profile
+        args = dict(nside=g.nside, ntheta=g.ntheta, nphi=g.nphi, dtype=w.dtype)
+        if p.kind == "gaussian":
+            args["fwhm"] = p.fwhm
+        else:
+            args["knots"] = list(p.knots)
+            args["theta_max"] = p.theta_max
+        args.update(kw)
+        return cls(g.kind, w.radius, **args)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                self._lib.arkcos_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    # --------------------------------------------------------------- memory
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.info.workspace_bytes)
+
+    def workspace(self) -> torch.Tensor:
+        """A cached workspace for calls on the current stream."""
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _ws_ptr(self, ws: Optional[torch.Tensor]) -> ctypes.c_void_p:
+        ws = self.workspace() if ws is None else ws
+        if ws.numel() < self.workspace_bytes or not ws.is_cuda:
+            raise ArkcosError("workspace too small")
+        addr = ws.data_ptr()
+        addr = (addr + 255) // 256 * 256
+        if addr + self.workspace_bytes > ws.data_ptr() + ws.numel():
+            raise ArkcosError("workspace too small after alignment")
+        return ctypes.c_void_p(addr)
+
+    def _map(self, t: torch.Tensor, name: str) -> torch.Tensor:
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise ArkcosError(f"{name} must be a CUDA tensor")
+        if t.dtype != self.dtype or t.numel() != self.npix or not t.is_contiguous():
+            raise ArkcosError(f"{name} must be a contiguous {self.dtype} tensor with {self.npix} elements")
+        return t
+
+    # ----------------------------------------------------------- operations
+    def convolve(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, ws=None, stream=None):
+        x = self._map(x, "x")
+        y = torch.empty_like(x) if out is None else self._map(out, "out")
+        _check(self._lib.arkcos_convolve(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                         ctypes.c_void_p(y.data_ptr()), self._ws_ptr(ws),
+                                         _stream_ptr(stream)), "arkcos_convolve")
+        return y
+
+    def adjoint(self, r: torch.Tensor, out: Optional[torch.Tensor] = None, ws=None, stream=None):
+        r = self._map(r, "r")
+        xb = torch.empty_like(r) if out is None else self._map(out, "out")
+        _check(self._lib.arkcos_convolve_adjoint(self.handle, ctypes.c_void_p(r.data_ptr()),
+                                                 ctypes.c_void_p(xb.data_ptr()), self._ws_ptr(ws),
+                                                 _stream_ptr(stream)), "arkcos_convolve_adjoint")
+        return xb
+
+    def kernel_grad(self, x: torch.Tensor, r: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    ws=None, reuse_spectra: bool = False, stream=None):
+        x = self._map(x, "x")
+        r = self._map(r, "r")
+        g = torch.empty(self.n_knots, dtype=torch.float64, device=x.device) if out is None else out
+        _check(self._lib.arkcos_kernel_grad(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                            self._ws_ptr(ws), 1 if reuse_spectra else 0,
+                                            _stream_ptr(stream)), "arkcos_kernel_grad")
+        return g
+
+    def set_knots(self, knots: Sequence[float]):
+        arr = (ctypes.c_double * self.n_knots)(*[float(v) for v in knots])
+        _check(self._lib.arkcos_set_knots(self.handle, arr), "arkcos_set_knots")
+
+
+def pixel_bytes(plan: Plan) -> int:
+    return torch.tensor([], dtype=plan.dtype).element_size()
+
+
+def fwhm_to_sigma(fwhm: float) -> float:
+    return fwhm / math.sqrt(8.0 * math.log(2.0))

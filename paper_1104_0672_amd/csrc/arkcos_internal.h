@@ -1,0 +1,153 @@
+// Internal structures shared by the host plan builder, the C ABI and the HIP
+// kernels of the ARKCoS library.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "arkcos.h"
+
+namespace arkcos {
+
+constexpr double kSupportTol = 1e-9;   // pairs with theta <= R + 1e-9 are inside
+constexpr int kBlock = 256;            // threads per block for every kernel
+constexpr int kModeTile = 256;         // modes per accumulation work item
+constexpr int kDirectMax = 64;         // rings up to this length use a plain DFT
+constexpr int kOtfMaxCoef = 48;        // wider kernel rows use a K_ij(m) table (auto mode)
+
+// FFT strategy of one ring length.
+enum FftKind : int32_t { FFT_DIRECT = 0, FFT_POW2 = 1, FFT_BLUESTEIN = 2 };
+
+// K_ij(m) source of one ring pair.
+//  KG_CENTRED  : nodes 2 pi d / (p L), recurrence on cos(m nu)
+//  KG_SHIFTED  : nodes 2 pi (d + 1/2) / L (equatorial pairs offset by pi/L)
+//  KG_TABLE    : precomputed K_ij(m), m <= band
+enum PairKind : int32_t { KG_CENTRED = 0, KG_SHIFTED = 1, KG_TABLE = 2 };
+
+// Per-ring table, device side (struct of arrays).
+struct RingTables {
+  int32_t* n = nullptr;          // pixels in the ring
+  int64_t* start = nullptr;      // first pixel (RING order)
+  int32_t* phase_den = nullptr;  // longitude offset phi0 = pi / phase_den (0: none)
+  int32_t* fft_kind = nullptr;
+  int32_t* fft_m = nullptr;      // pow2: n/2; Bluestein: convolution length M
+  int64_t* bl_off = nullptr;     // Bluestein filter offset (complex elements)
+  int64_t* spec_off = nullptr;   // extended spectrum offset (complex elements)
+  int32_t* spec_len = nullptr;   // extended spectrum length (modes 0 .. len-1)
+  int64_t* out_off = nullptr;    // B_i offset (complex elements)
+  int32_t* out_len = nullptr;    // B_i length
+  double* w = nullptr;           // pixel area of the ring
+};
+
+// One ring pair (i, j) of a north output ring i; its mirror pair (i', j')
+// with i' = nr-1-i, j' = nr-1-j uses the same K_ij(m).
+struct PairDev {
+  int32_t j;         // input ring
+  int32_t kind;      // PairKind
+  int32_t band;      // K_ij(m) = 0 for m > band
+  int32_t nyq;       // p L / 2: this mode carries half weight
+  int32_t ncoef;     // recurrence coefficients (KG_CENTRED / KG_SHIFTED)
+  int32_t p;         // oversampling of the kernel grid
+  int64_t off;       // coefficient offset (recurrence) or table offset
+};
+
+// An output unit: a north ring i and its mirror (or -1 for the self-mirror ring).
+struct UnitDev {
+  int32_t i, im;
+  int32_t pbeg, pend;   // pairs [pbeg, pend)
+  int32_t band;         // max band over the unit's pairs
+  int32_t pad;
+};
+
+struct WorkItem {
+  int32_t unit;
+  int32_t m0;
+};
+
+}  // namespace arkcos
+
+struct arkcos_plan_s {
+  int device = 0;
+  arkcos_dtype_t dtype = ARKCOS_F32;
+  arkcos_geometry_t geom{};
+  int32_t prof_kind = 0;
+  double fwhm = 0, theta_max = 0, radius = 0;
+  std::vector<double> knots;
+  arkcos_options_t opts{};
+  int32_t oversample = 1;
+  double band_tol = 0;
+
+  int64_t npix = 0, nrings = 0, L = 0;
+  int64_t n_units = 0, n_pairs = 0, n_table_pairs = 0;
+  int64_t spec_total = 0, out_total = 0, coef_total = 0, table_total = 0, bl_total = 0;
+  int64_t pair_modes = 0;
+  int32_t max_fft_lds = 0;     // bytes of LDS the ring FFT kernels need
+  int32_t max_bl_m = 0;
+  int32_t twiddle_n = 0;       // length of the twiddle table (largest power-of-two FFT)
+  int32_t max_units_pairs = 0;
+  int32_t max_coef_per_unit = 0;
+
+  // host copies
+  std::vector<double> h_theta, h_sin, h_cos, h_w;
+  std::vector<int32_t> h_n, h_phase_den;
+  std::vector<int64_t> h_start;
+  std::vector<arkcos::UnitDev> h_units;
+  std::vector<arkcos::PairDev> h_pairs;
+  std::vector<int32_t> h_pair_i;         // output ring of each pair
+  std::vector<int32_t> h_pair_shift;     // half-shift flag per pair
+  std::vector<int64_t> h_coef_off;       // recurrence-coefficient offset per pair
+  std::vector<arkcos::WorkItem> h_items;
+  std::vector<int32_t> h_spec_len, h_out_len;
+  std::vector<int64_t> h_spec_off, h_out_off;
+
+  // device
+  arkcos::RingTables rt;
+  arkcos::UnitDev* d_units = nullptr;
+  arkcos::PairDev* d_pairs = nullptr;
+  arkcos::WorkItem* d_items = nullptr;
+  void* d_coef = nullptr;       // recurrence coefficients, plan dtype
+  double* d_coef64 = nullptr;   // the same in FP64 (plan-time table building, gradient)
+  void* d_table = nullptr;      // K_ij(m) tables, plan dtype
+  void* d_bl = nullptr;         // Bluestein filters, complex plan dtype
+  void* d_twiddle = nullptr;    // exp(-2 pi i k / twiddle_n), complex plan dtype
+  double* d_theta = nullptr;    // ring colatitudes
+  double* d_sin = nullptr;
+  double* d_cos = nullptr;
+  double* d_knots = nullptr;    // spline knot values
+  double* d_spline_mom = nullptr;   // spline moments of the current knots
+  int32_t* d_pair_i = nullptr;
+  int32_t* d_pair_shift = nullptr;
+  int64_t* d_coef_off = nullptr;    // recurrence-coefficient offset of every pair
+  int32_t* d_pole_rings = nullptr;  // rings within reach of a pole pixel
+  int32_t n_pole_rings = 0;
+  size_t plan_bytes = 0;
+
+  std::vector<void*> allocations;
+};
+
+namespace arkcos {
+
+void set_error(const std::string& msg);
+arkcos_status_t fail(arkcos_status_t st, const std::string& msg);
+
+// Kernel launchers (defined next to their kernels).
+hipError_t launch_kernel_rows(arkcos_plan_s* P, double* coef_abs_sum, hipStream_t s);
+hipError_t launch_band(arkcos_plan_s* P, double threshold, int32_t* band_out, hipStream_t s);
+hipError_t launch_table_list(arkcos_plan_s* P, const int32_t* d_list, const int64_t* d_coef_off,
+                             int32_t count, hipStream_t s);
+hipError_t configure_fft_kernels(arkcos_plan_s* P);
+int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count);
+void workspace_split(const arkcos_plan_s* P, void* ws, void** spec, void** bout);
+size_t workspace_bytes(const arkcos_plan_s* P);
+hipError_t launch_bluestein_filters(arkcos_plan_s* P, const int32_t* d_ring_list, int32_t count,
+                                    hipStream_t s);
+hipError_t launch_r2c(arkcos_plan_s* P, const void* x, void* spec, int32_t adjoint,
+                      int32_t zero_pole_rings, hipStream_t s);
+hipError_t launch_accumulate(arkcos_plan_s* P, const void* spec, void* bout, hipStream_t s);
+hipError_t launch_c2r(arkcos_plan_s* P, const void* bout, void* y, int32_t adjoint, hipStream_t s);
+hipError_t launch_pole_fix(arkcos_plan_s* P, const void* x, void* y, int32_t adjoint, hipStream_t s);
+
+}  // namespace arkcos

@@ -1,0 +1,208 @@
+// The extern "C" entry points declared in include/arkcos.h: argument checks
+// on the host, then asynchronous launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "arkcos_internal.h"
+
+namespace arkcos {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+arkcos_status_t fail(arkcos_status_t st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* prof, double R,
+                           arkcos_dtype_t dtype, const arkcos_options_t* o, arkcos_plan_s** out);
+arkcos_status_t upload_knots(arkcos_plan_s* P);
+arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time);
+arkcos_status_t run_kernel_grad(arkcos_plan_s* P, const void* x, const void* r, double* grad,
+                                void* ws, uint32_t flags, hipStream_t s);
+
+static size_t elem_size(const arkcos_plan_s* P) {
+  return P->dtype == ARKCOS_F32 ? sizeof(float) : sizeof(double);
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+static arkcos_status_t check_device(const arkcos_plan_s* P) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(ARKCOS_ERR_DEVICE, "hipGetDevice failed");
+  if (dev != P->device) return fail(ARKCOS_ERR_INVALID_VALUE, "plan was created on another device");
+  return ARKCOS_OK;
+}
+
+static arkcos_status_t check_maps(const arkcos_plan_s* P, const void* in, const void* out, const void* ws) {
+  if (!in || !out || !ws) return fail(ARKCOS_ERR_INVALID_VALUE, "null map or workspace pointer");
+  const size_t bytes = (size_t)P->npix * elem_size(P);
+  if (overlaps(in, bytes, out, bytes)) return fail(ARKCOS_ERR_INVALID_VALUE, "input and output maps overlap");
+  const size_t wsb = workspace_bytes(P);
+  if (overlaps(in, bytes, ws, wsb) || overlaps(out, bytes, ws, wsb))
+    return fail(ARKCOS_ERR_INVALID_VALUE, "workspace overlaps a map");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(ARKCOS_ERR_INVALID_VALUE, "workspace must be 256-byte aligned");
+  if (reinterpret_cast<uintptr_t>(in) % elem_size(P) || reinterpret_cast<uintptr_t>(out) % elem_size(P))
+    return fail(ARKCOS_ERR_INVALID_VALUE, "misaligned map pointer");
+  return check_device(P);
+}
+
+void workspace_split(const arkcos_plan_s* P, void* ws, void** spec, void** bout) {
+  const size_t csz = P->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
+  size_t a = ((size_t)std::max<int64_t>(P->spec_total, 1) * csz + 255) / 256 * 256;
+  *spec = ws;
+  *bout = static_cast<char*>(ws) + a;
+}
+
+#define LAUNCH(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+arkcos_status_t run_pipeline(arkcos_plan_s* P, const void* x, void* y, void* ws, int adjoint,
+                             hipStream_t s) {
+  void *spec, *bout;
+  workspace_split(P, ws, &spec, &bout);
+  const bool fix = P->geom.kind == 1 && P->opts.fix_pole_pixels;
+  LAUNCH(launch_r2c(P, x, spec, adjoint, adjoint && fix ? 1 : 0, s));
+  LAUNCH(launch_accumulate(P, spec, bout, s));
+  LAUNCH(launch_c2r(P, bout, y, adjoint, s));
+  if (fix) LAUNCH(launch_pole_fix(P, x, y, adjoint, s));
+  return ARKCOS_OK;
+}
+
+}  // namespace arkcos
+
+using namespace arkcos;
+
+extern "C" {
+
+void arkcos_default_options(arkcos_options_t* o) {
+  if (!o) return;
+  o->oversample = 0;
+  o->kgen = 0;
+  o->fix_pole_pixels = 1;
+  o->band_tol = -1.0;
+}
+
+arkcos_status_t arkcos_plan(const arkcos_geometry_t* geom, const arkcos_profile_t* profile,
+                            double support_radius_rad, arkcos_dtype_t dtype,
+                            const arkcos_options_t* opts, arkcos_plan_t* out) {
+  g_last_error.clear();
+  try {
+    return build_plan(geom, profile, support_radius_rad, dtype, opts, out);
+  } catch (const std::bad_alloc&) {
+    return fail(ARKCOS_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(ARKCOS_ERR_INTERNAL, "unexpected exception in plan creation");
+  }
+}
+
+arkcos_status_t arkcos_plan_destroy(arkcos_plan_t plan) {
+  if (!plan) return fail(ARKCOS_ERR_INVALID_VALUE, "null plan");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != plan->device) (void)hipSetDevice(plan->device);
+  for (void* a : plan->allocations) (void)hipFree(a);
+  if (cur != plan->device) (void)hipSetDevice(cur);
+  delete plan;
+  return ARKCOS_OK;
+}
+
+arkcos_status_t arkcos_plan_get_info(arkcos_plan_t P, arkcos_plan_info_t* info) {
+  if (!P || !info) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
+  std::memset(info, 0, sizeof(*info));
+  info->npix = P->npix;
+  info->nrings = P->nrings;
+  for (const auto& U : P->h_units) info->n_pairs += (int64_t)(U.pend - U.pbeg) * (U.im >= 0 ? 2 : 1);
+  info->n_table_pairs = P->n_table_pairs;
+  info->spectrum_modes = P->spec_total;
+  info->output_modes = P->out_total;
+  info->pair_modes = P->pair_modes;
+  info->taps = P->coef_total;
+  info->table_entries = P->table_total;
+  info->oversample = P->oversample;
+  info->dtype = P->dtype;
+  info->n_knots = (int32_t)P->knots.size();
+  info->workspace_bytes = workspace_bytes(P);
+  info->plan_bytes = P->plan_bytes;
+  return ARKCOS_OK;
+}
+
+arkcos_status_t arkcos_workspace_size(arkcos_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
+  *bytes = workspace_bytes(plan);
+  return ARKCOS_OK;
+}
+
+arkcos_status_t arkcos_convolve(arkcos_plan_t plan, const void* x, void* y, void* ws, hipStream_t stream) {
+  if (!plan) return fail(ARKCOS_ERR_INVALID_VALUE, "null plan");
+  arkcos_status_t st = check_maps(plan, x, y, ws);
+  if (st != ARKCOS_OK) return st;
+  return run_pipeline(plan, x, y, ws, 0, stream);
+}
+
+arkcos_status_t arkcos_convolve_adjoint(arkcos_plan_t plan, const void* r, void* xbar, void* ws,
+                                        hipStream_t stream) {
+  if (!plan) return fail(ARKCOS_ERR_INVALID_VALUE, "null plan");
+  arkcos_status_t st = check_maps(plan, r, xbar, ws);
+  if (st != ARKCOS_OK) return st;
+  return run_pipeline(plan, r, xbar, ws, 1, stream);
+}
+
+arkcos_status_t arkcos_kernel_grad(arkcos_plan_t plan, const void* x, const void* r, double* grad,
+                                   void* ws, uint32_t flags, hipStream_t stream) {
+  if (!plan) return fail(ARKCOS_ERR_INVALID_VALUE, "null plan");
+  if (plan->prof_kind != 1) return fail(ARKCOS_ERR_NOT_SUPPORTED, "knot gradient needs a spline profile");
+  if (!grad) return fail(ARKCOS_ERR_INVALID_VALUE, "null gradient pointer");
+  if (!x || !r || !ws) return fail(ARKCOS_ERR_INVALID_VALUE, "null map or workspace pointer");
+  const size_t bytes = (size_t)plan->npix * elem_size(plan);
+  const size_t wsb = workspace_bytes(plan);
+  if (overlaps(x, bytes, ws, wsb) || overlaps(r, bytes, ws, wsb) ||
+      overlaps(grad, plan->knots.size() * sizeof(double), ws, wsb))
+    return fail(ARKCOS_ERR_INVALID_VALUE, "workspace overlaps an argument");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(ARKCOS_ERR_INVALID_VALUE, "workspace must be 256-byte aligned");
+  arkcos_status_t st = check_device(plan);
+  if (st != ARKCOS_OK) return st;
+  return run_kernel_grad(plan, x, r, grad, ws, flags, stream);
+}
+
+arkcos_status_t arkcos_set_knots(arkcos_plan_t plan, const double* knot_values) {
+  if (!plan || !knot_values) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
+  if (plan->prof_kind != 1) return fail(ARKCOS_ERR_NOT_SUPPORTED, "plan has no spline profile");
+  arkcos_status_t st = check_device(plan);
+  if (st != ARKCOS_OK) return st;
+  try {
+    plan->knots.assign(knot_values, knot_values + plan->knots.size());
+    st = upload_knots(plan);
+    if (st != ARKCOS_OK) return st;
+    return build_kernel_tables(plan, false);
+  } catch (...) {
+    return fail(ARKCOS_ERR_INTERNAL, "unexpected exception in knot update");
+  }
+}
+
+const char* arkcos_status_string(arkcos_status_t s) {
+  switch (s) {
+    case ARKCOS_OK: return "ARKCOS_OK";
+    case ARKCOS_ERR_INVALID_VALUE: return "ARKCOS_ERR_INVALID_VALUE";
+    case ARKCOS_ERR_NOT_SUPPORTED: return "ARKCOS_ERR_NOT_SUPPORTED";
+    case ARKCOS_ERR_OUT_OF_MEMORY: return "ARKCOS_ERR_OUT_OF_MEMORY";
+    case ARKCOS_ERR_DEVICE: return "ARKCOS_ERR_DEVICE";
+    case ARKCOS_ERR_INTERNAL: return "ARKCOS_ERR_INTERNAL";
+  }
+  return "ARKCOS_UNKNOWN_STATUS";
+}
+
+const char* arkcos_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,247 @@
+// Ring transforms: step (a) and step (d) of the hybrid method (paper
+// Sect. 4.1, with the artifact suppression of Sect. 4.3).
+//
+// Step (a), per input ring j of N_j pixels at longitudes phi0_j + 2 pi k / N_j:
+//   A_j(m) = sum_k x_jk exp(-2 pi i m k / N_j),  m = 0 .. N_j/2,
+// then the phase shift to absolute longitude (eq. "fftrot") and the periodic
+// extension past the ring's Nyquist mode:
+//   A~_j(m) = A_j(m mod N_j) exp(-i m phi0_j),  m = 0 .. spec_len_j - 1,
+// where A_j(N_j - r) = conj(A_j(r)).
+//
+// Step (d), per output ring i:
+//   G_i(r) = sum_{m = r mod N_i} B_i(m) e^{i m phi0_i} + sum_{m = -r mod N_i, m > 0} conj(B_i(m) e^{i m phi0_i}),
+//   y_ik   = sum_{r < N_i} G_i(r) exp(2 pi i r k / N_i)     (inverse real FFT),
+// i.e. the reverse phase shift and the aliasing of super-Nyquist modes onto
+// the ring's own modes.
+//
+// A real ring of even length N is transformed as a complex sequence of length
+// N/2 (even samples in the real part, odd samples in the imaginary part) with
+// the usual split; the complex DFT is a power-of-two LDS FFT or, for other
+// lengths, Bluestein's chirp convolution through a power-of-two FFT.  Rings of
+// up to 64 pixels use a plain DFT.  One block transforms one ring.
+#include "arkcos_internal.h"
+#include "device_common.h"
+
+namespace arkcos {
+
+template <typename R> struct RingArgs {
+  const int32_t* n;
+  const int64_t* start;
+  const int32_t* phase_den;
+  const int32_t* fft_kind;
+  const int32_t* fft_m;
+  const int64_t* bl_off;
+  const int64_t* off;    // spectrum (step a) or B (step d) offsets
+  const int32_t* len;
+  const double* w;
+  const cx_t<R>* bl;
+  const cx_t<R>* tw;
+  int32_t TN;
+  int32_t nrings;
+  int32_t adjoint;
+  int32_t zero_pole_rings;
+};
+
+// exp(-i m phi0) for phi0 = pi / den (den = 0: no offset).
+template <typename R> __device__ __forceinline__ cx_t<R> unshift(int m, int den) {
+  using C = cx_t<R>;
+  if (den == 0) return cmake<C>(R(1), R(0));
+  int t = (int)(((int64_t)m) % (2 * (int64_t)den));
+  return cconj(expipi<R>(t, den));
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) r2c_kernel(RingArgs<R> a, const R* __restrict__ x,
+                                                     cx_t<R>* __restrict__ spec) {
+  using C = cx_t<R>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* buf = reinterpret_cast<C*>(smem);
+  const int j = blockIdx.x;
+  const int N = a.n[j], half = N / 2, kind = a.fft_kind[j];
+  const int den = a.phase_den[j], len = a.len[j];
+  C* out = spec + a.off[j];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if (a.zero_pole_rings && (j == 0 || j == a.nrings - 1)) {
+    for (int m = tid; m < len; m += nth) out[m] = cmake<C>(R(0), R(0));
+    return;
+  }
+  const R scale = a.adjoint ? R(1.0 / a.w[j]) : R(1);
+  const R* xr = x + a.start[j];
+  if (kind == FFT_DIRECT) {
+    C* tab = buf + (half + 1);
+    R* xs = reinterpret_cast<R*>(tab + N);
+    for (int t = tid; t < N; t += nth) {
+      tab[t] = cconj(expipi<R>(2 * t, N));  // exp(-2 pi i t / N)
+      xs[t] = xr[t] * scale;
+    }
+    __syncthreads();
+    for (int m = tid; m <= half; m += nth) {
+      C acc = cmake<C>(R(0), R(0));
+      int idx = 0;
+      for (int k = 0; k < N; ++k) {
+        acc = cadd(acc, cscale(tab[idx], xs[k]));
+        idx += m;
+        if (idx >= N) idx -= N;
+      }
+      buf[m] = acc;
+    }
+    __syncthreads();
+  } else {
+    const int n = half;
+    for (int l = tid; l < n; l += nth) buf[l] = cmake<C>(xr[2 * l] * scale, xr[2 * l + 1] * scale);
+    __syncthreads();
+    if (kind == FFT_POW2)
+      ring_dft<R, false>(buf, n, 1, n, nullptr, a.tw, a.TN);
+    else
+      ring_dft<R, false>(buf, n, 2, a.fft_m[j], a.bl + a.bl_off[j], a.tw, a.TN);
+    // split Z into A(r) = E(r) + exp(-2 pi i r / N) O(r), in place, pairing r with n - r
+    for (int r = tid; r <= n / 2; r += nth) {
+      int r2 = n - r;
+      C z1 = buf[r], z2 = buf[r2 == n ? 0 : r2];
+      // A(r)
+      C e = cscale(cadd(z1, cconj(z2)), R(0.5));
+      C o = cscale(csub(z1, cconj(z2)), R(0.5));  // times -i below
+      C om = cmake<C>(o.y, -o.x);
+      C ar = cadd(e, cmul(cconj(expipi<R>(2 * r, N)), om));
+      // A(r2)
+      C e2 = cscale(cadd(z2, cconj(z1)), R(0.5));
+      C o2 = cscale(csub(z2, cconj(z1)), R(0.5));
+      C om2 = cmake<C>(o2.y, -o2.x);
+      C ar2 = cadd(e2, cmul(cconj(expipi<R>(2 * r2, N)), om2));
+      buf[r] = ar;
+      if (r2 != r) buf[r2] = ar2;
+    }
+    __syncthreads();
+  }
+  // periodic extension with the phase shift to absolute longitude
+  for (int m = tid; m < len; m += nth) {
+    int r = m % N;
+    C v = r <= half ? buf[r] : cconj(buf[N - r]);
+    out[m] = cmul(v, unshift<R>(m, den));
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) c2r_kernel(RingArgs<R> a, const cx_t<R>* __restrict__ bin,
+                                                     R* __restrict__ y) {
+  using C = cx_t<R>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* buf = reinterpret_cast<C*>(smem);
+  const int i = blockIdx.x;
+  const int N = a.n[i], half = N / 2, kind = a.fft_kind[i];
+  const int den = a.phase_den[i], len = a.len[i];
+  const C* b = bin + a.off[i];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const R scale = a.adjoint ? R(a.w[i]) : R(1);
+  // fold: reverse phase shift and aliasing onto m mod N
+  for (int r = tid; r <= half; r += nth) {
+    C g = cmake<C>(R(0), R(0));
+    for (int m = r; m < len; m += N) g = cadd(g, cmul(b[m], cconj(unshift<R>(m, den))));
+    for (int m = (r == 0 ? N : N - r); m < len; m += N)
+      g = cadd(g, cconj(cmul(b[m], cconj(unshift<R>(m, den)))));
+    buf[r] = cscale(g, scale);
+  }
+  __syncthreads();
+  R* yr = y + a.start[i];
+  if (kind == FFT_DIRECT) {
+    C* tab = buf + (half + 1);
+    for (int t = tid; t < N; t += nth) tab[t] = expipi<R>(2 * t, N);  // exp(+2 pi i t / N)
+    __syncthreads();
+    for (int k = tid; k < N; k += nth) {
+      R acc = buf[0].x + ((k & 1) ? -buf[half].x : buf[half].x);
+      int idx = k;
+      for (int r = 1; r < half; ++r) {
+        C t = tab[idx];
+        acc += R(2) * (buf[r].x * t.x - buf[r].y * t.y);
+        idx += k;
+        if (idx >= N) idx -= N;
+      }
+      yr[k] = acc;
+    }
+    return;
+  }
+  const int n = half;
+  // Z(r) = E(r) + i O(r), E(r) = G(r) + conj(G(n-r)), O(r) = e^{2 pi i r/N} (G(r) - conj(G(n-r)))
+  for (int r = tid; r <= n / 2; r += nth) {
+    int r2 = n - r;
+    C g1 = buf[r], g2 = buf[r2];
+    C e1 = cadd(g1, cconj(g2));
+    C o1 = cmul(expipi<R>(2 * r, N), csub(g1, cconj(g2)));
+    C z1 = cadd(e1, cmake<C>(-o1.y, o1.x));
+    buf[r] = z1;
+    if (r2 < n && r2 != r) {
+      C e2 = cadd(g2, cconj(g1));
+      C o2 = cmul(expipi<R>(2 * r2, N), csub(g2, cconj(g1)));
+      buf[r2] = cadd(e2, cmake<C>(-o2.y, o2.x));
+    }
+  }
+  __syncthreads();
+  if (kind == FFT_POW2)
+    ring_dft<R, true>(buf, n, 1, n, nullptr, a.tw, a.TN);
+  else
+    ring_dft<R, true>(buf, n, 2, a.fft_m[i], a.bl + a.bl_off[i], a.tw, a.TN);
+  for (int l = tid; l < n; l += nth) {
+    C z = buf[l];
+    yr[2 * l] = z.x;
+    yr[2 * l + 1] = z.y;
+  }
+}
+
+template <typename R> static RingArgs<R> ring_args(arkcos_plan_s* P, bool out_side, int adjoint,
+                                                   int zero_pole) {
+  RingArgs<R> a{};
+  a.n = P->rt.n;
+  a.start = P->rt.start;
+  a.phase_den = P->rt.phase_den;
+  a.fft_kind = P->rt.fft_kind;
+  a.fft_m = P->rt.fft_m;
+  a.bl_off = P->rt.bl_off;
+  a.off = out_side ? P->rt.out_off : P->rt.spec_off;
+  a.len = out_side ? P->rt.out_len : P->rt.spec_len;
+  a.w = P->rt.w;
+  a.bl = (const cx_t<R>*)P->d_bl;
+  a.tw = (const cx_t<R>*)P->d_twiddle;
+  a.TN = P->twiddle_n;
+  a.nrings = (int32_t)P->nrings;
+  a.adjoint = adjoint;
+  a.zero_pole_rings = zero_pole;
+  return a;
+}
+
+hipError_t configure_fft_kernels(arkcos_plan_s* P) {
+  if (P->max_fft_lds <= 65536) return hipSuccess;
+  hipError_t e;
+  if (P->dtype == ARKCOS_F32) {
+    e = hipFuncSetAttribute((const void*)r2c_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_fft_lds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)c2r_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_fft_lds);
+  } else {
+    e = hipFuncSetAttribute((const void*)r2c_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_fft_lds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)c2r_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_fft_lds);
+  }
+  return e;
+}
+
+hipError_t launch_r2c(arkcos_plan_s* P, const void* x, void* spec, int32_t adjoint,
+                      int32_t zero_pole_rings, hipStream_t s) {
+  if (P->dtype == ARKCOS_F32)
+    r2c_kernel<float><<<(unsigned)P->nrings, kBlock, P->max_fft_lds, s>>>(
+        ring_args<float>(P, false, adjoint, zero_pole_rings), (const float*)x, (float2*)spec);
+  else
+    r2c_kernel<double><<<(unsigned)P->nrings, kBlock, P->max_fft_lds, s>>>(
+        ring_args<double>(P, false, adjoint, zero_pole_rings), (const double*)x, (double2*)spec);
+  return hipGetLastError();
+}
+
+hipError_t launch_c2r(arkcos_plan_s* P, const void* bout, void* y, int32_t adjoint, hipStream_t s) {
+  if (P->dtype == ARKCOS_F32)
+    c2r_kernel<float><<<(unsigned)P->nrings, kBlock, P->max_fft_lds, s>>>(
+        ring_args<float>(P, true, adjoint, 0), (const float2*)bout, (float*)y);
+  else
+    c2r_kernel<double><<<(unsigned)P->nrings, kBlock, P->max_fft_lds, s>>>(
+        ring_args<double>(P, true, adjoint, 0), (const double2*)bout, (double*)y);
+  return hipGetLastError();
+}
+
+}  // namespace arkcos

@@ -1,0 +1,552 @@
+// Host side of plan creation: ring geometry, ring pairs inside the kernel
+// support, kernel-sample windows, bands, tables, FFT strategies and the
+// device-memory layout of spectra and output coefficients.
+//
+// Geometry (paper Sect. 4.1; HEALPix after Gorski et al. 2005): rings
+// r = 1 .. 4 nside - 1; polar rings hold 4r pixels offset by pi/(4r) at
+// z = 1 - r^2/(3 nside^2); equatorial rings hold 4 nside pixels at
+// z = 4/3 - 2r/(3 nside), offset by pi/(4 nside) when r - nside is even; the
+// south cap mirrors the north.  ECP rings are at theta_i = (i + 1/2) pi / n_theta
+// with n_phi unshifted pixels and band areas as weights.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "arkcos_internal.h"
+
+namespace arkcos {
+
+namespace {
+
+struct Status {
+  arkcos_status_t st = ARKCOS_OK;
+  std::string msg;
+};
+
+template <typename T> hipError_t dev_alloc(arkcos_plan_s* P, T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess) return e;
+  P->allocations.push_back(p);
+  P->plan_bytes += count * sizeof(T);
+  *ptr = static_cast<T*>(p);
+  return hipSuccess;
+}
+
+template <typename T> hipError_t upload(arkcos_plan_s* P, T** ptr, const std::vector<T>& v) {
+  hipError_t e = dev_alloc(P, ptr, v.size());
+  if (e != hipSuccess || v.empty()) return e;
+  return hipMemcpy(*ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+int64_t next_pow2(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Clamped cubic spline moments (second derivatives at the knots) for
+// equispaced knots with spacing h; end slopes zero.
+void spline_moments(const std::vector<double>& c, double h, std::vector<double>& M) {
+  const int n = (int)c.size();
+  std::vector<double> sub(n), diag(n), sup(n), rhs(n);
+  const double s = 6.0 / (h * h);
+  for (int k = 0; k < n; ++k) {
+    if (k == 0) { sub[k] = 0; diag[k] = 2; sup[k] = 1; rhs[k] = s * (c[1] - c[0]); }
+    else if (k == n - 1) { sub[k] = 1; diag[k] = 2; sup[k] = 0; rhs[k] = -s * (c[n - 1] - c[n - 2]); }
+    else { sub[k] = 1; diag[k] = 4; sup[k] = 1; rhs[k] = s * (c[k + 1] - 2 * c[k] + c[k - 1]); }
+  }
+  for (int k = 1; k < n; ++k) {
+    double f = sub[k] / diag[k - 1];
+    diag[k] -= f * sup[k - 1];
+    rhs[k] -= f * rhs[k - 1];
+  }
+  M.assign(n, 0.0);
+  M[n - 1] = rhs[n - 1] / diag[n - 1];
+  for (int k = n - 2; k >= 0; --k) M[k] = (rhs[k] - sup[k] * M[k + 1]) / diag[k];
+}
+
+}  // namespace
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      return fail(_e == hipErrorOutOfMemory ? ARKCOS_ERR_OUT_OF_MEMORY : ARKCOS_ERR_DEVICE, \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));                     \
+  } while (0)
+
+// Uploads the spline knots and their moments (spline plans only).
+arkcos_status_t upload_knots(arkcos_plan_s* P) {
+  if (P->prof_kind != 1) return ARKCOS_OK;
+  std::vector<double> mom;
+  spline_moments(P->knots, P->theta_max / (P->knots.size() - 1), mom);
+  HIPCHK(hipMemcpy(P->d_knots, P->knots.data(), P->knots.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(P->d_spline_mom, mom.data(), mom.size() * sizeof(double), hipMemcpyHostToDevice));
+  return ARKCOS_OK;
+}
+
+// Kernel samples, bands and tables from the current profile.  Called at plan
+// creation and again by arkcos_set_knots; ring pairs and windows stay fixed.
+arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
+  hipStream_t s = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  struct Guard { hipStream_t s; ~Guard() { hipStreamDestroy(s); } } guard{s};
+
+  const int64_t np = P->n_pairs;
+  double* d_abs = nullptr;
+  int32_t* d_band = nullptr;
+  std::vector<double> abs_sum(np);
+  std::vector<int32_t> band(np);
+  if (np > 0) {
+    HIPCHK(hipMalloc(&d_abs, np * sizeof(double)));
+    HIPCHK(hipMalloc(&d_band, np * sizeof(int32_t)));
+  }
+  struct Free { void* a; void* b; ~Free() { if (a) hipFree(a); if (b) hipFree(b); } } fr{d_abs, d_band};
+
+  // the recurrence coefficients are indexed by their own offsets
+  std::vector<arkcos::PairDev> pcoef = P->h_pairs;
+  for (int64_t q = 0; q < np; ++q) pcoef[q].off = P->h_coef_off[q];
+  HIPCHK(hipMemcpy(P->d_pairs, pcoef.data(), np * sizeof(PairDev), hipMemcpyHostToDevice));
+  HIPCHK(launch_kernel_rows(P, d_abs, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (np > 0) HIPCHK(hipMemcpy(abs_sum.data(), d_abs, np * sizeof(double), hipMemcpyDeviceToHost));
+
+  double scale = 0.0;
+  for (double v : abs_sum) scale = std::max(scale, v);
+  if (P->band_tol > 0 && np > 0) {
+    HIPCHK(launch_band(P, P->band_tol * scale, d_band, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(band.data(), d_band, np * sizeof(int32_t), hipMemcpyDeviceToHost));
+  } else {
+    for (int64_t q = 0; q < np; ++q) band[q] = abs_sum[q] > 0 ? P->h_pairs[q].nyq : -1;
+  }
+  if (!first_time) {
+    // the memory layout was sized for the original bands: keep them
+    for (int64_t q = 0; q < np; ++q) band[q] = P->h_pairs[q].band;
+  }
+
+  // table selection and offsets
+  int64_t table_total = 0, ntab = 0;
+  std::vector<int32_t> tab_list;
+  std::vector<int64_t> tab_coef;
+  for (int64_t q = 0; q < np; ++q) {
+    PairDev& pr = P->h_pairs[q];
+    pr.band = band[q];
+    bool table = false;
+    if (pr.band >= 0) {
+      if (P->opts.kgen == 2) table = true;
+      else if (P->opts.kgen == 0) table = pr.ncoef > kOtfMaxCoef;
+    }
+    if (table) {
+      pr.kind = KG_TABLE;
+      pr.off = table_total;
+      table_total += pr.band + 1;
+      tab_list.push_back((int32_t)q);
+      tab_coef.push_back(P->h_coef_off[q]);
+      ++ntab;
+    } else {
+      pr.kind = P->h_pair_shift[q] ? KG_SHIFTED : KG_CENTRED;
+      pr.off = P->h_coef_off[q];
+    }
+  }
+  if (!first_time && table_total != P->table_total)
+    return fail(ARKCOS_ERR_INTERNAL, "table layout changed on knot update");
+  P->n_table_pairs = ntab;
+  P->table_total = table_total;
+  const size_t rsz = P->dtype == ARKCOS_F32 ? sizeof(float) : sizeof(double);
+  if (first_time) {
+    void* t = nullptr;
+    HIPCHK(hipMalloc(&t, std::max<int64_t>(table_total, 1) * rsz));
+    P->allocations.push_back(t);
+    P->plan_bytes += std::max<int64_t>(table_total, 1) * rsz;
+    P->d_table = t;
+  }
+  HIPCHK(hipMemcpy(P->d_pairs, P->h_pairs.data(), np * sizeof(PairDev), hipMemcpyHostToDevice));
+  if (ntab > 0) {
+    int32_t* d_list = nullptr;
+    int64_t* d_co = nullptr;
+    HIPCHK(hipMalloc(&d_list, ntab * sizeof(int32_t)));
+    HIPCHK(hipMalloc(&d_co, ntab * sizeof(int64_t)));
+    struct Free2 { void* a; void* b; ~Free2() { hipFree(a); hipFree(b); } } f2{d_list, d_co};
+    HIPCHK(hipMemcpy(d_list, tab_list.data(), ntab * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_co, tab_coef.data(), ntab * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(launch_table_list(P, d_list, d_co, (int32_t)ntab, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return ARKCOS_OK;
+}
+
+arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* prof, double R,
+                           arkcos_dtype_t dtype, const arkcos_options_t* o, arkcos_plan_s** out) {
+  // ---------------------------------------------------------- validation
+  if (!g || !prof || !out) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
+  if (dtype != ARKCOS_F32 && dtype != ARKCOS_F64) return fail(ARKCOS_ERR_INVALID_VALUE, "bad dtype");
+  if (!(R > 0) || !(R < M_PI)) return fail(ARKCOS_ERR_INVALID_VALUE, "support radius must be in (0, pi)");
+  arkcos_options_t opts;
+  arkcos_default_options(&opts);
+  if (o) opts = *o;
+  if (opts.oversample != 0 && !(is_pow2(opts.oversample) && opts.oversample <= 16))
+    return fail(ARKCOS_ERR_INVALID_VALUE, "oversample must be 0, 1, 2, 4, 8 or 16");
+  if (opts.kgen < 0 || opts.kgen > 2) return fail(ARKCOS_ERR_INVALID_VALUE, "kgen must be 0, 1 or 2");
+  if (g->kind == 0) {
+    if (g->n_theta < 1 || g->n_phi < 4 || (g->n_phi & 1) || g->n_theta > (1 << 20) || g->n_phi > (1 << 20))
+      return fail(ARKCOS_ERR_INVALID_VALUE, "ECP needs n_theta >= 1 and an even n_phi >= 4");
+  } else if (g->kind == 1) {
+    if (g->nside < 1 || g->nside > 8192) return fail(ARKCOS_ERR_INVALID_VALUE, "nside must be in 1 .. 8192");
+  } else {
+    return fail(ARKCOS_ERR_INVALID_VALUE, "geometry kind must be 0 (ECP) or 1 (HEALPix)");
+  }
+  if (prof->kind == 0) {
+    if (!(prof->fwhm_rad > 0)) return fail(ARKCOS_ERR_INVALID_VALUE, "Gaussian FWHM must be > 0");
+  } else if (prof->kind == 1) {
+    if (prof->n_knots < 3 || prof->n_knots > 64 || !(prof->theta_max_rad > 0) || !prof->knot_values)
+      return fail(ARKCOS_ERR_INVALID_VALUE, "spline needs 3..64 knots, theta_max > 0 and knot values");
+  } else {
+    return fail(ARKCOS_ERR_INVALID_VALUE, "profile kind must be 0 (Gaussian) or 1 (spline)");
+  }
+
+  auto* P = new arkcos_plan_s();
+  struct Owner {
+    arkcos_plan_s* p;
+    ~Owner() {
+      if (p) {
+        for (void* a : p->allocations) hipFree(a);
+        delete p;
+      }
+    }
+  } owner{P};
+  HIPCHK(hipGetDevice(&P->device));
+  P->dtype = dtype;
+  P->geom = *g;
+  P->prof_kind = prof->kind;
+  P->fwhm = prof->fwhm_rad;
+  P->theta_max = prof->theta_max_rad;
+  if (prof->kind == 1) P->knots.assign(prof->knot_values, prof->knot_values + prof->n_knots);
+  P->radius = R;
+  P->opts = opts;
+  P->band_tol = opts.band_tol >= 0 ? opts.band_tol : (dtype == ARKCOS_F32 ? 1e-9 : 0.0);
+
+  // ------------------------------------------------------------ geometry
+  int64_t nr, npix, L;
+  if (g->kind == 1) {
+    const int64_t ns = g->nside;
+    nr = 4 * ns - 1;
+    npix = 12 * ns * ns;
+    L = 4 * ns;
+  } else {
+    nr = g->n_theta;
+    npix = g->n_theta * g->n_phi;
+    L = g->n_phi;
+  }
+  P->nrings = nr;
+  P->npix = npix;
+  P->L = L;
+  P->h_theta.resize(nr); P->h_sin.resize(nr); P->h_cos.resize(nr); P->h_w.resize(nr);
+  P->h_n.resize(nr); P->h_phase_den.resize(nr); P->h_start.resize(nr);
+  if (g->kind == 1) {
+    const int64_t ns = g->nside;
+    const double area = 4.0 * M_PI / (double)npix;
+    for (int64_t k = 0; k < nr; ++k) {
+      const int64_t r = k + 1;
+      double th;
+      if (r < ns) {
+        th = 2.0 * asin(r / (sqrt(6.0) * ns));
+        P->h_n[k] = (int32_t)(4 * r);
+        P->h_phase_den[k] = (int32_t)(4 * r);
+        P->h_start[k] = 2 * r * (r - 1);
+      } else if (r <= 3 * ns) {
+        th = acos(4.0 / 3.0 - 2.0 * r / (3.0 * ns));
+        P->h_n[k] = (int32_t)(4 * ns);
+        P->h_phase_den[k] = ((r - ns) % 2 == 0) ? (int32_t)(4 * ns) : 0;
+        P->h_start[k] = 2 * ns * (ns - 1) + 4 * ns * (r - ns);
+      } else {
+        const int64_t sr = 4 * ns - r;
+        th = M_PI - 2.0 * asin(sr / (sqrt(6.0) * ns));
+        P->h_n[k] = (int32_t)(4 * sr);
+        P->h_phase_den[k] = (int32_t)(4 * sr);
+        P->h_start[k] = npix - 2 * sr * (sr + 1);
+      }
+      P->h_theta[k] = th;
+      P->h_w[k] = area;
+    }
+  } else {
+    const int64_t nt = g->n_theta, nphi = g->n_phi;
+    for (int64_t i = 0; i < nt; ++i) {
+      double a = M_PI * i / nt, b = M_PI * (i + 1) / nt;
+      P->h_theta[i] = M_PI * (i + 0.5) / nt;
+      P->h_w[i] = (2.0 * M_PI / nphi) * 2.0 * sin(0.5 * (a + b)) * sin(0.5 * (b - a));
+      P->h_n[i] = (int32_t)nphi;
+      P->h_phase_den[i] = 0;
+      P->h_start[i] = i * nphi;
+    }
+  }
+  for (int64_t k = 0; k < nr; ++k) {
+    P->h_sin[k] = sin(P->h_theta[k]);
+    P->h_cos[k] = cos(P->h_theta[k]);
+  }
+
+  // ------------------------------------------------------- oversampling
+  int32_t p = opts.oversample;
+  if (g->kind == 0) {
+    p = 1;  // every ECP ring pair is aligned and exact
+  } else if (p == 0) {
+    const double pix = sqrt(4.0 * M_PI / (double)npix);
+    double width = prof->kind == 0 ? prof->fwhm_rad : 2.0 * prof->theta_max_rad / (prof->n_knots - 1);
+    int64_t need = (int64_t)ceil(4.3 * pix / width);
+    p = (int32_t)std::min<int64_t>(16, std::max<int64_t>(1, next_pow2(need)));
+  }
+  P->oversample = p;
+
+  // ------------------------------------------------------ units, pairs
+  const int64_t nunits = (nr + 1) / 2;
+  const double rt = R + kSupportTol;
+  const double hav_r = sin(0.5 * rt) * sin(0.5 * rt);
+  P->h_units.resize(nunits);
+  for (int64_t u = 0; u < nunits; ++u) {
+    const int64_t i = u, im = nr - 1 - u;
+    UnitDev& U = P->h_units[u];
+    U.i = (int32_t)i;
+    U.im = im != i ? (int32_t)im : -1;
+    U.pbeg = (int32_t)P->h_pairs.size();
+    for (int64_t j = 0; j < nr; ++j) {
+      const double dth = P->h_theta[i] - P->h_theta[j];
+      if (fabs(dth) > rt) continue;
+      PairDev pr{};
+      pr.j = (int32_t)j;
+      const bool aligned = P->h_n[i] == L && P->h_n[j] == L &&
+                           (P->h_phase_den[i] == 0 || P->h_phase_den[i] == L) &&
+                           (P->h_phase_den[j] == 0 || P->h_phase_den[j] == L);
+      int32_t shift = 0, pp = p;
+      if (aligned) {
+        pp = 1;
+        shift = ((P->h_phase_den[i] != 0) != (P->h_phase_den[j] != 0)) ? 1 : 0;
+      }
+      pr.p = pp;
+      pr.nyq = (int32_t)(pp * L / 2);
+      // kernel-sample window from hav(R) >= sin^2(dtheta/2) + sin_i sin_j sin^2(nu/2)
+      const double sa = sin(0.5 * dth);
+      const double den = P->h_sin[i] * P->h_sin[j];
+      const double qv = den > 0 ? (hav_r - sa * sa) / den : 2.0;
+      const int64_t pl = pp * L;
+      const double hstep = 2.0 * M_PI / (double)pl;
+      int64_t ncoef;
+      if (qv >= 1.0) {
+        ncoef = shift ? pl / 2 : pl / 2 + 1;
+      } else {
+        const double numax = 2.0 * asin(sqrt(std::max(qv, 0.0)));
+        if (shift)
+          ncoef = std::min<int64_t>(pl / 2, (int64_t)floor(numax / hstep - 0.5) + 2);
+        else
+          ncoef = std::min<int64_t>(pl / 2 + 1, (int64_t)floor(numax / hstep) + 2);
+        ncoef = std::max<int64_t>(ncoef, 1);
+      }
+      pr.ncoef = (int32_t)ncoef;
+      P->h_coef_off.push_back(P->coef_total);
+      P->coef_total += ncoef;
+      P->h_pairs.push_back(pr);
+      P->h_pair_i.push_back((int32_t)i);
+      P->h_pair_shift.push_back(shift);
+    }
+    U.pend = (int32_t)P->h_pairs.size();
+    P->max_units_pairs = std::max(P->max_units_pairs, U.pend - U.pbeg);
+  }
+  P->n_units = nunits;
+  P->n_pairs = (int64_t)P->h_pairs.size();
+
+  // ------------------------------------------------------ FFT strategies
+  const int64_t maxM = dtype == ARKCOS_F32 ? 8192 : 4096;
+  const size_t csz = dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
+  const size_t rsz = dtype == ARKCOS_F32 ? sizeof(float) : sizeof(double);
+  std::vector<int32_t> fft_kind(nr), fft_m(nr);
+  std::vector<int64_t> bl_off(nr, 0);
+  std::map<int32_t, int64_t> bl_of_len;
+  std::vector<int32_t> bl_rings;
+  int64_t twn = 4;
+  size_t lds = 0;
+  for (int64_t k = 0; k < nr; ++k) {
+    const int64_t N = P->h_n[k];
+    if (N <= kDirectMax) {
+      fft_kind[k] = FFT_DIRECT;
+      fft_m[k] = 0;
+      lds = std::max(lds, (size_t)(N / 2 + 1 + N) * csz + N * rsz);
+      continue;
+    }
+    const int64_t n = N / 2;
+    if (is_pow2(n)) {
+      if (n > maxM) return fail(ARKCOS_ERR_NOT_SUPPORTED, "ring FFT longer than the LDS limit");
+      fft_kind[k] = FFT_POW2;
+      fft_m[k] = (int32_t)n;
+      twn = std::max(twn, n);
+      lds = std::max(lds, (size_t)(n + 1) * csz);
+    } else {
+      const int64_t M = next_pow2(2 * n - 1);
+      if (M > maxM) return fail(ARKCOS_ERR_NOT_SUPPORTED, "Bluestein FFT longer than the LDS limit");
+      fft_kind[k] = FFT_BLUESTEIN;
+      fft_m[k] = (int32_t)M;
+      twn = std::max(twn, M);
+      lds = std::max(lds, (size_t)std::max(M, n + 1) * csz);
+      auto it = bl_of_len.find((int32_t)N);
+      if (it == bl_of_len.end()) {
+        bl_of_len[(int32_t)N] = P->bl_total;
+        bl_off[k] = P->bl_total;
+        P->bl_total += M;
+        bl_rings.push_back((int32_t)k);
+        P->max_bl_m = std::max<int32_t>(P->max_bl_m, (int32_t)M);
+      } else {
+        bl_off[k] = it->second;
+      }
+    }
+  }
+  P->twiddle_n = (int32_t)twn;
+  P->max_fft_lds = (int32_t)((lds + 15) / 16 * 16);
+
+  // ------------------------------------------------------ device tables
+  HIPCHK(upload(P, &P->rt.n, P->h_n));
+  HIPCHK(upload(P, &P->rt.start, P->h_start));
+  HIPCHK(upload(P, &P->rt.phase_den, P->h_phase_den));
+  HIPCHK(upload(P, &P->rt.fft_kind, fft_kind));
+  HIPCHK(upload(P, &P->rt.fft_m, fft_m));
+  HIPCHK(upload(P, &P->rt.bl_off, bl_off));
+  HIPCHK(upload(P, &P->rt.w, P->h_w));
+  HIPCHK(upload(P, &P->d_theta, P->h_theta));
+  HIPCHK(upload(P, &P->d_sin, P->h_sin));
+  HIPCHK(upload(P, &P->d_pair_i, P->h_pair_i));
+  HIPCHK(upload(P, &P->d_pair_shift, P->h_pair_shift));
+  HIPCHK(upload(P, &P->d_coef_off, P->h_coef_off));
+  HIPCHK(dev_alloc(P, &P->d_pairs, P->h_pairs.size()));
+  HIPCHK(dev_alloc(P, &P->d_coef64, P->coef_total));
+  {
+    void* c = nullptr;
+    HIPCHK(hipMalloc(&c, std::max<int64_t>(P->coef_total, 1) * rsz));
+    P->allocations.push_back(c);
+    P->plan_bytes += std::max<int64_t>(P->coef_total, 1) * rsz;
+    P->d_coef = c;
+  }
+  HIPCHK(dev_alloc(P, &P->d_knots, std::max<size_t>(P->knots.size(), 1)));
+  HIPCHK(dev_alloc(P, &P->d_spline_mom, std::max<size_t>(P->knots.size(), 1)));
+  {
+    arkcos_status_t st = upload_knots(P);
+    if (st != ARKCOS_OK) return st;
+  }
+
+  // twiddles exp(-2 pi i k / twn), computed in FP64
+  {
+    std::vector<double> tw(2 * twn);
+    for (int64_t k = 0; k < twn; ++k) {
+      double a = -2.0 * M_PI * (double)k / (double)twn;
+      tw[2 * k] = cos(a);
+      tw[2 * k + 1] = sin(a);
+    }
+    void* d = nullptr;
+    HIPCHK(hipMalloc(&d, twn * csz));
+    P->allocations.push_back(d);
+    P->plan_bytes += twn * csz;
+    if (dtype == ARKCOS_F32) {
+      std::vector<float> tf(tw.begin(), tw.end());
+      HIPCHK(hipMemcpy(d, tf.data(), twn * csz, hipMemcpyHostToDevice));
+    } else {
+      HIPCHK(hipMemcpy(d, tw.data(), twn * csz, hipMemcpyHostToDevice));
+    }
+    P->d_twiddle = d;
+  }
+  {
+    void* d = nullptr;
+    HIPCHK(hipMalloc(&d, std::max<int64_t>(P->bl_total, 1) * csz));
+    P->allocations.push_back(d);
+    P->plan_bytes += std::max<int64_t>(P->bl_total, 1) * csz;
+    P->d_bl = d;
+  }
+  HIPCHK(configure_fft_kernels(P));
+  if (!bl_rings.empty()) {
+    int32_t* d_list = nullptr;
+    HIPCHK(hipMalloc(&d_list, bl_rings.size() * sizeof(int32_t)));
+    struct F { void* a; ~F() { hipFree(a); } } f{d_list};
+    HIPCHK(hipMemcpy(d_list, bl_rings.data(), bl_rings.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(launch_bluestein_filters(P, d_list, (int32_t)bl_rings.size(), nullptr));
+    HIPCHK(hipDeviceSynchronize());
+  }
+
+  // ------------------------------------------- kernel samples and bands
+  {
+    arkcos_status_t st = build_kernel_tables(P, true);
+    if (st != ARKCOS_OK) return st;
+  }
+
+  // ----------------------------------------- spectra / output layout
+  P->h_spec_len.assign(nr, 0);
+  P->h_out_len.assign(nr, 0);
+  P->pair_modes = 0;
+  for (int64_t u = 0; u < nunits; ++u) {
+    UnitDev& U = P->h_units[u];
+    int32_t ub = -1;
+    for (int32_t q = U.pbeg; q < U.pend; ++q) {
+      const PairDev& pr = P->h_pairs[q];
+      ub = std::max(ub, pr.band);
+      if (pr.band < 0) continue;
+      P->h_spec_len[pr.j] = std::max(P->h_spec_len[pr.j], pr.band + 1);
+      P->pair_modes += (int64_t)(pr.band + 1) * (U.im >= 0 ? 2 : 1);
+      if (U.im >= 0) {
+        const int64_t jm = nr - 1 - pr.j;
+        P->h_spec_len[jm] = std::max(P->h_spec_len[jm], pr.band + 1);
+      }
+    }
+    U.band = ub;
+    P->h_out_len[U.i] = ub + 1;
+    if (U.im >= 0) P->h_out_len[U.im] = ub + 1;
+  }
+  P->h_spec_off.assign(nr, 0);
+  P->h_out_off.assign(nr, 0);
+  for (int64_t k = 0; k < nr; ++k) {
+    P->h_spec_off[k] = P->spec_total;
+    P->spec_total += P->h_spec_len[k];
+    P->h_out_off[k] = P->out_total;
+    P->out_total += P->h_out_len[k];
+  }
+  HIPCHK(upload(P, &P->rt.spec_off, P->h_spec_off));
+  HIPCHK(upload(P, &P->rt.spec_len, P->h_spec_len));
+  HIPCHK(upload(P, &P->rt.out_off, P->h_out_off));
+  HIPCHK(upload(P, &P->rt.out_len, P->h_out_len));
+  HIPCHK(upload(P, &P->d_units, P->h_units));
+
+  // work items: (unit, first mode) tiles
+  for (int64_t u = 0; u < nunits; ++u)
+    for (int32_t m0 = 0; m0 <= P->h_units[u].band; m0 += kModeTile)
+      P->h_items.push_back(WorkItem{(int32_t)u, m0});
+  HIPCHK(upload(P, &P->d_items, P->h_items));
+
+  // rings whose pixels can lie within R of a pole pixel (direct-sum columns)
+  if (g->kind == 1) {
+    std::vector<int32_t> lst;
+    for (int64_t j = 0; j < nr; ++j)
+      if (fabs(P->h_theta[j] - P->h_theta[0]) <= rt || fabs(P->h_theta[j] - P->h_theta[nr - 1]) <= rt)
+        lst.push_back((int32_t)j);
+    P->n_pole_rings = (int32_t)lst.size();
+    HIPCHK(upload(P, &P->d_pole_rings, lst));
+  }
+
+  HIPCHK(hipDeviceSynchronize());
+  *out = P;
+  owner.p = nullptr;
+  return ARKCOS_OK;
+}
+
+int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count) {
+  *count = P->n_pole_rings;
+  return P->d_pole_rings;
+}
+
+size_t workspace_bytes(const arkcos_plan_s* P) {
+  const size_t csz = P->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  return al(std::max<int64_t>(P->spec_total, 1) * csz) + al(std::max<int64_t>(P->out_total, 1) * csz);
+}
+
+}  // namespace arkcos

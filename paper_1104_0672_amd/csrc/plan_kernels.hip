@@ -1,0 +1,226 @@
+// Plan-time kernels: the kernel rows of every ring pair (step b of the
+// hybrid method, paper Sect. 4.1), their bands, the optional K_ij(m) tables,
+// and the Bluestein filters of the ring FFTs.
+//
+// The angular distance between a pixel of output ring i (at longitude 0) and
+// a longitude nu on input ring j is evaluated in FP64 haversine form,
+//   hav = sin^2((theta_i - theta_j)/2) + sin(theta_i) sin(theta_j) sin^2(nu/2),
+//   theta = 2 asin(sqrt(hav)),
+// which equals the paper's alpha^2 = 2(1 - cos alpha) parametrisation
+// (eq. "kernel_angle") without its cancellation at small angles.
+#include "arkcos_internal.h"
+#include "device_common.h"
+
+namespace arkcos {
+
+struct ProfileDev {
+  int32_t kind;      // 0 Gaussian, 1 spline
+  double inv2s2;     // 1 / (2 sigma^2)
+  double radius;     // support radius + tolerance
+  int32_t nk;
+  double h, theta_max;
+  const double* knots;
+  const double* mom;
+};
+
+__device__ __forceinline__ double profile_eval(const ProfileDev& P, double t) {
+  if (t > P.radius) return 0.0;
+  if (P.kind == 0) return exp(-t * t * P.inv2s2);
+  if (t > P.theta_max + kSupportTol) return 0.0;
+  int a = (int)floor(t / P.h);
+  a = a < 0 ? 0 : (a > P.nk - 2 ? P.nk - 2 : a);
+  double u = t / P.h - a, v = 1.0 - u, h2 = P.h * P.h / 6.0;
+  return v * P.knots[a] + u * P.knots[a + 1] +
+         h2 * ((v * v * v - v) * P.mom[a] + (u * u * u - u) * P.mom[a + 1]);
+}
+
+// Distance between (theta_i, 0) and (theta_j, nu) with nu = pi * num / den.
+__device__ __forceinline__ double ring_distance(double ti, double tj, double si, double sj,
+                                                int64_t num, int64_t den) {
+  double a = sin(0.5 * (ti - tj));
+  double b = sinpi(0.5 * (double)num / (double)den);
+  double hav = a * a + si * sj * b * b;
+  double r = sqrt(hav);
+  return 2.0 * asin(r < 1.0 ? r : 1.0);
+}
+
+// Node d of pair q: nu_d / pi = 2 (d + s/2) / (p L) = (2d + s) / (p L).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) kernel_rows_kernel(
+    const PairDev* __restrict__ pairs, const int32_t* __restrict__ pair_i,
+    const int32_t* __restrict__ pair_shift, const double* __restrict__ theta,
+    const double* __restrict__ sint, const double* __restrict__ w, int64_t L, ProfileDev prof,
+    double* __restrict__ coef64, R* __restrict__ coef, double* __restrict__ abs_sum) {
+  const int q = blockIdx.x;
+  const PairDev pr = pairs[q];
+  const int i = pair_i[q], j = pr.j, s = pair_shift[q];
+  const int64_t pl = (int64_t)pr.p * L;
+  const double ti = theta[i], tj = theta[j], si = sint[i], sj = sint[j];
+  double part = 0.0;
+  for (int d = threadIdx.x; d < pr.ncoef; d += blockDim.x) {
+    double t = ring_distance(ti, tj, si, sj, 2 * (int64_t)d + s, pl);
+    double g = w[j] * profile_eval(prof, t);
+    double c = 2.0;
+    if (s == 0 && (d == 0 || 2 * (int64_t)d == pl)) c = 1.0;
+    double a = c * g / (double)pl;
+    coef64[pr.off + d] = a;
+    coef[pr.off + d] = (R)a;
+    part += fabs(a);
+  }
+  __shared__ double red[kBlock];
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) abs_sum[q] = red[0];
+}
+
+// K_ij(m) in FP64 by the Clenshaw recurrence over the kernel samples:
+//   centred grid:  K(m) = sum_d a_d cos(d x),        x = 2 pi m / (p L)
+//   shifted grid:  K(m) = sum_d a_d cos((2d+1) y),   y = pi m / L
+// with the half weight of the grid's Nyquist mode m = p L / 2.
+__device__ __forceinline__ double k_of_m_fp64(const double* __restrict__ a, int n, int m, int shift,
+                                              int64_t pl, int nyq) {
+  double cx, cy;
+  if (shift) {
+    cx = cospi(2.0 * (double)m / (double)pl);  // cos(2y)
+    cy = cospi((double)m / (double)pl);
+  } else {
+    cx = cospi(2.0 * (double)m / (double)pl);
+    cy = cx;
+  }
+  double al = 2.0 * cx, b1 = 0.0, b2 = 0.0;
+  for (int d = n - 1; d >= 0; --d) {
+    double b0 = fma(al, b1, a[d] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  double k = shift ? (b1 - b2) * cy : b1 - b2 * cx;
+  return m == nyq ? 0.5 * k : k;
+}
+
+__global__ void __launch_bounds__(kBlock) band_kernel(
+    const PairDev* __restrict__ pairs, const int32_t* __restrict__ pair_shift,
+    const double* __restrict__ coef64, int64_t L, double thr, int32_t* __restrict__ band_out) {
+  const int q = blockIdx.x;
+  const PairDev pr = pairs[q];
+  const int64_t pl = (int64_t)pr.p * L;
+  int best = -1;
+  for (int m = threadIdx.x; m <= pr.nyq; m += blockDim.x) {
+    double k = k_of_m_fp64(coef64 + pr.off, pr.ncoef, m, pair_shift[q], pl, pr.nyq);
+    if (fabs(k) > thr) best = m;
+  }
+  __shared__ int red[kBlock];
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) band_out[q] = red[0];
+}
+
+// Tables: K_ij(m) for m <= band of the pairs listed in `list` (their coef64
+// offsets are read from `coef_off`, their table offsets from pairs[].off).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) table_kernel(
+    const PairDev* __restrict__ pairs, const int32_t* __restrict__ pair_shift,
+    const int32_t* __restrict__ list, const int64_t* __restrict__ coef_off,
+    const double* __restrict__ coef64, int64_t L, R* __restrict__ table) {
+  const int t = blockIdx.x;
+  const int q = list[t];
+  const PairDev pr = pairs[q];
+  const int64_t pl = (int64_t)pr.p * L;
+  for (int m = threadIdx.x; m <= pr.band; m += blockDim.x)
+    table[pr.off + m] = (R)k_of_m_fp64(coef64 + coef_off[t], pr.ncoef, m, pair_shift[q], pl, pr.nyq);
+}
+
+// Bluestein filter of length n: FFT_M of b_l = exp(+i pi l^2 / n) placed at l
+// and M - l for 0 <= l < n.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) bluestein_filter_kernel(
+    const int32_t* __restrict__ rings, const int32_t* __restrict__ ring_n,
+    const int32_t* __restrict__ fft_m, const int64_t* __restrict__ bl_off,
+    const cx_t<R>* __restrict__ tw, int TN, cx_t<R>* __restrict__ out) {
+  using C = cx_t<R>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* buf = reinterpret_cast<C*>(smem);
+  const int ring = rings[blockIdx.x];
+  const int n = ring_n[ring] / 2, M = fft_m[ring];
+  for (int l = threadIdx.x; l < M; l += blockDim.x) {
+    int src = -1;
+    if (l < n) src = l;
+    else if (M - l < n) src = M - l;
+    buf[l] = src >= 0 ? cconj(chirp<R>(src, n)) : cmake<C>(R(0), R(0));
+  }
+  __syncthreads();
+  lds_fft<R, false>(buf, M, tw, TN);
+  C* o = out + bl_off[ring];
+  for (int l = threadIdx.x; l < M; l += blockDim.x) o[l] = buf[l];
+}
+
+static ProfileDev make_profile(arkcos_plan_s* P) {
+  ProfileDev pd{};
+  pd.kind = P->prof_kind;
+  double sigma = P->fwhm / sqrt(8.0 * log(2.0));
+  pd.inv2s2 = P->prof_kind == 0 ? 1.0 / (2.0 * sigma * sigma) : 0.0;
+  pd.radius = P->radius + kSupportTol;
+  pd.nk = (int32_t)P->knots.size();
+  pd.theta_max = P->theta_max;
+  pd.h = pd.nk > 1 ? P->theta_max / (pd.nk - 1) : 0.0;
+  pd.knots = P->d_knots;
+  pd.mom = P->d_spline_mom;
+  return pd;
+}
+
+hipError_t launch_kernel_rows(arkcos_plan_s* P, double* abs_sum, hipStream_t s) {
+  if (P->n_pairs == 0) return hipSuccess;
+  ProfileDev pd = make_profile(P);
+  if (P->dtype == ARKCOS_F32)
+    kernel_rows_kernel<float><<<(unsigned)P->n_pairs, kBlock, 0, s>>>(
+        P->d_pairs, P->d_pair_i, P->d_pair_shift, P->d_theta, P->d_sin, P->rt.w, P->L, pd,
+        P->d_coef64, (float*)P->d_coef, abs_sum);
+  else
+    kernel_rows_kernel<double><<<(unsigned)P->n_pairs, kBlock, 0, s>>>(
+        P->d_pairs, P->d_pair_i, P->d_pair_shift, P->d_theta, P->d_sin, P->rt.w, P->L, pd,
+        P->d_coef64, (double*)P->d_coef, abs_sum);
+  return hipGetLastError();
+}
+
+hipError_t launch_band(arkcos_plan_s* P, double thr, int32_t* band_out, hipStream_t s) {
+  if (P->n_pairs == 0) return hipSuccess;
+  band_kernel<<<(unsigned)P->n_pairs, kBlock, 0, s>>>(P->d_pairs, P->d_pair_shift, P->d_coef64,
+                                                       P->L, thr, band_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_list(arkcos_plan_s* P, const int32_t* d_list, const int64_t* d_coef_off,
+                             int32_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (P->dtype == ARKCOS_F32)
+    table_kernel<float><<<count, kBlock, 0, s>>>(P->d_pairs, P->d_pair_shift, d_list, d_coef_off,
+                                                P->d_coef64, P->L, (float*)P->d_table);
+  else
+    table_kernel<double><<<count, kBlock, 0, s>>>(P->d_pairs, P->d_pair_shift, d_list, d_coef_off,
+                                                 P->d_coef64, P->L, (double*)P->d_table);
+  return hipGetLastError();
+}
+
+hipError_t launch_bluestein_filters(arkcos_plan_s* P, const int32_t* d_ring_list, int32_t count,
+                                    hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  size_t lds = (size_t)P->max_bl_m * (P->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2));
+  if (P->dtype == ARKCOS_F32)
+    bluestein_filter_kernel<float><<<count, kBlock, lds, s>>>(
+        d_ring_list, P->rt.n, P->rt.fft_m, P->rt.bl_off, (const float2*)P->d_twiddle,
+        P->twiddle_n, (float2*)P->d_bl);
+  else
+    bluestein_filter_kernel<double><<<count, kBlock, lds, s>>>(
+        d_ring_list, P->rt.n, P->rt.fft_m, P->rt.bl_off, (const double2*)P->d_twiddle,
+        P->twiddle_n, (double2*)P->d_bl);
+  return hipGetLastError();
+}
+
+}  // namespace arkcos

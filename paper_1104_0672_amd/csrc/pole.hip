@@ -1,0 +1,131 @@
+// The first and last HEALPix ring (4 pixels each) recomputed by the direct
+// sum y_p = sum_q K(theta_pq) x_q w_q (paper Sect. 4.2), in FP64 with the
+// haversine distance.  In the transposed map the same 8 rows become 8
+// columns: xbar_q += w_q sum_{p in poles} K(theta_pq) r_p.
+#include "arkcos_internal.h"
+#include "device_common.h"
+
+namespace arkcos {
+
+struct PoleArgs {
+  const int32_t* n;
+  const int64_t* start;
+  const int32_t* phase_den;
+  const double* theta;
+  const double* sint;
+  const double* w;
+  int32_t nrings;
+  int32_t kind;     // profile
+  double inv2s2, radius, h, theta_max;
+  int32_t nk;
+  const double* knots;
+  const double* mom;
+};
+
+__device__ __forceinline__ double pole_profile(const PoleArgs& P, double t) {
+  if (t > P.radius) return 0.0;
+  if (P.kind == 0) return exp(-t * t * P.inv2s2);
+  if (t > P.theta_max + kSupportTol) return 0.0;
+  int a = (int)floor(t / P.h);
+  a = a < 0 ? 0 : (a > P.nk - 2 ? P.nk - 2 : a);
+  double u = t / P.h - a, v = 1.0 - u, h2 = P.h * P.h / 6.0;
+  return v * P.knots[a] + u * P.knots[a + 1] +
+         h2 * ((v * v * v - v) * P.mom[a] + (u * u * u - u) * P.mom[a + 1]);
+}
+
+// Longitude of pixel k of a ring, in units of pi: (2k + s) / N with s = 1 for
+// rings offset by pi / N (all HEALPix polar rings and the shifted equatorial
+// rings, where phase_den = N), s = 0 otherwise.
+__device__ __forceinline__ double pixel_distance(const PoleArgs& P, int ia, int ka, int ib, int kb) {
+  int64_t na = P.n[ia], nb = P.n[ib];
+  int64_t sa = P.phase_den[ia] ? 1 : 0, sb = P.phase_den[ib] ? 1 : 0;
+  // (phi_a - phi_b) / (2 pi) = ((2ka + sa) nb - (2kb + sb) na) / (2 na nb)
+  int64_t num = (2 * (int64_t)ka + sa) * nb - (2 * (int64_t)kb + sb) * na;
+  double half_dphi = sinpi((double)num / (double)(2 * na * nb));
+  double a = sin(0.5 * (P.theta[ia] - P.theta[ib]));
+  double hav = a * a + P.sint[ia] * P.sint[ib] * half_dphi * half_dphi;
+  double r = sqrt(hav);
+  return 2.0 * asin(r < 1.0 ? r : 1.0);
+}
+
+// Forward: one block per pole pixel (blockIdx.x < 8).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) pole_forward_kernel(PoleArgs P, const R* __restrict__ x,
+                                                              R* __restrict__ y) {
+  const int b = blockIdx.x;
+  const int ip = b < 4 ? 0 : P.nrings - 1, kp = b & 3;
+  double acc = 0.0;
+  for (int j = 0; j < P.nrings; ++j) {
+    if (fabs(P.theta[j] - P.theta[ip]) > P.radius) continue;
+    const int nj = P.n[j];
+    const double wj = P.w[j];
+    for (int k = threadIdx.x; k < nj; k += blockDim.x) {
+      double t = pixel_distance(P, ip, kp, j, k);
+      acc += pole_profile(P, t) * wj * (double)x[P.start[j] + k];
+    }
+  }
+  __shared__ double red[kBlock];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) y[P.start[ip] + kp] = (R)red[0];
+}
+
+// Transpose: one block per ring j within the support of either pole ring.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) pole_adjoint_kernel(PoleArgs P, const int32_t* __restrict__ rings,
+                                                              const R* __restrict__ r, R* __restrict__ xbar) {
+  const int j = rings[blockIdx.x];
+  const int nj = P.n[j];
+  for (int k = threadIdx.x; k < nj; k += blockDim.x) {
+    double acc = 0.0;
+    for (int b = 0; b < 8; ++b) {
+      const int ip = b < 4 ? 0 : P.nrings - 1, kp = b & 3;
+      if (fabs(P.theta[j] - P.theta[ip]) > P.radius) continue;
+      double t = pixel_distance(P, ip, kp, j, k);
+      acc += pole_profile(P, t) * (double)r[P.start[ip] + kp];
+    }
+    int64_t q = P.start[j] + k;
+    xbar[q] = (R)((double)xbar[q] + P.w[j] * acc);
+  }
+}
+
+hipError_t launch_pole_fix(arkcos_plan_s* P, const void* x, void* y, int32_t adjoint, hipStream_t s) {
+  PoleArgs a{};
+  a.n = P->rt.n;
+  a.start = P->rt.start;
+  a.phase_den = P->rt.phase_den;
+  a.theta = P->d_theta;
+  a.sint = P->d_sin;
+  a.w = P->rt.w;
+  a.nrings = (int32_t)P->nrings;
+  a.kind = P->prof_kind;
+  double sigma = P->fwhm / sqrt(8.0 * log(2.0));
+  a.inv2s2 = P->prof_kind == 0 ? 1.0 / (2.0 * sigma * sigma) : 0.0;
+  a.radius = P->radius + kSupportTol;
+  a.nk = (int32_t)P->knots.size();
+  a.theta_max = P->theta_max;
+  a.h = a.nk > 1 ? P->theta_max / (a.nk - 1) : 0.0;
+  a.knots = P->d_knots;
+  a.mom = P->d_spline_mom;
+  if (!adjoint) {
+    if (P->dtype == ARKCOS_F32)
+      pole_forward_kernel<float><<<8, kBlock, 0, s>>>(a, (const float*)x, (float*)y);
+    else
+      pole_forward_kernel<double><<<8, kBlock, 0, s>>>(a, (const double*)x, (double*)y);
+  } else {
+    int32_t count = 0;
+    int32_t* list = pole_ring_list(P, &count);
+    if (count == 0) return hipSuccess;
+    if (P->dtype == ARKCOS_F32)
+      pole_adjoint_kernel<float><<<count, kBlock, 0, s>>>(a, list, (const float*)x, (float*)y);
+    else
+      pole_adjoint_kernel<double><<<count, kBlock, 0, s>>>(a, list, (const double*)x, (double*)y);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace arkcos

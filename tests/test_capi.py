@@ -1,0 +1,85 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/arkcos.h declares, and rejects bad arguments on the host before any
+device work (no GPU call is needed for these)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "arkcos.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(arkcos_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1104_0672_amd import arkcos as ak
+    path = ak.LIB_PATH
+    if not os.path.exists(path):
+        from paper_1104_0672_amd import build
+        build.build()
+    return ak.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("arkcos_plan", "arkcos_convolve", "arkcos_convolve_adjoint", "arkcos_kernel_grad",
+                 "arkcos_batch_plan", "arkcos_batch_convolve", "arkcos_workspace_size"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1104_0672_amd import arkcos as ak
+    out = subprocess.run(["nm", "-D", "--defined-only", ak.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (arkcos_[a-z_0-9]+)$", out, flags=re.M))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    assert set(_declared()) == set(ak.EXPORTED)
+
+
+def _plan_status(lib, geom, prof, radius=0.1, dtype=0, opts=None):
+    from paper_1104_0672_amd import arkcos as ak
+    h = ctypes.c_void_p()
+    st = lib.arkcos_plan(ctypes.byref(geom), ctypes.byref(prof), radius, dtype,
+                         ctypes.byref(opts) if opts is not None else None, ctypes.byref(h))
+    return st, lib.arkcos_last_error().decode(), h
+
+
+def test_host_argument_checks(lib):
+    from paper_1104_0672_amd import arkcos as ak
+    good_g = ak.Geometry(1, 8, 0, 0)
+    good_p = ak.ProfileC(0, 0.05, 0, 0.0, None)
+    cases = [
+        (ak.Geometry(1, 0, 0, 0), good_p, 0.1, 0, None, "nside"),
+        (ak.Geometry(0, 0, 8, 7), good_p, 0.1, 0, None, "ECP"),
+        (ak.Geometry(2, 8, 0, 0), good_p, 0.1, 0, None, "kind"),
+        (good_g, ak.ProfileC(0, -1.0, 0, 0.0, None), 0.1, 0, None, "FWHM"),
+        (good_g, ak.ProfileC(1, 0.0, 2, 0.1, None), 0.1, 0, None, "spline"),
+        (good_g, good_p, 0.0, 0, None, "radius"),
+        (good_g, good_p, 4.0, 0, None, "radius"),
+        (good_g, good_p, 0.1, 7, None, "dtype"),
+        (good_g, good_p, 0.1, 0, ak.Options(3, 0, 1, -1.0), "oversample"),
+        (good_g, good_p, 0.1, 0, ak.Options(2, 5, 1, -1.0), "kgen"),
+    ]
+    for g, p, r, dt, o, word in cases:
+        st, msg, h = _plan_status(lib, g, p, r, dt, o)
+        assert st == 1, (word, st, msg)
+        assert word.lower() in msg.lower()
+        assert not h.value
+    assert lib.arkcos_convolve(None, None, None, None, None) == 1
+    assert lib.arkcos_plan_destroy(None) == 1
+    assert lib.arkcos_status_string(0) == b"ARKCOS_OK"
+
+
+def test_default_options(lib):
+    from paper_1104_0672_amd import arkcos as ak
+    o = ak.Options(9, 9, 9, 9.0)
+    lib.arkcos_default_options(ctypes.byref(o))
+    assert (o.oversample, o.kgen, o.fix_pole_pixels, o.band_tol) == (0, 0, 1, -1.0)

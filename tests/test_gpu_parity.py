@@ -1,0 +1,146 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (fractional RMS = |y - y_ref|_2 / |y_ref|_2, the paper's accuracy
+measure, Sect. 4.3):
+* ECP, FP64: <= 1e-12 and max |dy| <= 1e-11 max |y_ref|, against the direct
+  sum (the ring FFT form is exact there, Sect. 4.3 last paragraph);
+* ECP, FP32: <= 1e-6 against the direct sum;
+* HEALPix, FP32: <= 1e-4 against the direct sum; against the step-by-step
+  FP64 hybrid reference (same method) <= 1e-5;
+* HEALPix, FP64: <= 1e-11 against the step-by-step hybrid reference (same
+  oversampling), which checks the method itself, caps included.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _plan(w, **kw):
+    from paper_1104_0672_amd import Plan
+    return Plan.from_workload(w, **kw)
+
+
+def _tt(x, w):
+    return torch.tensor(x, dtype=torch.float32 if w.dtype == "f32" else torch.float64, device=_dev())
+
+
+def _frac(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _run(w, x, **kw):
+    plan = _plan(w, **kw)
+    y = plan.convolve(_tt(x, w))
+    torch.cuda.synchronize()
+    return plan, y.cpu().numpy().astype(np.float64)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_ecp_64x128_fp64_is_exact():
+    w = W.ecp_64x128()
+    _say(f"case {w.name} f64")
+    x = W.make_input(w)
+    _, y = _run(w, x)
+    ref = oracle.direct(w.grid, w.profile, w.radius, x)
+    assert _frac(y, ref) <= 1e-12
+    assert np.abs(y - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("kgen", [0, 1, 2])
+def test_ecp_fp32_all_kernel_sources(kgen):
+    w = W.Workload("ecp64x128_f32", W.Grid("ecp", ntheta=64, nphi=128),
+                   W.Profile("gaussian", fwhm=3 * math.pi / 64), 9 * math.pi / 64, "f32", 1)
+    _say(f"case {w.name} kgen={kgen}")
+    x = W.make_input(w)
+    _, y = _run(w, x, kgen=kgen)
+    ref = oracle.direct(w.grid, w.profile, w.radius, x)
+    assert _frac(y, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("ntheta,nphi", [(1, 4), (3, 10), (17, 96), (40, 200)])
+def test_ecp_ragged_shapes_fp64(ntheta, nphi):
+    """Odd ring counts (self-mirrored middle ring), tiny rings, non-power-of-
+    two ring lengths (Bluestein)."""
+    g = W.Grid("ecp", ntheta=ntheta, nphi=nphi)
+    prof = W.Profile("gaussian", fwhm=2.5 * math.pi / max(ntheta, 2))
+    w = W.Workload("ecp_ragged", g, prof, min(3.0, 3 * prof.fwhm), "f64", 9)
+    _say(f"case ecp {ntheta}x{nphi} f64")
+    x = W.make_input(w)
+    _, y = _run(w, x)
+    ref = oracle.direct(g, prof, w.radius, x)
+    assert _frac(y, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("nside,p", [(4, 2), (16, 1), (16, 2), (40, 2), (24, 4)])
+def test_healpix_fp64_matches_step_by_step_method(nside, p):
+    w = W.scaled_healpix(nside, fwhm_arcmin=2.5 * 60 * math.degrees(math.sqrt(math.pi / 3) / nside),
+                         radius_fwhm=3.0, dtype="f64", seed=nside)
+    _say(f"case {w.name} f64 p={p}")
+    x = W.make_input(w)
+    _, y = _run(w, x, oversample=p)
+    ref = oracle.hybrid(w.grid, w.profile, w.radius, x, oversample=p)
+    assert _frac(y, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("nside", [8, 32, 64])
+def test_healpix_fp32_small(nside):
+    w = W.scaled_healpix(nside, fwhm_arcmin=2.0 * 60 * math.degrees(math.sqrt(math.pi / 3) / nside),
+                         radius_fwhm=3.0, seed=nside)
+    _say(f"case {w.name} f32")
+    x = W.make_input(w)
+    plan, y = _run(w, x)
+    p = plan.info.oversample
+    ref_m = oracle.hybrid(w.grid, w.profile, w.radius, x, oversample=p)
+    ref_d = oracle.direct(w.grid, w.profile, w.radius, x)
+    assert _frac(y, ref_m) <= 1e-5
+    assert _frac(y, ref_d) <= 1e-4
+
+
+def test_healpix256_30arcmin_full_map():
+    w = W.healpix256()
+    _say(f"case {w.name}")
+    x = W.make_input(w)
+    plan, y = _run(w, x)
+    ref = oracle.direct(w.grid, w.profile, w.radius, x)
+    err = _frac(y, ref)
+    _say(f"  oversample {plan.info.oversample}: fractional RMS vs direct sum {err:.3e}")
+    assert err <= 1e-4
+
+
+def test_fp64_adjoint_dot_product_and_transpose():
+    for w in (W.ecp_64x128(), W.scaled_healpix(16, 200.0, 3.0, dtype="f64")):
+        _say(f"case adjoint {w.name}")
+        plan = _plan(w)
+        rng = np.random.default_rng(21)
+        x, r = rng.standard_normal(w.grid.npix), rng.standard_normal(w.grid.npix)
+        cx = plan.convolve(_tt(x, w)).cpu().numpy()
+        ct = plan.adjoint(_tt(r, w)).cpu().numpy()
+        a, b = float(np.dot(cx, r)), float(np.dot(x, ct))
+        assert abs(a - b) <= 1e-12 * np.linalg.norm(cx) * np.linalg.norm(r)
+        if w.grid.kind == "ecp":
+            ref = oracle.adjoint(w.grid, w.profile, w.radius, r)
+        else:
+            ref = oracle.hybrid_adjoint(w.grid, w.profile, w.radius, r, oversample=plan.info.oversample)
+        assert _frac(ct, ref) <= 1e-11

@@ -1,0 +1,195 @@
+#!/usr/bin/env python
+"""Benchmark of the hybrid sphere convolution on one MI355X.
+
+Workload: HEALPix nside 2048 (50,331,648 pixels), FP32, Gaussian beam of
+5' FWHM truncated at 20' (Planck-HFI-like channel); input 1e-4 N(0,1) white
+noise plus 2000 point sources with log-uniform amplitudes in [1e-3, 1]
+(synthetic, seeded).  A step is one full forward convolution (ring R2C,
+ring-pair accumulation with on-the-fly kernel coefficients, fold + C2R,
+pole-ring fix) of the map already resident in HBM.  The plan (geometry,
+kernel samples, bands) is built once before timing and reported separately.
+
+Prints one JSON line: output pixels/s of the plain forward form, the
+roofline of the dominant kernel (HIP events on the library's stream), the
+adjoint form's throughput, and the FP64 oracle timed on the host cores on a
+bounded sample of output pixels.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "output pixels/sec (nside 2048, 5' beam) & % HBM roofline, plain vs batched/adjoint"
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 off
+STAGES = ["ring_r2c", "accumulate", "fold_c2r", "pole_fix"]
+KERNEL_NAMES = {"ring_r2c": "r2c_kernel", "accumulate": "accumulate_kernel", "fold_c2r": "c2r_kernel",
+                "pole_fix": "pole_forward_kernel"}
+KERNEL_SOURCES = {"ring_r2c": ["fft.hip", "device_common.h"], "accumulate": ["accum.hip", "device_common.h"],
+                  "fold_c2r": ["fft.hip", "device_common.h"], "pole_fix": ["pole.hip"]}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash(stage: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[stage]:
+        with open(os.path.join(ROOT, "paper_1104_0672_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(stage: str, plan, elem: int) -> int:
+    """Compulsory HBM bytes per launch of each staged kernel: the map in and
+    its half spectrum out (R2C), the input spectra in and the output-ring
+    coefficients out (accumulation), the output coefficients in and the map
+    out (C2R): elem bytes per pixel each way, i.e. 2*elem per pixel per stage
+    (3 stages: 24 B/px in FP32).  The pole fix reads and writes 8 pixels."""
+    npix = plan.npix
+    if stage == "pole_fix":
+        return 16 * elem
+    return 2 * elem * npix
+
+
+def measured_traffic(stage: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_healpix2048_5arcmin.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    ent = data.get("kernels", {}).get(KERNEL_NAMES[stage])
+    if not ent or ent.get("source_sha") != kernel_source_hash(stage):
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, x, budget_s: float):
+    import numpy as np
+
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    n = 512
+    while True:
+        idx = np.sort(np.random.default_rng(99).choice(w.grid.npix, size=n, replace=False))
+        t0 = time.perf_counter()
+        oracle.direct(w.grid, w.profile, w.radius, x, idx=idx, nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= budget_s / 4 or n >= w.grid.npix:
+            break
+        n = min(w.grid.npix, int(n * max(2.0, min(16.0, budget_s / 4 / max(dt, 1e-3)))))
+    return {"value": n / dt, "unit": "pixels/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} random output pixels of the nside-2048 map (FP64 direct sum, "
+                      f"{dt:.1f} s wall), throughput extrapolated per pixel"}
+
+
+def time_form(plan, fn, x, y, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn(x, out=y)
+    torch.cuda.synchronize()
+    plan.start_timing(steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn(x, out=y)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms, calls = plan.stage_times()
+    plan.start_timing(0)
+    return wall, [t / max(calls, 1) for t in stage_ms]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle budget (0: skip)")
+    ap.add_argument("--no-adjoint", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the single-map path "
+              "shards by latitude band across GPUs, which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1104_0672_amd import Plan
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = W.healpix2048()
+    log(f"bench: building plan for {w.name}")
+    t0 = time.perf_counter()
+    plan = Plan.from_workload(w)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = plan.info
+    log(f"bench: plan {plan_s:.2f} s, oversample {info.oversample}, pairs {info.n_pairs}, "
+        f"pair modes {info.pair_modes}, workspace {info.workspace_bytes / 2**20:.0f} MiB")
+    xh = W.make_input(w)
+    x = torch.tensor(xh, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    plan.workspace()
+
+    log(f"bench: forward, {args.warmup} warmup + {args.steps} timed steps")
+    wall, stage_ms = time_form(plan, plan.convolve, x, y, args.steps, args.warmup)
+    ms_per_step = 1e3 * wall / args.steps
+    value = plan.npix * args.steps / wall
+    log(f"bench: forward {ms_per_step:.3f} ms/step, stages (ms) "
+        + ", ".join(f"{n}={t:.3f}" for n, t in zip(STAGES, stage_ms)))
+
+    elem = 4
+    dom = int(np.argmax(stage_ms))
+    stage = STAGES[dom]
+    dur_s = stage_ms[dom] * 1e-3
+    bytes_per_launch = algorithmic_bytes(stage, plan, elem)
+    achieved = bytes_per_launch / dur_s / 1e9
+    traffic = measured_traffic(stage)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL_NAMES[stage],
+                "kernel_ms": round(stage_ms[dom], 4), "algorithmic_bytes_per_launch": bytes_per_launch}
+    total_alg = 3 * 2 * elem * plan.npix
+    forms = {"plain": {"pixels_per_s": value, "ms": ms_per_step,
+                       "hbm_roofline_frac_24B_per_px": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "stages_ms": dict(zip(STAGES, [round(t, 4) for t in stage_ms]))}}
+
+    if not args.no_adjoint:
+        steps_a = max(3, args.steps // 2)
+        log(f"bench: adjoint, {steps_a} timed steps")
+        wall_a, stage_a = time_form(plan, plan.adjoint, x, y, steps_a, 1)
+        ms_a = 1e3 * wall_a / steps_a
+        forms["adjoint"] = {"pixels_per_s": plan.npix * steps_a / wall_a, "ms": ms_a,
+                            "hbm_roofline_frac_24B_per_px": round(total_alg / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "stages_ms": dict(zip(STAGES, [round(t, 4) for t in stage_a]))}
+    forms["batched"] = None
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        log("bench: oracle CPU baseline")
+        cpu = cpu_baseline(w, xh, args.cpu_seconds)
+
+    out = {"metric": METRIC, "value": value, "unit": "pixels/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": w.name, "nside": 2048, "npix": plan.npix, "fwhm_arcmin": 5.0,
+                      "radius_arcmin": 20.0, "oversample": int(info.oversample), "kgen": "auto",
+                      "plan_seconds": round(plan_s, 3)},
+           "roofline": roofline, "cpu_baseline": cpu, "forms": forms}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

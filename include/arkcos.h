@@ -179,6 +179,20 @@ arkcos_status_t arkcos_batch_convolve(arkcos_batch_t batch, const void* const* x
                                       int32_t adjoint, void* ws, hipStream_t stream);
 arkcos_status_t arkcos_batch_destroy(arkcos_batch_t batch);
 
+/* ---- profiling aid ---- */
+
+/* Stage timing: with max_calls > 0, the next max_calls convolve / adjoint
+ * calls on this plan record HIP events on their own stream around each of
+ * their kernels: stage 0 ring R2C (step a), 1 ring-pair accumulation (steps b
+ * and c), 2 fold + C2R (step d), 3 pole-ring direct sum.  The events are
+ * created here (this call allocates); max_calls = 0 releases them.  Must not
+ * overlap with calls using the plan. */
+arkcos_status_t arkcos_plan_timing(arkcos_plan_t plan, int32_t max_calls);
+/* Milliseconds per stage summed over the calls recorded since the last
+ * arkcos_plan_timing / arkcos_stage_times (ms: 4 doubles), and their count.
+ * Waits for the recorded events; then starts a new recording window. */
+arkcos_status_t arkcos_stage_times(arkcos_plan_t plan, double* ms, int64_t* calls);
+
 const char* arkcos_status_string(arkcos_status_t status);
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* arkcos_last_error(void);

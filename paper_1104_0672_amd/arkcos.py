@@ -53,7 +53,8 @@ class PlanInfo(ctypes.Structure):
 EXPORTED = ["arkcos_default_options", "arkcos_plan", "arkcos_plan_destroy", "arkcos_plan_get_info",
             "arkcos_workspace_size", "arkcos_convolve", "arkcos_convolve_adjoint", "arkcos_kernel_grad",
             "arkcos_set_knots", "arkcos_batch_plan", "arkcos_batch_workspace_size",
-            "arkcos_batch_convolve", "arkcos_batch_destroy", "arkcos_status_string", "arkcos_last_error"]
+            "arkcos_batch_convolve", "arkcos_batch_destroy", "arkcos_plan_timing", "arkcos_stage_times",
+            "arkcos_status_string", "arkcos_last_error"]
 
 _lib = None
 
@@ -83,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.arkcos_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.arkcos_batch_convolve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, vp]
     lib.arkcos_batch_destroy.argtypes = [vp]
+    lib.arkcos_plan_timing.argtypes = [vp, i32]
+    lib.arkcos_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.arkcos_status_string.argtypes = [st]
     lib.arkcos_status_string.restype = ctypes.c_char_p
     lib.arkcos_last_error.argtypes = []
@@ -220,6 +223,17 @@ class Plan:
                                             self._ws_ptr(ws), 1 if reuse_spectra else 0,
                                             _stream_ptr(stream)), "arkcos_kernel_grad")
         return g
+
+    def start_timing(self, max_calls: int):
+        """Record per-stage HIP events for the next max_calls calls."""
+        _check(self._lib.arkcos_plan_timing(self.handle, int(max_calls)), "arkcos_plan_timing")
+
+    def stage_times(self):
+        """(ms per stage summed over the recorded calls, number of calls)."""
+        ms = (ctypes.c_double * 4)()
+        calls = ctypes.c_int64()
+        _check(self._lib.arkcos_stage_times(self.handle, ms, ctypes.byref(calls)), "arkcos_stage_times")
+        return list(ms), int(calls.value)
 
     def set_knots(self, knots: Sequence[float]):
         arr = (ctypes.c_double * self.n_knots)(*[float(v) for v in knots])

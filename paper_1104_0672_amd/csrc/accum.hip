@@ -11,15 +11,18 @@
 #include "arkcos_internal.h"
 #include "device_common.h"
 
+#include <algorithm>
+
 namespace arkcos {
 
 template <typename R> struct AccArgs {
   const UnitDev* units;
   const PairDev* pairs;
   const WorkItem* items;
+  const BandDev* bands;
   const int64_t* spec_off;
+  const int32_t* spec_len;
   const int64_t* out_off;
-  const int32_t* out_len;
   const R* coef;
   const R* table;
   int32_t nrings;
@@ -27,77 +30,208 @@ template <typename R> struct AccArgs {
   int32_t p;
 };
 
-// cos(pi * num / den) for the mode angles.
-template <typename R> __device__ __forceinline__ R cospi_frac(int num, int den) {
-  int64_t t = ((int64_t)num) % (2 * (int64_t)den);
-  return expipi<R>((int)t, den).x;
+// cos(pi * num / den) and sin(pi * num / den) for the mode angles.
+template <typename R> __device__ __forceinline__ cx_t<R> cispi_frac(int num, int den) {
+  int t = (int)((uint32_t)num % (2u * (uint32_t)den));
+  return expipi<R>(t, den);
 }
 
+// Per-thread constants of the three kernel grids at mode m.
+template <typename R> struct ModeAngles {
+  R c1, cp;        // cos(2 pi m / L), cos(2 pi m / (p L))
+  R s1h, c1h;      // sin, cos of pi m / L       (half angle of the p = 1 grid; shifted grid)
+  R sph, cph;      // sin, cos of pi m / (p L)   (half angle of the p > 1 grid)
+};
+
+// K(m) of one pair from its kernel samples (step b).  Sample rows are stored
+// zero-padded to whole chunks of 8; the recurrence runs over chunks of 4
+// (one uniform load each), i.e. over ceil(n / 4) * 4 samples.
 template <typename R>
-__global__ void __launch_bounds__(kBlock) accumulate_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec,
-                                                            cx_t<R>* __restrict__ bout) {
-  using C = cx_t<R>;
-  const WorkItem it = a.items[blockIdx.x];
-  const UnitDev u = a.units[it.unit];
-  const int m = it.m0 + threadIdx.x;
-  const int L = a.L, pl = a.p * a.L;
-  // cos of the mode angle on the three kernel grids
-  const R c1 = cospi_frac<R>(2 * m, L);    // centred, p = 1:  cos(2 pi m / L)
-  const R ch = cospi_frac<R>(m, L);        // shifted grid:    cos(pi m / L)
-  const R cp = cospi_frac<R>(2 * m, pl);   // centred, p > 1:  cos(2 pi m / (p L))
-  C acc0 = cmake<C>(R(0), R(0)), acc1 = acc0;
-  const bool mirror = u.im >= 0;
-  for (int q = u.pbeg; q < u.pend; ++q) {
-    const PairDev pr = a.pairs[q];
-    if (it.m0 > pr.band) continue;  // whole tile above the pair's band
-    R k;
-    if (pr.kind == KG_TABLE) {
-      k = m <= pr.band ? a.table[pr.off + m] : R(0);
+__device__ __forceinline__ R pair_k(int kind, int p, int ncoef, int nyq, int band, int64_t off,
+                                    const R* __restrict__ coef, const R* __restrict__ table,
+                                    const ModeAngles<R>& A, int m) {
+  R k;
+  const int n4 = (ncoef + 3) & ~3;
+  if (kind == KG_TABLE) {
+    k = m <= band ? table[off + m] : R(0);
+  } else if (kind == KG_REINSCH) {
+    // centred grid, Reinsch's form: stable for longer rows near x = 0 and pi
+    const R* cf = coef + off;
+    const R sh = p == 1 ? A.s1h : A.sph, ch = p == 1 ? A.c1h : A.cph;
+    R b = R(0), dd = R(0);
+    if (ch * ch >= R(0.5)) {
+      const R lam = R(-4) * sh * sh;
+      for (int c = n4 - 4; c >= 0; c -= 4) {
+        R cc[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cc[e] = cf[c + e];
+#pragma unroll
+        for (int e = 3; e >= 0; --e) {
+          dd = fma(lam, b, dd + cc[e]);
+          b = b + dd;
+        }
+      }
+      k = dd - R(0.5) * lam * (b - dd);
     } else {
-      const R* cf = a.coef + pr.off;
-      const R cx = pr.kind == KG_SHIFTED ? c1 : (pr.p == 1 ? c1 : cp);
-      const R al = R(2) * cx;
-      R b1 = R(0), b2 = R(0);
-      for (int d = pr.ncoef - 1; d >= 0; --d) {
-        R b0 = fma(al, b1, cf[d] - b2);
+      const R lam = R(4) * ch * ch;
+      for (int c = n4 - 4; c >= 0; c -= 4) {
+        R cc[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cc[e] = cf[c + e];
+#pragma unroll
+        for (int e = 3; e >= 0; --e) {
+          dd = fma(lam, b, cc[e] - dd);
+          b = dd - b;
+        }
+      }
+      k = dd - R(0.5) * lam * (dd - b);
+    }
+    if (m == nyq) k *= R(0.5);
+  } else {
+    const R* cf = coef + off;
+    const R cx = (kind == KG_SHIFTED || p == 1) ? A.c1 : A.cp;
+    const R al = R(2) * cx;
+    R b1 = R(0), b2 = R(0);
+    for (int c = n4 - 4; c >= 0; c -= 4) {
+      R cc[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cc[e] = cf[c + e];
+#pragma unroll
+      for (int e = 3; e >= 0; --e) {
+        R b0 = fma(al, b1, cc[e] - b2);
         b2 = b1;
         b1 = b0;
       }
-      k = pr.kind == KG_SHIFTED ? (b1 - b2) * ch : b1 - b2 * cx;
-      if (m == pr.nyq) k *= R(0.5);
     }
-    if (m <= pr.band) {
-      const C s0 = spec[a.spec_off[pr.j] + m];
-      acc0 = cmake<C>(fma(k, s0.x, acc0.x), fma(k, s0.y, acc0.y));
-      if (mirror) {
-        const C s1 = spec[a.spec_off[a.nrings - 1 - pr.j] + m];
-        acc1 = cmake<C>(fma(k, s1.x, acc1.x), fma(k, s1.y, acc1.y));
+    k = kind == KG_SHIFTED ? (b1 - b2) * A.c1h : b1 - b2 * cx;
+    if (m == nyq) k *= R(0.5);
+  }
+  return k;
+}
+
+// One work item: a band of up to kBandUnits consecutive units and kAccTile
+// modes.  The block first stages A~_j(m) (and the mirror ring's spectrum) of
+// every input ring in the band's window into LDS, one coalesced row per ring;
+// then wavefront w accumulates unit u0 + w over its pairs, lane = mode, with
+// all pair data wave-uniform.
+template <typename R> struct AccLds { static constexpr int kRings = 48; };
+template <> struct AccLds<double> { static constexpr int kRings = 24; };
+
+template <typename R>
+__global__ void __launch_bounds__(kAccThreads) accumulate_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec,
+                                                                 cx_t<R>* __restrict__ bout) {
+  using C = cx_t<R>;
+  constexpr int CH = AccLds<R>::kRings;  // input rings staged at a time
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* sa = reinterpret_cast<C*>(smem);  // [2 * CH][kAccTile]: ring, mirror ring
+  const WorkItem it = a.items[blockIdx.x];
+  const BandDev bd = a.bands[it.unit];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int m = it.m0 + lane;
+  const bool active = w < bd.nu;
+  UnitDev u{};
+  if (active) u = a.units[bd.u0 + w];
+  const bool busy = active && it.m0 <= u.band;
+  const bool mirror = u.im >= 0;
+  const int L = a.L, pl = a.p * a.L;
+  ModeAngles<R> ang;
+  {
+    const C e1 = cispi_frac<R>(2 * m, L), ep = cispi_frac<R>(2 * m, pl);
+    const C h1 = cispi_frac<R>(m, L), hp = cispi_frac<R>(m, pl);
+    ang.c1 = e1.x; ang.cp = ep.x;
+    ang.c1h = h1.x; ang.s1h = h1.y;
+    ang.cph = hp.x; ang.sph = hp.y;
+  }
+  C acc0 = cmake<C>(R(0), R(0)), acc1 = acc0;
+  // the unit's pair descriptors, one pair per lane (64 at a time), read back
+  // with readlane as wave-uniform values
+  const int npair = u.pend - u.pbeg;
+  int qi = 0, base = -64;
+  int vj = 0, vband = -1, vkind = 0, vp = 1, vnc = 0, vnyq = 0, voff_lo = 0, voff_hi = 0;
+  const int win = bd.jhi - bd.jlo + 1;
+  for (int c0 = 0; c0 < win; c0 += CH) {
+    const int c1 = min(win, c0 + CH);
+    for (int r = w; r < 2 * (c1 - c0); r += kBandUnits) {
+      int j = bd.jlo + c0 + (r >> 1);
+      if (r & 1) j = a.nrings - 1 - j;
+      C v = cmake<C>(R(0), R(0));
+      if (m < a.spec_len[j]) v = spec[a.spec_off[j] + m];
+      sa[r * kAccTile + lane] = v;
+    }
+    __syncthreads();
+    if (busy) {
+      for (; qi < npair; ++qi) {
+        if (qi - base >= 64) {
+          base = qi;
+          if (base + lane < npair) {
+            const PairDev mine = a.pairs[u.pbeg + base + lane];
+            vj = mine.j; vband = mine.band; vkind = mine.kind; vp = mine.p;
+            vnc = mine.ncoef; vnyq = mine.nyq;
+            voff_lo = (int)(uint32_t)(uint64_t)mine.off;
+            voff_hi = (int)(uint32_t)((uint64_t)mine.off >> 32);
+          }
+        }
+        const int t = qi - base;
+        const int j = __builtin_amdgcn_readlane(vj, t);
+        if (j >= bd.jlo + c1) break;
+        const int band = __builtin_amdgcn_readlane(vband, t);
+        if (it.m0 > band) continue;
+        const int kind = __builtin_amdgcn_readlane(vkind, t);
+        const int pp = __builtin_amdgcn_readlane(vp, t);
+        const int nc = __builtin_amdgcn_readlane(vnc, t);
+        const int nyq = __builtin_amdgcn_readlane(vnyq, t);
+        const int64_t off = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(voff_hi, t) << 32) |
+                                      (uint64_t)(uint32_t)__builtin_amdgcn_readlane(voff_lo, t));
+        R k = pair_k<R>(kind, pp, nc, nyq, band, off, a.coef, a.table, ang, m);
+        if (m > band) k = R(0);
+        const int row = 2 * (j - bd.jlo - c0);
+        const C s0 = sa[row * kAccTile + lane];
+        acc0 = cmake<C>(fma(k, s0.x, acc0.x), fma(k, s0.y, acc0.y));
+        if (mirror) {
+          const C s1 = sa[(row + 1) * kAccTile + lane];
+          acc1 = cmake<C>(fma(k, s1.x, acc1.x), fma(k, s1.y, acc1.y));
+        }
       }
     }
+    __syncthreads();
   }
-  if (m <= u.band) {
+  if (busy && m <= u.band) {
     bout[a.out_off[u.i] + m] = acc0;
     if (mirror) bout[a.out_off[u.im] + m] = acc1;
   }
 }
 
+static size_t acc_lds(const arkcos_plan_s* P) {
+  if (P->dtype == ARKCOS_F32)
+    return 2 * (size_t)std::min<int32_t>(P->max_window, AccLds<float>::kRings) * kAccTile * sizeof(float2);
+  return 2 * (size_t)std::min<int32_t>(P->max_window, AccLds<double>::kRings) * kAccTile * sizeof(double2);
+}
+
 // Modes beyond a unit's band stay zero (B_i has out_len_i = band_i + 1 modes,
 // so nothing is left unwritten).
+
+hipError_t configure_accumulate(arkcos_plan_s* P) {
+  const size_t lds = acc_lds(P);
+  if (P->dtype == ARKCOS_F32)
+    return hipFuncSetAttribute((const void*)accumulate_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipFuncSetAttribute((const void*)accumulate_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
 
 hipError_t launch_accumulate(arkcos_plan_s* P, const void* spec, void* bout, hipStream_t s) {
   if (P->h_items.empty()) return hipSuccess;
   if (P->dtype == ARKCOS_F32) {
-    AccArgs<float> a{P->d_units, P->d_pairs, P->d_items, P->rt.spec_off, P->rt.out_off,
-                     P->rt.out_len, (const float*)P->d_coef, (const float*)P->d_table,
+    AccArgs<float> a{P->d_units, P->d_pairs, P->d_items, P->d_bands, P->rt.spec_off, P->rt.spec_len,
+                     P->rt.out_off, (const float*)P->d_coef, (const float*)P->d_table,
                      (int32_t)P->nrings, (int32_t)P->L, P->oversample};
-    accumulate_kernel<float><<<(unsigned)P->h_items.size(), kBlock, 0, s>>>(
-        a, (const float2*)spec, (float2*)bout);
+    accumulate_kernel<float><<<(unsigned)P->h_items.size(), kAccThreads,
+                                acc_lds(P), s>>>(a, (const float2*)spec, (float2*)bout);
   } else {
-    AccArgs<double> a{P->d_units, P->d_pairs, P->d_items, P->rt.spec_off, P->rt.out_off,
-                      P->rt.out_len, (const double*)P->d_coef, (const double*)P->d_table,
+    AccArgs<double> a{P->d_units, P->d_pairs, P->d_items, P->d_bands, P->rt.spec_off, P->rt.spec_len,
+                      P->rt.out_off, (const double*)P->d_coef, (const double*)P->d_table,
                       (int32_t)P->nrings, (int32_t)P->L, P->oversample};
-    accumulate_kernel<double><<<(unsigned)P->h_items.size(), kBlock, 0, s>>>(
-        a, (const double2*)spec, (double2*)bout);
+    accumulate_kernel<double><<<(unsigned)P->h_items.size(), kAccThreads,
+                                 acc_lds(P), s>>>(a, (const double2*)spec, (double2*)bout);
   }
   return hipGetLastError();
 }

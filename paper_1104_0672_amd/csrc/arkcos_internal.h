@@ -17,6 +17,10 @@ constexpr int kBlock = 256;            // threads per block for every kernel
 constexpr int kModeTile = 256;         // modes per accumulation work item
 constexpr int kDirectMax = 64;         // rings up to this length use a plain DFT
 constexpr int kOtfMaxCoef = 48;        // wider kernel rows use a K_ij(m) table (auto mode)
+constexpr int kClenshawMaxCoef = 16;   // longer centred rows use Reinsch's recurrence
+constexpr int kBandUnits = 8;          // output units (ring + mirror) per accumulation work item
+constexpr int kAccTile = 64;           // modes per accumulation work item (one per lane)
+constexpr int kAccThreads = 64 * kBandUnits;  // one wavefront per unit
 
 // FFT strategy of one ring length.
 enum FftKind : int32_t { FFT_DIRECT = 0, FFT_POW2 = 1, FFT_BLUESTEIN = 2 };
@@ -25,7 +29,8 @@ enum FftKind : int32_t { FFT_DIRECT = 0, FFT_POW2 = 1, FFT_BLUESTEIN = 2 };
 //  KG_CENTRED  : nodes 2 pi d / (p L), recurrence on cos(m nu)
 //  KG_SHIFTED  : nodes 2 pi (d + 1/2) / L (equatorial pairs offset by pi/L)
 //  KG_TABLE    : precomputed K_ij(m), m <= band
-enum PairKind : int32_t { KG_CENTRED = 0, KG_SHIFTED = 1, KG_TABLE = 2 };
+//  KG_REINSCH  : centred nodes, Reinsch's form of the recurrence (longer rows)
+enum PairKind : int32_t { KG_CENTRED = 0, KG_SHIFTED = 1, KG_TABLE = 2, KG_REINSCH = 3 };
 
 // Per-ring table, device side (struct of arrays).
 struct RingTables {
@@ -63,8 +68,24 @@ struct UnitDev {
 };
 
 struct WorkItem {
-  int32_t unit;
+  int32_t unit;   // first unit of the band
   int32_t m0;
+};
+
+// A band of kBandUnits consecutive units: the input rings they need.
+struct BandDev {
+  int32_t u0, nu;       // units [u0, u0 + nu)
+  int32_t jlo, jhi;     // input rings [jlo, jhi]
+  int32_t band;         // max band over the units
+  int32_t pad;
+};
+
+// Rings whose FFTs share one launch: similar LDS needs, so small rings are
+// not held to the occupancy of the largest.
+struct FftClass {
+  int32_t* d_rings = nullptr;
+  int32_t count = 0;
+  int32_t lds = 0;
 };
 
 }  // namespace arkcos
@@ -99,6 +120,8 @@ struct arkcos_plan_s {
   std::vector<int32_t> h_pair_i;         // output ring of each pair
   std::vector<int32_t> h_pair_shift;     // half-shift flag per pair
   std::vector<int64_t> h_coef_off;       // recurrence-coefficient offset per pair
+  std::vector<int32_t> h_ncoef_window;   // kernel samples inside each pair's window
+  std::vector<arkcos::FftClass> fft_classes;
   std::vector<arkcos::WorkItem> h_items;
   std::vector<int32_t> h_spec_len, h_out_len;
   std::vector<int64_t> h_spec_off, h_out_off;
@@ -108,6 +131,9 @@ struct arkcos_plan_s {
   arkcos::UnitDev* d_units = nullptr;
   arkcos::PairDev* d_pairs = nullptr;
   arkcos::WorkItem* d_items = nullptr;
+  arkcos::BandDev* d_bands = nullptr;
+  int32_t max_window = 0;      // input rings staged per accumulation band
+  std::vector<arkcos::BandDev> h_bands;
   void* d_coef = nullptr;       // recurrence coefficients, plan dtype
   double* d_coef64 = nullptr;   // the same in FP64 (plan-time table building, gradient)
   void* d_table = nullptr;      // K_ij(m) tables, plan dtype
@@ -126,6 +152,10 @@ struct arkcos_plan_s {
   size_t plan_bytes = 0;
 
   std::vector<void*> allocations;
+
+  // stage timing (profiling aid): 5 events per recorded call
+  std::vector<hipEvent_t> timing_events;
+  int32_t timing_slots = 0, timing_used = 0;
 };
 
 namespace arkcos {
@@ -139,6 +169,7 @@ hipError_t launch_band(arkcos_plan_s* P, double threshold, int32_t* band_out, hi
 hipError_t launch_table_list(arkcos_plan_s* P, const int32_t* d_list, const int64_t* d_coef_off,
                              int32_t count, hipStream_t s);
 hipError_t configure_fft_kernels(arkcos_plan_s* P);
+hipError_t configure_accumulate(arkcos_plan_s* P);
 int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count);
 void workspace_split(const arkcos_plan_s* P, void* ws, void** spec, void** bout);
 size_t workspace_bytes(const arkcos_plan_s* P);

@@ -73,10 +73,17 @@ arkcos_status_t run_pipeline(arkcos_plan_s* P, const void* x, void* y, void* ws,
   void *spec, *bout;
   workspace_split(P, ws, &spec, &bout);
   const bool fix = P->geom.kind == 1 && P->opts.fix_pole_pixels;
+  hipEvent_t* ev = nullptr;
+  if (P->timing_used < P->timing_slots) ev = &P->timing_events[5 * P->timing_used++];
+  if (ev) LAUNCH(hipEventRecord(ev[0], s));
   LAUNCH(launch_r2c(P, x, spec, adjoint, adjoint && fix ? 1 : 0, s));
+  if (ev) LAUNCH(hipEventRecord(ev[1], s));
   LAUNCH(launch_accumulate(P, spec, bout, s));
+  if (ev) LAUNCH(hipEventRecord(ev[2], s));
   LAUNCH(launch_c2r(P, bout, y, adjoint, s));
+  if (ev) LAUNCH(hipEventRecord(ev[3], s));
   if (fix) LAUNCH(launch_pole_fix(P, x, y, adjoint, s));
+  if (ev) LAUNCH(hipEventRecord(ev[4], s));
   return ARKCOS_OK;
 }
 
@@ -113,6 +120,7 @@ arkcos_status_t arkcos_plan_destroy(arkcos_plan_t plan) {
   (void)hipGetDevice(&cur);
   if (cur != plan->device) (void)hipSetDevice(plan->device);
   for (void* a : plan->allocations) (void)hipFree(a);
+  for (hipEvent_t e : plan->timing_events) (void)hipEventDestroy(e);
   if (cur != plan->device) (void)hipSetDevice(cur);
   delete plan;
   return ARKCOS_OK;
@@ -189,6 +197,37 @@ arkcos_status_t arkcos_set_knots(arkcos_plan_t plan, const double* knot_values) 
   } catch (...) {
     return fail(ARKCOS_ERR_INTERNAL, "unexpected exception in knot update");
   }
+}
+
+arkcos_status_t arkcos_plan_timing(arkcos_plan_t plan, int32_t max_calls) {
+  if (!plan || max_calls < 0) return fail(ARKCOS_ERR_INVALID_VALUE, "bad argument");
+  for (hipEvent_t e : plan->timing_events) (void)hipEventDestroy(e);
+  plan->timing_events.clear();
+  plan->timing_slots = plan->timing_used = 0;
+  if (max_calls == 0) return ARKCOS_OK;
+  plan->timing_events.resize(5 * (size_t)max_calls);
+  for (auto& e : plan->timing_events)
+    if (hipEventCreate(&e) != hipSuccess) return fail(ARKCOS_ERR_DEVICE, "hipEventCreate failed");
+  plan->timing_slots = max_calls;
+  return ARKCOS_OK;
+}
+
+arkcos_status_t arkcos_stage_times(arkcos_plan_t plan, double* ms, int64_t* calls) {
+  if (!plan || !ms || !calls) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
+  for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+  for (int32_t c = 0; c < plan->timing_used; ++c) {
+    hipEvent_t* ev = &plan->timing_events[5 * c];
+    if (hipEventSynchronize(ev[4]) != hipSuccess) return fail(ARKCOS_ERR_DEVICE, "hipEventSynchronize failed");
+    for (int k = 0; k < 4; ++k) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess)
+        return fail(ARKCOS_ERR_DEVICE, "hipEventElapsedTime failed");
+      ms[k] += t;
+    }
+  }
+  *calls = plan->timing_used;
+  plan->timing_used = 0;
+  return ARKCOS_OK;
 }
 
 const char* arkcos_status_string(arkcos_status_t s) {

@@ -47,101 +47,195 @@ template <typename R> __device__ __forceinline__ cx_t<R> expipi(int num, int den
   return expipi_frac(R(0), num, den);
 }
 
-// e^{-i pi l^2 / n}, the Bluestein chirp, with l^2 reduced modulo 2n exactly.
+// e^{-i pi l^2 / n}, the Bluestein chirp, with l^2 reduced modulo 2n exactly
+// (l < 65536, so l^2 fits 32 bits).
 template <typename R> __device__ __forceinline__ cx_t<R> chirp(int l, int n) {
-  int64_t t = ((int64_t)l * (int64_t)l) % (2 * (int64_t)n);
+  uint32_t t = ((uint32_t)l * (uint32_t)l) % (2u * (uint32_t)n);
   return cconj(expipi<R>((int)t, n));
 }
 
 // ---------------------------------------------------------------------------
-// In-place power-of-two complex FFT of length M in LDS (Stockham formulation,
-// radix-4 passes and one radix-2 pass when log2 M is odd).  All threads of the
-// block take part; on entry and exit the data are in natural order and the
-// block is synchronised.  INV = true computes the unnormalised inverse.
-// tw: exp(-2 pi i k / TN) for k < TN, TN a multiple of M.
+// In-place power-of-two complex FFT of length M in LDS, Stockham formulation
+// with radix-16 passes (plus one radix-2/4/8 pass for the leftover factor).
+// Each butterfly keeps its R points in registers; its twiddles are the powers
+// of one table value w = exp(-2 pi i k / (Ns R)), formed by at most four
+// multiplications.  The LDS buffer is padded by one element every 32
+// (index i lives at lidx(i)) so the strided writes of the first pass do not
+// collide in the same banks.  All threads of the block take part; the block
+// is synchronised on entry and exit.  INV = true gives the unnormalised
+// inverse.  tw: exp(-2 pi i k / TN) for k < TN, TN a multiple of M.
 // ---------------------------------------------------------------------------
 template <typename R> struct FftLimits;
 template <> struct FftLimits<float> { static constexpr int kMaxM = 8192; };
 template <> struct FftLimits<double> { static constexpr int kMaxM = 4096; };
 
-template <typename R, bool INV>
-__device__ void lds_fft(cx_t<R>* buf, int M, const cx_t<R>* __restrict__ tw, int TN) {
-  using C = cx_t<R>;
-  constexpr int MAXB4 = FftLimits<R>::kMaxM / 4 / 256;
-  constexpr int MAXB2 = FftLimits<R>::kMaxM / 2 / 256;
-  const int tid = threadIdx.x, nth = blockDim.x;
-  int lg = 31 - __clz(M);
-  int Ns = 1;
-  while (lg >= 2) {
-    const int Q = M >> 2;
-    const int tstep = TN / (Ns * 4);
-    C v[MAXB4][4];
+__device__ __forceinline__ int lidx(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int lds_elems(int m) { return m + (m >> 5) + 1; }
+
+// Unnormalised forward (INV = false) or inverse DFT of R points in registers.
+template <typename C, bool INV> __device__ __forceinline__ C mul_mi(C a) {
+  // forward: multiply by -i; inverse: by +i
+  return INV ? cmake<C>(-a.y, a.x) : cmake<C>(a.y, -a.x);
+}
+
+template <typename C, bool INV> __device__ __forceinline__ void dft2(C& a, C& b) {
+  C t = csub(a, b);
+  a = cadd(a, b);
+  b = t;
+}
+
+template <typename C, bool INV> __device__ __forceinline__ void dft4(C& x0, C& x1, C& x2, C& x3) {
+  C a0 = cadd(x0, x2), a1 = csub(x0, x2), a2 = cadd(x1, x3), a3 = mul_mi<C, INV>(csub(x1, x3));
+  x0 = cadd(a0, a2);
+  x2 = csub(a0, a2);
+  x1 = cadd(a1, a3);
+  x3 = csub(a1, a3);
+}
+
+// v[k] <- sum_n v[n] W_R^{nk}, natural order in and out.
+template <typename C, bool INV, int R> __device__ __forceinline__ void dft_reg(C* v) {
+  using T = decltype(C{}.x);
+  if constexpr (R == 2) {
+    dft2<C, INV>(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4<C, INV>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    // n = 2 n1 + n2, k = k1 + 4 k2
+    dft4<C, INV>(v[0], v[2], v[4], v[6]);
+    dft4<C, INV>(v[1], v[3], v[5], v[7]);
+    const T h = T(0.70710678118654752440);
+    // twiddles W8^{k1} on the odd half
+    C t1 = v[3], t2 = v[5], t3 = v[7];
+    v[3] = INV ? cmake<C>(h * (t1.x - t1.y), h * (t1.x + t1.y)) : cmake<C>(h * (t1.x + t1.y), h * (t1.y - t1.x));
+    v[5] = mul_mi<C, INV>(t2);
+    v[7] = INV ? cmake<C>(-h * (t3.x + t3.y), h * (t3.x - t3.y)) : cmake<C>(h * (t3.y - t3.x), -h * (t3.x + t3.y));
+    C o[8];
 #pragma unroll
-    for (int b = 0; b < MAXB4; ++b) {
-      int j = tid + b * nth;
-      if (j < Q) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[b][r] = buf[j + r * Q];
-      }
+    for (int k1 = 0; k1 < 4; ++k1) {
+      C a = v[2 * k1], b = v[2 * k1 + 1];
+      o[k1] = cadd(a, b);
+      o[k1 + 4] = csub(a, b);
     }
-    __syncthreads();
 #pragma unroll
-    for (int b = 0; b < MAXB4; ++b) {
-      int j = tid + b * nth;
-      if (j < Q) {
-        int k = j & (Ns - 1);
+    for (int k = 0; k < 8; ++k) v[k] = o[k];
+  } else {
+    static_assert(R == 16, "radix");
+    // n = 4 n1 + n2, k = k1 + 4 k2
 #pragma unroll
-        for (int r = 1; r < 4; ++r) {
-          C t = tw[(k * r) * tstep];
-          if (INV) t = cconj(t);
-          v[b][r] = cmul(v[b][r], t);
+    for (int n2 = 0; n2 < 4; ++n2) dft4<C, INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    // now v[4 k1 + n2] = Y[n2][k1]; multiply by W16^{n2 k1}
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173), h = T(0.70710678118654752440);
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) {
+#pragma unroll
+      for (int n2 = 1; n2 < 4; ++n2) {
+        const int e = k1 * n2;  // exponent of W16 in 1..9
+        T wc, ws;               // cos, -sin of 2 pi e / 16
+        switch (e) {
+          case 1: wc = c1; ws = -s1; break;
+          case 2: wc = h; ws = -h; break;
+          case 3: wc = s1; ws = -c1; break;
+          case 4: wc = 0; ws = -1; break;
+          case 6: wc = -h; ws = -h; break;
+          case 9: wc = -c1; ws = s1; break;
+          default: wc = 1; ws = 0; break;
         }
-        C a0 = cadd(v[b][0], v[b][2]), a1 = csub(v[b][0], v[b][2]);
-        C a2 = cadd(v[b][1], v[b][3]), d = csub(v[b][1], v[b][3]);
-        // forward: multiply d by -i; inverse: by +i
-        C a3 = INV ? cmake<C>(-d.y, d.x) : cmake<C>(d.y, -d.x);
-        int o = (j - k) * 4 + k;
-        buf[o] = cadd(a0, a2);
-        buf[o + Ns] = cadd(a1, a3);
-        buf[o + 2 * Ns] = csub(a0, a2);
-        buf[o + 3 * Ns] = csub(a1, a3);
+        if (INV) ws = -ws;
+        v[4 * k1 + n2] = cmul(v[4 * k1 + n2], cmake<C>(wc, ws));
       }
     }
-    __syncthreads();
-    Ns <<= 2;
-    lg -= 2;
-  }
-  if (lg == 1) {
-    const int Q = M >> 1;
-    const int tstep = TN / (Ns * 2);
-    C v[MAXB2][2];
+    C o[16];
 #pragma unroll
-    for (int b = 0; b < MAXB2; ++b) {
-      int j = tid + b * nth;
-      if (j < Q) { v[b][0] = buf[j]; v[b][1] = buf[j + Q]; }
+    for (int k1 = 0; k1 < 4; ++k1) {
+      C a0 = v[4 * k1], a1 = v[4 * k1 + 1], a2 = v[4 * k1 + 2], a3 = v[4 * k1 + 3];
+      dft4<C, INV>(a0, a1, a2, a3);
+      o[k1] = a0;
+      o[k1 + 4] = a1;
+      o[k1 + 8] = a2;
+      o[k1 + 12] = a3;
     }
-    __syncthreads();
 #pragma unroll
-    for (int b = 0; b < MAXB2; ++b) {
-      int j = tid + b * nth;
-      if (j < Q) {
-        int k = j & (Ns - 1);
-        C t = tw[k * tstep];
-        if (INV) t = cconj(t);
-        C x1 = cmul(v[b][1], t);
-        int o = (j - k) * 2 + k;
-        buf[o] = cadd(v[b][0], x1);
-        buf[o + Ns] = csub(v[b][0], x1);
-      }
-    }
-    __syncthreads();
+    for (int k = 0; k < 16; ++k) v[k] = o[k];
   }
 }
 
-// Complex DFT of length n held in buf[0..n), in place, by the ring's method:
-// power of two directly, otherwise Bluestein's chirp convolution of length M
-// (buf must hold M elements; filt = FFT_M of the conjugate chirp).  INV gives
-// the unnormalised inverse DFT.  Synchronises the block on exit.
+// powers w^r, r = 1 .. R-1, each formed by at most four multiplications
+template <typename C, int R> __device__ __forceinline__ void twiddle_powers(C w, C* p) {
+  p[1] = w;
+  if constexpr (R > 2) {
+    p[2] = cmul(w, w);
+    p[3] = cmul(p[2], w);
+  }
+  if constexpr (R > 4) {
+    p[4] = cmul(p[2], p[2]);
+    p[5] = cmul(p[4], w);
+    p[6] = cmul(p[4], p[2]);
+    p[7] = cmul(p[4], p[3]);
+  }
+  if constexpr (R > 8) {
+    p[8] = cmul(p[4], p[4]);
+#pragma unroll
+    for (int r = 1; r < 8; ++r) p[8 + r] = cmul(p[8], p[r]);
+  }
+}
+
+template <typename R, bool INV, int RAD>
+__device__ __forceinline__ void stockham_pass(cx_t<R>* buf, int M, int Ns, const cx_t<R>* __restrict__ tw, int TN) {
+  using C = cx_t<R>;
+  const int Q = M / RAD;
+  const int tstep = TN / (Ns * RAD);
+  constexpr int MAXB = (FftLimits<R>::kMaxM / RAD + 255) / 256;
+  C v[MAXB][RAD];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = threadIdx.x + b * 256;
+    if (j < Q) {
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[b][r] = buf[lidx(j + r * Q)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = threadIdx.x + b * 256;
+    if (j < Q) {
+      const int k = j & (Ns - 1);
+      if (Ns > 1) {
+        C w = tw[k * tstep];
+        if (INV) w = cconj(w);
+        C p[RAD];
+        twiddle_powers<C, RAD>(w, p);
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) v[b][r] = cmul(v[b][r], p[r]);
+      }
+      dft_reg<C, INV, RAD>(v[b]);
+      const int o = (j - k) * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf[lidx(o + r * Ns)] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, bool INV>
+__device__ void lds_fft(cx_t<R>* buf, int M, const cx_t<R>* __restrict__ tw, int TN) {
+  int lg = 31 - __clz(M);
+  int Ns = 1;
+  const int rest = lg % 4;
+  if (rest == 1) { stockham_pass<R, INV, 2>(buf, M, Ns, tw, TN); Ns <<= 1; }
+  else if (rest == 2) { stockham_pass<R, INV, 4>(buf, M, Ns, tw, TN); Ns <<= 2; }
+  else if (rest == 3) { stockham_pass<R, INV, 8>(buf, M, Ns, tw, TN); Ns <<= 3; }
+  for (int t = 0; t < lg / 4; ++t) {
+    stockham_pass<R, INV, 16>(buf, M, Ns, tw, TN);
+    Ns <<= 4;
+  }
+}
+
+// Complex DFT of length n held in buf (padded layout) in place, by the ring's
+// method: power of two directly, otherwise Bluestein's chirp convolution of
+// length M (buf must hold lds_elems(M) elements; filt = FFT_M of the
+// conjugate chirp, followed by the chirp e^{-i pi l^2 / n} itself for l < n).
+// INV gives the unnormalised inverse DFT.  Synchronises the block on exit.
 template <typename R, bool INV>
 __device__ void ring_dft(cx_t<R>* buf, int n, int kind, int M, const cx_t<R>* __restrict__ filt,
                          const cx_t<R>* __restrict__ tw, int TN) {
@@ -154,22 +248,22 @@ __device__ void ring_dft(cx_t<R>* buf, int n, int kind, int M, const cx_t<R>* __
   for (int l = tid; l < M; l += nth) {
     C v = cmake<C>(R(0), R(0));
     if (l < n) {
-      v = buf[l];
+      v = buf[lidx(l)];
       if (INV) v = cconj(v);
-      v = cmul(v, chirp<R>(l, n));
+      v = cmul(v, filt[M + l]);
     }
-    buf[l] = v;
+    buf[lidx(l)] = v;
   }
   __syncthreads();
   lds_fft<R, false>(buf, M, tw, TN);
-  for (int k = tid; k < M; k += nth) buf[k] = cmul(buf[k], filt[k]);
+  for (int k = tid; k < M; k += nth) buf[lidx(k)] = cmul(buf[lidx(k)], filt[k]);
   __syncthreads();
   lds_fft<R, true>(buf, M, tw, TN);
   const R inv = R(1) / R(M);
   for (int k = tid; k < n; k += nth) {
-    C v = cscale(cmul(buf[k], chirp<R>(k, n)), inv);
+    C v = cscale(cmul(buf[lidx(k)], filt[M + k]), inv);
     if (INV) v = cconj(v);
-    buf[k] = v;
+    buf[lidx(k)] = v;
   }
   __syncthreads();
 }

@@ -46,17 +46,18 @@ template <typename R> struct RingArgs {
 template <typename R> __device__ __forceinline__ cx_t<R> unshift(int m, int den) {
   using C = cx_t<R>;
   if (den == 0) return cmake<C>(R(1), R(0));
-  int t = (int)(((int64_t)m) % (2 * (int64_t)den));
+  int t = (int)((uint32_t)m % (2u * (uint32_t)den));
   return cconj(expipi<R>(t, den));
 }
 
 template <typename R>
-__global__ void __launch_bounds__(kBlock) r2c_kernel(RingArgs<R> a, const R* __restrict__ x,
-                                                     cx_t<R>* __restrict__ spec) {
+__global__ void __launch_bounds__(kBlock) r2c_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
+                                                     const R* __restrict__ x, cx_t<R>* __restrict__ spec) {
   using C = cx_t<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* buf = reinterpret_cast<C*>(smem);
-  const int j = blockIdx.x;
+  __shared__ C nyq;  // A(N/2), kept outside the padded buffer
+  const int j = list[blockIdx.x];
   const int N = a.n[j], half = N / 2, kind = a.fft_kind[j];
   const int den = a.phase_den[j], len = a.len[j];
   C* out = spec + a.off[j];
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(kBlock) r2c_kernel(RingArgs<R> a, const R* __r
   const R scale = a.adjoint ? R(1.0 / a.w[j]) : R(1);
   const R* xr = x + a.start[j];
   if (kind == FFT_DIRECT) {
-    C* tab = buf + (half + 1);
+    C* tab = buf + lds_elems(half);
     R* xs = reinterpret_cast<R*>(tab + N);
     for (int t = tid; t < N; t += nth) {
       tab[t] = cconj(expipi<R>(2 * t, N));  // exp(-2 pi i t / N)
@@ -83,12 +84,13 @@ __global__ void __launch_bounds__(kBlock) r2c_kernel(RingArgs<R> a, const R* __r
         idx += m;
         if (idx >= N) idx -= N;
       }
-      buf[m] = acc;
+      if (m < half) buf[lidx(m)] = acc;
+      else nyq = acc;
     }
     __syncthreads();
   } else {
     const int n = half;
-    for (int l = tid; l < n; l += nth) buf[l] = cmake<C>(xr[2 * l] * scale, xr[2 * l + 1] * scale);
+    for (int l = tid; l < n; l += nth) buf[lidx(l)] = cmake<C>(xr[2 * l] * scale, xr[2 * l + 1] * scale);
     __syncthreads();
     if (kind == FFT_POW2)
       ring_dft<R, false>(buf, n, 1, n, nullptr, a.tw, a.TN);
@@ -96,38 +98,39 @@ __global__ void __launch_bounds__(kBlock) r2c_kernel(RingArgs<R> a, const R* __r
       ring_dft<R, false>(buf, n, 2, a.fft_m[j], a.bl + a.bl_off[j], a.tw, a.TN);
     // split Z into A(r) = E(r) + exp(-2 pi i r / N) O(r), in place, pairing r with n - r
     for (int r = tid; r <= n / 2; r += nth) {
-      int r2 = n - r;
-      C z1 = buf[r], z2 = buf[r2 == n ? 0 : r2];
-      // A(r)
+      const int r2 = n - r;
+      const C z1 = buf[lidx(r)], z2 = buf[lidx(r2 == n ? 0 : r2)];
       C e = cscale(cadd(z1, cconj(z2)), R(0.5));
-      C o = cscale(csub(z1, cconj(z2)), R(0.5));  // times -i below
-      C om = cmake<C>(o.y, -o.x);
-      C ar = cadd(e, cmul(cconj(expipi<R>(2 * r, N)), om));
-      // A(r2)
+      C o = cscale(csub(z1, cconj(z2)), R(0.5));
+      C ar = cadd(e, cmul(cconj(expipi<R>(2 * r, N)), cmake<C>(o.y, -o.x)));
       C e2 = cscale(cadd(z2, cconj(z1)), R(0.5));
       C o2 = cscale(csub(z2, cconj(z1)), R(0.5));
-      C om2 = cmake<C>(o2.y, -o2.x);
-      C ar2 = cadd(e2, cmul(cconj(expipi<R>(2 * r2, N)), om2));
-      buf[r] = ar;
-      if (r2 != r) buf[r2] = ar2;
+      C ar2 = cadd(e2, cmul(cconj(expipi<R>(2 * r2, N)), cmake<C>(o2.y, -o2.x)));
+      buf[lidx(r)] = ar;
+      if (r2 == n) nyq = ar2;
+      else if (r2 != r) buf[lidx(r2)] = ar2;
     }
     __syncthreads();
   }
   // periodic extension with the phase shift to absolute longitude
   for (int m = tid; m < len; m += nth) {
-    int r = m % N;
-    C v = r <= half ? buf[r] : cconj(buf[N - r]);
+    const int r = m % N;
+    C v;
+    if (r == half) v = nyq;
+    else if (r < half) v = buf[lidx(r)];
+    else v = cconj(buf[lidx(N - r)]);
     out[m] = cmul(v, unshift<R>(m, den));
   }
 }
 
 template <typename R>
-__global__ void __launch_bounds__(kBlock) c2r_kernel(RingArgs<R> a, const cx_t<R>* __restrict__ bin,
-                                                     R* __restrict__ y) {
+__global__ void __launch_bounds__(kBlock) c2r_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
+                                                     const cx_t<R>* __restrict__ bin, R* __restrict__ y) {
   using C = cx_t<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* buf = reinterpret_cast<C*>(smem);
-  const int i = blockIdx.x;
+  __shared__ C nyq;  // G(N/2)
+  const int i = list[blockIdx.x];
   const int N = a.n[i], half = N / 2, kind = a.fft_kind[i];
   const int den = a.phase_den[i], len = a.len[i];
   const C* b = bin + a.off[i];
@@ -139,20 +142,23 @@ __global__ void __launch_bounds__(kBlock) c2r_kernel(RingArgs<R> a, const cx_t<R
     for (int m = r; m < len; m += N) g = cadd(g, cmul(b[m], cconj(unshift<R>(m, den))));
     for (int m = (r == 0 ? N : N - r); m < len; m += N)
       g = cadd(g, cconj(cmul(b[m], cconj(unshift<R>(m, den)))));
-    buf[r] = cscale(g, scale);
+    g = cscale(g, scale);
+    if (r < half) buf[lidx(r)] = g;
+    else nyq = g;
   }
   __syncthreads();
   R* yr = y + a.start[i];
   if (kind == FFT_DIRECT) {
-    C* tab = buf + (half + 1);
+    C* tab = buf + lds_elems(half);
     for (int t = tid; t < N; t += nth) tab[t] = expipi<R>(2 * t, N);  // exp(+2 pi i t / N)
     __syncthreads();
+    const C g0 = buf[lidx(0)];
     for (int k = tid; k < N; k += nth) {
-      R acc = buf[0].x + ((k & 1) ? -buf[half].x : buf[half].x);
+      R acc = g0.x + ((k & 1) ? -nyq.x : nyq.x);
       int idx = k;
       for (int r = 1; r < half; ++r) {
-        C t = tab[idx];
-        acc += R(2) * (buf[r].x * t.x - buf[r].y * t.y);
+        const C t = tab[idx], g = buf[lidx(r)];
+        acc += R(2) * (g.x * t.x - g.y * t.y);
         idx += k;
         if (idx >= N) idx -= N;
       }
@@ -163,16 +169,15 @@ __global__ void __launch_bounds__(kBlock) c2r_kernel(RingArgs<R> a, const cx_t<R
   const int n = half;
   // Z(r) = E(r) + i O(r), E(r) = G(r) + conj(G(n-r)), O(r) = e^{2 pi i r/N} (G(r) - conj(G(n-r)))
   for (int r = tid; r <= n / 2; r += nth) {
-    int r2 = n - r;
-    C g1 = buf[r], g2 = buf[r2];
-    C e1 = cadd(g1, cconj(g2));
-    C o1 = cmul(expipi<R>(2 * r, N), csub(g1, cconj(g2)));
-    C z1 = cadd(e1, cmake<C>(-o1.y, o1.x));
-    buf[r] = z1;
+    const int r2 = n - r;
+    const C g1 = buf[lidx(r)], g2 = r2 == n ? nyq : buf[lidx(r2)];
+    const C e1 = cadd(g1, cconj(g2));
+    const C o1 = cmul(expipi<R>(2 * r, N), csub(g1, cconj(g2)));
+    buf[lidx(r)] = cadd(e1, cmake<C>(-o1.y, o1.x));
     if (r2 < n && r2 != r) {
-      C e2 = cadd(g2, cconj(g1));
-      C o2 = cmul(expipi<R>(2 * r2, N), csub(g2, cconj(g1)));
-      buf[r2] = cadd(e2, cmake<C>(-o2.y, o2.x));
+      const C e2 = cadd(g2, cconj(g1));
+      const C o2 = cmul(expipi<R>(2 * r2, N), csub(g2, cconj(g1)));
+      buf[lidx(r2)] = cadd(e2, cmake<C>(-o2.y, o2.x));
     }
   }
   __syncthreads();
@@ -181,7 +186,7 @@ __global__ void __launch_bounds__(kBlock) c2r_kernel(RingArgs<R> a, const cx_t<R
   else
     ring_dft<R, true>(buf, n, 2, a.fft_m[i], a.bl + a.bl_off[i], a.tw, a.TN);
   for (int l = tid; l < n; l += nth) {
-    C z = buf[l];
+    const C z = buf[lidx(l)];
     yr[2 * l] = z.x;
     yr[2 * l + 1] = z.y;
   }
@@ -209,7 +214,7 @@ template <typename R> static RingArgs<R> ring_args(arkcos_plan_s* P, bool out_si
 }
 
 hipError_t configure_fft_kernels(arkcos_plan_s* P) {
-  if (P->max_fft_lds <= 65536) return hipSuccess;
+  // dynamic LDS above 64 KiB (plus the static Nyquist slot) needs the attribute
   hipError_t e;
   if (P->dtype == ARKCOS_F32) {
     e = hipFuncSetAttribute((const void*)r2c_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_fft_lds);
@@ -225,22 +230,26 @@ hipError_t configure_fft_kernels(arkcos_plan_s* P) {
 
 hipError_t launch_r2c(arkcos_plan_s* P, const void* x, void* spec, int32_t adjoint,
                       int32_t zero_pole_rings, hipStream_t s) {
-  if (P->dtype == ARKCOS_F32)
-    r2c_kernel<float><<<(unsigned)P->nrings, kBlock, P->max_fft_lds, s>>>(
-        ring_args<float>(P, false, adjoint, zero_pole_rings), (const float*)x, (float2*)spec);
-  else
-    r2c_kernel<double><<<(unsigned)P->nrings, kBlock, P->max_fft_lds, s>>>(
-        ring_args<double>(P, false, adjoint, zero_pole_rings), (const double*)x, (double2*)spec);
+  for (const FftClass& c : P->fft_classes) {
+    if (P->dtype == ARKCOS_F32)
+      r2c_kernel<float><<<(unsigned)c.count, kBlock, c.lds, s>>>(
+          ring_args<float>(P, false, adjoint, zero_pole_rings), c.d_rings, (const float*)x, (float2*)spec);
+    else
+      r2c_kernel<double><<<(unsigned)c.count, kBlock, c.lds, s>>>(
+          ring_args<double>(P, false, adjoint, zero_pole_rings), c.d_rings, (const double*)x, (double2*)spec);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_c2r(arkcos_plan_s* P, const void* bout, void* y, int32_t adjoint, hipStream_t s) {
-  if (P->dtype == ARKCOS_F32)
-    c2r_kernel<float><<<(unsigned)P->nrings, kBlock, P->max_fft_lds, s>>>(
-        ring_args<float>(P, true, adjoint, 0), (const float2*)bout, (float*)y);
-  else
-    c2r_kernel<double><<<(unsigned)P->nrings, kBlock, P->max_fft_lds, s>>>(
-        ring_args<double>(P, true, adjoint, 0), (const double2*)bout, (double*)y);
+  for (const FftClass& c : P->fft_classes) {
+    if (P->dtype == ARKCOS_F32)
+      c2r_kernel<float><<<(unsigned)c.count, kBlock, c.lds, s>>>(
+          ring_args<float>(P, true, adjoint, 0), c.d_rings, (const float2*)bout, (float*)y);
+    else
+      c2r_kernel<double><<<(unsigned)c.count, kBlock, c.lds, s>>>(
+          ring_args<double>(P, true, adjoint, 0), c.d_rings, (const double2*)bout, (double*)y);
+  }
   return hipGetLastError();
 }
 

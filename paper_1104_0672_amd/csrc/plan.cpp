@@ -16,6 +16,7 @@
 #include <map>
 
 #include "arkcos_internal.h"
+#include "device_common.h"
 
 namespace arkcos {
 
@@ -111,9 +112,12 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
   }
   struct Free { void* a; void* b; ~Free() { if (a) hipFree(a); if (b) hipFree(b); } } fr{d_abs, d_band};
 
-  // the recurrence coefficients are indexed by their own offsets
+  // kernel samples over each pair's full window, indexed by coefficient offsets
   std::vector<arkcos::PairDev> pcoef = P->h_pairs;
-  for (int64_t q = 0; q < np; ++q) pcoef[q].off = P->h_coef_off[q];
+  for (int64_t q = 0; q < np; ++q) {
+    pcoef[q].off = P->h_coef_off[q];
+    pcoef[q].ncoef = P->h_ncoef_window[q];
+  }
   HIPCHK(hipMemcpy(P->d_pairs, pcoef.data(), np * sizeof(PairDev), hipMemcpyHostToDevice));
   HIPCHK(launch_kernel_rows(P, d_abs, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -121,7 +125,25 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
 
   double scale = 0.0;
   for (double v : abs_sum) scale = std::max(scale, v);
-  if (P->band_tol > 0 && np > 0) {
+  // drop trailing samples whose magnitudes sum to at most a tenth of the band
+  // tolerance: |K_ij(m)| then changes by less than 0.1 band_tol times the
+  // largest kernel-row magnitude at every m, so the row is not cut off with a
+  // step that would widen its spectrum
+  if (np > 0) {
+    std::vector<double> c64(P->coef_total);
+    HIPCHK(hipMemcpy(c64.data(), P->d_coef64, P->coef_total * sizeof(double), hipMemcpyDeviceToHost));
+    const double cut = 0.1 * P->band_tol * scale;
+    for (int64_t q = 0; q < np; ++q) {
+      int32_t n = P->h_ncoef_window[q];
+      const double* a = c64.data() + P->h_coef_off[q];
+      double dropped = 0.0;
+      while (n > 1 && dropped + fabs(a[n - 1]) <= cut) dropped += fabs(a[--n]);
+      pcoef[q].ncoef = n;
+      P->h_pairs[q].ncoef = n;
+    }
+    HIPCHK(hipMemcpy(P->d_pairs, pcoef.data(), np * sizeof(PairDev), hipMemcpyHostToDevice));
+  }
+  if (first_time && P->band_tol > 0 && np > 0) {
     HIPCHK(launch_band(P, P->band_tol * scale, d_band, s));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemcpy(band.data(), d_band, np * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -129,7 +151,7 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
     for (int64_t q = 0; q < np; ++q) band[q] = abs_sum[q] > 0 ? P->h_pairs[q].nyq : -1;
   }
   if (!first_time) {
-    // the memory layout was sized for the original bands: keep them
+    // the memory layout was sized for the original bands and table choices: keep them
     for (int64_t q = 0; q < np; ++q) band[q] = P->h_pairs[q].band;
   }
 
@@ -141,7 +163,9 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
     PairDev& pr = P->h_pairs[q];
     pr.band = band[q];
     bool table = false;
-    if (pr.band >= 0) {
+    if (!first_time) {
+      table = pr.kind == KG_TABLE;
+    } else if (pr.band >= 0) {
       if (P->opts.kgen == 2) table = true;
       else if (P->opts.kgen == 0) table = pr.ncoef > kOtfMaxCoef;
     }
@@ -153,7 +177,7 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
       tab_coef.push_back(P->h_coef_off[q]);
       ++ntab;
     } else {
-      pr.kind = P->h_pair_shift[q] ? KG_SHIFTED : KG_CENTRED;
+      pr.kind = P->h_pair_shift[q] ? KG_SHIFTED : (pr.ncoef > kClenshawMaxCoef ? KG_REINSCH : KG_CENTRED);
       pr.off = P->h_coef_off[q];
     }
   }
@@ -349,8 +373,9 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
         ncoef = std::max<int64_t>(ncoef, 1);
       }
       pr.ncoef = (int32_t)ncoef;
+      P->h_ncoef_window.push_back((int32_t)ncoef);
       P->h_coef_off.push_back(P->coef_total);
-      P->coef_total += ncoef;
+      P->coef_total += (ncoef + 7) / 8 * 8;  // rows padded with zeros to whole 8-sample chunks
       P->h_pairs.push_back(pr);
       P->h_pair_i.push_back((int32_t)i);
       P->h_pair_shift.push_back(shift);
@@ -369,6 +394,7 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   std::vector<int64_t> bl_off(nr, 0);
   std::map<int32_t, int64_t> bl_of_len;
   std::vector<int32_t> bl_rings;
+  std::vector<size_t> ring_lds(nr, 0);
   int64_t twn = 4;
   size_t lds = 0;
   for (int64_t k = 0; k < nr; ++k) {
@@ -376,7 +402,8 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
     if (N <= kDirectMax) {
       fft_kind[k] = FFT_DIRECT;
       fft_m[k] = 0;
-      lds = std::max(lds, (size_t)(N / 2 + 1 + N) * csz + N * rsz);
+      ring_lds[k] = (size_t)(lds_elems((int)(N / 2)) + N) * csz + N * rsz;
+      lds = std::max(lds, ring_lds[k]);
       continue;
     }
     const int64_t n = N / 2;
@@ -385,19 +412,21 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       fft_kind[k] = FFT_POW2;
       fft_m[k] = (int32_t)n;
       twn = std::max(twn, n);
-      lds = std::max(lds, (size_t)(n + 1) * csz);
+      ring_lds[k] = (size_t)lds_elems((int)n) * csz;
+      lds = std::max(lds, ring_lds[k]);
     } else {
       const int64_t M = next_pow2(2 * n - 1);
       if (M > maxM) return fail(ARKCOS_ERR_NOT_SUPPORTED, "Bluestein FFT longer than the LDS limit");
       fft_kind[k] = FFT_BLUESTEIN;
       fft_m[k] = (int32_t)M;
       twn = std::max(twn, M);
-      lds = std::max(lds, (size_t)std::max(M, n + 1) * csz);
+      ring_lds[k] = (size_t)lds_elems((int)M) * csz;
+      lds = std::max(lds, ring_lds[k]);
       auto it = bl_of_len.find((int32_t)N);
       if (it == bl_of_len.end()) {
         bl_of_len[(int32_t)N] = P->bl_total;
         bl_off[k] = P->bl_total;
-        P->bl_total += M;
+        P->bl_total += M + n;
         bl_rings.push_back((int32_t)k);
         P->max_bl_m = std::max<int32_t>(P->max_bl_m, (int32_t)M);
       } else {
@@ -407,6 +436,29 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   }
   P->twiddle_n = (int32_t)twn;
   P->max_fft_lds = (int32_t)((lds + 15) / 16 * 16);
+  {
+    // launch classes by LDS size (power-of-two buckets from 4 KiB); a ring
+    // and its mirror stay adjacent so they share cached filters
+    std::map<size_t, std::vector<int32_t>> cls;
+    auto bucket = [&](int64_t k) {
+      size_t b = 4096;
+      while (b < ring_lds[k]) b <<= 1;
+      cls[b].push_back((int32_t)k);
+    };
+    for (int64_t k = 0; k < (nr + 1) / 2; ++k) {
+      bucket(k);
+      if (nr - 1 - k != k) bucket(nr - 1 - k);
+    }
+    for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
+      FftClass c;
+      c.count = (int32_t)it->second.size();
+      size_t mx = 0;
+      for (int32_t k : it->second) mx = std::max(mx, ring_lds[k]);
+      c.lds = (int32_t)((mx + 15) / 16 * 16);
+      HIPCHK(upload(P, &c.d_rings, it->second));
+      P->fft_classes.push_back(c);
+    }
+  }
 
   // ------------------------------------------------------ device tables
   HIPCHK(upload(P, &P->rt.n, P->h_n));
@@ -423,9 +475,11 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   HIPCHK(upload(P, &P->d_coef_off, P->h_coef_off));
   HIPCHK(dev_alloc(P, &P->d_pairs, P->h_pairs.size()));
   HIPCHK(dev_alloc(P, &P->d_coef64, P->coef_total));
+  HIPCHK(hipMemset(P->d_coef64, 0, std::max<int64_t>(P->coef_total, 1) * sizeof(double)));
   {
     void* c = nullptr;
     HIPCHK(hipMalloc(&c, std::max<int64_t>(P->coef_total, 1) * rsz));
+    HIPCHK(hipMemset(c, 0, std::max<int64_t>(P->coef_total, 1) * rsz));
     P->allocations.push_back(c);
     P->plan_bytes += std::max<int64_t>(P->coef_total, 1) * rsz;
     P->d_coef = c;
@@ -516,11 +570,30 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   HIPCHK(upload(P, &P->rt.out_len, P->h_out_len));
   HIPCHK(upload(P, &P->d_units, P->h_units));
 
-  // work items: (unit, first mode) tiles
-  for (int64_t u = 0; u < nunits; ++u)
-    for (int32_t m0 = 0; m0 <= P->h_units[u].band; m0 += kModeTile)
-      P->h_items.push_back(WorkItem{(int32_t)u, m0});
+  // bands of consecutive units, and work items: (band, first mode) tiles
+  for (int64_t u0 = 0; u0 < nunits; u0 += kBandUnits) {
+    BandDev B{};
+    B.u0 = (int32_t)u0;
+    B.nu = (int32_t)std::min<int64_t>(kBandUnits, nunits - u0);
+    B.jlo = (int32_t)nr;
+    B.jhi = -1;
+    B.band = -1;
+    for (int64_t u = u0; u < u0 + B.nu; ++u) {
+      const UnitDev& U = P->h_units[u];
+      if (U.pend > U.pbeg) {
+        B.jlo = std::min(B.jlo, P->h_pairs[U.pbeg].j);
+        B.jhi = std::max(B.jhi, P->h_pairs[U.pend - 1].j);
+      }
+      B.band = std::max(B.band, U.band);
+    }
+    const int32_t b = (int32_t)P->h_bands.size();
+    P->h_bands.push_back(B);
+    if (B.jhi >= B.jlo) P->max_window = std::max(P->max_window, B.jhi - B.jlo + 1);
+    for (int32_t m0 = 0; m0 <= B.band; m0 += kAccTile) P->h_items.push_back(WorkItem{b, m0});
+  }
   HIPCHK(upload(P, &P->d_items, P->h_items));
+  HIPCHK(upload(P, &P->d_bands, P->h_bands));
+  HIPCHK(configure_accumulate(P));
 
   // rings whose pixels can lie within R of a pole pixel (direct-sum columns)
   if (g->kind == 1) {

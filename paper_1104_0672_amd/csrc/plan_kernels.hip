@@ -77,27 +77,47 @@ __global__ void __launch_bounds__(kBlock) kernel_rows_kernel(
   if (threadIdx.x == 0) abs_sum[q] = red[0];
 }
 
-// K_ij(m) in FP64 by the Clenshaw recurrence over the kernel samples:
+// K_ij(m) in FP64 from the kernel samples:
 //   centred grid:  K(m) = sum_d a_d cos(d x),        x = 2 pi m / (p L)
 //   shifted grid:  K(m) = sum_d a_d cos((2d+1) y),   y = pi m / L
-// with the half weight of the grid's Nyquist mode m = p L / 2.
+// with the half weight of the grid's Nyquist mode m = p L / 2.  The centred
+// sum uses Reinsch's modification of the Clenshaw recurrence, which carries
+// the differences b_k -/+ b_k+1 and the exactly computed 1 -/+ cos x, so its
+// rounding error does not grow with the number of samples near x = 0 and
+// x = pi (where the plain recurrence loses ~n^2 eps, enough to fake a wide
+// band for full-ring pairs).
 __device__ __forceinline__ double k_of_m_fp64(const double* __restrict__ a, int n, int m, int shift,
                                               int64_t pl, int nyq) {
-  double cx, cy;
+  double k;
   if (shift) {
-    cx = cospi(2.0 * (double)m / (double)pl);  // cos(2y)
-    cy = cospi((double)m / (double)pl);
+    const double cx = cospi(2.0 * (double)m / (double)pl), cy = cospi((double)m / (double)pl);
+    double al = 2.0 * cx, b1 = 0.0, b2 = 0.0;
+    for (int d = n - 1; d >= 0; --d) {
+      double b0 = fma(al, b1, a[d] - b2);
+      b2 = b1;
+      b1 = b0;
+    }
+    k = (b1 - b2) * cy;
   } else {
-    cx = cospi(2.0 * (double)m / (double)pl);
-    cy = cx;
+    const double hx = (double)m / (double)pl;      // x / (2 pi)
+    const double sh = sinpi(hx), ch = cospi(hx);  // sin(x/2), cos(x/2)
+    double b = 0.0, dd = 0.0;
+    if (ch * ch >= 0.5) {                          // cos x >= 0: d_k = b_k - b_k+1
+      const double lam = -4.0 * sh * sh;           // 2 cos x - 2
+      for (int d = n - 1; d >= 0; --d) {
+        dd = fma(lam, b, dd + a[d]);
+        b = b + dd;
+      }
+      k = dd - 0.5 * lam * (b - dd);               // S = d_0 - (lam/2) b_1
+    } else {                                       // cos x < 0: d_k = b_k + b_k+1
+      const double lam = 4.0 * ch * ch;            // 2 cos x + 2
+      for (int d = n - 1; d >= 0; --d) {
+        dd = fma(lam, b, a[d] - dd);
+        b = dd - b;
+      }
+      k = dd - 0.5 * lam * (dd - b);               // S = d_0 - (lam/2) b_1
+    }
   }
-  double al = 2.0 * cx, b1 = 0.0, b2 = 0.0;
-  for (int d = n - 1; d >= 0; --d) {
-    double b0 = fma(al, b1, a[d] - b2);
-    b2 = b1;
-    b1 = b0;
-  }
-  double k = shift ? (b1 - b2) * cy : b1 - b2 * cx;
   return m == nyq ? 0.5 * k : k;
 }
 
@@ -138,7 +158,7 @@ __global__ void __launch_bounds__(kBlock) table_kernel(
 }
 
 // Bluestein filter of length n: FFT_M of b_l = exp(+i pi l^2 / n) placed at l
-// and M - l for 0 <= l < n.
+// and M - l for 0 <= l < n, followed by the chirp exp(-i pi l^2 / n), l < n.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) bluestein_filter_kernel(
     const int32_t* __restrict__ rings, const int32_t* __restrict__ ring_n,
@@ -153,12 +173,13 @@ __global__ void __launch_bounds__(kBlock) bluestein_filter_kernel(
     int src = -1;
     if (l < n) src = l;
     else if (M - l < n) src = M - l;
-    buf[l] = src >= 0 ? cconj(chirp<R>(src, n)) : cmake<C>(R(0), R(0));
+    buf[lidx(l)] = src >= 0 ? cconj(chirp<R>(src, n)) : cmake<C>(R(0), R(0));
   }
   __syncthreads();
   lds_fft<R, false>(buf, M, tw, TN);
   C* o = out + bl_off[ring];
-  for (int l = threadIdx.x; l < M; l += blockDim.x) o[l] = buf[l];
+  for (int l = threadIdx.x; l < M; l += blockDim.x) o[l] = buf[lidx(l)];
+  for (int l = threadIdx.x; l < n; l += blockDim.x) o[M + l] = chirp<R>(l, n);
 }
 
 static ProfileDev make_profile(arkcos_plan_s* P) {
@@ -211,7 +232,15 @@ hipError_t launch_table_list(arkcos_plan_s* P, const int32_t* d_list, const int6
 hipError_t launch_bluestein_filters(arkcos_plan_s* P, const int32_t* d_ring_list, int32_t count,
                                     hipStream_t s) {
   if (count == 0) return hipSuccess;
-  size_t lds = (size_t)P->max_bl_m * (P->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2));
+  size_t lds = (size_t)lds_elems(P->max_bl_m) * (P->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2));
+  hipError_t e;
+  if (P->dtype == ARKCOS_F32)
+    e = hipFuncSetAttribute((const void*)bluestein_filter_kernel<float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  else
+    e = hipFuncSetAttribute((const void*)bluestein_filter_kernel<double>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   if (P->dtype == ARKCOS_F32)
     bluestein_filter_kernel<float><<<count, kBlock, lds, s>>>(
         d_ring_list, P->rt.n, P->rt.fft_m, P->rt.bl_off, (const float2*)P->d_twiddle,

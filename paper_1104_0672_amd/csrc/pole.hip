@@ -48,14 +48,17 @@ __device__ __forceinline__ double pixel_distance(const PoleArgs& P, int ia, int 
   return 2.0 * asin(r < 1.0 ? r : 1.0);
 }
 
-// Forward: one block per pole pixel (blockIdx.x < 8).
+// Forward: one block per pole pixel (blockIdx.x < 8); `rings` lists the
+// rings within R of either pole ring.
 template <typename R>
-__global__ void __launch_bounds__(kBlock) pole_forward_kernel(PoleArgs P, const R* __restrict__ x,
+__global__ void __launch_bounds__(kBlock) pole_forward_kernel(PoleArgs P, const int32_t* __restrict__ rings,
+                                                              int32_t nlist, const R* __restrict__ x,
                                                               R* __restrict__ y) {
   const int b = blockIdx.x;
   const int ip = b < 4 ? 0 : P.nrings - 1, kp = b & 3;
   double acc = 0.0;
-  for (int j = 0; j < P.nrings; ++j) {
+  for (int t = 0; t < nlist; ++t) {
+    const int j = rings[t];
     if (fabs(P.theta[j] - P.theta[ip]) > P.radius) continue;
     const int nj = P.n[j];
     const double wj = P.w[j];
@@ -111,15 +114,15 @@ hipError_t launch_pole_fix(arkcos_plan_s* P, const void* x, void* y, int32_t adj
   a.h = a.nk > 1 ? P->theta_max / (a.nk - 1) : 0.0;
   a.knots = P->d_knots;
   a.mom = P->d_spline_mom;
+  int32_t count = 0;
+  int32_t* list = pole_ring_list(P, &count);
+  if (count == 0) return hipSuccess;
   if (!adjoint) {
     if (P->dtype == ARKCOS_F32)
-      pole_forward_kernel<float><<<8, kBlock, 0, s>>>(a, (const float*)x, (float*)y);
+      pole_forward_kernel<float><<<8, kBlock, 0, s>>>(a, list, count, (const float*)x, (float*)y);
     else
-      pole_forward_kernel<double><<<8, kBlock, 0, s>>>(a, (const double*)x, (double*)y);
+      pole_forward_kernel<double><<<8, kBlock, 0, s>>>(a, list, count, (const double*)x, (double*)y);
   } else {
-    int32_t count = 0;
-    int32_t* list = pole_ring_list(P, &count);
-    if (count == 0) return hipSuccess;
     if (P->dtype == ARKCOS_F32)
       pole_adjoint_kernel<float><<<count, kBlock, 0, s>>>(a, list, (const float*)x, (float*)y);
     else

@@ -147,6 +147,8 @@ struct arkcos_plan_s {
   int32_t* d_pair_i = nullptr;
   int32_t* d_pair_shift = nullptr;
   int64_t* d_coef_off = nullptr;    // recurrence-coefficient offset of every pair
+  int32_t* d_ncoef_window = nullptr;  // kernel samples inside each pair's window
+  double* d_basis_mom = nullptr;    // spline basis moments S[a][k], n_knots^2
   int32_t* d_pole_rings = nullptr;  // rings within reach of a pole pixel
   int32_t n_pole_rings = 0;
   size_t plan_bytes = 0;
@@ -172,6 +174,9 @@ hipError_t configure_fft_kernels(arkcos_plan_s* P);
 hipError_t configure_accumulate(arkcos_plan_s* P);
 int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count);
 void workspace_split(const arkcos_plan_s* P, void* ws, void** spec, void** bout);
+double* grad_slots(const arkcos_plan_s* P, void* ws);
+hipError_t launch_r2c_layout(arkcos_plan_s* P, const void* x, void* spec, bool out_layout, int32_t zero_pole,
+                             hipStream_t s);
 size_t workspace_bytes(const arkcos_plan_s* P);
 hipError_t launch_bluestein_filters(arkcos_plan_s* P, const int32_t* d_ring_list, int32_t count,
                                     hipStream_t s);

@@ -241,6 +241,21 @@ hipError_t launch_r2c(arkcos_plan_s* P, const void* x, void* spec, int32_t adjoi
   return hipGetLastError();
 }
 
+// Step (a) into the output-ring layout (lengths out_len): the extended
+// spectra of a map on the output rings, for the kernel-profile gradient.
+hipError_t launch_r2c_layout(arkcos_plan_s* P, const void* x, void* spec, bool out_layout, int32_t zero_pole,
+                             hipStream_t s) {
+  for (const FftClass& c : P->fft_classes) {
+    if (P->dtype == ARKCOS_F32)
+      r2c_kernel<float><<<(unsigned)c.count, kBlock, c.lds, s>>>(
+          ring_args<float>(P, out_layout, 0, zero_pole), c.d_rings, (const float*)x, (float2*)spec);
+    else
+      r2c_kernel<double><<<(unsigned)c.count, kBlock, c.lds, s>>>(
+          ring_args<double>(P, out_layout, 0, zero_pole), c.d_rings, (const double*)x, (double2*)spec);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_c2r(arkcos_plan_s* P, const void* bout, void* y, int32_t adjoint, hipStream_t s) {
   for (const FftClass& c : P->fft_classes) {
     if (P->dtype == ARKCOS_F32)

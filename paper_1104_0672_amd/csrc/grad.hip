@@ -1,28 +1,326 @@
-// Kernel-profile gradient (placeholder until the correlation kernels land).
+// Gradient of L = 1/2 |C x - t|^2 with respect to the spline knot values c_k
+// of the kernel profile, given r = C x - t.
+//
+// The ring pipeline computes y_ik = sum_{|m| <= M_i} B_i(m) e^{i m phi_ik} with
+// B_i(m) = sum_j K_ij(m) A~_j(m) and K_ij(m) = h_ij(m) sum_d a_ijd cos(m nu_d)
+// (h = 1/2 at the grid's Nyquist mode, 1 elsewhere; a_ijd = c_d w_j K(theta_ijd)
+// / (p L), c_d the symmetric-node multiplicity).  Hence
+//   <r, y> = sum_pairs sum_m eps_m h_ij(m) K~_ij(m) X_ij(m),
+//   X_ij(m) = Re[conj(R~_i(m)) A~_j(m)],  eps_0 = 1, eps_m = 2 (m >= 1),
+// where R~_i is the extended spectrum of r on output ring i, and
+//   dL/dc_k = sum_pairs sum_d (c_d w_j / (p L)) phi_k(theta_ijd) Y_ij(d),
+//   Y_ij(d) = sum_m eps_m h_ij(m) cos(m nu_d) X_ij(m)
+// (a per-pair Fourier-space correlation reduced over m, then over the kernel
+// samples).  phi_k is the cardinal clamped cubic spline: on knot interval a,
+// with u = (theta - theta_a) / h,
+//   phi_k = (1-u) [a = k] + u [a+1 = k] + h^2/6 ((1-u)^3-(1-u)) S_ak + h^2/6 (u^3-u) S_a+1,k
+// (S: second-derivative moments of the basis splines).  Each unit (output
+// ring and mirror) accumulates the four interval sums per knot interval in
+// FP64; a final single-block pass adds the per-unit partials in a fixed order
+// and maps them onto the knots, so the result is deterministic.  The pole
+// rows recomputed by the direct sum contribute
+//   sum_{p in poles} r_p sum_q phi_k(theta_pq) x_q w_q.
 #include "arkcos_internal.h"
+#include "device_common.h"
+
+#include <string>
 
 namespace arkcos {
 
-arkcos_status_t run_kernel_grad(arkcos_plan_s* P, const void* x, const void* r, double* grad,
-                                void* ws, uint32_t flags, hipStream_t s) {
-  (void)P; (void)x; (void)r; (void)grad; (void)ws; (void)flags; (void)s;
-  return fail(ARKCOS_ERR_NOT_SUPPORTED, "knot gradient not built yet");
+struct GradArgs {
+  const UnitDev* units;
+  const PairDev* pairs;
+  const int32_t* pair_shift;
+  const int32_t* ncoef_window;
+  const double* theta;
+  const double* sint;
+  const double* w;
+  const int64_t* spec_off;
+  const int64_t* out_off;
+  const int32_t* n;
+  const int64_t* start;
+  const int32_t* phase_den;
+  int32_t nrings;
+  int64_t L;
+  int32_t nk;
+  double h, radius, theta_max;
+  double* slots;  // [slot][4 * (nk - 1)]
+};
+
+constexpr int kGradMaxCoef = 48;  // rows up to this length: threads over modes
+
+__device__ __forceinline__ double grad_distance(double ti, double tj, double si, double sj, int64_t num,
+                                                int64_t den) {
+  double a = sin(0.5 * (ti - tj));
+  double b = sinpi(0.5 * (double)num / (double)den);
+  double hav = a * a + si * sj * b * b;
+  double r = sqrt(hav);
+  return 2.0 * asin(r < 1.0 ? r : 1.0);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Adds weight * (basis pieces at distance t) into the interval sums U[a][0..3]
+// (nothing beyond the support or the last knot).
+__device__ __forceinline__ void interval_add(double* U, const GradArgs& g, double t, double weight) {
+  if (t > g.radius || t > g.theta_max + kSupportTol) return;
+  int a = (int)floor(t / g.h);
+  a = a < 0 ? 0 : (a > g.nk - 2 ? g.nk - 2 : a);
+  const double u = t / g.h - a, v = 1.0 - u, h2 = g.h * g.h / 6.0;
+  U[4 * a + 0] += weight * v;
+  U[4 * a + 1] += weight * u;
+  U[4 * a + 2] += weight * h2 * (v * v * v - v);
+  U[4 * a + 3] += weight * h2 * (u * u * u - u);
+}
+
+// Ordered scatter of up to blockDim samples: thread k provides the distance
+// t_k and weight of its sample; thread 0 adds them into U in index order.
+__device__ __forceinline__ void ordered_scatter(double* U, const GradArgs& g, double* st, double* sw, int count,
+                                                double t, double wgt) {
+  st[threadIdx.x] = t;
+  sw[threadIdx.x] = wgt;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < count; ++k) interval_add(U, g, st[k], sw[k]);
+  __syncthreads();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) grad_pairs_kernel(GradArgs g, const cx_t<R>* __restrict__ aspec,
+                                                            const cx_t<R>* __restrict__ rspec) {
+  using C = cx_t<R>;
+  __shared__ double U[4 * 63];
+  __shared__ double Y[kGradMaxCoef];
+  __shared__ double part[kBlock / 64];
+  __shared__ double xs[kBlock];
+  __shared__ double st[kBlock];
+  __shared__ double sw[kBlock];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nint4 = 4 * (g.nk - 1);
+  for (int e = tid; e < nint4; e += blockDim.x) U[e] = 0.0;
+  const UnitDev u = g.units[blockIdx.x];
+  const bool mirror = u.im >= 0;
+  __syncthreads();
+  for (int q = u.pbeg; q < u.pend; ++q) {
+    const PairDev pr = g.pairs[q];
+    if (pr.band < 0) continue;
+    const int j = pr.j, jm = g.nrings - 1 - j;
+    const int nc = g.ncoef_window[q], s = g.pair_shift[q];
+    const int64_t pl = (int64_t)pr.p * g.L;
+    const C* ai = aspec + g.spec_off[j];
+    const C* ri = rspec + g.out_off[u.i];
+    const C* am = aspec + g.spec_off[jm];
+    const C* rm = mirror ? rspec + g.out_off[u.im] : ri;
+    const double scale = g.w[j] / (double)pl;
+    auto xcorr = [&](int m) -> double {  // eps_m h(m) (X_ij(m) + X_i'j'(m))
+      const C a0 = ai[m], r0 = ri[m];
+      double X = (double)r0.x * a0.x + (double)r0.y * a0.y;
+      if (mirror) {
+        const C a1 = am[m], r1 = rm[m];
+        X += (double)r1.x * a1.x + (double)r1.y * a1.y;
+      }
+      double wm = m == 0 ? 1.0 : 2.0;
+      if (m == pr.nyq) wm *= 0.5;
+      return X * wm;
+    };
+    auto sample = [&](int d, double& t, double& cd) {
+      t = grad_distance(g.theta[u.i], g.theta[j], g.sint[u.i], g.sint[j], 2 * (int64_t)d + s, pl);
+      cd = (s == 0 && (d == 0 || 2 * (int64_t)d == pl)) ? 1.0 : 2.0;
+    };
+    if (nc <= kGradMaxCoef) {
+      // threads over modes; per-thread sums for every sample d
+      double acc[kGradMaxCoef];
+#pragma unroll
+      for (int d = 0; d < kGradMaxCoef; ++d) acc[d] = 0.0;
+      for (int m = tid; m <= pr.band; m += blockDim.x) {
+        const double X = xcorr(m);
+        // cos(m nu_d), nu_d = pi (2d + s) / (p L), by the Chebyshev recurrence in d
+        double c0, c1, step;
+        if (s == 0) {
+          c0 = 1.0;
+          c1 = cospi(2.0 * (double)m / (double)pl);
+          step = 2.0 * c1;
+        } else {
+          c0 = cospi((double)m / (double)pl);
+          c1 = cospi(3.0 * (double)m / (double)pl);
+          step = 2.0 * cospi(2.0 * (double)m / (double)pl);
+        }
+#pragma unroll
+        for (int d = 0; d < kGradMaxCoef; ++d) {
+          if (d < nc) acc[d] = fma(X, c0, acc[d]);
+          const double c2 = fma(step, c1, -c0);
+          c0 = c1;
+          c1 = c2;
+        }
+      }
+      for (int d = 0; d < nc; ++d) {
+        const double v = wave_sum(acc[d]);
+        if (lane == 0) part[wv] = v;
+        __syncthreads();
+        if (tid == 0) {
+          double t = 0.0;
+          for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k];
+          Y[d] = t;
+        }
+        __syncthreads();
+      }
+      double t = 0.0, cd = 0.0, wgt = 0.0;
+      if (tid < nc) {
+        sample(tid, t, cd);
+        wgt = cd * scale * Y[tid];
+      }
+      ordered_scatter(U, g, st, sw, nc, t, wgt);
+    } else {
+      // wide rows: threads over samples, modes staged in chunks
+      for (int d0 = 0; d0 < nc; d0 += blockDim.x) {
+        const int d = d0 + tid;
+        double sn = 0.0, cs = 1.0;
+        if (d < nc) sincospi((double)(2 * (int64_t)d + s) / (double)pl, &sn, &cs);  // e^{i nu_d}
+        double y = 0.0;
+        for (int m0 = 0; m0 <= pr.band; m0 += blockDim.x) {
+          const int m = m0 + tid;
+          xs[tid] = m <= pr.band ? xcorr(m) : 0.0;
+          __syncthreads();
+          if (d < nc) {
+            const int64_t ph = ((2 * (int64_t)d + s) * (int64_t)m0) % (2 * pl);
+            double zi, zr;  // e^{i m0 nu_d}
+            sincospi((double)ph / (double)pl, &zi, &zr);
+            const int mc = min((int)blockDim.x, pr.band - m0 + 1);
+            for (int k = 0; k < mc; ++k) {
+              y = fma(xs[k], zr, y);
+              const double nr = zr * cs - zi * sn;
+              zi = zr * sn + zi * cs;
+              zr = nr;
+            }
+          }
+          __syncthreads();
+        }
+        double t = 0.0, cd = 0.0, wgt = 0.0;
+        if (d < nc) {
+          sample(d, t, cd);
+          wgt = cd * scale * y;
+        }
+        ordered_scatter(U, g, st, sw, min((int)blockDim.x, nc - d0), t, wgt);
+      }
+    }
+  }
+  double* out = g.slots + (size_t)blockIdx.x * nint4;
+  for (int e = tid; e < nint4; e += blockDim.x) out[e] = U[e];
+}
+
+// Direct-sum pole rows: one block per pole pixel p, slot n_units + b.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) grad_pole_kernel(GradArgs g, const int32_t* __restrict__ rings,
+                                                           int32_t nlist, const R* __restrict__ x,
+                                                           const R* __restrict__ r, int32_t slot0) {
+  __shared__ double U[4 * 63];
+  __shared__ double st[kBlock];
+  __shared__ double sw[kBlock];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int nint4 = 4 * (g.nk - 1);
+  for (int e = tid; e < nint4; e += blockDim.x) U[e] = 0.0;
+  __syncthreads();
+  const int ip = b < 4 ? 0 : g.nrings - 1, kp = b & 3;
+  const double rp = (double)r[g.start[ip] + kp];
+  for (int li = 0; li < nlist; ++li) {
+    const int jr = rings[li];
+    if (fabs(g.theta[jr] - g.theta[ip]) > g.radius) continue;
+    const int nj = g.n[jr];
+    for (int k0 = 0; k0 < nj; k0 += blockDim.x) {
+      const int k = k0 + tid;
+      double t = 1e300, wgt = 0.0;
+      if (k < nj) {
+        const int64_t na = g.n[ip], nb = nj;
+        const int64_t sa = g.phase_den[ip] ? 1 : 0, sb = g.phase_den[jr] ? 1 : 0;
+        const int64_t num = (2 * (int64_t)kp + sa) * nb - (2 * (int64_t)k + sb) * na;
+        const double hd = sinpi((double)num / (double)(2 * na * nb));
+        const double a = sin(0.5 * (g.theta[ip] - g.theta[jr]));
+        const double hav = a * a + g.sint[ip] * g.sint[jr] * hd * hd;
+        const double rr = sqrt(hav);
+        t = 2.0 * asin(rr < 1.0 ? rr : 1.0);
+        wgt = rp * (double)x[g.start[jr] + k] * g.w[jr];
+      }
+      ordered_scatter(U, g, st, sw, min((int)blockDim.x, nj - k0), t, wgt);
+    }
+  }
+  double* out = g.slots + (size_t)(slot0 + b) * nint4;
+  for (int e = tid; e < nint4; e += blockDim.x) out[e] = U[e];
+}
+
+// Sum of the slots in a fixed order, then the map onto the knots.
+__global__ void __launch_bounds__(kBlock) grad_final_kernel(const double* __restrict__ slots, int32_t nslots,
+                                                            int32_t nk, const double* __restrict__ basis_mom,
+                                                            double* __restrict__ grad) {
+  __shared__ double Us[4 * 63];
+  const int nint4 = 4 * (nk - 1);
+  for (int e = threadIdx.x; e < nint4; e += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nslots; ++k) s += slots[(size_t)k * nint4 + e];
+    Us[e] = s;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nk; k += blockDim.x) {
+    double gk = 0.0;
+    if (k <= nk - 2) gk += Us[4 * k + 0];
+    if (k >= 1) gk += Us[4 * (k - 1) + 1];
+    for (int a = 0; a <= nk - 2; ++a)
+      gk += Us[4 * a + 2] * basis_mom[a * nk + k] + Us[4 * a + 3] * basis_mom[(a + 1) * nk + k];
+    grad[k] = gk;
+  }
+}
+
+arkcos_status_t run_kernel_grad(arkcos_plan_s* P, const void* x, const void* r, double* grad, void* ws,
+                                uint32_t flags, hipStream_t s) {
+  void *spec, *bout;
+  workspace_split(P, ws, &spec, &bout);
+  double* slots = grad_slots(P, ws);
+  const bool fix = P->geom.kind == 1 && P->opts.fix_pole_pixels;
+  hipError_t e = hipSuccess;
+  if (!(flags & 1u)) e = launch_r2c_layout(P, x, spec, false, 0, s);
+  if (e == hipSuccess) e = launch_r2c_layout(P, r, bout, true, fix ? 1 : 0, s);
+  if (e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string("ring transform: ") + hipGetErrorString(e));
+  GradArgs g{};
+  g.units = P->d_units;
+  g.pairs = P->d_pairs;
+  g.pair_shift = P->d_pair_shift;
+  g.ncoef_window = P->d_ncoef_window;
+  g.theta = P->d_theta;
+  g.sint = P->d_sin;
+  g.w = P->rt.w;
+  g.spec_off = P->rt.spec_off;
+  g.out_off = P->rt.out_off;
+  g.n = P->rt.n;
+  g.start = P->rt.start;
+  g.phase_den = P->rt.phase_den;
+  g.nrings = (int32_t)P->nrings;
+  g.L = P->L;
+  g.nk = (int32_t)P->knots.size();
+  g.h = P->theta_max / (g.nk - 1);
+  g.radius = P->radius + kSupportTol;
+  g.theta_max = P->theta_max;
+  g.slots = slots;
+  const int32_t nunits = (int32_t)P->n_units;
+  if (P->dtype == ARKCOS_F32)
+    grad_pairs_kernel<float><<<nunits, kBlock, 0, s>>>(g, (const float2*)spec, (const float2*)bout);
+  else
+    grad_pairs_kernel<double><<<nunits, kBlock, 0, s>>>(g, (const double2*)spec, (const double2*)bout);
+  int32_t nslots = nunits;
+  if (fix) {
+    int32_t count = 0;
+    int32_t* list = pole_ring_list(P, &count);
+    if (P->dtype == ARKCOS_F32)
+      grad_pole_kernel<float><<<8, kBlock, 0, s>>>(g, list, count, (const float*)x, (const float*)r, nunits);
+    else
+      grad_pole_kernel<double><<<8, kBlock, 0, s>>>(g, list, count, (const double*)x, (const double*)r, nunits);
+    nslots += 8;
+  }
+  grad_final_kernel<<<1, kBlock, 0, s>>>(slots, nslots, g.nk, P->d_basis_mom, grad);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string("gradient kernels: ") + hipGetErrorString(e));
+  return ARKCOS_OK;
 }
 
 }  // namespace arkcos
-
-extern "C" {
-arkcos_status_t arkcos_batch_plan(int32_t, const arkcos_plan_t*, arkcos_batch_t*) {
-  return arkcos::fail(ARKCOS_ERR_NOT_SUPPORTED, "batched form not built yet");
-}
-arkcos_status_t arkcos_batch_workspace_size(arkcos_batch_t, size_t*) {
-  return arkcos::fail(ARKCOS_ERR_NOT_SUPPORTED, "batched form not built yet");
-}
-arkcos_status_t arkcos_batch_convolve(arkcos_batch_t, const void* const*, void* const*, int32_t, void*,
-                                      hipStream_t) {
-  return arkcos::fail(ARKCOS_ERR_NOT_SUPPORTED, "batched form not built yet");
-}
-arkcos_status_t arkcos_batch_destroy(arkcos_batch_t) {
-  return arkcos::fail(ARKCOS_ERR_NOT_SUPPORTED, "batched form not built yet");
-}
-}

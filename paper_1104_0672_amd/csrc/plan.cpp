@@ -473,6 +473,19 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   HIPCHK(upload(P, &P->d_pair_i, P->h_pair_i));
   HIPCHK(upload(P, &P->d_pair_shift, P->h_pair_shift));
   HIPCHK(upload(P, &P->d_coef_off, P->h_coef_off));
+  HIPCHK(upload(P, &P->d_ncoef_window, P->h_ncoef_window));
+  if (prof->kind == 1) {
+    // moments of the basis splines (the spline through e_k), S[a][k]
+    const int nk = (int)P->knots.size();
+    std::vector<double> S((size_t)nk * nk), e(nk, 0.0), mom;
+    for (int k = 0; k < nk; ++k) {
+      e[k] = 1.0;
+      spline_moments(e, P->theta_max / (nk - 1), mom);
+      for (int a = 0; a < nk; ++a) S[(size_t)a * nk + k] = mom[a];
+      e[k] = 0.0;
+    }
+    HIPCHK(upload(P, &P->d_basis_mom, S));
+  }
   HIPCHK(dev_alloc(P, &P->d_pairs, P->h_pairs.size()));
   HIPCHK(dev_alloc(P, &P->d_coef64, P->coef_total));
   HIPCHK(hipMemset(P->d_coef64, 0, std::max<int64_t>(P->coef_total, 1) * sizeof(double)));
@@ -616,10 +629,25 @@ int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count) {
   return P->d_pole_rings;
 }
 
+// Workspace: extended input spectra | output-ring coefficients | (spline
+// plans) per-unit gradient partials, each 256-byte aligned.
+static size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+
+static size_t grad_slot_bytes(const arkcos_plan_s* P) {
+  if (P->prof_kind != 1) return 0;
+  return al256((size_t)(P->n_units + 8) * 4 * (P->knots.size() - 1) * sizeof(double));
+}
+
 size_t workspace_bytes(const arkcos_plan_s* P) {
   const size_t csz = P->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
-  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-  return al(std::max<int64_t>(P->spec_total, 1) * csz) + al(std::max<int64_t>(P->out_total, 1) * csz);
+  return al256(std::max<int64_t>(P->spec_total, 1) * csz) + al256(std::max<int64_t>(P->out_total, 1) * csz) +
+         grad_slot_bytes(P);
+}
+
+double* grad_slots(const arkcos_plan_s* P, void* ws) {
+  const size_t csz = P->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
+  return reinterpret_cast<double*>(static_cast<char*>(ws) + al256(std::max<int64_t>(P->spec_total, 1) * csz) +
+                                   al256(std::max<int64_t>(P->out_total, 1) * csz));
 }
 
 }  // namespace arkcos

@@ -109,6 +109,58 @@ def time_form(plan, fn, x, y, steps, warmup):
     return wall, [t / max(calls, 1) for t in stage_ms]
 
 
+def bench_batch(n_maps: int, steps: int, dev):
+    """Batched form: n_maps HEALPix maps, nside drawn from {512, 1024, 2048}
+    (weights 0.5/0.3/0.2), each with its own Gaussian beam of FWHM U[4', 30']
+    truncated at 3 FWHM; N(0,1) white noise generated on the GPU from the
+    map's seed; forward and transpose, each one batched call."""
+    import torch
+
+    import workloads as W
+    from paper_1104_0672_amd import Batch, Plan
+
+    wl = W.batch256(n_maps)
+    log(f"bench: batch of {n_maps} maps, building plans")
+    t0 = time.perf_counter()
+    plans = [Plan.from_workload(w) for w in wl]
+    batch = Batch(plans)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = batch.info
+    npix = int(info.npix_total)
+    log(f"bench: batch plans {plan_s:.1f} s, {info.n_items} items, {info.units_per_band} units/band, "
+        f"grid {info.grid}, {npix / 1e9:.2f} Gpix, workspace {info.workspace_bytes / 2**30:.1f} GiB")
+    xs = []
+    for w in wl:
+        g = torch.Generator(device=dev)
+        g.manual_seed(w.seed)
+        xs.append(torch.randn(w.grid.npix, generator=g, device=dev, dtype=torch.float32))
+    ys = [torch.empty_like(x) for x in xs]
+    ws = batch.workspace()
+    out = {"n_maps": n_maps, "npix_total": npix, "plan_seconds": round(plan_s, 2),
+           "units_per_band": int(info.units_per_band), "grid": int(info.grid), "items": int(info.n_items)}
+    total_alg = 3 * 2 * 4 * npix
+    for name, adj in (("forward", False), ("adjoint", True)):
+        batch.convolve(xs, outs=ys, adjoint=adj, ws=ws)
+        torch.cuda.synchronize()
+        batch.start_timing(steps)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch.convolve(xs, outs=ys, adjoint=adj, ws=ws)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st, calls = batch.stage_times()
+        batch.start_timing(0)
+        ms = 1e3 * wall / steps
+        out[name] = {"pixels_per_s": npix * steps / wall, "ms": ms,
+                     "hbm_roofline_frac_24B_per_px": round(total_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "stages_ms": dict(zip(STAGES, [round(t / max(calls, 1), 3) for t in st]))}
+        log(f"bench: batch {name} {ms:.2f} ms, {npix * steps / wall:.3e} px/s")
+    del xs, ys, ws, batch, plans
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +168,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle budget (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--batch-maps", type=int, default=256, help="maps in the batched form (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the single-map path "
@@ -175,6 +229,8 @@ def main():
                             "hbm_roofline_frac_24B_per_px": round(total_alg / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                             "stages_ms": dict(zip(STAGES, [round(t, 4) for t in stage_a]))}
     forms["batched"] = None
+    if args.batch_maps > 0:
+        forms["batched"] = bench_batch(args.batch_maps, args.batch_steps, dev)
 
     cpu = None
     if args.cpu_seconds > 0:

@@ -166,17 +166,39 @@ arkcos_status_t arkcos_set_knots(arkcos_plan_t plan, const double* knot_values);
 
 /* ---- batched form: many maps of uneven size, each with its own plan ---- */
 
-/* Group n plans (same dtype) into one batch: a work queue of (map, output
- * ring, mode tile) items ordered heaviest first, with tile sizes chosen per
- * plan by the autotuner.  The plans must outlive the batch. */
+typedef struct {
+  int32_t n_maps;
+  int32_t units_per_band;   /* output rings (with mirrors) per work item, autotuned */
+  int32_t grid;             /* workgroups of the persistent accumulation launch, autotuned */
+  int32_t tuned;            /* 1: measured now, 2: read from the autotune cache */
+  int64_t n_items;          /* work items in the queue */
+  int64_t npix_total;
+  size_t workspace_bytes;
+} arkcos_batch_info_t;
+
+/* Group n plans (same dtype, same device) into one batch: one work queue of
+ * (map, band of output rings, mode tile) items over all maps, ordered
+ * heaviest first.  The band size and the persistent grid are chosen by an
+ * autotuner that times the accumulation on a representative subset of the
+ * maps (results cached in the file named by ARKCOS_AUTOTUNE_CACHE, if set).
+ * Blocks the host.  The plans must outlive the batch. */
 arkcos_status_t arkcos_batch_plan(int32_t n, const arkcos_plan_t* plans, arkcos_batch_t* out);
+arkcos_status_t arkcos_batch_get_info(arkcos_batch_t batch, arkcos_batch_info_t* info);
 arkcos_status_t arkcos_batch_workspace_size(arkcos_batch_t batch, size_t* bytes);
-/* Forward (adjoint = 0) or transpose (adjoint = 1) of every map.  x, y: host
- * arrays of n device pointers.  One persistent launch performs step (c) for
- * all maps; the call makes no host synchronisation and no allocation, so it
- * can be captured in a hipGraph. */
+/* Forward (adjoint = 0) or transpose (adjoint = 1) of every map i:
+ * y[i] = C_i x[i].  x, y: host arrays of n device pointers (maps as for
+ * arkcos_convolve; no x[i] may overlap any y[k]).  ws: arkcos_batch_workspace_size
+ * bytes, 256-byte aligned.  Ring transforms run batched over all rings of all
+ * maps; one persistent launch performs step (c) for every map.  When the set
+ * of map pointers differs from the previous call's, it is uploaded first
+ * (a small synchronous copy); with unchanged pointers the call only enqueues
+ * kernels, allocates nothing and can be captured in a hipGraph. */
 arkcos_status_t arkcos_batch_convolve(arkcos_batch_t batch, const void* const* x, void* const* y,
                                       int32_t adjoint, void* ws, hipStream_t stream);
+/* Stage timing of batch calls, as arkcos_plan_timing / arkcos_stage_times
+ * (stage 1 is the persistent accumulation launch). */
+arkcos_status_t arkcos_batch_timing(arkcos_batch_t batch, int32_t max_calls);
+arkcos_status_t arkcos_batch_stage_times(arkcos_batch_t batch, double* ms, int64_t* calls);
 arkcos_status_t arkcos_batch_destroy(arkcos_batch_t batch);
 
 /* ---- profiling aid ---- */

@@ -50,11 +50,17 @@ class PlanInfo(ctypes.Structure):
                 ("plan_bytes", ctypes.c_size_t)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_maps", ctypes.c_int32), ("units_per_band", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("tuned", ctypes.c_int32), ("n_items", ctypes.c_int64), ("npix_total", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
 EXPORTED = ["arkcos_default_options", "arkcos_plan", "arkcos_plan_destroy", "arkcos_plan_get_info",
             "arkcos_workspace_size", "arkcos_convolve", "arkcos_convolve_adjoint", "arkcos_kernel_grad",
-            "arkcos_set_knots", "arkcos_batch_plan", "arkcos_batch_workspace_size",
-            "arkcos_batch_convolve", "arkcos_batch_destroy", "arkcos_plan_timing", "arkcos_stage_times",
-            "arkcos_status_string", "arkcos_last_error"]
+            "arkcos_set_knots", "arkcos_batch_plan", "arkcos_batch_get_info", "arkcos_batch_workspace_size",
+            "arkcos_batch_convolve", "arkcos_batch_timing", "arkcos_batch_stage_times", "arkcos_batch_destroy",
+            "arkcos_plan_timing", "arkcos_stage_times", "arkcos_status_string", "arkcos_last_error"]
 
 _lib = None
 
@@ -84,6 +90,9 @@ def load_library(path: str = LIB_PATH):
     lib.arkcos_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.arkcos_batch_convolve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, vp]
     lib.arkcos_batch_destroy.argtypes = [vp]
+    lib.arkcos_batch_get_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    lib.arkcos_batch_timing.argtypes = [vp, i32]
+    lib.arkcos_batch_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.arkcos_plan_timing.argtypes = [vp, i32]
     lib.arkcos_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.arkcos_status_string.argtypes = [st]
@@ -246,3 +255,65 @@ def pixel_bytes(plan: Plan) -> int:
 
 def fwhm_to_sigma(fwhm: float) -> float:
     return fwhm / math.sqrt(8.0 * math.log(2.0))
+
+
+class Batch:
+    """Many plans (same dtype) convolved together: batched ring transforms and
+    one persistent accumulation launch over a shared work queue."""
+
+    def __init__(self, plans: Sequence[Plan]):
+        lib = load_library()
+        self._lib = lib
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        self.handle = ctypes.c_void_p()
+        _check(lib.arkcos_batch_plan(len(self.plans), arr, ctypes.byref(self.handle)), "arkcos_batch_plan")
+        info = BatchInfo()
+        _check(lib.arkcos_batch_get_info(self.handle, ctypes.byref(info)), "arkcos_batch_get_info")
+        self.info = info
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                self._lib.arkcos_batch_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.info.workspace_bytes)
+
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            dev = self.plans[0].device
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        return self._ws
+
+    def convolve(self, xs: Sequence[torch.Tensor], outs: Optional[Sequence[torch.Tensor]] = None,
+                 adjoint: bool = False, ws=None, stream=None):
+        if len(xs) != len(self.plans):
+            raise ArkcosError("one input map per plan")
+        xs = [p._map(x, f"x[{i}]") for i, (p, x) in enumerate(zip(self.plans, xs))]
+        ys = [torch.empty_like(x) for x in xs] if outs is None else \
+            [p._map(y, f"out[{i}]") for i, (p, y) in enumerate(zip(self.plans, outs))]
+        wst = self.workspace() if ws is None else ws
+        addr = (wst.data_ptr() + 255) // 256 * 256
+        if addr + self.workspace_bytes > wst.data_ptr() + wst.numel():
+            raise ArkcosError("workspace too small")
+        xa = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        ya = (ctypes.c_void_p * len(ys))(*[y.data_ptr() for y in ys])
+        _check(self._lib.arkcos_batch_convolve(self.handle, xa, ya, 1 if adjoint else 0, ctypes.c_void_p(addr),
+                                               _stream_ptr(stream)), "arkcos_batch_convolve")
+        return ys
+
+    def start_timing(self, max_calls: int):
+        _check(self._lib.arkcos_batch_timing(self.handle, int(max_calls)), "arkcos_batch_timing")
+
+    def stage_times(self):
+        ms = (ctypes.c_double * 4)()
+        calls = ctypes.c_int64()
+        _check(self._lib.arkcos_batch_stage_times(self.handle, ms, ctypes.byref(calls)), "arkcos_batch_stage_times")
+        return list(ms), int(calls.value)

@@ -109,30 +109,31 @@ __device__ __forceinline__ R pair_k(int kind, int p, int ncoef, int nyq, int ban
   return k;
 }
 
+template <typename R> struct AccLds { static constexpr int kRings = 48; };
+template <> struct AccLds<double> { static constexpr int kRings = 24; };
+
 // One work item: a band of up to kBandUnits consecutive units and kAccTile
 // modes.  The block first stages A~_j(m) (and the mirror ring's spectrum) of
 // every input ring in the band's window into LDS, one coalesced row per ring;
 // then wavefront w accumulates unit u0 + w over its pairs, lane = mode, with
 // all pair data wave-uniform.
-template <typename R> struct AccLds { static constexpr int kRings = 48; };
-template <> struct AccLds<double> { static constexpr int kRings = 24; };
-
+// One work item (band of units, kAccTile modes) with the block's waves; the
+// band table is the caller's (a plan's own bands, or a batch's).  Every wave
+// of the block must call it; it synchronises the block.
 template <typename R>
-__global__ void __launch_bounds__(kAccThreads) accumulate_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec,
-                                                                 cx_t<R>* __restrict__ bout) {
+__device__ __forceinline__ void accumulate_item(const AccArgs<R>& a, const BandDev& bd, int m0,
+                                                const cx_t<R>* __restrict__ spec, cx_t<R>* __restrict__ bout,
+                                                cx_t<R>* sa) {
   using C = cx_t<R>;
   constexpr int CH = AccLds<R>::kRings;  // input rings staged at a time
-  extern __shared__ __align__(16) unsigned char smem[];
-  C* sa = reinterpret_cast<C*>(smem);  // [2 * CH][kAccTile]: ring, mirror ring
-  const WorkItem it = a.items[blockIdx.x];
-  const BandDev bd = a.bands[it.unit];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int m = it.m0 + lane;
+  const int nwaves = blockDim.x >> 6;
+  const int m = m0 + lane;
   const bool active = w < bd.nu;
   UnitDev u{};
   if (active) u = a.units[bd.u0 + w];
-  const bool busy = active && it.m0 <= u.band;
+  const bool busy = active && m0 <= u.band;
   const bool mirror = u.im >= 0;
   const int L = a.L, pl = a.p * a.L;
   ModeAngles<R> ang;
@@ -152,7 +153,7 @@ __global__ void __launch_bounds__(kAccThreads) accumulate_kernel(AccArgs<R> a, c
   const int win = bd.jhi - bd.jlo + 1;
   for (int c0 = 0; c0 < win; c0 += CH) {
     const int c1 = min(win, c0 + CH);
-    for (int r = w; r < 2 * (c1 - c0); r += kBandUnits) {
+    for (int r = w; r < 2 * (c1 - c0); r += nwaves) {
       int j = bd.jlo + c0 + (r >> 1);
       if (r & 1) j = a.nrings - 1 - j;
       C v = cmake<C>(R(0), R(0));
@@ -176,7 +177,7 @@ __global__ void __launch_bounds__(kAccThreads) accumulate_kernel(AccArgs<R> a, c
         const int j = __builtin_amdgcn_readlane(vj, t);
         if (j >= bd.jlo + c1) break;
         const int band = __builtin_amdgcn_readlane(vband, t);
-        if (it.m0 > band) continue;
+        if (m0 > band) continue;
         const int kind = __builtin_amdgcn_readlane(vkind, t);
         const int pp = __builtin_amdgcn_readlane(vp, t);
         const int nc = __builtin_amdgcn_readlane(vnc, t);
@@ -200,6 +201,87 @@ __global__ void __launch_bounds__(kAccThreads) accumulate_kernel(AccArgs<R> a, c
     bout[a.out_off[u.i] + m] = acc0;
     if (mirror) bout[a.out_off[u.im] + m] = acc1;
   }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kAccThreads) accumulate_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec,
+                                                                 cx_t<R>* __restrict__ bout) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const WorkItem it = a.items[blockIdx.x];
+  accumulate_item<R>(a, a.bands[it.unit], it.m0, spec, bout, reinterpret_cast<cx_t<R>*>(smem));
+}
+
+// Batched form: one persistent launch drains a queue of (map, band, first
+// mode) items shared by many plans; every block exits once the queue counter
+// passes the item count.
+template <typename R>
+__global__ void __launch_bounds__(kAccThreads) accumulate_batch_kernel(
+    const AccArgs<R>* __restrict__ maps, const int64_t* __restrict__ spec_base,
+    const int64_t* __restrict__ out_base, const BatchItem* __restrict__ items, int32_t n_items,
+    int32_t* __restrict__ counter, const cx_t<R>* __restrict__ spec, cx_t<R>* __restrict__ bout) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int cur;
+  for (;;) {
+    __syncthreads();  // the previous item is done with `cur` and the LDS tiles
+    if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = cur;
+    if (it >= n_items) break;
+    const BatchItem bi = items[it];
+    const AccArgs<R> a = maps[bi.map];
+    accumulate_item<R>(a, a.bands[bi.band], bi.m0, spec + spec_base[bi.map], bout + out_base[bi.map],
+                       reinterpret_cast<cx_t<R>*>(smem));
+  }
+}
+
+__global__ void reset_counter_kernel(int32_t* counter) {
+  if (threadIdx.x == 0) counter[0] = 0;
+}
+
+size_t acc_args_size() { return sizeof(AccArgs<float>); }
+
+void fill_acc_args(arkcos_plan_s* P, const BandDev* bands, void* out) {
+  if (P->dtype == ARKCOS_F32) {
+    AccArgs<float> a{P->d_units, P->d_pairs, P->d_items, bands, P->rt.spec_off, P->rt.spec_len,
+                     P->rt.out_off, (const float*)P->d_coef, (const float*)P->d_table,
+                     (int32_t)P->nrings, (int32_t)P->L, P->oversample};
+    *reinterpret_cast<AccArgs<float>*>(out) = a;
+  } else {
+    AccArgs<double> a{P->d_units, P->d_pairs, P->d_items, bands, P->rt.spec_off, P->rt.spec_len,
+                      P->rt.out_off, (const double*)P->d_coef, (const double*)P->d_table,
+                      (int32_t)P->nrings, (int32_t)P->L, P->oversample};
+    *reinterpret_cast<AccArgs<double>*>(out) = a;
+  }
+}
+
+size_t acc_lds_bytes(arkcos_dtype_t dt, int32_t max_window) {
+  if (dt == ARKCOS_F32)
+    return 2 * (size_t)std::min<int32_t>(max_window, AccLds<float>::kRings) * kAccTile * sizeof(float2);
+  return 2 * (size_t)std::min<int32_t>(max_window, AccLds<double>::kRings) * kAccTile * sizeof(double2);
+}
+
+hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const int64_t* spec_base,
+                                   const int64_t* out_base, const BatchItem* items, int32_t n_items,
+                                   int32_t* counter, const void* spec, void* bout, int32_t grid,
+                                   int32_t units_per_band, size_t lds, hipStream_t s) {
+  reset_counter_kernel<<<1, 64, 0, s>>>(counter);
+  const int threads = 64 * units_per_band;
+  if (dt == ARKCOS_F32) {
+    hipError_t e = hipFuncSetAttribute((const void*)accumulate_batch_kernel<float>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    accumulate_batch_kernel<float><<<grid, threads, lds, s>>>((const AccArgs<float>*)maps, spec_base, out_base,
+                                                              items, n_items, counter, (const float2*)spec,
+                                                              (float2*)bout);
+  } else {
+    hipError_t e = hipFuncSetAttribute((const void*)accumulate_batch_kernel<double>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    accumulate_batch_kernel<double><<<grid, threads, lds, s>>>((const AccArgs<double>*)maps, spec_base, out_base,
+                                                               items, n_items, counter, (const double2*)spec,
+                                                               (double2*)bout);
+  }
+  return hipGetLastError();
 }
 
 static size_t acc_lds(const arkcos_plan_s* P) {

@@ -72,7 +72,12 @@ struct WorkItem {
   int32_t m0;
 };
 
-// A band of kBandUnits consecutive units: the input rings they need.
+// One queue entry of the batched accumulation.
+struct BatchItem {
+  int32_t map, band, m0, pad;
+};
+
+// A band of up to kBandUnits consecutive units: the input rings they need.
 struct BandDev {
   int32_t u0, nu;       // units [u0, u0 + nu)
   int32_t jlo, jhi;     // input rings [jlo, jhi]
@@ -122,6 +127,7 @@ struct arkcos_plan_s {
   std::vector<int64_t> h_coef_off;       // recurrence-coefficient offset per pair
   std::vector<int32_t> h_ncoef_window;   // kernel samples inside each pair's window
   std::vector<arkcos::FftClass> fft_classes;
+  std::vector<int32_t> h_ring_lds;       // LDS bytes of each ring's transform
   std::vector<arkcos::WorkItem> h_items;
   std::vector<int32_t> h_spec_len, h_out_len;
   std::vector<int64_t> h_spec_off, h_out_off;
@@ -172,6 +178,24 @@ hipError_t launch_table_list(arkcos_plan_s* P, const int32_t* d_list, const int6
                              int32_t count, hipStream_t s);
 hipError_t configure_fft_kernels(arkcos_plan_s* P);
 hipError_t configure_accumulate(arkcos_plan_s* P);
+// batched form
+size_t acc_args_size();
+void fill_acc_args(arkcos_plan_s* P, const BandDev* bands, void* out);
+size_t acc_lds_bytes(arkcos_dtype_t dt, int32_t max_window);
+hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const int64_t* spec_base,
+                                   const int64_t* out_base, const BatchItem* items, int32_t n_items,
+                                   int32_t* counter, const void* spec, void* bout, int32_t grid,
+                                   int32_t units_per_band, size_t lds, hipStream_t s);
+size_t ring_args_size();
+void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out);
+hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, const void* entries, int32_t count,
+                             int32_t lds, const void* maps, void* ws, const int64_t* base, hipStream_t s);
+size_t pole_map_size();
+void fill_pole_map(arkcos_plan_s* P, void* out);
+hipError_t launch_pole_batch(arkcos_dtype_t dt, const void* maps, const int2* entries, int32_t count, int32_t adjoint,
+                             const void* xs, const void* ys, hipStream_t s);
+void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<BandDev>& bands,
+                 int32_t* max_window);
 int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count);
 void workspace_split(const arkcos_plan_s* P, void* ws, void** spec, void** bout);
 double* grad_slots(const arkcos_plan_s* P, void* ws);

@@ -1,18 +1,548 @@
-// Batched form (placeholder until the persistent work-queue kernel lands).
+// Batched form: many maps of uneven size, each with its own plan (its own
+// geometry and kernel profile), convolved by one pass of batched ring
+// transforms, one persistent accumulation launch over a shared work queue,
+// and one pass of batched inverse transforms.
+//
+// The queue holds (map, band of output rings, 64-mode tile) items of every
+// map, ordered by decreasing estimated cost so the persistent workgroups end
+// together.  The band size (output rings per item) and the number of
+// persistent workgroups are chosen by timing the accumulation on a subset of
+// the maps (one to four maps of each ring count).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "arkcos_internal.h"
 
+using namespace arkcos;
+
+namespace {
+
+struct ClassDev {
+  int2* entries = nullptr;
+  int32_t count = 0;
+  int32_t lds = 0;
+};
+
+}  // namespace
+
+struct arkcos_batch_s {
+  int device = 0;
+  arkcos_dtype_t dtype = ARKCOS_F32;
+  int32_t n = 0;
+  std::vector<arkcos_plan_s*> plans;
+  int32_t units_per_band = kBandUnits, grid = 0, tuned = 0;
+  size_t acc_lds = 0;
+  int64_t spec_total = 0, out_total = 0, npix_total = 0;
+  std::vector<int64_t> h_spec_base, h_out_base;
+  // device
+  int64_t* d_spec_base = nullptr;
+  int64_t* d_out_base = nullptr;
+  void* d_acc_args = nullptr;            // AccArgs per map
+  arkcos::BatchItem* d_items = nullptr;
+  int32_t n_items = 0;
+  void* d_rargs[4] = {nullptr, nullptr, nullptr, nullptr};  // R2C fwd, R2C adj, C2R fwd, C2R adj
+  std::vector<ClassDev> classes;
+  void* d_pole_maps = nullptr;
+  int2* d_pole_fwd = nullptr;
+  int2* d_pole_adj = nullptr;
+  int32_t n_pole_fwd = 0, n_pole_adj = 0;
+  void** d_xs = nullptr;
+  void** d_ys = nullptr;
+  std::vector<const void*> h_xs, h_ys;  // last uploaded map pointers
+  std::vector<void*> allocations;
+  std::vector<hipEvent_t> timing_events;
+  int32_t timing_slots = 0, timing_used = 0;
+};
+
+namespace {
+
+#define BCHK(expr)                                                                          \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return fail(_e == hipErrorOutOfMemory ? ARKCOS_ERR_OUT_OF_MEMORY : ARKCOS_ERR_DEVICE, \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));                       \
+  } while (0)
+
+template <typename T> hipError_t balloc(arkcos_batch_s* B, T** p, size_t count) {
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  B->allocations.push_back(v);
+  *p = static_cast<T*>(v);
+  return hipSuccess;
+}
+
+template <typename T> hipError_t bupload(arkcos_batch_s* B, T** p, const std::vector<T>& v) {
+  hipError_t e = balloc(B, p, v.size());
+  if (e != hipSuccess || v.empty()) return e;
+  return hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Queue of one batch configuration: per-map bands on the device, the AccArgs
+// pointing at them, and the items sorted by decreasing estimated cost.
+struct Queue {
+  std::vector<BandDev*> d_bands;
+  std::vector<char> acc_args;
+  std::vector<BatchItem> items;
+  int32_t max_window = 0;
+};
+
+hipError_t build_queue(arkcos_batch_s* B, const std::vector<int32_t>& maps, int32_t upb, Queue& Q,
+                       std::vector<void*>& owned) {
+  const size_t asz = acc_args_size();
+  Q.acc_args.assign(asz * maps.size(), 0);
+  std::vector<std::pair<double, BatchItem>> costed;
+  for (size_t mi = 0; mi < maps.size(); ++mi) {
+    arkcos_plan_s* P = B->plans[maps[mi]];
+    std::vector<BandDev> bands;
+    int32_t mw = 0;
+    build_bands(P, upb, bands, &mw);
+    Q.max_window = std::max(Q.max_window, mw);
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, std::max<size_t>(bands.size(), 1) * sizeof(BandDev));
+    if (e != hipSuccess) return e;
+    owned.push_back(d);
+    e = hipMemcpy(d, bands.data(), bands.size() * sizeof(BandDev), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    Q.d_bands.push_back((BandDev*)d);
+    fill_acc_args(P, (const BandDev*)d, Q.acc_args.data() + asz * mi);
+    for (int32_t b = 0; b < (int32_t)bands.size(); ++b) {
+      const BandDev& bd = bands[b];
+      for (int32_t m0 = 0; m0 <= bd.band; m0 += kAccTile) {
+        double cost = 0.0;
+        for (int32_t u = bd.u0; u < bd.u0 + bd.nu; ++u) {
+          const UnitDev& U = P->h_units[u];
+          for (int32_t q = U.pbeg; q < U.pend; ++q) {
+            const PairDev& pr = P->h_pairs[q];
+            if (pr.band < m0) continue;
+            cost += pr.kind == KG_TABLE ? 3.0 : (double)((pr.ncoef + 3) / 4 * 4) + 4.0;
+          }
+        }
+        costed.push_back({cost, BatchItem{(int32_t)mi, b, m0, 0}});
+      }
+    }
+  }
+  std::stable_sort(costed.begin(), costed.end(),
+                   [](const std::pair<double, BatchItem>& a, const std::pair<double, BatchItem>& b) {
+                     return a.first > b.first;
+                   });
+  Q.items.clear();
+  for (auto& c : costed) Q.items.push_back(c.second);
+  return hipSuccess;
+}
+
+std::string tune_key(const arkcos_batch_s* B) {
+  std::ostringstream k;
+  k << "dt" << (int)B->dtype << "_n" << B->n;
+  uint64_t h = 1469598103934665603ull;
+  for (auto* P : B->plans) {
+    const int64_t v[3] = {P->npix, P->pair_modes, P->coef_total};
+    for (int64_t x : v) {
+      h ^= (uint64_t)x;
+      h *= 1099511628211ull;
+    }
+  }
+  k << "_" << std::hex << h;
+  return k.str();
+}
+
+bool read_cache(const std::string& key, int32_t* upb, int32_t* bpc) {
+  const char* path = getenv("ARKCOS_AUTOTUNE_CACHE");
+  if (!path || !*path) return false;
+  std::ifstream f(path);
+  std::string k;
+  int32_t a, b;
+  while (f >> k >> a >> b)
+    if (k == key) {
+      *upb = a;
+      *bpc = b;
+      return true;
+    }
+  return false;
+}
+
+void write_cache(const std::string& key, int32_t upb, int32_t bpc) {
+  const char* path = getenv("ARKCOS_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << upb << " " << bpc << "\n";
+}
+
+// Times the accumulation of one queue on the subset's workspace (zero
+// spectra); returns milliseconds per launch.
+hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64_t>& sb,
+                      const std::vector<int64_t>& ob, void* spec, void* bout, int32_t* counter, int32_t upb,
+                      int32_t grid, float* ms) {
+  void *dargs = nullptr, *ditems = nullptr, *dsb = nullptr, *dob = nullptr;
+  hipError_t e = hipMalloc(&dargs, Q.acc_args.size());
+  if (e == hipSuccess) e = hipMalloc(&ditems, std::max<size_t>(Q.items.size(), 1) * sizeof(BatchItem));
+  if (e == hipSuccess) e = hipMalloc(&dsb, sb.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&dob, ob.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemcpy(dargs, Q.acc_args.data(), Q.acc_args.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ditems, Q.items.data(), Q.items.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dsb, sb.data(), sb.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dob, ob.data(), ob.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const size_t lds = acc_lds_bytes(B->dtype, Q.max_window);
+  const int reps = 3;
+  for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+    if (r == 1) e = hipEventRecord(e0, nullptr);
+    if (e == hipSuccess)
+      e = launch_accumulate_batch(B->dtype, dargs, (const int64_t*)dsb, (const int64_t*)dob, (const BatchItem*)ditems,
+                                  (int32_t)Q.items.size(), counter, spec, bout, grid, upb, lds, nullptr);
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  *ms = t / reps;
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(dargs);
+  hipFree(ditems);
+  hipFree(dsb);
+  hipFree(dob);
+  return e;
+}
+
+arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out) {
+  // subset: up to four maps per ring count
+  std::map<int64_t, int> seen;
+  std::vector<int32_t> sub;
+  for (int32_t i = 0; i < B->n; ++i)
+    if (seen[B->plans[i]->nrings]++ < 4) sub.push_back(i);
+  std::vector<int64_t> sb, ob;
+  int64_t st = 0, ot = 0;
+  for (int32_t i : sub) {
+    sb.push_back(st);
+    ob.push_back(ot);
+    st += B->plans[i]->spec_total;
+    ot += B->plans[i]->out_total;
+  }
+  const size_t csz = B->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
+  void *spec = nullptr, *bout = nullptr, *ctr = nullptr;
+  BCHK(hipMalloc(&spec, std::max<int64_t>(st, 1) * csz));
+  struct F { void* a; ~F() { hipFree(a); } } f1{spec};
+  BCHK(hipMalloc(&bout, std::max<int64_t>(ot, 1) * csz));
+  F f2{bout};
+  BCHK(hipMalloc(&ctr, 256));
+  F f3{ctr};
+  BCHK(hipMemset(spec, 0, std::max<int64_t>(st, 1) * csz));
+  int cus = 0;
+  BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
+  float best = 1e30f;
+  int32_t bu = kBandUnits, bb = 2;
+  for (int32_t upb : {4, 8}) {
+    Queue Q;
+    std::vector<void*> owned;
+    hipError_t e = build_queue(B, sub, upb, Q, owned);
+    for (int32_t bpc : {1, 2, 4}) {
+      float ms = 0.f;
+      if (e == hipSuccess) e = time_queue(B, Q, sb, ob, spec, bout, (int32_t*)ctr, upb, cus * bpc, &ms);
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        bu = upb;
+        bb = bpc;
+      }
+    }
+    for (void* p : owned) hipFree(p);
+    if (e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  }
+  *upb_out = bu;
+  *bpc_out = bb;
+  return ARKCOS_OK;
+}
+
+arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_t* out) {
+  if (n < 1 || !plans || !out) return fail(ARKCOS_ERR_INVALID_VALUE, "need n >= 1 plans and an output handle");
+  int dev = -1;
+  BCHK(hipGetDevice(&dev));
+  for (int32_t i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(ARKCOS_ERR_INVALID_VALUE, "null plan in batch");
+    if (plans[i]->device != dev) return fail(ARKCOS_ERR_INVALID_VALUE, "plans live on another device");
+    if (plans[i]->dtype != plans[0]->dtype) return fail(ARKCOS_ERR_INVALID_VALUE, "plans of mixed dtype");
+  }
+  auto* B = new arkcos_batch_s();
+  struct Owner {
+    arkcos_batch_s* b;
+    ~Owner() {
+      if (b) {
+        for (void* a : b->allocations) hipFree(a);
+        delete b;
+      }
+    }
+  } owner{B};
+  B->device = dev;
+  B->n = n;
+  B->dtype = plans[0]->dtype;
+  B->plans.assign(plans, plans + n);
+  for (auto* P : B->plans) {
+    B->h_spec_base.push_back(B->spec_total);
+    B->h_out_base.push_back(B->out_total);
+    B->spec_total += P->spec_total;
+    B->out_total += P->out_total;
+    B->npix_total += P->npix;
+  }
+  BCHK(bupload(B, &B->d_spec_base, B->h_spec_base));
+  BCHK(bupload(B, &B->d_out_base, B->h_out_base));
+
+  // ring-transform arguments (forward/transpose, both layouts) and classes
+  const size_t rsz = ring_args_size();
+  for (int v = 0; v < 4; ++v) {
+    std::vector<char> h(rsz * n);
+    for (int32_t i = 0; i < n; ++i) {
+      arkcos_plan_s* P = B->plans[i];
+      const bool fix = P->geom.kind == 1 && P->opts.fix_pole_pixels;
+      const bool outl = v >= 2, adj = (v & 1) != 0;
+      fill_ring_args(P, outl, adj ? 1 : 0, (!outl && adj && fix) ? 1 : 0, h.data() + rsz * i);
+    }
+    void* d = nullptr;
+    BCHK(hipMalloc(&d, h.size()));
+    B->allocations.push_back(d);
+    BCHK(hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice));
+    B->d_rargs[v] = d;
+  }
+  {
+    std::map<int32_t, std::vector<int2>> cls;
+    for (int32_t i = 0; i < n; ++i) {
+      arkcos_plan_s* P = B->plans[i];
+      for (int64_t k = 0; k < P->nrings; ++k) {
+        int32_t b = 4096;
+        while (b < P->h_ring_lds[k]) b <<= 1;
+        cls[b].push_back(make_int2(i, (int)k));
+      }
+    }
+    for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
+      ClassDev c;
+      c.count = (int32_t)it->second.size();
+      int32_t mx = 0;
+      for (const int2& e : it->second) mx = std::max(mx, B->plans[e.x]->h_ring_lds[e.y]);
+      c.lds = mx;
+      BCHK(bupload(B, &c.entries, it->second));
+      B->classes.push_back(c);
+    }
+  }
+  // pole rows
+  {
+    const size_t psz = pole_map_size();
+    std::vector<char> h(psz * n);
+    std::vector<int2> fwd, adj;
+    for (int32_t i = 0; i < n; ++i) {
+      arkcos_plan_s* P = B->plans[i];
+      fill_pole_map(P, h.data() + psz * i);
+      if (P->geom.kind == 1 && P->opts.fix_pole_pixels && P->n_pole_rings > 0) {
+        for (int b = 0; b < 8; ++b) fwd.push_back(make_int2(i, b));
+        for (int k = 0; k < P->n_pole_rings; ++k) adj.push_back(make_int2(i, k));
+      }
+    }
+    void* d = nullptr;
+    BCHK(hipMalloc(&d, h.size()));
+    B->allocations.push_back(d);
+    BCHK(hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice));
+    B->d_pole_maps = d;
+    BCHK(bupload(B, &B->d_pole_fwd, fwd));
+    BCHK(bupload(B, &B->d_pole_adj, adj));
+    B->n_pole_fwd = (int32_t)fwd.size();
+    B->n_pole_adj = (int32_t)adj.size();
+  }
+  BCHK(balloc(B, &B->d_xs, n));
+  BCHK(balloc(B, &B->d_ys, n));
+
+  // band size and grid: cached, else measured
+  int32_t upb = kBandUnits, bpc = 2;
+  const std::string key = tune_key(B);
+  if (read_cache(key, &upb, &bpc)) {
+    B->tuned = 2;
+  } else {
+    arkcos_status_t st = autotune(B, &upb, &bpc);
+    if (st != ARKCOS_OK) return st;
+    write_cache(key, upb, bpc);
+    B->tuned = 1;
+  }
+  int cus = 0;
+  BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  B->units_per_band = upb;
+  B->grid = cus * bpc;
+  std::vector<int32_t> all(n);
+  for (int32_t i = 0; i < n; ++i) all[i] = i;
+  Queue Q;
+  std::vector<void*> owned;
+  hipError_t e = build_queue(B, all, upb, Q, owned);
+  for (void* p : owned) B->allocations.push_back(p);
+  BCHK(e);
+  B->acc_lds = acc_lds_bytes(B->dtype, Q.max_window);
+  void* d = nullptr;
+  BCHK(hipMalloc(&d, Q.acc_args.size()));
+  B->allocations.push_back(d);
+  BCHK(hipMemcpy(d, Q.acc_args.data(), Q.acc_args.size(), hipMemcpyHostToDevice));
+  B->d_acc_args = d;
+  BCHK(bupload(B, &B->d_items, Q.items));
+  B->n_items = (int32_t)Q.items.size();
+  BCHK(hipDeviceSynchronize());
+  *out = B;
+  owner.b = nullptr;
+  return ARKCOS_OK;
+}
+
+size_t batch_ws_bytes(const arkcos_batch_s* B) {
+  const size_t csz = B->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  return 256 + al(std::max<int64_t>(B->spec_total, 1) * csz) + al(std::max<int64_t>(B->out_total, 1) * csz);
+}
+
+#define BLAUNCH(expr)                                                                              \
+  do {                                                                                             \
+    hipError_t _e = (expr);                                                                        \
+    if (_e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+arkcos_status_t run_batch(arkcos_batch_s* B, const void* const* x, void* const* y, int32_t adjoint, void* ws,
+                          hipStream_t s) {
+  if (!x || !y || !ws) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(ARKCOS_ERR_INVALID_VALUE, "workspace must be 256-byte aligned");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != B->device)
+    return fail(ARKCOS_ERR_INVALID_VALUE, "batch was created on another device");
+  const size_t esz = B->dtype == ARKCOS_F32 ? sizeof(float) : sizeof(double);
+  for (int32_t i = 0; i < B->n; ++i) {
+    if (!x[i] || !y[i]) return fail(ARKCOS_ERR_INVALID_VALUE, "null map pointer");
+    const size_t bi = (size_t)B->plans[i]->npix * esz;
+    for (int32_t k = 0; k < B->n; ++k) {
+      const size_t bk = (size_t)B->plans[k]->npix * esz;
+      auto px = reinterpret_cast<uintptr_t>(x[i]), py = reinterpret_cast<uintptr_t>(y[k]);
+      if (px < py + bk && py < px + bi) return fail(ARKCOS_ERR_INVALID_VALUE, "an input map overlaps an output map");
+    }
+  }
+  // map pointers: upload when they changed since the last call
+  if (B->h_xs.size() != (size_t)B->n || !std::equal(x, x + B->n, B->h_xs.begin()) ||
+      !std::equal(y, y + B->n, B->h_ys.begin())) {
+    B->h_xs.assign(x, x + B->n);
+    B->h_ys.assign(y, y + B->n);
+    BLAUNCH(hipStreamSynchronize(s));
+    BLAUNCH(hipMemcpy(B->d_xs, x, B->n * sizeof(void*), hipMemcpyHostToDevice));
+    BLAUNCH(hipMemcpy(B->d_ys, y, B->n * sizeof(void*), hipMemcpyHostToDevice));
+  }
+  const size_t csz = B->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  char* base = static_cast<char*>(ws);
+  int32_t* counter = reinterpret_cast<int32_t*>(base);
+  void* spec = base + 256;
+  void* bout = base + 256 + al(std::max<int64_t>(B->spec_total, 1) * csz);
+  hipEvent_t* ev = nullptr;
+  if (B->timing_used < B->timing_slots) ev = &B->timing_events[5 * B->timing_used++];
+  if (ev) BLAUNCH(hipEventRecord(ev[0], s));
+  for (const ClassDev& c : B->classes)
+    BLAUNCH(launch_ring_batch(B->dtype, false, B->d_rargs[adjoint ? 1 : 0], c.entries, c.count, c.lds, B->d_xs, spec,
+                              B->d_spec_base, s));
+  if (ev) BLAUNCH(hipEventRecord(ev[1], s));
+  BLAUNCH(launch_accumulate_batch(B->dtype, B->d_acc_args, B->d_spec_base, B->d_out_base, B->d_items, B->n_items,
+                                  counter, spec, bout, B->grid, B->units_per_band, B->acc_lds, s));
+  if (ev) BLAUNCH(hipEventRecord(ev[2], s));
+  for (const ClassDev& c : B->classes)
+    BLAUNCH(launch_ring_batch(B->dtype, true, B->d_rargs[adjoint ? 3 : 2], c.entries, c.count, c.lds, B->d_ys, bout,
+                              B->d_out_base, s));
+  if (ev) BLAUNCH(hipEventRecord(ev[3], s));
+  if (!adjoint)
+    BLAUNCH(launch_pole_batch(B->dtype, B->d_pole_maps, B->d_pole_fwd, B->n_pole_fwd, 0, B->d_xs, B->d_ys, s));
+  else
+    BLAUNCH(launch_pole_batch(B->dtype, B->d_pole_maps, B->d_pole_adj, B->n_pole_adj, 1, B->d_xs, B->d_ys, s));
+  if (ev) BLAUNCH(hipEventRecord(ev[4], s));
+  return ARKCOS_OK;
+}
+
+}  // namespace
+
 extern "C" {
-arkcos_status_t arkcos_batch_plan(int32_t, const arkcos_plan_t*, arkcos_batch_t*) {
-  return arkcos::fail(ARKCOS_ERR_NOT_SUPPORTED, "batched form not built yet");
+
+arkcos_status_t arkcos_batch_plan(int32_t n, const arkcos_plan_t* plans, arkcos_batch_t* out) {
+  try {
+    return build_batch(n, plans, out);
+  } catch (const std::bad_alloc&) {
+    return fail(ARKCOS_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(ARKCOS_ERR_INTERNAL, "unexpected exception in batch creation");
+  }
 }
-arkcos_status_t arkcos_batch_workspace_size(arkcos_batch_t, size_t*) {
-  return arkcos::fail(ARKCOS_ERR_NOT_SUPPORTED, "batched form not built yet");
+
+arkcos_status_t arkcos_batch_get_info(arkcos_batch_t B, arkcos_batch_info_t* info) {
+  if (!B || !info) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
+  std::memset(info, 0, sizeof(*info));
+  info->n_maps = B->n;
+  info->units_per_band = B->units_per_band;
+  info->grid = B->grid;
+  info->tuned = B->tuned;
+  info->n_items = B->n_items;
+  info->npix_total = B->npix_total;
+  info->workspace_bytes = batch_ws_bytes(B);
+  return ARKCOS_OK;
 }
-arkcos_status_t arkcos_batch_convolve(arkcos_batch_t, const void* const*, void* const*, int32_t, void*,
-                                      hipStream_t) {
-  return arkcos::fail(ARKCOS_ERR_NOT_SUPPORTED, "batched form not built yet");
+
+arkcos_status_t arkcos_batch_workspace_size(arkcos_batch_t B, size_t* bytes) {
+  if (!B || !bytes) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
+  *bytes = batch_ws_bytes(B);
+  return ARKCOS_OK;
 }
-arkcos_status_t arkcos_batch_destroy(arkcos_batch_t) {
-  return arkcos::fail(ARKCOS_ERR_NOT_SUPPORTED, "batched form not built yet");
+
+arkcos_status_t arkcos_batch_convolve(arkcos_batch_t B, const void* const* x, void* const* y, int32_t adjoint,
+                                      void* ws, hipStream_t stream) {
+  if (!B) return fail(ARKCOS_ERR_INVALID_VALUE, "null batch");
+  if (adjoint != 0 && adjoint != 1) return fail(ARKCOS_ERR_INVALID_VALUE, "adjoint must be 0 or 1");
+  try {
+    return run_batch(B, x, y, adjoint, ws, stream);
+  } catch (...) {
+    return fail(ARKCOS_ERR_INTERNAL, "unexpected exception in batch call");
+  }
 }
+
+arkcos_status_t arkcos_batch_timing(arkcos_batch_t B, int32_t max_calls) {
+  if (!B || max_calls < 0) return fail(ARKCOS_ERR_INVALID_VALUE, "bad argument");
+  for (hipEvent_t e : B->timing_events) (void)hipEventDestroy(e);
+  B->timing_events.clear();
+  B->timing_slots = B->timing_used = 0;
+  if (max_calls == 0) return ARKCOS_OK;
+  B->timing_events.resize(5 * (size_t)max_calls);
+  for (auto& e : B->timing_events)
+    if (hipEventCreate(&e) != hipSuccess) return fail(ARKCOS_ERR_DEVICE, "hipEventCreate failed");
+  B->timing_slots = max_calls;
+  return ARKCOS_OK;
 }
+
+arkcos_status_t arkcos_batch_stage_times(arkcos_batch_t B, double* ms, int64_t* calls) {
+  if (!B || !ms || !calls) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
+  for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+  for (int32_t c = 0; c < B->timing_used; ++c) {
+    hipEvent_t* ev = &B->timing_events[5 * c];
+    if (hipEventSynchronize(ev[4]) != hipSuccess) return fail(ARKCOS_ERR_DEVICE, "hipEventSynchronize failed");
+    for (int k = 0; k < 4; ++k) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess)
+        return fail(ARKCOS_ERR_DEVICE, "hipEventElapsedTime failed");
+      ms[k] += t;
+    }
+  }
+  *calls = B->timing_used;
+  B->timing_used = 0;
+  return ARKCOS_OK;
+}
+
+arkcos_status_t arkcos_batch_destroy(arkcos_batch_t B) {
+  if (!B) return fail(ARKCOS_ERR_INVALID_VALUE, "null batch");
+  for (void* a : B->allocations) (void)hipFree(a);
+  for (hipEvent_t e : B->timing_events) (void)hipEventDestroy(e);
+  delete B;
+  return ARKCOS_OK;
+}
+
+}  // extern "C"

@@ -50,14 +50,12 @@ template <typename R> __device__ __forceinline__ cx_t<R> unshift(int m, int den)
   return cconj(expipi<R>(t, den));
 }
 
+// Step (a) for ring j of one plan; x and spec are that plan's map and
+// spectrum buffer.  buf: dynamic LDS, nyq: one shared slot.
 template <typename R>
-__global__ void __launch_bounds__(kBlock) r2c_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
-                                                     const R* __restrict__ x, cx_t<R>* __restrict__ spec) {
+__device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, const R* __restrict__ x,
+                                         cx_t<R>* __restrict__ spec, cx_t<R>* buf, cx_t<R>& nyq) {
   using C = cx_t<R>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  C* buf = reinterpret_cast<C*>(smem);
-  __shared__ C nyq;  // A(N/2), kept outside the padded buffer
-  const int j = list[blockIdx.x];
   const int N = a.n[j], half = N / 2, kind = a.fft_kind[j];
   const int den = a.phase_den[j], len = a.len[j];
   C* out = spec + a.off[j];
@@ -123,14 +121,11 @@ __global__ void __launch_bounds__(kBlock) r2c_kernel(RingArgs<R> a, const int32_
   }
 }
 
+// Step (d) for ring i of one plan.
 template <typename R>
-__global__ void __launch_bounds__(kBlock) c2r_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
-                                                     const cx_t<R>* __restrict__ bin, R* __restrict__ y) {
+__device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, const cx_t<R>* __restrict__ bin,
+                                         R* __restrict__ y, cx_t<R>* buf, cx_t<R>& nyq) {
   using C = cx_t<R>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  C* buf = reinterpret_cast<C*>(smem);
-  __shared__ C nyq;  // G(N/2)
-  const int i = list[blockIdx.x];
   const int N = a.n[i], half = N / 2, kind = a.fft_kind[i];
   const int den = a.phase_den[i], len = a.len[i];
   const C* b = bin + a.off[i];
@@ -192,7 +187,50 @@ __global__ void __launch_bounds__(kBlock) c2r_kernel(RingArgs<R> a, const int32_
   }
 }
 
-template <typename R> static RingArgs<R> ring_args(arkcos_plan_s* P, bool out_side, int adjoint,
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) r2c_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
+                                                     const R* __restrict__ x, cx_t<R>* __restrict__ spec) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ cx_t<R> nyq;  // A(N/2), kept outside the padded buffer
+  r2c_ring<R>(a, list[blockIdx.x], x, spec, reinterpret_cast<cx_t<R>*>(smem), nyq);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) c2r_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
+                                                     const cx_t<R>* __restrict__ bin, R* __restrict__ y) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ cx_t<R> nyq;  // G(N/2)
+  c2r_ring<R>(a, list[blockIdx.x], bin, y, reinterpret_cast<cx_t<R>*>(smem), nyq);
+}
+
+// Batched forms: entry (map, ring); per-map arguments, maps and workspace
+// offsets in device arrays.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) r2c_batch_kernel(const RingArgs<R>* __restrict__ args,
+                                                           const int2* __restrict__ entries,
+                                                           const R* const* __restrict__ xs,
+                                                           cx_t<R>* __restrict__ ws, const int64_t* __restrict__ base) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ cx_t<R> nyq;
+  const int2 e = entries[blockIdx.x];
+  const RingArgs<R> a = args[e.x];
+  r2c_ring<R>(a, e.y, xs[e.x], ws + base[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) c2r_batch_kernel(const RingArgs<R>* __restrict__ args,
+                                                           const int2* __restrict__ entries,
+                                                           const cx_t<R>* __restrict__ ws,
+                                                           const int64_t* __restrict__ base, R* const* __restrict__ ys) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ cx_t<R> nyq;
+  const int2 e = entries[blockIdx.x];
+  const RingArgs<R> a = args[e.x];
+  c2r_ring<R>(a, e.y, ws + base[e.x], ys[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
+}
+
+template <typename R> RingArgs<R> ring_args(arkcos_plan_s* P, bool out_side, int adjoint,
                                                    int zero_pole) {
   RingArgs<R> a{};
   a.n = P->rt.n;
@@ -237,6 +275,49 @@ hipError_t launch_r2c(arkcos_plan_s* P, const void* x, void* spec, int32_t adjoi
     else
       r2c_kernel<double><<<(unsigned)c.count, kBlock, c.lds, s>>>(
           ring_args<double>(P, false, adjoint, zero_pole_rings), c.d_rings, (const double*)x, (double2*)spec);
+  }
+  return hipGetLastError();
+}
+
+size_t ring_args_size() { return sizeof(RingArgs<float>); }
+
+void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out) {
+  if (P->dtype == ARKCOS_F32)
+    *reinterpret_cast<RingArgs<float>*>(out) = ring_args<float>(P, out_side, adjoint, zero_pole);
+  else
+    *reinterpret_cast<RingArgs<double>*>(out) = ring_args<double>(P, out_side, adjoint, zero_pole);
+}
+
+// Batched ring transforms: forward (R2C of maps[m] into ws + base[m]) or
+// inverse (C2R of ws + base[m] into maps[m]).
+hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, const void* entries, int32_t count,
+                             int32_t lds, const void* maps, void* ws, const int64_t* base, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipError_t e;
+  if (dt == ARKCOS_F32) {
+    if (!inverse) {
+      e = hipFuncSetAttribute((const void*)r2c_batch_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      if (e != hipSuccess) return e;
+      r2c_batch_kernel<float><<<count, kBlock, lds, s>>>((const RingArgs<float>*)args, (const int2*)entries,
+                                                         (const float* const*)maps, (float2*)ws, base);
+    } else {
+      e = hipFuncSetAttribute((const void*)c2r_batch_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      if (e != hipSuccess) return e;
+      c2r_batch_kernel<float><<<count, kBlock, lds, s>>>((const RingArgs<float>*)args, (const int2*)entries,
+                                                         (const float2*)ws, base, (float* const*)maps);
+    }
+  } else {
+    if (!inverse) {
+      e = hipFuncSetAttribute((const void*)r2c_batch_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      if (e != hipSuccess) return e;
+      r2c_batch_kernel<double><<<count, kBlock, lds, s>>>((const RingArgs<double>*)args, (const int2*)entries,
+                                                          (const double* const*)maps, (double2*)ws, base);
+    } else {
+      e = hipFuncSetAttribute((const void*)c2r_batch_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      if (e != hipSuccess) return e;
+      c2r_batch_kernel<double><<<count, kBlock, lds, s>>>((const RingArgs<double>*)args, (const int2*)entries,
+                                                          (const double2*)ws, base, (double* const*)maps);
+    }
   }
   return hipGetLastError();
 }

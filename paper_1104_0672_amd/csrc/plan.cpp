@@ -436,6 +436,8 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   }
   P->twiddle_n = (int32_t)twn;
   P->max_fft_lds = (int32_t)((lds + 15) / 16 * 16);
+  P->h_ring_lds.resize(nr);
+  for (int64_t k = 0; k < nr; ++k) P->h_ring_lds[k] = (int32_t)((ring_lds[k] + 15) / 16 * 16);
   {
     // launch classes by LDS size (power-of-two buckets from 4 KiB); a ring
     // and its mirror stay adjacent so they share cached filters
@@ -584,26 +586,9 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   HIPCHK(upload(P, &P->d_units, P->h_units));
 
   // bands of consecutive units, and work items: (band, first mode) tiles
-  for (int64_t u0 = 0; u0 < nunits; u0 += kBandUnits) {
-    BandDev B{};
-    B.u0 = (int32_t)u0;
-    B.nu = (int32_t)std::min<int64_t>(kBandUnits, nunits - u0);
-    B.jlo = (int32_t)nr;
-    B.jhi = -1;
-    B.band = -1;
-    for (int64_t u = u0; u < u0 + B.nu; ++u) {
-      const UnitDev& U = P->h_units[u];
-      if (U.pend > U.pbeg) {
-        B.jlo = std::min(B.jlo, P->h_pairs[U.pbeg].j);
-        B.jhi = std::max(B.jhi, P->h_pairs[U.pend - 1].j);
-      }
-      B.band = std::max(B.band, U.band);
-    }
-    const int32_t b = (int32_t)P->h_bands.size();
-    P->h_bands.push_back(B);
-    if (B.jhi >= B.jlo) P->max_window = std::max(P->max_window, B.jhi - B.jlo + 1);
-    for (int32_t m0 = 0; m0 <= B.band; m0 += kAccTile) P->h_items.push_back(WorkItem{b, m0});
-  }
+  build_bands(P, kBandUnits, P->h_bands, &P->max_window);
+  for (int32_t b = 0; b < (int32_t)P->h_bands.size(); ++b)
+    for (int32_t m0 = 0; m0 <= P->h_bands[b].band; m0 += kAccTile) P->h_items.push_back(WorkItem{b, m0});
   HIPCHK(upload(P, &P->d_items, P->h_items));
   HIPCHK(upload(P, &P->d_bands, P->h_bands));
   HIPCHK(configure_accumulate(P));
@@ -622,6 +607,33 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   *out = P;
   owner.p = nullptr;
   return ARKCOS_OK;
+}
+
+// Groups consecutive units into bands of units_per_band, with the input-ring
+// window of each band and the largest window.
+void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<BandDev>& bands,
+                 int32_t* max_window) {
+  bands.clear();
+  *max_window = 0;
+  const int64_t nunits = P->n_units, nr = P->nrings;
+  for (int64_t u0 = 0; u0 < nunits; u0 += units_per_band) {
+    BandDev B{};
+    B.u0 = (int32_t)u0;
+    B.nu = (int32_t)std::min<int64_t>(units_per_band, nunits - u0);
+    B.jlo = (int32_t)nr;
+    B.jhi = -1;
+    B.band = -1;
+    for (int64_t u = u0; u < u0 + B.nu; ++u) {
+      const UnitDev& U = P->h_units[u];
+      if (U.pend > U.pbeg) {
+        B.jlo = std::min(B.jlo, P->h_pairs[U.pbeg].j);
+        B.jhi = std::max(B.jhi, P->h_pairs[U.pend - 1].j);
+      }
+      B.band = std::max(B.band, U.band);
+    }
+    if (B.jhi >= B.jlo) *max_window = std::max(*max_window, B.jhi - B.jlo + 1);
+    bands.push_back(B);
+  }
 }
 
 int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count) {

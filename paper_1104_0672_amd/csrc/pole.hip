@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kBlock) pole_adjoint_kernel(PoleArgs P, const 
   }
 }
 
-hipError_t launch_pole_fix(arkcos_plan_s* P, const void* x, void* y, int32_t adjoint, hipStream_t s) {
+PoleArgs make_pole_args(arkcos_plan_s* P) {
   PoleArgs a{};
   a.n = P->rt.n;
   a.start = P->rt.start;
@@ -114,6 +114,11 @@ hipError_t launch_pole_fix(arkcos_plan_s* P, const void* x, void* y, int32_t adj
   a.h = a.nk > 1 ? P->theta_max / (a.nk - 1) : 0.0;
   a.knots = P->d_knots;
   a.mom = P->d_spline_mom;
+  return a;
+}
+
+hipError_t launch_pole_fix(arkcos_plan_s* P, const void* x, void* y, int32_t adjoint, hipStream_t s) {
+  PoleArgs a = make_pole_args(P);
   int32_t count = 0;
   int32_t* list = pole_ring_list(P, &count);
   if (count == 0) return hipSuccess;
@@ -128,6 +133,81 @@ hipError_t launch_pole_fix(arkcos_plan_s* P, const void* x, void* y, int32_t adj
     else
       pole_adjoint_kernel<double><<<count, kBlock, 0, s>>>(a, list, (const double*)x, (double*)y);
   }
+  return hipGetLastError();
+}
+
+// Batched pole rows: entry (map, k) with k < 8 (forward: pole pixel) or k an
+// index into the map's pole-ring list (transpose).
+struct PoleMap {
+  PoleArgs a;
+  const int32_t* rings;
+  int32_t nlist;
+  int32_t pad;
+};
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) pole_batch_kernel(const PoleMap* __restrict__ maps,
+                                                            const int2* __restrict__ entries, int32_t adjoint,
+                                                            const R* const* __restrict__ xs, R* const* __restrict__ ys) {
+  const int2 e = entries[blockIdx.x];
+  const PoleMap pm = maps[e.x];
+  const PoleArgs& P = pm.a;
+  const R* x = xs[e.x];
+  R* y = ys[e.x];
+  if (!adjoint) {
+    const int b = e.y;
+    const int ip = b < 4 ? 0 : P.nrings - 1, kp = b & 3;
+    double acc = 0.0;
+    for (int t = 0; t < pm.nlist; ++t) {
+      const int j = pm.rings[t];
+      if (fabs(P.theta[j] - P.theta[ip]) > P.radius) continue;
+      const int nj = P.n[j];
+      const double wj = P.w[j];
+      for (int k = threadIdx.x; k < nj; k += blockDim.x)
+        acc += pole_profile(P, pixel_distance(P, ip, kp, j, k)) * wj * (double)x[P.start[j] + k];
+    }
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) y[P.start[ip] + kp] = (R)red[0];
+  } else {
+    const int j = pm.rings[e.y];
+    const int nj = P.n[j];
+    for (int k = threadIdx.x; k < nj; k += blockDim.x) {
+      double acc = 0.0;
+      for (int b = 0; b < 8; ++b) {
+        const int ip = b < 4 ? 0 : P.nrings - 1, kp = b & 3;
+        if (fabs(P.theta[j] - P.theta[ip]) > P.radius) continue;
+        acc += pole_profile(P, pixel_distance(P, ip, kp, j, k)) * (double)x[P.start[ip] + kp];
+      }
+      const int64_t q = P.start[j] + k;
+      y[q] = (R)((double)y[q] + P.w[j] * acc);
+    }
+  }
+}
+
+size_t pole_map_size() { return sizeof(PoleMap); }
+
+void fill_pole_map(arkcos_plan_s* P, void* out) {
+  PoleMap pm{};
+  pm.a = make_pole_args(P);
+  pm.rings = pole_ring_list(P, &pm.nlist);
+  *reinterpret_cast<PoleMap*>(out) = pm;
+}
+
+hipError_t launch_pole_batch(arkcos_dtype_t dt, const void* maps, const int2* entries, int32_t count, int32_t adjoint,
+                             const void* xs, const void* ys, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (dt == ARKCOS_F32)
+    pole_batch_kernel<float><<<count, kBlock, 0, s>>>((const PoleMap*)maps, entries, adjoint,
+                                                      (const float* const*)xs, (float* const*)ys);
+  else
+    pole_batch_kernel<double><<<count, kBlock, 0, s>>>((const PoleMap*)maps, entries, adjoint,
+                                                       (const double* const*)xs, (double* const*)ys);
   return hipGetLastError();
 }
 

@@ -17,8 +17,10 @@ Sect. 4.3):
     FFT ``K_ij(m)``.  Equatorial ring pairs with equal ring lengths do not use
     the phase shift: the kernel is sampled at the true pixel offsets, i.e. at
     longitudes shifted by ``phi0_i - phi0_j`` (Sect. 4.3), which makes them
-    exact.  In absolute longitude this is the grid ``2 pi (d + s/2) / L`` with
-    s = 1 when the two rings are offset by an odd multiple of pi / L.
+    exact; the same holds for any two rings of equal length N (a polar ring
+    with itself or its mirror).  In absolute longitude this is the grid
+    ``2 pi (d + s/2) / N`` with s = 1 when the rings are offset by an odd
+    multiple of pi / N.
 (c) ``B_i(m) = sum_j K_ij(m) A~_j(m)`` (the theta-direction summation).
 (d) reverse phase shift, fold the super-Nyquist modes onto the ring's own
     modes (Sect. 4.3), inverse real FFT of length N_i.
@@ -27,13 +29,14 @@ Sect. 4.3):
 
 Readings taken where the paper is silent (each listed in the design doc):
 
-* Oversampling ``p``: pairs that involve a polar ring sample the kernel on
-  ``p L`` points (``p = 1`` is the paper's grid) and keep modes up to
-  ``p L / 2``; equatorial equal-length pairs always use ``p = 1`` (exact).
+* Kernel grids: pairs of equal-length rings sample the kernel at their true
+  pixel offsets on a grid of their own length (exact); other pairs sample it
+  on ``p L`` longitudes (``p = 1`` is the paper's grid) and keep modes up to
+  ``p L / 2``.
 * The Nyquist mode of each pair's grid is split symmetrically (half weight),
   so every pair contributes the real trigonometric interpolant of its kernel
   row, evaluated at the true pixel offsets.
-* The 1 / (p L) normalisation of the kernel FFT is applied per pair.
+* The 1 / (grid length) normalisation of the kernel FFT is applied per pair.
 """
 from __future__ import annotations
 
@@ -57,8 +60,14 @@ def _grid_length(grid):
 
 
 def pair_plan(grid, radius, oversample):
-    """For each output ring i: list of (j, p, s) -- input ring, oversampling
-    factor and half-shift flag of the kernel grid."""
+    """For each output ring i: list of (j, G, s) -- input ring, number of
+    kernel-grid longitudes and half-shift flag of the grid.
+
+    Rings of equal length (a HEALPix ring with itself or its mirror, any two
+    equatorial rings, any ECP pair) are sampled at their true pixel offsets on
+    a grid of their own length (the equatorial modification of Sect. 4.3,
+    applied to every equal-length pair); the rest use oversample * L
+    longitudes (L = 4 nside: the paper's kernel grid when oversample = 1)."""
     th, ph0, w, n, st = rings(grid)
     L = _grid_length(grid)
     out = []
@@ -67,11 +76,12 @@ def pair_plan(grid, radius, oversample):
         for j in range(len(th)):
             if abs(th[j] - th[i]) > radius + 1e-6:
                 continue
-            e = (ph0[i] - ph0[j]) * L / np.pi
-            aligned = n[i] == L and n[j] == L and abs(e - round(e)) < 1e-9
-            p = 1 if aligned else int(oversample)
-            s = int(round(e) * p) % 2 if aligned else 0
-            lst.append((j, p, s))
+            e = (ph0[i] - ph0[j]) * n[i] / np.pi
+            aligned = n[i] == n[j] and abs(e - round(e)) < 1e-9
+            if aligned:
+                lst.append((j, int(n[i]), int(round(e)) % 2))
+            else:
+                lst.append((j, int(oversample) * L, 0))
         out.append(lst)
     return out
 
@@ -85,11 +95,11 @@ def _extended_spectrum(a, phi0, nring, mmax):
     return base * np.exp(-1j * m * phi0)
 
 
-def _kernel_row_spectrum(profile, radius, th_i, th_j, w_j, p, s, L, values=None):
-    """K_ij(m), m = 0..pL/2, with the 1/(pL) normalisation and the half-weight
-    Nyquist mode.  ``values`` optionally replaces K by another radial function
-    (used for the knot basis)."""
-    nn = p * L
+def _kernel_row_spectrum(profile, radius, th_i, th_j, w_j, nn, s, values=None):
+    """K_ij(m), m = 0..nn/2, for the kernel sampled on nn longitudes, with the
+    1/nn normalisation and the half-weight Nyquist mode.  ``values``
+    optionally replaces K by another radial function (used for the knot
+    basis)."""
     nu = 2.0 * np.pi * (np.arange(nn) + 0.5 * s) / nn
     t = _ring_distance(th_i, th_j, nu)
     g = w_j * (kernel(profile, radius, t) if values is None else values(t))
@@ -123,10 +133,10 @@ def _hybrid_core(grid, profile, radius, x, oversample, values=None):
     plan = pair_plan(grid, radius, oversample)
     y = np.empty(grid.npix)
     for i, pairs in enumerate(plan):
-        mmax = max(p * L // 2 for (_, p, _) in pairs)
+        mmax = max(nn // 2 for (_, nn, _) in pairs)
         b = np.zeros(mmax + 1, complex)
-        for (j, p, s) in pairs:
-            kf = _kernel_row_spectrum(profile, radius, th[i], th[j], w[j], p, s, L, values)  # (b)
+        for (j, nn, s) in pairs:
+            kf = _kernel_row_spectrum(profile, radius, th[i], th[j], w[j], nn, s, values)  # (b)
             b[: kf.size] += kf * _extended_spectrum(spec[j], ph0[j], n[j], kf.size - 1)     # (c)
         y[st[i]: st[i] + n[i]] = _fold_inverse(b, ph0[i], n[i])                             # (d)
     return y

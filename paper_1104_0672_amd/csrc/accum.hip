@@ -25,6 +25,7 @@ template <typename R> struct AccArgs {
   const int64_t* out_off;
   const R* coef;
   const R* table;
+  const int32_t* ring_n;
   int32_t nrings;
   int32_t L;
   int32_t p;
@@ -36,18 +37,21 @@ template <typename R> __device__ __forceinline__ cx_t<R> cispi_frac(int num, int
   return expipi<R>(t, den);
 }
 
-// Per-thread constants of the three kernel grids at mode m.
+// Per-thread constants of the two kernel grids a unit's pairs use at mode m:
+// the output ring's own length N_i (equal-length pairs) and the fine grid
+// p L (all other pairs).
 template <typename R> struct ModeAngles {
-  R c1, cp;        // cos(2 pi m / L), cos(2 pi m / (p L))
-  R s1h, c1h;      // sin, cos of pi m / L       (half angle of the p = 1 grid; shifted grid)
-  R sph, cph;      // sin, cos of pi m / (p L)   (half angle of the p > 1 grid)
+  int32_t fine;    // p L
+  R c1, cp;        // cos(2 pi m / N_i), cos(2 pi m / (p L))
+  R s1h, c1h;      // sin, cos of pi m / N_i      (half angle; shifted grid)
+  R sph, cph;      // sin, cos of pi m / (p L)    (half angle)
 };
 
 // K(m) of one pair from its kernel samples (step b).  Sample rows are stored
 // zero-padded to whole chunks of 8; the recurrence runs over chunks of 4
 // (one uniform load each), i.e. over ceil(n / 4) * 4 samples.
 template <typename R>
-__device__ __forceinline__ R pair_k(int kind, int p, int ncoef, int nyq, int band, int64_t off,
+__device__ __forceinline__ R pair_k(int kind, int grid, int ncoef, int nyq, int band, int64_t off,
                                     const R* __restrict__ coef, const R* __restrict__ table,
                                     const ModeAngles<R>& A, int m) {
   R k;
@@ -57,7 +61,8 @@ __device__ __forceinline__ R pair_k(int kind, int p, int ncoef, int nyq, int ban
   } else if (kind == KG_REINSCH) {
     // centred grid, Reinsch's form: stable for longer rows near x = 0 and pi
     const R* cf = coef + off;
-    const R sh = p == 1 ? A.s1h : A.sph, ch = p == 1 ? A.c1h : A.cph;
+    const bool own = grid != A.fine;
+    const R sh = own ? A.s1h : A.sph, ch = own ? A.c1h : A.cph;
     R b = R(0), dd = R(0);
     if (ch * ch >= R(0.5)) {
       const R lam = R(-4) * sh * sh;
@@ -89,7 +94,7 @@ __device__ __forceinline__ R pair_k(int kind, int p, int ncoef, int nyq, int ban
     if (m == nyq) k *= R(0.5);
   } else {
     const R* cf = coef + off;
-    const R cx = (kind == KG_SHIFTED || p == 1) ? A.c1 : A.cp;
+    const R cx = grid != A.fine ? A.c1 : A.cp;
     const R al = R(2) * cx;
     R b1 = R(0), b2 = R(0);
     for (int c = n4 - 4; c >= 0; c -= 4) {
@@ -135,11 +140,13 @@ __device__ __forceinline__ void accumulate_item(const AccArgs<R>& a, const BandD
   if (active) u = a.units[bd.u0 + w];
   const bool busy = active && m0 <= u.band;
   const bool mirror = u.im >= 0;
-  const int L = a.L, pl = a.p * a.L;
+  const int pl = a.p * a.L;
+  const int Ni = active ? a.ring_n[u.i] : a.L;
   ModeAngles<R> ang;
   {
-    const C e1 = cispi_frac<R>(2 * m, L), ep = cispi_frac<R>(2 * m, pl);
-    const C h1 = cispi_frac<R>(m, L), hp = cispi_frac<R>(m, pl);
+    const C e1 = cispi_frac<R>(2 * m, Ni), ep = cispi_frac<R>(2 * m, pl);
+    const C h1 = cispi_frac<R>(m, Ni), hp = cispi_frac<R>(m, pl);
+    ang.fine = pl;
     ang.c1 = e1.x; ang.cp = ep.x;
     ang.c1h = h1.x; ang.s1h = h1.y;
     ang.cph = hp.x; ang.sph = hp.y;
@@ -167,7 +174,7 @@ __device__ __forceinline__ void accumulate_item(const AccArgs<R>& a, const BandD
           base = qi;
           if (base + lane < npair) {
             const PairDev mine = a.pairs[u.pbeg + base + lane];
-            vj = mine.j; vband = mine.band; vkind = mine.kind; vp = mine.p;
+            vj = mine.j; vband = mine.band; vkind = mine.kind; vp = mine.grid;
             vnc = mine.ncoef; vnyq = mine.nyq;
             voff_lo = (int)(uint32_t)(uint64_t)mine.off;
             voff_hi = (int)(uint32_t)((uint64_t)mine.off >> 32);
@@ -243,12 +250,12 @@ size_t acc_args_size() { return sizeof(AccArgs<float>); }
 void fill_acc_args(arkcos_plan_s* P, const BandDev* bands, void* out) {
   if (P->dtype == ARKCOS_F32) {
     AccArgs<float> a{P->d_units, P->d_pairs, P->d_items, bands, P->rt.spec_off, P->rt.spec_len,
-                     P->rt.out_off, (const float*)P->d_coef, (const float*)P->d_table,
+                     P->rt.out_off, (const float*)P->d_coef, (const float*)P->d_table, P->rt.n,
                      (int32_t)P->nrings, (int32_t)P->L, P->oversample};
     *reinterpret_cast<AccArgs<float>*>(out) = a;
   } else {
     AccArgs<double> a{P->d_units, P->d_pairs, P->d_items, bands, P->rt.spec_off, P->rt.spec_len,
-                      P->rt.out_off, (const double*)P->d_coef, (const double*)P->d_table,
+                      P->rt.out_off, (const double*)P->d_coef, (const double*)P->d_table, P->rt.n,
                       (int32_t)P->nrings, (int32_t)P->L, P->oversample};
     *reinterpret_cast<AccArgs<double>*>(out) = a;
   }
@@ -304,13 +311,13 @@ hipError_t launch_accumulate(arkcos_plan_s* P, const void* spec, void* bout, hip
   if (P->h_items.empty()) return hipSuccess;
   if (P->dtype == ARKCOS_F32) {
     AccArgs<float> a{P->d_units, P->d_pairs, P->d_items, P->d_bands, P->rt.spec_off, P->rt.spec_len,
-                     P->rt.out_off, (const float*)P->d_coef, (const float*)P->d_table,
+                     P->rt.out_off, (const float*)P->d_coef, (const float*)P->d_table, P->rt.n,
                      (int32_t)P->nrings, (int32_t)P->L, P->oversample};
     accumulate_kernel<float><<<(unsigned)P->h_items.size(), kAccThreads,
                                 acc_lds(P), s>>>(a, (const float2*)spec, (float2*)bout);
   } else {
     AccArgs<double> a{P->d_units, P->d_pairs, P->d_items, P->d_bands, P->rt.spec_off, P->rt.spec_len,
-                      P->rt.out_off, (const double*)P->d_coef, (const double*)P->d_table,
+                      P->rt.out_off, (const double*)P->d_coef, (const double*)P->d_table, P->rt.n,
                       (int32_t)P->nrings, (int32_t)P->L, P->oversample};
     accumulate_kernel<double><<<(unsigned)P->h_items.size(), kAccThreads,
                                  acc_lds(P), s>>>(a, (const double2*)spec, (double2*)bout);

@@ -26,8 +26,8 @@ constexpr int kAccThreads = 64 * kBandUnits;  // one wavefront per unit
 enum FftKind : int32_t { FFT_DIRECT = 0, FFT_POW2 = 1, FFT_BLUESTEIN = 2 };
 
 // K_ij(m) source of one ring pair.
-//  KG_CENTRED  : nodes 2 pi d / (p L), recurrence on cos(m nu)
-//  KG_SHIFTED  : nodes 2 pi (d + 1/2) / L (equatorial pairs offset by pi/L)
+//  KG_CENTRED  : nodes 2 pi d / G, recurrence on cos(m nu)
+//  KG_SHIFTED  : nodes 2 pi (d + 1/2) / G (equal-length rings offset by pi/G)
 //  KG_TABLE    : precomputed K_ij(m), m <= band
 //  KG_REINSCH  : centred nodes, Reinsch's form of the recurrence (longer rows)
 enum PairKind : int32_t { KG_CENTRED = 0, KG_SHIFTED = 1, KG_TABLE = 2, KG_REINSCH = 3 };
@@ -55,7 +55,7 @@ struct PairDev {
   int32_t band;      // K_ij(m) = 0 for m > band
   int32_t nyq;       // p L / 2: this mode carries half weight
   int32_t ncoef;     // recurrence coefficients (KG_CENTRED / KG_SHIFTED)
-  int32_t p;         // oversampling of the kernel grid
+  int32_t grid;      // longitudes of the kernel grid (ring length, or oversample * L)
   int64_t off;       // coefficient offset (recurrence) or table offset
 };
 

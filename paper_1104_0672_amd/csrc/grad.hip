@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(kBlock) grad_pairs_kernel(GradArgs g, const cx
     if (pr.band < 0) continue;
     const int j = pr.j, jm = g.nrings - 1 - j;
     const int nc = g.ncoef_window[q], s = g.pair_shift[q];
-    const int64_t pl = (int64_t)pr.p * g.L;
+    const int64_t pl = (int64_t)pr.grid;
     const C* ai = aspec + g.spec_off[j];
     const C* ri = rspec + g.out_off[u.i];
     const C* am = aspec + g.spec_off[jm];

@@ -345,21 +345,24 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       if (fabs(dth) > rt) continue;
       PairDev pr{};
       pr.j = (int32_t)j;
-      const bool aligned = P->h_n[i] == L && P->h_n[j] == L &&
-                           (P->h_phase_den[i] == 0 || P->h_phase_den[i] == L) &&
-                           (P->h_phase_den[j] == 0 || P->h_phase_den[j] == L);
-      int32_t shift = 0, pp = p;
+      // rings of equal length (with offsets 0 or pi/N) are sampled at their
+      // true pixel offsets on a grid of their own length: exact
+      const bool aligned = P->h_n[i] == P->h_n[j] &&
+                           (P->h_phase_den[i] == 0 || P->h_phase_den[i] == P->h_n[i]) &&
+                           (P->h_phase_den[j] == 0 || P->h_phase_den[j] == P->h_n[j]);
+      int32_t shift = 0;
+      int64_t G = (int64_t)p * L;
       if (aligned) {
-        pp = 1;
+        G = P->h_n[i];
         shift = ((P->h_phase_den[i] != 0) != (P->h_phase_den[j] != 0)) ? 1 : 0;
       }
-      pr.p = pp;
-      pr.nyq = (int32_t)(pp * L / 2);
+      pr.grid = (int32_t)G;
+      pr.nyq = (int32_t)(G / 2);
       // kernel-sample window from hav(R) >= sin^2(dtheta/2) + sin_i sin_j sin^2(nu/2)
       const double sa = sin(0.5 * dth);
       const double den = P->h_sin[i] * P->h_sin[j];
       const double qv = den > 0 ? (hav_r - sa * sa) / den : 2.0;
-      const int64_t pl = pp * L;
+      const int64_t pl = G;
       const double hstep = 2.0 * M_PI / (double)pl;
       int64_t ncoef;
       if (qv >= 1.0) {

@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(kBlock) kernel_rows_kernel(
   const int q = blockIdx.x;
   const PairDev pr = pairs[q];
   const int i = pair_i[q], j = pr.j, s = pair_shift[q];
-  const int64_t pl = (int64_t)pr.p * L;
+  const int64_t pl = (int64_t)pr.grid;
   const double ti = theta[i], tj = theta[j], si = sint[i], sj = sint[j];
   double part = 0.0;
   for (int d = threadIdx.x; d < pr.ncoef; d += blockDim.x) {
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kBlock) band_kernel(
     const double* __restrict__ coef64, int64_t L, double thr, int32_t* __restrict__ band_out) {
   const int q = blockIdx.x;
   const PairDev pr = pairs[q];
-  const int64_t pl = (int64_t)pr.p * L;
+  const int64_t pl = (int64_t)pr.grid;
   int best = -1;
   for (int m = threadIdx.x; m <= pr.nyq; m += blockDim.x) {
     double k = k_of_m_fp64(coef64 + pr.off, pr.ncoef, m, pair_shift[q], pl, pr.nyq);
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(kBlock) table_kernel(
   const int t = blockIdx.x;
   const int q = list[t];
   const PairDev pr = pairs[q];
-  const int64_t pl = (int64_t)pr.p * L;
+  const int64_t pl = (int64_t)pr.grid;
   for (int m = threadIdx.x; m <= pr.band; m += blockDim.x)
     table[pr.off + m] = (R)k_of_m_fp64(coef64 + coef_off[t], pr.ncoef, m, pair_shift[q], pl, pr.nyq);
 }

@@ -74,6 +74,106 @@ def measured_traffic(stage: str):
     return ent.get("hbm_bytes_per_launch")
 
 
+def copy_calibration(mib: int, dev):
+    """A plain device-to-device copy of known size (mib MiB read, mib MiB
+    written), run before the workload so that a counter run can scale the
+    kernels' FETCH_SIZE / WRITE_SIZE by what the counters read for it."""
+    import torch
+    n = mib * 2**20 // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+
+
+def _counter_rows(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name: str) -> str:
+    name = name.split("(")[0].replace("void ", "")
+    return name.split("::")[-1].split("<")[0]
+
+
+def summarize_traffic(fetch_csv: str, write_csv: str, calib_mib: int, out_path: str, cmd: str):
+    """Per-stage HBM bytes per forward step from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by the ratio of
+    the known size of the copy-calibration dispatches to what the same counter
+    reads for them."""
+    import collections
+    calib_bytes = calib_mib * 2**20
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        per = collections.defaultdict(float)
+        steps = 0
+        cal = []
+        for r in _counter_rows(path):
+            if r["Counter_Name"] != counter:
+                continue
+            name = _short(r["Kernel_Name"])
+            kib = float(r["Counter_Value"])
+            if name == "__amd_rocclr_copyBuffer" and kib * 1024 > 0.5 * calib_bytes:
+                cal.append(kib * 1024)
+                continue
+            per[name] += kib * 1024
+            if name == "accumulate_kernel":
+                steps += 1
+        if not cal or not steps:
+            raise SystemExit(f"{path}: no calibration copy or no accumulate dispatch found")
+        factor = calib_bytes / (sum(cal) / len(cal))
+        res[counter] = (per, steps, factor, sum(cal) / len(cal))
+    kernels = {}
+    for stage, kname in KERNEL_NAMES.items():
+        fper, fsteps, ffac, _ = res["FETCH_SIZE"]
+        wper, wsteps, wfac, _ = res["WRITE_SIZE"]
+        fb = fper.get(kname, 0.0) / fsteps * ffac
+        wb = wper.get(kname, 0.0) / wsteps * wfac
+        kernels[kname] = {"stage": stage, "source_sha": kernel_source_hash(stage),
+                          "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
+                          "hbm_bytes_per_launch": round(fb + wb)}
+    out = {"workload": "healpix2048_5arcmin (forward step)", "command": cmd,
+           "calibration": {"copy_bytes": calib_bytes,
+                           "fetch_counter_bytes": res["FETCH_SIZE"][3], "fetch_factor": res["FETCH_SIZE"][2],
+                           "write_counter_bytes": res["WRITE_SIZE"][3], "write_factor": res["WRITE_SIZE"][2]},
+           "steps_counted": {"fetch": res["FETCH_SIZE"][1], "write": res["WRITE_SIZE"][1]},
+           "kernels": kernels}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out, indent=1))
+
+
+def summarize_kernels(trace_dir: str, cmd: str, title: str):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run: the stats
+    table plus per-launch-shape averages of the convolution kernels."""
+    import collections
+    stats = _counter_rows(os.path.join(trace_dir, "run_kernel_stats.csv"))
+    trace = _counter_rows(os.path.join(trace_dir, "run_kernel_trace.csv"))
+    lines = [f"# {title}", "", "Command (from the repository root, one MI355X):", "", "```", cmd, "```", "",
+             "All dispatches of the run (plan build, warmup and timed steps), from `run_kernel_stats.csv`:", "",
+             "| kernel | calls | total us | average us | % |", "|---|---:|---:|---:|---:|"]
+    for s in stats:
+        lines.append(f"| `{_short(s['Name'])}` | {s['Calls']} | {float(s['TotalDurationNs']) / 1e3:.1f} | "
+                     f"{float(s['AverageNs']) / 1e3:.1f} | {float(s['Percentage']):.1f} |")
+    agg = collections.defaultdict(list)
+    for r in trace:
+        n = _short(r["Kernel_Name"])
+        if n in KERNEL_NAMES.values() or "batch" in n or "grad" in n or "adjoint" in n:
+            key = (n, int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"])), int(r["Workgroup_Size_X"]),
+                   int(r["LDS_Block_Size"]))
+            agg[key].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    lines += ["", "Per launch shape, from `run_kernel_trace.csv`:", "",
+              "| kernel | workgroups | threads | LDS bytes | launches | average us |", "|---|---:|---:|---:|---:|---:|"]
+    for k, v in sorted(agg.items()):
+        lines.append(f"| `{k[0]}` | {k[1]} | {k[2]} | {k[3]} | {len(v)} | {sum(v) / len(v) / 1e3:.1f} |")
+    print("\n".join(lines))
+
+
 def cpu_baseline(w, x, budget_s: float):
     import numpy as np
 
@@ -170,7 +270,22 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batch-maps", type=int, default=256, help="maps in the batched form (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a device copy of this size first (for counter calibration)")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="offline: write the per-kernel HBM traffic summary from two counter runs")
+    ap.add_argument("--summarize-kernels", metavar="TRACE_DIR",
+                    help="offline: print a markdown summary of a kernel-trace run")
+    ap.add_argument("--summary-command", default="", help="command line recorded in a summary")
+    ap.add_argument("--summary-title", default="")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, args.copy_calibration_mib,
+                          os.path.join(ROOT, "profiles", "traffic_healpix2048_5arcmin.json"), args.summary_command)
+        return
+    if args.summarize_kernels:
+        summarize_kernels(args.summarize_kernels, args.summary_command, args.summary_title)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the single-map path "
               "shards by latitude band across GPUs, which this build does not run.", file=sys.stderr)
@@ -184,6 +299,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration_mib > 0:
+        log(f"bench: copy calibration, {args.copy_calibration_mib} MiB")
+        copy_calibration(args.copy_calibration_mib, dev)
     w = W.healpix2048()
     log(f"bench: building plan for {w.name}")
     t0 = time.perf_counter()

@@ -91,6 +91,7 @@ struct FftClass {
   int32_t* d_rings = nullptr;
   int32_t count = 0;
   int32_t lds = 0;
+  int32_t threads = 256;  // block size: 512 when an FFT is longer than 4096 points
 };
 
 }  // namespace arkcos
@@ -128,6 +129,7 @@ struct arkcos_plan_s {
   std::vector<int32_t> h_ncoef_window;   // kernel samples inside each pair's window
   std::vector<arkcos::FftClass> fft_classes;
   std::vector<int32_t> h_ring_lds;       // LDS bytes of each ring's transform
+  std::vector<int32_t> h_fft_len;        // its complex FFT length (0: plain DFT)
   std::vector<arkcos::WorkItem> h_items;
   std::vector<int32_t> h_spec_len, h_out_len;
   std::vector<int64_t> h_spec_off, h_out_off;
@@ -189,7 +191,9 @@ hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const in
 size_t ring_args_size();
 void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out);
 hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, const void* entries, int32_t count,
-                             int32_t lds, const void* maps, void* ws, const int64_t* base, hipStream_t s);
+                             int32_t lds, int32_t threads, const void* maps, void* ws, const int64_t* base,
+                             hipStream_t s);
+int fft_threads(arkcos_dtype_t dt, int32_t fft_len);
 size_t pole_map_size();
 void fill_pole_map(arkcos_plan_s* P, void* out);
 hipError_t launch_pole_batch(arkcos_dtype_t dt, const void* maps, const int2* entries, int32_t count, int32_t adjoint,

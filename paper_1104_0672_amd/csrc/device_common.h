@@ -179,16 +179,22 @@ template <typename C, int R> __device__ __forceinline__ void twiddle_powers(C w,
   }
 }
 
-template <typename R, bool INV, int RAD>
-__device__ __forceinline__ void stockham_pass(cx_t<R>* buf, int M, int Ns, const cx_t<R>* __restrict__ tw, int TN) {
+// The ring transforms run NT = 256 or 512 threads per block; a block handles
+// FFT lengths up to kFftCap<NT> = 16 NT, so every thread holds one radix-16
+// butterfly per pass and at most 16 points in any phase.
+template <int NT> constexpr int kFftCap = 16 * NT;
+
+// One Stockham pass of radix RAD over the M points in LDS (butterflies
+// j = threadIdx.x + b NT, b < MAXB).  w: the butterfly's twiddle base
+// (unused when Ns = 1).
+template <typename R, bool INV, int RAD, int MAXB, int NT>
+__device__ __forceinline__ void stockham_pass(cx_t<R>* buf, int M, int Ns, cx_t<R> w) {
   using C = cx_t<R>;
   const int Q = M / RAD;
-  const int tstep = TN / (Ns * RAD);
-  constexpr int MAXB = (FftLimits<R>::kMaxM / RAD + 255) / 256;
   C v[MAXB][RAD];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
-    const int j = threadIdx.x + b * 256;
+    const int j = threadIdx.x + b * NT;
     if (j < Q) {
 #pragma unroll
       for (int r = 0; r < RAD; ++r) v[b][r] = buf[lidx(j + r * Q)];
@@ -197,14 +203,12 @@ __device__ __forceinline__ void stockham_pass(cx_t<R>* buf, int M, int Ns, const
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
-    const int j = threadIdx.x + b * 256;
+    const int j = threadIdx.x + b * NT;
     if (j < Q) {
       const int k = j & (Ns - 1);
       if (Ns > 1) {
-        C w = tw[k * tstep];
-        if (INV) w = cconj(w);
         C p[RAD];
-        twiddle_powers<C, RAD>(w, p);
+        twiddle_powers<C, RAD>(INV ? cconj(w) : w, p);
 #pragma unroll
         for (int r = 1; r < RAD; ++r) v[b][r] = cmul(v[b][r], p[r]);
       }
@@ -217,53 +221,97 @@ __device__ __forceinline__ void stockham_pass(cx_t<R>* buf, int M, int Ns, const
   __syncthreads();
 }
 
-template <typename R, bool INV>
+// Power-of-two FFT of length M <= kFftCap<NT> in LDS: one radix-2, 4 or 8
+// pass for the leftover factor (its Ns is 1: no twiddles), then radix-16
+// passes.  The twiddles of the radix-16 passes are loaded from the table
+// before the first pass so their latency is paid once.
+template <typename R, bool INV, int NT>
 __device__ void lds_fft(cx_t<R>* buf, int M, const cx_t<R>* __restrict__ tw, int TN) {
-  int lg = 31 - __clz(M);
-  int Ns = 1;
-  const int rest = lg % 4;
-  if (rest == 1) { stockham_pass<R, INV, 2>(buf, M, Ns, tw, TN); Ns <<= 1; }
-  else if (rest == 2) { stockham_pass<R, INV, 4>(buf, M, Ns, tw, TN); Ns <<= 2; }
-  else if (rest == 3) { stockham_pass<R, INV, 8>(buf, M, Ns, tw, TN); Ns <<= 3; }
-  for (int t = 0; t < lg / 4; ++t) {
-    stockham_pass<R, INV, 16>(buf, M, Ns, tw, TN);
-    Ns <<= 4;
-  }
+  using C = cx_t<R>;
+  constexpr int CAP = kFftCap<NT>;
+  const int lg = 31 - __clz(M);
+  const int rest = lg & 3, n16 = lg >> 2;
+  const int j = threadIdx.x;
+  auto tw_at = [&](int t) {
+    const int Ns = (1 << rest) << (4 * t);
+    return (t < n16 && Ns > 1 && j < M / 16) ? tw[(j & (Ns - 1)) * (TN / (Ns * 16))] : cmake<C>(R(1), R(0));
+  };
+  const C w0 = tw_at(0), w1 = tw_at(1), w2 = tw_at(2);
+  if (rest == 1) stockham_pass<R, INV, 2, CAP / 2 / NT, NT>(buf, M, 1, w0);
+  else if (rest == 2) stockham_pass<R, INV, 4, CAP / 4 / NT, NT>(buf, M, 1, w0);
+  else if (rest == 3) stockham_pass<R, INV, 8, CAP / 8 / NT, NT>(buf, M, 1, w0);
+  if (n16 > 0) stockham_pass<R, INV, 16, 1, NT>(buf, M, 1 << rest, w0);
+  if (n16 > 1) stockham_pass<R, INV, 16, 1, NT>(buf, M, (1 << rest) << 4, w1);
+  if (n16 > 2) stockham_pass<R, INV, 16, 1, NT>(buf, M, (1 << rest) << 8, w2);
 }
 
-// Complex DFT of length n held in buf (padded layout) in place, by the ring's
-// method: power of two directly, otherwise Bluestein's chirp convolution of
-// length M (buf must hold lds_elems(M) elements; filt = FFT_M of the
-// conjugate chirp, followed by the chirp e^{-i pi l^2 / n} itself for l < n).
-// INV gives the unnormalised inverse DFT.  Synchronises the block on exit.
-template <typename R, bool INV>
-__device__ void ring_dft(cx_t<R>* buf, int n, int kind, int M, const cx_t<R>* __restrict__ filt,
-                         const cx_t<R>* __restrict__ tw, int TN) {
+// Bluestein's chirp convolution: the length-n DFT of buf[0..n) (padded
+// layout) through power-of-two FFTs of length M >= 2n - 1, M <= kFftCap<NT>,
+// in place.  filt: FFT_M of the conjugate chirp, followed by the chirp
+// e^{-i pi l^2 / n} for l < n.  INV gives the unnormalised inverse DFT.  The
+// block is synchronised on entry and on exit; the global loads of each phase
+// are issued together before their first use.
+template <typename R, bool INV, int NT>
+__device__ void bluestein(cx_t<R>* buf, int n, int M, const cx_t<R>* __restrict__ filt,
+                          const cx_t<R>* __restrict__ tw, int TN) {
   using C = cx_t<R>;
-  if (kind == 1) {
-    lds_fft<R, INV>(buf, n, tw, TN);
-    return;
-  }
-  const int tid = threadIdx.x, nth = blockDim.x;
-  for (int l = tid; l < M; l += nth) {
-    C v = cmake<C>(R(0), R(0));
-    if (l < n) {
-      v = buf[lidx(l)];
-      if (INV) v = cconj(v);
-      v = cmul(v, filt[M + l]);
+  constexpr int EPT = kFftCap<NT> / NT;
+  const int tid = threadIdx.x;
+  {
+    C c[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int l = tid + e * NT;
+      if (l < n) c[e] = filt[M + l];
     }
-    buf[lidx(l)] = v;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int l = tid + e * NT;
+      if (l < M) {
+        C v = cmake<C>(R(0), R(0));
+        if (l < n) {
+          v = buf[lidx(l)];
+          if (INV) v = cconj(v);
+          v = cmul(v, c[e]);
+        }
+        buf[lidx(l)] = v;
+      }
+    }
   }
   __syncthreads();
-  lds_fft<R, false>(buf, M, tw, TN);
-  for (int k = tid; k < M; k += nth) buf[lidx(k)] = cmul(buf[lidx(k)], filt[k]);
+  lds_fft<R, false, NT>(buf, M, tw, TN);
+  {
+    C f[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int k = tid + e * NT;
+      if (k < M) f[e] = filt[k];
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int k = tid + e * NT;
+      if (k < M) buf[lidx(k)] = cmul(buf[lidx(k)], f[e]);
+    }
+  }
   __syncthreads();
-  lds_fft<R, true>(buf, M, tw, TN);
-  const R inv = R(1) / R(M);
-  for (int k = tid; k < n; k += nth) {
-    C v = cscale(cmul(buf[lidx(k)], filt[M + k]), inv);
-    if (INV) v = cconj(v);
-    buf[lidx(k)] = v;
+  lds_fft<R, true, NT>(buf, M, tw, TN);
+  {
+    const R inv = R(1) / R(M);
+    C c[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int k = tid + e * NT;
+      if (k < n) c[e] = filt[M + k];
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int k = tid + e * NT;
+      if (k < n) {
+        C v = cscale(cmul(buf[lidx(k)], c[e]), inv);
+        if (INV) v = cconj(v);
+        buf[lidx(k)] = v;
+      }
+    }
   }
   __syncthreads();
 }

@@ -42,39 +42,58 @@ template <typename R> struct RingArgs {
   int32_t zero_pole_rings;
 };
 
-// exp(-i m phi0) for phi0 = pi / den (den = 0: no offset).
-template <typename R> __device__ __forceinline__ cx_t<R> unshift(int m, int den) {
-  using C = cx_t<R>;
-  if (den == 0) return cmake<C>(R(1), R(0));
-  int t = (int)((uint32_t)m % (2u * (uint32_t)den));
-  return cconj(expipi<R>(t, den));
+// Every ring offset in longitude has phi0 = pi / N (HEALPix polar rings and
+// every other equatorial ring), so the phase factors of one ring are powers
+// of w = exp(-i pi / N).  With w_r = w^r:
+//   A~(m + N) = s A~(m),  A~(N - r) = s conj(A~(r)),  s = -1 (offset), +1,
+// so a ring needs w_r only for r <= N/2, and the split of the half-length
+// complex FFT needs w_r^2 = exp(-2 pi i r / N).  Power-of-two rings read w_r
+// from the twiddle table (TN a multiple of 2N); the others compute it.
+template <typename R>
+__device__ __forceinline__ cx_t<R> half_twiddle(int r, int N, bool table, const cx_t<R>* __restrict__ tw, int TN) {
+  if (table) return tw[r * (TN / (2 * N))];
+  return cconj(expipi<R>(r, N));
 }
+
+// q = m / N, r = m mod N for 0 <= m < 2^20, 0 < N < 2^16 (the rounding
+// error of the float quotient is far below the 1/(2N) margin kept from the
+// integers).
+__device__ __forceinline__ void divmod_small(int m, int N, float invN, int& q, int& r) {
+  q = (int)(((float)m + 0.5f) * invN);
+  r = m - q * N;
+}
+
+// (r, n - r) pairs per thread per batch of loads
+template <typename R> struct PairBatch { static constexpr int value = sizeof(R) == 4 ? 4 : 2; };
 
 // Step (a) for ring j of one plan; x and spec are that plan's map and
 // spectrum buffer.  buf: dynamic LDS, nyq: one shared slot.
-template <typename R>
+template <typename R, int NT>
 __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, const R* __restrict__ x,
                                          cx_t<R>* __restrict__ spec, cx_t<R>* buf, cx_t<R>& nyq) {
   using C = cx_t<R>;
-  const int N = a.n[j], half = N / 2, kind = a.fft_kind[j];
-  const int den = a.phase_den[j], len = a.len[j];
+  constexpr int EPT = kFftCap<NT> / NT;
+  const int N = a.n[j], n = N / 2, kind = a.fft_kind[j];
+  const bool shifted = a.phase_den[j] != 0;
+  const int len = a.len[j];
   C* out = spec + a.off[j];
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x;
   if (a.zero_pole_rings && (j == 0 || j == a.nrings - 1)) {
-    for (int m = tid; m < len; m += nth) out[m] = cmake<C>(R(0), R(0));
+    for (int m = tid; m < len; m += NT) out[m] = cmake<C>(R(0), R(0));
     return;
   }
   const R scale = a.adjoint ? R(1.0 / a.w[j]) : R(1);
   const R* xr = x + a.start[j];
+  const bool table = kind == FFT_POW2;
   if (kind == FFT_DIRECT) {
-    C* tab = buf + lds_elems(half);
+    C* tab = buf + lds_elems(n);
     R* xs = reinterpret_cast<R*>(tab + N);
-    for (int t = tid; t < N; t += nth) {
+    for (int t = tid; t < N; t += NT) {
       tab[t] = cconj(expipi<R>(2 * t, N));  // exp(-2 pi i t / N)
       xs[t] = xr[t] * scale;
     }
     __syncthreads();
-    for (int m = tid; m <= half; m += nth) {
+    for (int m = tid; m <= n; m += NT) {
       C acc = cmake<C>(R(0), R(0));
       int idx = 0;
       for (int k = 0; k < N; ++k) {
@@ -82,76 +101,175 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
         idx += m;
         if (idx >= N) idx -= N;
       }
-      if (m < half) buf[lidx(m)] = acc;
+      if (shifted) acc = cmul(acc, half_twiddle<R>(m, N, false, a.tw, a.TN));
+      if (m < n) buf[lidx(m)] = acc;
       else nyq = acc;
     }
     __syncthreads();
   } else {
-    const int n = half;
-    for (int l = tid; l < n; l += nth) buf[lidx(l)] = cmake<C>(xr[2 * l] * scale, xr[2 * l + 1] * scale);
+    // the ring as n complex samples (x_2l, x_2l+1), all loads issued at once
+    {
+      const cx_t<R>* xc = reinterpret_cast<const cx_t<R>*>(xr);
+      C z[EPT];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int l = tid + e * NT;
+        if (l < n) z[e] = xc[l];
+      }
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int l = tid + e * NT;
+        if (l < n) buf[lidx(l)] = cscale(z[e], scale);
+      }
+    }
     __syncthreads();
     if (kind == FFT_POW2)
-      ring_dft<R, false>(buf, n, 1, n, nullptr, a.tw, a.TN);
+      lds_fft<R, false, NT>(buf, n, a.tw, a.TN);
     else
-      ring_dft<R, false>(buf, n, 2, a.fft_m[j], a.bl + a.bl_off[j], a.tw, a.TN);
-    // split Z into A(r) = E(r) + exp(-2 pi i r / N) O(r), in place, pairing r with n - r
-    for (int r = tid; r <= n / 2; r += nth) {
-      const int r2 = n - r;
-      const C z1 = buf[lidx(r)], z2 = buf[lidx(r2 == n ? 0 : r2)];
-      C e = cscale(cadd(z1, cconj(z2)), R(0.5));
-      C o = cscale(csub(z1, cconj(z2)), R(0.5));
-      C ar = cadd(e, cmul(cconj(expipi<R>(2 * r, N)), cmake<C>(o.y, -o.x)));
-      C e2 = cscale(cadd(z2, cconj(z1)), R(0.5));
-      C o2 = cscale(csub(z2, cconj(z1)), R(0.5));
-      C ar2 = cadd(e2, cmul(cconj(expipi<R>(2 * r2, N)), cmake<C>(o2.y, -o2.x)));
-      buf[lidx(r)] = ar;
-      if (r2 == n) nyq = ar2;
-      else if (r2 != r) buf[lidx(r2)] = ar2;
+      bluestein<R, false, NT>(buf, n, a.fft_m[j], a.bl + a.bl_off[j], a.tw, a.TN);
+    constexpr int kPairBatch = PairBatch<R>::value;
+    // split Z into A(r) = E(r) - i exp(-2 pi i r / N) O(r) for the pair
+    // (r, n - r), then the phase shift A~(r) = A(r) w_r, w_{n-r} = -i conj(w_r)
+    for (int base = 0; base <= n / 2; base += NT * kPairBatch) {
+      C wr[kPairBatch];
+#pragma unroll
+      for (int u = 0; u < kPairBatch; ++u) {
+        const int r = base + tid + u * NT;
+        if (r <= n / 2) wr[u] = half_twiddle<R>(r, N, table, a.tw, a.TN);
+      }
+#pragma unroll
+      for (int u = 0; u < kPairBatch; ++u) {
+        const int r = base + tid + u * NT;
+        if (r <= n / 2) {
+          const int r2 = n - r;
+          const C z1 = buf[lidx(r)], z2 = buf[lidx(r2 == n ? 0 : r2)];
+          const C t = cmul(wr[u], wr[u]);                 // exp(-2 pi i r / N)
+          const C t2 = cmake<C>(-t.x, t.y);               // exp(-2 pi i (n - r) / N) = -conj(t)
+          const C e1 = cscale(cadd(z1, cconj(z2)), R(0.5)), o1 = cscale(csub(z1, cconj(z2)), R(0.5));
+          const C e2 = cscale(cadd(z2, cconj(z1)), R(0.5)), o2 = cscale(csub(z2, cconj(z1)), R(0.5));
+          C a1 = cadd(e1, cmul(t, cmake<C>(o1.y, -o1.x)));
+          C a2 = cadd(e2, cmul(t2, cmake<C>(o2.y, -o2.x)));
+          if (shifted) {
+            a1 = cmul(a1, wr[u]);
+            const C w2 = cmake<C>(-wr[u].y, -wr[u].x);    // -i conj(w_r)
+            a2 = cmul(a2, w2);
+          }
+          buf[lidx(r)] = a1;
+          if (r2 == n) nyq = a2;
+          else if (r2 != r) buf[lidx(r2)] = a2;
+        }
+      }
     }
     __syncthreads();
   }
-  // periodic extension with the phase shift to absolute longitude
-  for (int m = tid; m < len; m += nth) {
-    const int r = m % N;
+  // periodic extension: A~(qN + r) = s^q A~(r), A~(N - r) = s conj(A~(r))
+  const float invN = 1.0f / (float)N;
+  const R s = shifted ? R(-1) : R(1);
+  for (int m = tid; m < len; m += NT) {
+    int q, r;
+    divmod_small(m, N, invN, q, r);
     C v;
-    if (r == half) v = nyq;
-    else if (r < half) v = buf[lidx(r)];
-    else v = cconj(buf[lidx(N - r)]);
-    out[m] = cmul(v, unshift<R>(m, den));
+    if (r == n) v = nyq;
+    else if (r < n) v = buf[lidx(r)];
+    else {
+      const C c = buf[lidx(N - r)];
+      v = cmake<C>(s * c.x, -s * c.y);
+    }
+    if (shifted && (q & 1)) v = cmake<C>(-v.x, -v.y);
+    out[m] = v;
   }
 }
 
-// Step (d) for ring i of one plan.
-template <typename R>
+// Step (d) for ring i of one plan.  With P(r) = sum_q s^q B(qN + r) the
+// fold onto the ring's own modes is
+//   G(r) = conj(w_r) (P(r) - conj(P(N - r)))   (offset rings),
+//   G(r) = P(r) + conj(P(N - r))               (others),
+// for 0 <= r <= N/2 (P(N) collects the modes qN, q >= 1).
+template <typename R, int NT>
 __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, const cx_t<R>* __restrict__ bin,
                                          R* __restrict__ y, cx_t<R>* buf, cx_t<R>& nyq) {
   using C = cx_t<R>;
-  const int N = a.n[i], half = N / 2, kind = a.fft_kind[i];
-  const int den = a.phase_den[i], len = a.len[i];
+  constexpr int EPT = kFftCap<NT> / NT;
+  const int N = a.n[i], n = N / 2, kind = a.fft_kind[i];
+  const bool shifted = a.phase_den[i] != 0;
+  const int len = a.len[i];
   const C* b = bin + a.off[i];
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x;
   const R scale = a.adjoint ? R(a.w[i]) : R(1);
-  // fold: reverse phase shift and aliasing onto m mod N
-  for (int r = tid; r <= half; r += nth) {
-    C g = cmake<C>(R(0), R(0));
-    for (int m = r; m < len; m += N) g = cadd(g, cmul(b[m], cconj(unshift<R>(m, den))));
-    for (int m = (r == 0 ? N : N - r); m < len; m += N)
-      g = cadd(g, cconj(cmul(b[m], cconj(unshift<R>(m, den)))));
-    g = cscale(g, scale);
-    if (r < half) buf[lidx(r)] = g;
-    else nyq = g;
+  const bool table = kind == FFT_POW2;
+  const bool direct = kind == FFT_DIRECT;
+  constexpr int kPairBatch = PairBatch<R>::value;
+  const int nq = (len + N - 1) / N;
+  for (int base = 0; base <= n / 2; base += NT * kPairBatch) {
+    // P at r, N - r, n - r and n + r for each pair (r, n - r)
+    C p[kPairBatch][4];
+#pragma unroll
+    for (int u = 0; u < kPairBatch; ++u)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) p[u][c] = cmake<C>(R(0), R(0));
+    for (int q = 0; q < nq; ++q) {
+      const R sg = (shifted && (q & 1)) ? R(-1) : R(1);
+      const int m0 = q * N;
+      C v[kPairBatch][4];
+#pragma unroll
+      for (int u = 0; u < kPairBatch; ++u) {
+        const int r = base + tid + u * NT;
+        const int ms[4] = {m0 + r, m0 + N - r, m0 + n - r, m0 + n + r};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          v[u][c] = cmake<C>(R(0), R(0));
+          if (r <= n / 2 && ms[c] < len) v[u][c] = b[ms[c]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kPairBatch; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) p[u][c] = cadd(p[u][c], cscale(v[u][c], sg));
+    }
+#pragma unroll
+    for (int u = 0; u < kPairBatch; ++u) {
+      const int r = base + tid + u * NT;
+      if (r > n / 2) continue;
+      const int r2 = n - r;
+      const C w = half_twiddle<R>(r, N, table, a.tw, a.TN);
+      C g1, g2;
+      if (shifted) {
+        g1 = cmul(cconj(w), csub(p[u][0], cconj(p[u][1])));
+        g2 = cmul(cmake<C>(-w.y, w.x), csub(p[u][2], cconj(p[u][3])));   // conj(w_{n-r}) = i w_r
+      } else {
+        g1 = cadd(p[u][0], cconj(p[u][1]));
+        g2 = cadd(p[u][2], cconj(p[u][3]));
+      }
+      g1 = cscale(g1, scale);
+      g2 = cscale(g2, scale);
+      if (direct) {
+        buf[lidx(r)] = g1;
+        if (r2 == n) nyq = g2;
+        else if (r2 != r) buf[lidx(r2)] = g2;
+        continue;
+      }
+      // Z(r) = E(r) + i O(r), E(r) = G(r) + conj(G(n-r)), O(r) = exp(2 pi i r/N) (G(r) - conj(G(n-r)))
+      const C t = cconj(cmul(w, w));                      // exp(2 pi i r / N)
+      const C t2 = cmake<C>(-t.x, t.y);                   // exp(2 pi i (n - r) / N)
+      const C e1 = cadd(g1, cconj(g2)), o1 = cmul(t, csub(g1, cconj(g2)));
+      buf[lidx(r)] = cadd(e1, cmake<C>(-o1.y, o1.x));
+      if (r2 < n && r2 != r) {
+        const C e2 = cadd(g2, cconj(g1)), o2 = cmul(t2, csub(g2, cconj(g1)));
+        buf[lidx(r2)] = cadd(e2, cmake<C>(-o2.y, o2.x));
+      }
+    }
   }
   __syncthreads();
   R* yr = y + a.start[i];
-  if (kind == FFT_DIRECT) {
-    C* tab = buf + lds_elems(half);
-    for (int t = tid; t < N; t += nth) tab[t] = expipi<R>(2 * t, N);  // exp(+2 pi i t / N)
+  if (direct) {
+    C* tab = buf + lds_elems(n);
+    for (int t = tid; t < N; t += NT) tab[t] = expipi<R>(2 * t, N);  // exp(+2 pi i t / N)
     __syncthreads();
     const C g0 = buf[lidx(0)];
-    for (int k = tid; k < N; k += nth) {
+    for (int k = tid; k < N; k += NT) {
       R acc = g0.x + ((k & 1) ? -nyq.x : nyq.x);
       int idx = k;
-      for (int r = 1; r < half; ++r) {
+      for (int r = 1; r < n; ++r) {
         const C t = tab[idx], g = buf[lidx(r)];
         acc += R(2) * (g.x * t.x - g.y * t.y);
         idx += k;
@@ -161,73 +279,63 @@ __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, cons
     }
     return;
   }
-  const int n = half;
-  // Z(r) = E(r) + i O(r), E(r) = G(r) + conj(G(n-r)), O(r) = e^{2 pi i r/N} (G(r) - conj(G(n-r)))
-  for (int r = tid; r <= n / 2; r += nth) {
-    const int r2 = n - r;
-    const C g1 = buf[lidx(r)], g2 = r2 == n ? nyq : buf[lidx(r2)];
-    const C e1 = cadd(g1, cconj(g2));
-    const C o1 = cmul(expipi<R>(2 * r, N), csub(g1, cconj(g2)));
-    buf[lidx(r)] = cadd(e1, cmake<C>(-o1.y, o1.x));
-    if (r2 < n && r2 != r) {
-      const C e2 = cadd(g2, cconj(g1));
-      const C o2 = cmul(expipi<R>(2 * r2, N), csub(g2, cconj(g1)));
-      buf[lidx(r2)] = cadd(e2, cmake<C>(-o2.y, o2.x));
-    }
-  }
-  __syncthreads();
   if (kind == FFT_POW2)
-    ring_dft<R, true>(buf, n, 1, n, nullptr, a.tw, a.TN);
+    lds_fft<R, true, NT>(buf, n, a.tw, a.TN);
   else
-    ring_dft<R, true>(buf, n, 2, a.fft_m[i], a.bl + a.bl_off[i], a.tw, a.TN);
-  for (int l = tid; l < n; l += nth) {
-    const C z = buf[lidx(l)];
-    yr[2 * l] = z.x;
-    yr[2 * l + 1] = z.y;
+    bluestein<R, true, NT>(buf, n, a.fft_m[i], a.bl + a.bl_off[i], a.tw, a.TN);
+  cx_t<R>* yc = reinterpret_cast<cx_t<R>*>(yr);
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int l = tid + e * NT;
+    if (l < n) yc[l] = buf[lidx(l)];
   }
 }
 
 
-template <typename R>
-__global__ void __launch_bounds__(kBlock) r2c_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
-                                                     const R* __restrict__ x, cx_t<R>* __restrict__ spec) {
+// Minimum waves per SIMD the ring kernels are compiled for: four blocks of
+// 256 threads (or two of 512) per CU in FP32, whose LDS also fits four.
+template <typename R> struct FftWaves { static constexpr int value = sizeof(R) == 4 ? 4 : 2; };
+
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT, FftWaves<R>::value) r2c_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
+                                                 const R* __restrict__ x, cx_t<R>* __restrict__ spec) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ cx_t<R> nyq;  // A(N/2), kept outside the padded buffer
-  r2c_ring<R>(a, list[blockIdx.x], x, spec, reinterpret_cast<cx_t<R>*>(smem), nyq);
+  r2c_ring<R, NT>(a, list[blockIdx.x], x, spec, reinterpret_cast<cx_t<R>*>(smem), nyq);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(kBlock) c2r_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
-                                                     const cx_t<R>* __restrict__ bin, R* __restrict__ y) {
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT, FftWaves<R>::value) c2r_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
+                                                 const cx_t<R>* __restrict__ bin, R* __restrict__ y) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ cx_t<R> nyq;  // G(N/2)
-  c2r_ring<R>(a, list[blockIdx.x], bin, y, reinterpret_cast<cx_t<R>*>(smem), nyq);
+  c2r_ring<R, NT>(a, list[blockIdx.x], bin, y, reinterpret_cast<cx_t<R>*>(smem), nyq);
 }
 
 // Batched forms: entry (map, ring); per-map arguments, maps and workspace
 // offsets in device arrays.
-template <typename R>
-__global__ void __launch_bounds__(kBlock) r2c_batch_kernel(const RingArgs<R>* __restrict__ args,
-                                                           const int2* __restrict__ entries,
-                                                           const R* const* __restrict__ xs,
-                                                           cx_t<R>* __restrict__ ws, const int64_t* __restrict__ base) {
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT, FftWaves<R>::value) r2c_batch_kernel(const RingArgs<R>* __restrict__ args,
+                                                       const int2* __restrict__ entries,
+                                                       const R* const* __restrict__ xs,
+                                                       cx_t<R>* __restrict__ ws, const int64_t* __restrict__ base) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ cx_t<R> nyq;
   const int2 e = entries[blockIdx.x];
   const RingArgs<R> a = args[e.x];
-  r2c_ring<R>(a, e.y, xs[e.x], ws + base[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
+  r2c_ring<R, NT>(a, e.y, xs[e.x], ws + base[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(kBlock) c2r_batch_kernel(const RingArgs<R>* __restrict__ args,
-                                                           const int2* __restrict__ entries,
-                                                           const cx_t<R>* __restrict__ ws,
-                                                           const int64_t* __restrict__ base, R* const* __restrict__ ys) {
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT, FftWaves<R>::value) c2r_batch_kernel(const RingArgs<R>* __restrict__ args,
+                                                       const int2* __restrict__ entries,
+                                                       const cx_t<R>* __restrict__ ws,
+                                                       const int64_t* __restrict__ base, R* const* __restrict__ ys) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ cx_t<R> nyq;
   const int2 e = entries[blockIdx.x];
   const RingArgs<R> a = args[e.x];
-  c2r_ring<R>(a, e.y, ws + base[e.x], ys[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
+  c2r_ring<R, NT>(a, e.y, ws + base[e.x], ys[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
 }
 
 template <typename R> RingArgs<R> ring_args(arkcos_plan_s* P, bool out_side, int adjoint,
@@ -251,30 +359,54 @@ template <typename R> RingArgs<R> ring_args(arkcos_plan_s* P, bool out_side, int
   return a;
 }
 
+// Threads per block for a ring class whose longest FFT has length fft_len.
+int fft_threads(arkcos_dtype_t dt, int32_t fft_len) {
+  return (dt == ARKCOS_F32 && fft_len > kFftCap<256>) ? 512 : 256;
+}
+
+template <typename K> static hipError_t allow_lds(K* k, int32_t bytes) {
+  return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 hipError_t configure_fft_kernels(arkcos_plan_s* P) {
   // dynamic LDS above 64 KiB (plus the static Nyquist slot) needs the attribute
-  hipError_t e;
+  hipError_t e = hipSuccess;
+  const int32_t b = P->max_fft_lds;
   if (P->dtype == ARKCOS_F32) {
-    e = hipFuncSetAttribute((const void*)r2c_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_fft_lds);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)c2r_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_fft_lds);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 256>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 512>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 256>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 512>, b);
   } else {
-    e = hipFuncSetAttribute((const void*)r2c_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_fft_lds);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)c2r_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_fft_lds);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<double, 256>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<double, 256>, b);
   }
   return e;
+}
+
+template <typename R>
+static void r2c_class(const FftClass& c, const RingArgs<R>& a, const void* x, void* spec, hipStream_t s) {
+  if (sizeof(R) == 4 && c.threads == 512)
+    r2c_kernel<R, 512><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, (const R*)x, (cx_t<R>*)spec);
+  else
+    r2c_kernel<R, 256><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, (const R*)x, (cx_t<R>*)spec);
+}
+
+template <typename R>
+static void c2r_class(const FftClass& c, const RingArgs<R>& a, const void* b, void* y, hipStream_t s) {
+  if (sizeof(R) == 4 && c.threads == 512)
+    c2r_kernel<R, 512><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, (const cx_t<R>*)b, (R*)y);
+  else
+    c2r_kernel<R, 256><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, (const cx_t<R>*)b, (R*)y);
 }
 
 hipError_t launch_r2c(arkcos_plan_s* P, const void* x, void* spec, int32_t adjoint,
                       int32_t zero_pole_rings, hipStream_t s) {
   for (const FftClass& c : P->fft_classes) {
     if (P->dtype == ARKCOS_F32)
-      r2c_kernel<float><<<(unsigned)c.count, kBlock, c.lds, s>>>(
-          ring_args<float>(P, false, adjoint, zero_pole_rings), c.d_rings, (const float*)x, (float2*)spec);
+      r2c_class<float>(c, ring_args<float>(P, false, adjoint, zero_pole_rings), x, spec, s);
     else
-      r2c_kernel<double><<<(unsigned)c.count, kBlock, c.lds, s>>>(
-          ring_args<double>(P, false, adjoint, zero_pole_rings), c.d_rings, (const double*)x, (double2*)spec);
+      r2c_class<double>(c, ring_args<double>(P, false, adjoint, zero_pole_rings), x, spec, s);
   }
   return hipGetLastError();
 }
@@ -290,36 +422,32 @@ void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t ze
 
 // Batched ring transforms: forward (R2C of maps[m] into ws + base[m]) or
 // inverse (C2R of ws + base[m] into maps[m]).
-hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, const void* entries, int32_t count,
-                             int32_t lds, const void* maps, void* ws, const int64_t* base, hipStream_t s) {
-  if (count == 0) return hipSuccess;
+template <typename R, int NT>
+static hipError_t ring_batch(bool inverse, const void* args, const void* entries, int32_t count, int32_t lds,
+                             const void* maps, void* ws, const int64_t* base, hipStream_t s) {
   hipError_t e;
-  if (dt == ARKCOS_F32) {
-    if (!inverse) {
-      e = hipFuncSetAttribute((const void*)r2c_batch_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-      if (e != hipSuccess) return e;
-      r2c_batch_kernel<float><<<count, kBlock, lds, s>>>((const RingArgs<float>*)args, (const int2*)entries,
-                                                         (const float* const*)maps, (float2*)ws, base);
-    } else {
-      e = hipFuncSetAttribute((const void*)c2r_batch_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-      if (e != hipSuccess) return e;
-      c2r_batch_kernel<float><<<count, kBlock, lds, s>>>((const RingArgs<float>*)args, (const int2*)entries,
-                                                         (const float2*)ws, base, (float* const*)maps);
-    }
+  if (!inverse) {
+    e = allow_lds(r2c_batch_kernel<R, NT>, lds);
+    if (e != hipSuccess) return e;
+    r2c_batch_kernel<R, NT><<<count, NT, lds, s>>>((const RingArgs<R>*)args, (const int2*)entries,
+                                                   (const R* const*)maps, (cx_t<R>*)ws, base);
   } else {
-    if (!inverse) {
-      e = hipFuncSetAttribute((const void*)r2c_batch_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-      if (e != hipSuccess) return e;
-      r2c_batch_kernel<double><<<count, kBlock, lds, s>>>((const RingArgs<double>*)args, (const int2*)entries,
-                                                          (const double* const*)maps, (double2*)ws, base);
-    } else {
-      e = hipFuncSetAttribute((const void*)c2r_batch_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-      if (e != hipSuccess) return e;
-      c2r_batch_kernel<double><<<count, kBlock, lds, s>>>((const RingArgs<double>*)args, (const int2*)entries,
-                                                          (const double2*)ws, base, (double* const*)maps);
-    }
+    e = allow_lds(c2r_batch_kernel<R, NT>, lds);
+    if (e != hipSuccess) return e;
+    c2r_batch_kernel<R, NT><<<count, NT, lds, s>>>((const RingArgs<R>*)args, (const int2*)entries,
+                                                   (const cx_t<R>*)ws, base, (R* const*)maps);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, const void* entries, int32_t count,
+                             int32_t lds, int32_t threads, const void* maps, void* ws, const int64_t* base,
+                             hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (dt == ARKCOS_F32)
+    return threads == 512 ? ring_batch<float, 512>(inverse, args, entries, count, lds, maps, ws, base, s)
+                          : ring_batch<float, 256>(inverse, args, entries, count, lds, maps, ws, base, s);
+  return ring_batch<double, 256>(inverse, args, entries, count, lds, maps, ws, base, s);
 }
 
 // Step (a) into the output-ring layout (lengths out_len): the extended
@@ -328,11 +456,9 @@ hipError_t launch_r2c_layout(arkcos_plan_s* P, const void* x, void* spec, bool o
                              hipStream_t s) {
   for (const FftClass& c : P->fft_classes) {
     if (P->dtype == ARKCOS_F32)
-      r2c_kernel<float><<<(unsigned)c.count, kBlock, c.lds, s>>>(
-          ring_args<float>(P, out_layout, 0, zero_pole), c.d_rings, (const float*)x, (float2*)spec);
+      r2c_class<float>(c, ring_args<float>(P, out_layout, 0, zero_pole), x, spec, s);
     else
-      r2c_kernel<double><<<(unsigned)c.count, kBlock, c.lds, s>>>(
-          ring_args<double>(P, out_layout, 0, zero_pole), c.d_rings, (const double*)x, (double2*)spec);
+      r2c_class<double>(c, ring_args<double>(P, out_layout, 0, zero_pole), x, spec, s);
   }
   return hipGetLastError();
 }
@@ -340,11 +466,9 @@ hipError_t launch_r2c_layout(arkcos_plan_s* P, const void* x, void* spec, bool o
 hipError_t launch_c2r(arkcos_plan_s* P, const void* bout, void* y, int32_t adjoint, hipStream_t s) {
   for (const FftClass& c : P->fft_classes) {
     if (P->dtype == ARKCOS_F32)
-      c2r_kernel<float><<<(unsigned)c.count, kBlock, c.lds, s>>>(
-          ring_args<float>(P, true, adjoint, 0), c.d_rings, (const float2*)bout, (float*)y);
+      c2r_class<float>(c, ring_args<float>(P, true, adjoint, 0), bout, y, s);
     else
-      c2r_kernel<double><<<(unsigned)c.count, kBlock, c.lds, s>>>(
-          ring_args<double>(P, true, adjoint, 0), c.d_rings, (const double2*)bout, (double*)y);
+      c2r_class<double>(c, ring_args<double>(P, true, adjoint, 0), bout, y, s);
   }
   return hipGetLastError();
 }

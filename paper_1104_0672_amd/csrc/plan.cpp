@@ -313,6 +313,9 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
     }
   }
   for (int64_t k = 0; k < nr; ++k) {
+    // the ring transforms take every longitude offset to be pi / N
+    if (P->h_phase_den[k] != 0 && P->h_phase_den[k] != P->h_n[k])
+      return fail(ARKCOS_ERR_INTERNAL, "ring offset other than pi / N");
     P->h_sin[k] = sin(P->h_theta[k]);
     P->h_cos[k] = cos(P->h_theta[k]);
   }
@@ -414,7 +417,7 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       if (n > maxM) return fail(ARKCOS_ERR_NOT_SUPPORTED, "ring FFT longer than the LDS limit");
       fft_kind[k] = FFT_POW2;
       fft_m[k] = (int32_t)n;
-      twn = std::max(twn, n);
+      twn = std::max(twn, 2 * N);  // w_r = exp(-i pi r / N) read from the table
       ring_lds[k] = (size_t)lds_elems((int)n) * csz;
       lds = std::max(lds, ring_lds[k]);
     } else {
@@ -440,6 +443,7 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   P->twiddle_n = (int32_t)twn;
   P->max_fft_lds = (int32_t)((lds + 15) / 16 * 16);
   P->h_ring_lds.resize(nr);
+  P->h_fft_len = fft_m;
   for (int64_t k = 0; k < nr; ++k) P->h_ring_lds[k] = (int32_t)((ring_lds[k] + 15) / 16 * 16);
   {
     // launch classes by LDS size (power-of-two buckets from 4 KiB); a ring
@@ -458,8 +462,13 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       FftClass c;
       c.count = (int32_t)it->second.size();
       size_t mx = 0;
-      for (int32_t k : it->second) mx = std::max(mx, ring_lds[k]);
+      int32_t len = 0;
+      for (int32_t k : it->second) {
+        mx = std::max(mx, ring_lds[k]);
+        len = std::max(len, fft_m[k]);
+      }
       c.lds = (int32_t)((mx + 15) / 16 * 16);
+      c.threads = fft_threads(dtype, len);
       HIPCHK(upload(P, &c.d_rings, it->second));
       P->fft_classes.push_back(c);
     }

@@ -159,8 +159,8 @@ __global__ void __launch_bounds__(kBlock) table_kernel(
 
 // Bluestein filter of length n: FFT_M of b_l = exp(+i pi l^2 / n) placed at l
 // and M - l for 0 <= l < n, followed by the chirp exp(-i pi l^2 / n), l < n.
-template <typename R>
-__global__ void __launch_bounds__(kBlock) bluestein_filter_kernel(
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT) bluestein_filter_kernel(
     const int32_t* __restrict__ rings, const int32_t* __restrict__ ring_n,
     const int32_t* __restrict__ fft_m, const int64_t* __restrict__ bl_off,
     const cx_t<R>* __restrict__ tw, int TN, cx_t<R>* __restrict__ out) {
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(kBlock) bluestein_filter_kernel(
     buf[lidx(l)] = src >= 0 ? cconj(chirp<R>(src, n)) : cmake<C>(R(0), R(0));
   }
   __syncthreads();
-  lds_fft<R, false>(buf, M, tw, TN);
+  lds_fft<R, false, NT>(buf, M, tw, TN);
   C* o = out + bl_off[ring];
   for (int l = threadIdx.x; l < M; l += blockDim.x) o[l] = buf[lidx(l)];
   for (int l = threadIdx.x; l < n; l += blockDim.x) o[M + l] = chirp<R>(l, n);
@@ -232,23 +232,31 @@ hipError_t launch_table_list(arkcos_plan_s* P, const int32_t* d_list, const int6
 hipError_t launch_bluestein_filters(arkcos_plan_s* P, const int32_t* d_ring_list, int32_t count,
                                     hipStream_t s) {
   if (count == 0) return hipSuccess;
-  size_t lds = (size_t)lds_elems(P->max_bl_m) * (P->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2));
+  const int lds = (int)((size_t)lds_elems(P->max_bl_m) * (P->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2)));
+  const int nt = fft_threads(P->dtype, P->max_bl_m);
   hipError_t e;
-  if (P->dtype == ARKCOS_F32)
-    e = hipFuncSetAttribute((const void*)bluestein_filter_kernel<float>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  else
-    e = hipFuncSetAttribute((const void*)bluestein_filter_kernel<double>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  if (P->dtype == ARKCOS_F32)
-    bluestein_filter_kernel<float><<<count, kBlock, lds, s>>>(
-        d_ring_list, P->rt.n, P->rt.fft_m, P->rt.bl_off, (const float2*)P->d_twiddle,
-        P->twiddle_n, (float2*)P->d_bl);
-  else
-    bluestein_filter_kernel<double><<<count, kBlock, lds, s>>>(
-        d_ring_list, P->rt.n, P->rt.fft_m, P->rt.bl_off, (const double2*)P->d_twiddle,
-        P->twiddle_n, (double2*)P->d_bl);
+  if (P->dtype == ARKCOS_F32 && nt == 512) {
+    e = hipFuncSetAttribute((const void*)bluestein_filter_kernel<float, 512>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    bluestein_filter_kernel<float, 512><<<count, 512, lds, s>>>(
+        d_ring_list, P->rt.n, P->rt.fft_m, P->rt.bl_off, (const float2*)P->d_twiddle, P->twiddle_n,
+        (float2*)P->d_bl);
+  } else if (P->dtype == ARKCOS_F32) {
+    e = hipFuncSetAttribute((const void*)bluestein_filter_kernel<float, 256>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    bluestein_filter_kernel<float, 256><<<count, 256, lds, s>>>(
+        d_ring_list, P->rt.n, P->rt.fft_m, P->rt.bl_off, (const float2*)P->d_twiddle, P->twiddle_n,
+        (float2*)P->d_bl);
+  } else {
+    e = hipFuncSetAttribute((const void*)bluestein_filter_kernel<double, 256>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    bluestein_filter_kernel<double, 256><<<count, 256, lds, s>>>(
+        d_ring_list, P->rt.n, P->rt.fft_m, P->rt.bl_off, (const double2*)P->d_twiddle, P->twiddle_n,
+        (double2*)P->d_bl);
+  }
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ constexpr int kDirectMax = 64;         // rings up to this length use a plain DF
 constexpr int kOtfMaxCoef = 48;        // wider kernel rows use a K_ij(m) table (auto mode)
 constexpr int kClenshawMaxCoef = 16;   // longer centred rows use Reinsch's recurrence
 constexpr int kBandUnits = 8;          // output units (ring + mirror) per accumulation work item
-constexpr int kAccTile = 64;           // modes per accumulation work item (one per lane)
+constexpr int kAccTile = 128;          // modes per accumulation tile (two per lane)
 constexpr int kAccThreads = 64 * kBandUnits;  // one wavefront per unit
 
 // FFT strategy of one ring length.
@@ -67,22 +67,33 @@ struct UnitDev {
   int32_t pad;
 };
 
+// One accumulation work item: band `band`, mode tiles [t0, t0 + nt) of
+// kAccTile modes each.
 struct WorkItem {
-  int32_t unit;   // first unit of the band
-  int32_t m0;
+  int32_t band, t0, nt, pad;
 };
 
-// One queue entry of the batched accumulation.
+// One queue entry of the batched accumulation: the same for plan `map`.
 struct BatchItem {
-  int32_t map, band, m0, pad;
+  int32_t map, band, t0, nt;
 };
+
+constexpr int kTilesPerItem = 8;     // mode tiles per accumulation work item
 
 // A band of up to kBandUnits consecutive units: the input rings they need.
 struct BandDev {
   int32_t u0, nu;       // units [u0, u0 + nu)
   int32_t jlo, jhi;     // input rings [jlo, jhi]
   int32_t band;         // max band over the units
+  int32_t pbeg, npair;  // the units' pairs [pbeg, pbeg + npair) (contiguous)
   int32_t pad;
+};
+
+// What sizes the LDS of an accumulation block: the widest input-ring window
+// and the most pairs of any band.
+struct AccShape {
+  int32_t max_window = 0;
+  int32_t max_band_pairs = 0;
 };
 
 // Rings whose FFTs share one launch: similar LDS needs, so small rings are
@@ -140,7 +151,7 @@ struct arkcos_plan_s {
   arkcos::PairDev* d_pairs = nullptr;
   arkcos::WorkItem* d_items = nullptr;
   arkcos::BandDev* d_bands = nullptr;
-  int32_t max_window = 0;      // input rings staged per accumulation band
+  arkcos::AccShape acc_shape;  // LDS needs of the accumulation bands
   std::vector<arkcos::BandDev> h_bands;
   void* d_coef = nullptr;       // recurrence coefficients, plan dtype
   double* d_coef64 = nullptr;   // the same in FP64 (plan-time table building, gradient)
@@ -183,11 +194,11 @@ hipError_t configure_accumulate(arkcos_plan_s* P);
 // batched form
 size_t acc_args_size();
 void fill_acc_args(arkcos_plan_s* P, const BandDev* bands, void* out);
-size_t acc_lds_bytes(arkcos_dtype_t dt, int32_t max_window);
+size_t acc_lds_bytes(arkcos_dtype_t dt, const AccShape& shape);
 hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const int64_t* spec_base,
                                    const int64_t* out_base, const BatchItem* items, int32_t n_items,
                                    int32_t* counter, const void* spec, void* bout, int32_t grid,
-                                   int32_t units_per_band, size_t lds, hipStream_t s);
+                                   int32_t units_per_band, const AccShape& shape, hipStream_t s);
 size_t ring_args_size();
 void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out);
 hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, const void* entries, int32_t count,
@@ -198,8 +209,9 @@ size_t pole_map_size();
 void fill_pole_map(arkcos_plan_s* P, void* out);
 hipError_t launch_pole_batch(arkcos_dtype_t dt, const void* maps, const int2* entries, int32_t count, int32_t adjoint,
                              const void* xs, const void* ys, hipStream_t s);
-void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<BandDev>& bands,
-                 int32_t* max_window);
+void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<BandDev>& bands, AccShape* shape);
+void accumulation_items(const arkcos_plan_s* P, const std::vector<BandDev>& bands, std::vector<WorkItem>& items,
+                        std::vector<double>& cost);
 int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count);
 void workspace_split(const arkcos_plan_s* P, void* ws, void** spec, void** bout);
 double* grad_slots(const arkcos_plan_s* P, void* ws);

@@ -41,7 +41,7 @@ struct arkcos_batch_s {
   int32_t n = 0;
   std::vector<arkcos_plan_s*> plans;
   int32_t units_per_band = kBandUnits, grid = 0, tuned = 0;
-  size_t acc_lds = 0;
+  AccShape acc_shape;
   int64_t spec_total = 0, out_total = 0, npix_total = 0;
   std::vector<int64_t> h_spec_base, h_out_base;
   // device
@@ -95,7 +95,7 @@ struct Queue {
   std::vector<BandDev*> d_bands;
   std::vector<char> acc_args;
   std::vector<BatchItem> items;
-  int32_t max_window = 0;
+  AccShape shape;
 };
 
 hipError_t build_queue(arkcos_batch_s* B, const std::vector<int32_t>& maps, int32_t upb, Queue& Q,
@@ -106,9 +106,10 @@ hipError_t build_queue(arkcos_batch_s* B, const std::vector<int32_t>& maps, int3
   for (size_t mi = 0; mi < maps.size(); ++mi) {
     arkcos_plan_s* P = B->plans[maps[mi]];
     std::vector<BandDev> bands;
-    int32_t mw = 0;
-    build_bands(P, upb, bands, &mw);
-    Q.max_window = std::max(Q.max_window, mw);
+    AccShape sh;
+    build_bands(P, upb, bands, &sh);
+    Q.shape.max_window = std::max(Q.shape.max_window, sh.max_window);
+    Q.shape.max_band_pairs = std::max(Q.shape.max_band_pairs, sh.max_band_pairs);
     void* d = nullptr;
     hipError_t e = hipMalloc(&d, std::max<size_t>(bands.size(), 1) * sizeof(BandDev));
     if (e != hipSuccess) return e;
@@ -117,21 +118,11 @@ hipError_t build_queue(arkcos_batch_s* B, const std::vector<int32_t>& maps, int3
     if (e != hipSuccess) return e;
     Q.d_bands.push_back((BandDev*)d);
     fill_acc_args(P, (const BandDev*)d, Q.acc_args.data() + asz * mi);
-    for (int32_t b = 0; b < (int32_t)bands.size(); ++b) {
-      const BandDev& bd = bands[b];
-      for (int32_t m0 = 0; m0 <= bd.band; m0 += kAccTile) {
-        double cost = 0.0;
-        for (int32_t u = bd.u0; u < bd.u0 + bd.nu; ++u) {
-          const UnitDev& U = P->h_units[u];
-          for (int32_t q = U.pbeg; q < U.pend; ++q) {
-            const PairDev& pr = P->h_pairs[q];
-            if (pr.band < m0) continue;
-            cost += pr.kind == KG_TABLE ? 3.0 : (double)((pr.ncoef + 3) / 4 * 4) + 4.0;
-          }
-        }
-        costed.push_back({cost, BatchItem{(int32_t)mi, b, m0, 0}});
-      }
-    }
+    std::vector<WorkItem> its;
+    std::vector<double> cost;
+    accumulation_items(P, bands, its, cost);
+    for (size_t k = 0; k < its.size(); ++k)
+      costed.push_back({cost[k], BatchItem{(int32_t)mi, its[k].band, its[k].t0, its[k].nt}});
   }
   std::stable_sort(costed.begin(), costed.end(),
                    [](const std::pair<double, BatchItem>& a, const std::pair<double, BatchItem>& b) {
@@ -196,13 +187,12 @@ hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  const size_t lds = acc_lds_bytes(B->dtype, Q.max_window);
   const int reps = 3;
   for (int r = 0; r <= reps && e == hipSuccess; ++r) {
     if (r == 1) e = hipEventRecord(e0, nullptr);
     if (e == hipSuccess)
       e = launch_accumulate_batch(B->dtype, dargs, (const int64_t*)dsb, (const int64_t*)dob, (const BatchItem*)ditems,
-                                  (int32_t)Q.items.size(), counter, spec, bout, grid, upb, lds, nullptr);
+                                  (int32_t)Q.items.size(), counter, spec, bout, grid, upb, Q.shape, nullptr);
   }
   if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -387,7 +377,7 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
   hipError_t e = build_queue(B, all, upb, Q, owned);
   for (void* p : owned) B->allocations.push_back(p);
   BCHK(e);
-  B->acc_lds = acc_lds_bytes(B->dtype, Q.max_window);
+  B->acc_shape = Q.shape;
   void* d = nullptr;
   BCHK(hipMalloc(&d, Q.acc_args.size()));
   B->allocations.push_back(d);
@@ -453,7 +443,7 @@ arkcos_status_t run_batch(arkcos_batch_s* B, const void* const* x, void* const* 
                               B->d_spec_base, s));
   if (ev) BLAUNCH(hipEventRecord(ev[1], s));
   BLAUNCH(launch_accumulate_batch(B->dtype, B->d_acc_args, B->d_spec_base, B->d_out_base, B->d_items, B->n_items,
-                                  counter, spec, bout, B->grid, B->units_per_band, B->acc_lds, s));
+                                  counter, spec, bout, B->grid, B->units_per_band, B->acc_shape, s));
   if (ev) BLAUNCH(hipEventRecord(ev[2], s));
   for (const ClassDev& c : B->classes)
     BLAUNCH(launch_ring_batch(B->dtype, true, B->d_rargs[adjoint ? 3 : 2], c.entries, c.count, c.lds, c.threads, B->d_ys, bout,

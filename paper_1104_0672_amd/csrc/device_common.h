@@ -316,6 +316,39 @@ __device__ void bluestein(cx_t<R>* buf, int n, int M, const cx_t<R>* __restrict_
   __syncthreads();
 }
 
+// Loads and stores through the global address space.  Pointers read from
+// memory (per-map argument blocks of the batched kernels) are otherwise
+// generic, and generic (flat) accesses count against the LDS wait counter
+// as well, which serialises LDS reads behind outstanding global loads.
+template <typename T> __device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T> __device__ __forceinline__ void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+typedef double d2v_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 gload(const float2* p) {
+  const f2v_t v = gload(reinterpret_cast<const f2v_t*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 gload(const double2* p) {
+  const d2v_t v = gload(reinterpret_cast<const d2v_t*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore(float2* p, float2 v) {
+  f2v_t w;
+  w.x = v.x;
+  w.y = v.y;
+  gstore(reinterpret_cast<f2v_t*>(p), w);
+}
+__device__ __forceinline__ void gstore(double2* p, double2 v) {
+  d2v_t w;
+  w.x = v.x;
+  w.y = v.y;
+  gstore(reinterpret_cast<d2v_t*>(p), w);
+}
+
 template <typename T> __device__ __forceinline__ T uniform(T v) {
   return __builtin_amdgcn_readfirstlane(v);
 }

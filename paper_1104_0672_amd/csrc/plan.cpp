@@ -183,6 +183,9 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
   }
   if (!first_time && table_total != P->table_total)
     return fail(ARKCOS_ERR_INTERNAL, "table layout changed on knot update");
+  // the accumulation addresses samples and tables with 32-bit offsets
+  if (table_total >= (int64_t(1) << 32) || P->coef_total >= (int64_t(1) << 32))
+    return fail(ARKCOS_ERR_NOT_SUPPORTED, "kernel samples or tables beyond 2^32 elements");
   P->n_table_pairs = ntab;
   P->table_total = table_total;
   const size_t rsz = P->dtype == ARKCOS_F32 ? sizeof(float) : sizeof(double);
@@ -440,6 +443,8 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       }
     }
   }
+  // the accumulation reads exp(i pi m / (p L)) from the table as well
+  if (is_pow2((int64_t)P->oversample * L)) twn = std::max<int64_t>(twn, 2 * (int64_t)P->oversample * L);
   P->twiddle_n = (int32_t)twn;
   P->max_fft_lds = (int32_t)((lds + 15) / 16 * 16);
   P->h_ring_lds.resize(nr);
@@ -504,11 +509,12 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   HIPCHK(dev_alloc(P, &P->d_coef64, P->coef_total));
   HIPCHK(hipMemset(P->d_coef64, 0, std::max<int64_t>(P->coef_total, 1) * sizeof(double)));
   {
+    // padded by 16 zeros: the accumulation prefetches 16 samples per pair
     void* c = nullptr;
-    HIPCHK(hipMalloc(&c, std::max<int64_t>(P->coef_total, 1) * rsz));
-    HIPCHK(hipMemset(c, 0, std::max<int64_t>(P->coef_total, 1) * rsz));
+    HIPCHK(hipMalloc(&c, (P->coef_total + 16) * rsz));
+    HIPCHK(hipMemset(c, 0, (P->coef_total + 16) * rsz));
     P->allocations.push_back(c);
-    P->plan_bytes += std::max<int64_t>(P->coef_total, 1) * rsz;
+    P->plan_bytes += (P->coef_total + 16) * rsz;
     P->d_coef = c;
   }
   HIPCHK(dev_alloc(P, &P->d_knots, std::max<size_t>(P->knots.size(), 1)));
@@ -598,9 +604,17 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   HIPCHK(upload(P, &P->d_units, P->h_units));
 
   // bands of consecutive units, and work items: (band, first mode) tiles
-  build_bands(P, kBandUnits, P->h_bands, &P->max_window);
-  for (int32_t b = 0; b < (int32_t)P->h_bands.size(); ++b)
-    for (int32_t m0 = 0; m0 <= P->h_bands[b].band; m0 += kAccTile) P->h_items.push_back(WorkItem{b, m0});
+  build_bands(P, kBandUnits, P->h_bands, &P->acc_shape);
+  {
+    std::vector<WorkItem> its;
+    std::vector<double> cost;
+    accumulation_items(P, P->h_bands, its, cost);
+    std::vector<size_t> ord(its.size());
+    for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    P->h_items.clear();
+    for (size_t k : ord) P->h_items.push_back(its[k]);
+  }
   HIPCHK(upload(P, &P->d_items, P->h_items));
   HIPCHK(upload(P, &P->d_bands, P->h_bands));
   HIPCHK(configure_accumulate(P));
@@ -621,12 +635,40 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   return ARKCOS_OK;
 }
 
+// Work items of the accumulation: each band's mode tiles in runs of
+// kTilesPerItem, with an estimate of their cost (recurrence length of the
+// pairs still inside their band, summed over the tiles).
+void accumulation_items(const arkcos_plan_s* P, const std::vector<BandDev>& bands, std::vector<WorkItem>& items,
+                        std::vector<double>& cost) {
+  items.clear();
+  cost.clear();
+  for (int32_t b = 0; b < (int32_t)bands.size(); ++b) {
+    const BandDev& bd = bands[b];
+    if (bd.band < 0) continue;
+    const int32_t ntile = bd.band / kAccTile + 1;
+    for (int32_t t0 = 0; t0 < ntile; t0 += kTilesPerItem) {
+      const int32_t nt = std::min(kTilesPerItem, ntile - t0);
+      double c = 0.0;
+      for (int32_t u = bd.u0; u < bd.u0 + bd.nu; ++u) {
+        const UnitDev& U = P->h_units[u];
+        for (int32_t q = U.pbeg; q < U.pend; ++q) {
+          const PairDev& pr = P->h_pairs[q];
+          const int32_t live = std::min(nt, pr.band / kAccTile + 1 - t0);
+          if (live <= 0) continue;
+          c += live * (pr.kind == KG_TABLE ? 3.0 : (double)((pr.ncoef + 3) / 4 * 4) + 4.0);
+        }
+      }
+      items.push_back(WorkItem{b, t0, nt, 0});
+      cost.push_back(c + 8.0 * nt);
+    }
+  }
+}
+
 // Groups consecutive units into bands of units_per_band, with the input-ring
 // window of each band and the largest window.
-void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<BandDev>& bands,
-                 int32_t* max_window) {
+void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<BandDev>& bands, AccShape* shape) {
   bands.clear();
-  *max_window = 0;
+  *shape = AccShape{};
   const int64_t nunits = P->n_units, nr = P->nrings;
   for (int64_t u0 = 0; u0 < nunits; u0 += units_per_band) {
     BandDev B{};
@@ -635,6 +677,8 @@ void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<Ban
     B.jlo = (int32_t)nr;
     B.jhi = -1;
     B.band = -1;
+    B.pbeg = P->h_units[u0].pbeg;
+    B.npair = P->h_units[u0 + B.nu - 1].pend - B.pbeg;
     for (int64_t u = u0; u < u0 + B.nu; ++u) {
       const UnitDev& U = P->h_units[u];
       if (U.pend > U.pbeg) {
@@ -643,7 +687,8 @@ void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<Ban
       }
       B.band = std::max(B.band, U.band);
     }
-    if (B.jhi >= B.jlo) *max_window = std::max(*max_window, B.jhi - B.jlo + 1);
+    if (B.jhi >= B.jlo) shape->max_window = std::max(shape->max_window, B.jhi - B.jlo + 1);
+    shape->max_band_pairs = std::max(shape->max_band_pairs, B.npair);
     bands.push_back(B);
   }
 }

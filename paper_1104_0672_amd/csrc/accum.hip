@@ -47,29 +47,35 @@ __device__ __forceinline__ cx_t<R> half_angle(int m, int den, const cx_t<R>* __r
   return expipi<R>(r, den);
 }
 
-// Per-mode constants of the two kernel grids a unit's pairs use at mode m:
-// the output ring's own length N_i (equal-length pairs) and the fine grid
-// p L (all other pairs).
-template <typename R> struct ModeAngles {
-  R c1, cp;        // cos(2 pi m / N_i), cos(2 pi m / (p L))
-  R s1h, c1h;      // sin, cos of pi m / N_i      (half angle; shifted grid)
-  R sph, cph;      // sin, cos of pi m / (p L)    (half angle)
+constexpr int kModesPerLane = kAccTile / 64;
+constexpr int kTableGroup = 2;     // table pairs whose values are loaded together
+
+// Per-mode constants of the two kernel grids a unit's pairs use at mode m
+// (the output ring's own length N_i for equal-length pairs, the fine grid
+// p L for the others), computed once per tile.
+template <typename R> struct ModeConst {
+  R al_own, al_fine;    // 2 cos(2 pi m / G): Clenshaw's multiplier
+  R c1h;                // cos(pi m / N_i): the shifted own grid's factor
+  R lam_own, lam_fine;  // Reinsch's multiplier (-4 sin^2 or 4 cos^2 of pi m / G)
+  R sg_own, sg_fine;    // Reinsch's form: +1 near x = 1, -1 near x = -1
 };
 
 template <typename R>
-__device__ __forceinline__ ModeAngles<R> mode_angles(int m, int Ni, int pl, const cx_t<R>* __restrict__ tw, int TN) {
+__device__ __forceinline__ ModeConst<R> mode_const(int m, int Ni, int pl, const cx_t<R>* __restrict__ tw, int TN) {
   using C = cx_t<R>;
   const C h1 = half_angle<R>(m, Ni, tw, TN), hp = half_angle<R>(m, pl, tw, TN);
-  ModeAngles<R> a;
-  a.c1h = h1.x; a.s1h = h1.y;
-  a.cph = hp.x; a.sph = hp.y;
-  a.c1 = (h1.x - h1.y) * (h1.x + h1.y);  // cos 2t = (cos t - sin t)(cos t + sin t)
-  a.cp = (hp.x - hp.y) * (hp.x + hp.y);
-  return a;
+  ModeConst<R> k;
+  // cos 2t = (cos t - sin t)(cos t + sin t)
+  k.al_own = R(2) * (h1.x - h1.y) * (h1.x + h1.y);
+  k.al_fine = R(2) * (hp.x - hp.y) * (hp.x + hp.y);
+  k.c1h = h1.x;
+  const bool po = h1.x * h1.x >= R(0.5), pf = hp.x * hp.x >= R(0.5);
+  k.lam_own = po ? R(-4) * h1.y * h1.y : R(4) * h1.x * h1.x;
+  k.lam_fine = pf ? R(-4) * hp.y * hp.y : R(4) * hp.x * hp.x;
+  k.sg_own = po ? R(1) : R(-1);
+  k.sg_fine = pf ? R(1) : R(-1);
+  return k;
 }
-
-constexpr int kModesPerLane = kAccTile / 64;
-constexpr int kPrefetchCoef = 16;  // kernel samples of the next pair held in registers
 
 // A pair as staged in LDS for one work item.
 struct PairLds {
@@ -79,125 +85,129 @@ struct PairLds {
   uint32_t off;    // coefficient or table offset
 };
 
-__device__ __forceinline__ int pl_row(const PairLds& d) { return (int)(d.meta & 0xffffff); }
-__device__ __forceinline__ int pl_kind(const PairLds& d) { return (int)((d.meta >> 24) & 3); }
-__device__ __forceinline__ bool pl_own(const PairLds& d) { return (d.meta >> 26) & 1; }
+__device__ __forceinline__ int pl_row(uint32_t meta) { return (int)(meta & 0xffffff); }
+__device__ __forceinline__ int pl_kind(uint32_t meta) { return (int)((meta >> 24) & 3); }
+__device__ __forceinline__ bool pl_own(uint32_t meta) { return (meta >> 26) & 1; }
 
-// Loads the kernel samples of pair d that its evaluation needs first: the
-// top kPrefetchCoef samples of its row, or the row and what follows it for
-// rows of at most 8 (the sample array is padded so this stays in bounds).
-// All lanes read the same addresses; rows are zero-padded to whole chunks
-// of 8.
-template <typename R>
-__device__ __forceinline__ void prefetch_coef(const PairLds& d, const R* __restrict__ coef, R (&buf)[kPrefetchCoef]) {
-  const int n8 = (d.ncoef + 7) & ~7;
-  const R* cf = coef + d.off + max(n8 - kPrefetchCoef, 0);
-#pragma unroll
-  for (int t = 0; t < kPrefetchCoef; ++t) buf[t] = gload(cf + t);
+// A pair's descriptor with wave-uniform fields.
+struct PairU {
+  uint32_t meta;
+  int32_t band, ncoef;
+  uint32_t off;
+};
+
+__device__ __forceinline__ PairU uniform_pair(const PairLds& d) {
+  PairU p;
+  p.meta = __builtin_amdgcn_readfirstlane(d.meta);
+  p.band = __builtin_amdgcn_readfirstlane(d.band);
+  p.ncoef = __builtin_amdgcn_readfirstlane(d.ncoef);
+  p.off = __builtin_amdgcn_readfirstlane(d.off);
+  return p;
 }
 
-// One step of the Clenshaw recurrence b_d = 2x b_{d+1} - b_{d+2} + a_d for
-// every mode of the lane.
-template <typename R, int MPL>
-__device__ __forceinline__ void clenshaw_step(R c, const R (&al)[MPL], R (&b1)[MPL], R (&b2)[MPL]) {
-#pragma unroll
-  for (int e = 0; e < MPL; ++e) {
-    const R b0 = fma(al[e], b1[e], c - b2[e]);
-    b2[e] = b1[e];
-    b1[e] = b0;
-  }
-}
-
-// One step of Reinsch's modified recurrence (stable near x = +-1) in the form
-// sigma = +1 (x > 0) or -1 (x < 0).
-template <typename R, int MPL>
-__device__ __forceinline__ void reinsch_step(R c, const R (&lam)[MPL], const R (&sg)[MPL], R (&b)[MPL],
-                                             R (&dd)[MPL]) {
-#pragma unroll
-  for (int e = 0; e < MPL; ++e) {
-    dd[e] = fma(lam[e], b[e], fma(sg[e], dd[e], c));
-    b[e] = fma(sg[e], b[e], dd[e]);
-  }
-}
-
-// Runs STEP over the kernel samples of a row of n8 (a multiple of 8)
-// samples from the top down: the top 16 (or 8) from the prefetched
-// registers, the rest from memory in chunks of 8, each loaded one chunk
-// ahead.
+// Runs STEP over a row of n8 (a multiple of 8) kernel samples from the top
+// down, in chunks of 8 read with wave-uniform (scalar) loads.
 template <typename R, typename STEP>
-__device__ __forceinline__ void recur_row(int n8, const R* __restrict__ cf, const R (&buf)[kPrefetchCoef], STEP step) {
-  if (n8 <= 8) {
-#pragma unroll
-    for (int t = 7; t >= 0; --t) step(buf[t]);
-    return;
-  }
-  R nx[8];
-  if (n8 > 16) {
-#pragma unroll
-    for (int t = 0; t < 8; ++t) nx[t] = gload(cf + n8 - 24 + t);
-  }
-#pragma unroll
-  for (int t = 15; t >= 0; --t) step(buf[t]);
-  for (int c = n8 - 24; c >= 0; c -= 8) {
+__device__ __forceinline__ void recur_row(int n8, const R* __restrict__ cf, STEP step) {
+  for (int c = n8 - 8; c >= 0; c -= 8) {
     R cc[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) cc[t] = nx[t];
-    if (c >= 8) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) nx[t] = gload(cf + c - 8 + t);
-    }
+    for (int t = 0; t < 8; ++t) cc[t] = cf[c + t];
 #pragma unroll
     for (int t = 7; t >= 0; --t) step(cc[t]);
   }
 }
 
-// K_ij(m) of an on-the-fly pair d at this lane's modes m[e] (step b), from
-// the prefetched registers and, for long rows, the rest of the row.
-template <typename R, int MPL>
-__device__ __forceinline__ void pair_k(const PairLds& d, const R* __restrict__ coef, const R (&buf)[kPrefetchCoef],
-                                       const ModeAngles<R> (&A)[MPL], const int (&m)[MPL], int ny_own, int ny_fine,
-                                       R (&k)[MPL]) {
-  const int kind = pl_kind(d);
-  const bool own = pl_own(d);
-  const int ny = own ? ny_own : ny_fine;
-  const int n8 = (d.ncoef + 7) & ~7;
-  const R* cf = coef + d.off;
-  if (kind == KG_REINSCH) {
-    R lam[MPL], sg[MPL], b[MPL], dd[MPL];
-#pragma unroll
-    for (int e = 0; e < MPL; ++e) {
-      const R sh = own ? A[e].s1h : A[e].sph, ch = own ? A[e].c1h : A[e].cph;
-      const bool pos = ch * ch >= R(0.5);
-      lam[e] = pos ? R(-4) * sh * sh : R(4) * ch * ch;
-      sg[e] = pos ? R(1) : R(-1);
-      b[e] = R(0);
-      dd[e] = R(0);
-    }
-    recur_row<R>(n8, cf, buf, [&](R c) { reinsch_step<R, MPL>(c, lam, sg, b, dd); });
-#pragma unroll
-    for (int e = 0; e < MPL; ++e) k[e] = dd[e] - sg[e] * R(0.5) * lam[e] * (b[e] - dd[e]);
-  } else {
-    R al[MPL], b1[MPL], b2[MPL];
-#pragma unroll
-    for (int e = 0; e < MPL; ++e) {
-      al[e] = R(2) * (own ? A[e].c1 : A[e].cp);
-      b1[e] = R(0);
-      b2[e] = R(0);
-    }
-    recur_row<R>(n8, cf, buf, [&](R c) { clenshaw_step<R, MPL>(c, al, b1, b2); });
-#pragma unroll
-    for (int e = 0; e < MPL; ++e)
-      k[e] = kind == KG_SHIFTED ? (b1[e] - b2[e]) * A[e].c1h : b1[e] - b2[e] * (R(0.5) * al[e]);
-  }
+template <typename R, int MPL, bool OWN>
+__device__ __forceinline__ void clenshaw_row(int n8, const R* __restrict__ cf, const ModeConst<R> (&A)[MPL],
+                                             R (&b1)[MPL], R (&b2)[MPL]) {
 #pragma unroll
   for (int e = 0; e < MPL; ++e) {
-    if (m[e] == ny) k[e] *= R(0.5);
-    if (m[e] > d.band) k[e] = R(0);
+    b1[e] = R(0);
+    b2[e] = R(0);
+  }
+  recur_row<R>(n8, cf, [&](R c) {
+#pragma unroll
+    for (int e = 0; e < MPL; ++e) {
+      const R b0 = fma(OWN ? A[e].al_own : A[e].al_fine, b1[e], c - b2[e]);
+      b2[e] = b1[e];
+      b1[e] = b0;
+    }
+  });
+}
+
+template <typename R, int MPL, bool OWN>
+__device__ __forceinline__ void reinsch_row(int n8, const R* __restrict__ cf, const ModeConst<R> (&A)[MPL],
+                                            R (&k)[MPL]) {
+  R b[MPL], dd[MPL];
+#pragma unroll
+  for (int e = 0; e < MPL; ++e) {
+    b[e] = R(0);
+    dd[e] = R(0);
+  }
+  recur_row<R>(n8, cf, [&](R c) {
+#pragma unroll
+    for (int e = 0; e < MPL; ++e) {
+      const R lam = OWN ? A[e].lam_own : A[e].lam_fine, sg = OWN ? A[e].sg_own : A[e].sg_fine;
+      dd[e] = fma(lam, b[e], fma(sg, dd[e], c));
+      b[e] = fma(sg, b[e], dd[e]);
+    }
+  });
+#pragma unroll
+  for (int e = 0; e < MPL; ++e) {
+    const R lam = OWN ? A[e].lam_own : A[e].lam_fine, sg = OWN ? A[e].sg_own : A[e].sg_fine;
+    k[e] = dd[e] - sg * R(0.5) * lam * (b[e] - dd[e]);
   }
 }
 
-template <typename R> struct AccLds { static constexpr int kRings = 22; };
-template <> struct AccLds<double> { static constexpr int kRings = 11; };
+// K_ij(m) of an on-the-fly pair d at this lane's modes m0 + lane + 64 e
+// (step b): Clenshaw's recurrence for rows of up to kClenshawMaxCoef samples,
+// Reinsch's modified form for longer rows; every branch is wave-uniform.
+template <typename R, int MPL>
+__device__ __forceinline__ void pair_k(const PairU& d, const R* __restrict__ coef, const ModeConst<R> (&A)[MPL],
+                                       int m0, int lane, int ny_own, int ny_fine, R (&k)[MPL]) {
+  const int kind = pl_kind(d.meta);
+  const bool own = pl_own(d.meta);
+  const int n8 = (d.ncoef + 7) & ~7;
+  const R* cf = coef + d.off;
+  if (kind == KG_REINSCH) {
+    if (own) reinsch_row<R, MPL, true>(n8, cf, A, k);
+    else reinsch_row<R, MPL, false>(n8, cf, A, k);
+  } else {
+    // (a shifted grid is always the output ring's own; with p = 1 the own
+    // grid of an equatorial ring is also the fine grid, so `own` may be
+    // false for it, with the same angles)
+    R b1[MPL], b2[MPL];
+    if (kind == KG_SHIFTED) {
+      clenshaw_row<R, MPL, true>(n8, cf, A, b1, b2);
+#pragma unroll
+      for (int e = 0; e < MPL; ++e) k[e] = (b1[e] - b2[e]) * A[e].c1h;
+    } else if (own) {
+      clenshaw_row<R, MPL, true>(n8, cf, A, b1, b2);
+#pragma unroll
+      for (int e = 0; e < MPL; ++e) k[e] = b1[e] - b2[e] * (R(0.5) * A[e].al_own);
+    } else {
+      clenshaw_row<R, MPL, false>(n8, cf, A, b1, b2);
+#pragma unroll
+      for (int e = 0; e < MPL; ++e) k[e] = b1[e] - b2[e] * (R(0.5) * A[e].al_fine);
+    }
+  }
+  // half weight at the grid's Nyquist mode, nothing beyond the pair's band
+  const int ny = own ? ny_own : ny_fine;
+  if (ny >= m0 && ny < m0 + 64 * MPL) {
+#pragma unroll
+    for (int e = 0; e < MPL; ++e)
+      if (m0 + 64 * e + lane == ny) k[e] *= R(0.5);
+  }
+  if (d.band < m0 + 64 * MPL - 1) {
+#pragma unroll
+    for (int e = 0; e < MPL; ++e)
+      if (m0 + 64 * e + lane > d.band) k[e] = R(0);
+  }
+}
+
+template <typename R> struct AccLds { static constexpr int kRings = 8; };
+template <> struct AccLds<double> { static constexpr int kRings = 4; };
 
 // Spectrum row of one staged input ring: offset and length in the workspace.
 struct RowRef {
@@ -211,8 +221,6 @@ struct AccLayout {
   int32_t rows_off, pairs_off;
 };
 
-constexpr int kTableGroup = 8;  // table pairs whose values are loaded together
-
 // One work item: the units of band bd (one wavefront each) over the tiles
 // [t0, t0 + nt) of kAccTile modes; lane l holds modes m0 + l + 64 e.  The
 // band's pair descriptors are staged into LDS once, each unit's list split
@@ -221,9 +229,9 @@ constexpr int kTableGroup = 8;  // table pairs whose values are loaded together
 // mirror per row pair), the spectra of the next (tile, chunk) stage loaded
 // into registers while the current stage is accumulated.  Per stage a wave
 // first streams its table pairs, kTableGroup at a time with all their loads
-// issued together, then evaluates its on-the-fly pairs with the next pair's
-// kernel samples in flight.  Every wave of the block must call this; it
-// synchronises the block.
+// issued together, then evaluates its on-the-fly pairs, the next pair's
+// kernel samples loaded while the current one is evaluated.  Every wave of
+// the block must call this; it synchronises the block.
 template <typename R, int NW>
 __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandDev& bd, const int t0, const int nt,
                                                 const cx_t<R>* __restrict__ spec, cx_t<R>* __restrict__ bout,
@@ -238,7 +246,12 @@ __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandD
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int win = max(bd.jhi - bd.jlo + 1, 0);
-  const int nch = max((win + CH - 1) / CH, 1);
+  // chunks are fixed ranges of CH input rings [cbase + c CH, cbase + (c + 1) CH),
+  // the same for every band layout, so that the order of the sum over a
+  // unit's pairs (by chunk, then tables before the rest, each by ring) does
+  // not depend on how units are grouped into bands
+  const int cbase = win > 0 ? bd.jlo / CH * CH : 0;
+  const int nch = win > 0 ? (bd.jhi + 1 - cbase + CH - 1) / CH : 1;
   const int pl = a.p * a.L;
   for (int r = threadIdx.x; r < 2 * win; r += NW * 64) {
     int j = bd.jlo + (r >> 1);
@@ -261,14 +274,12 @@ __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandD
   // this unit's descriptors: table pairs first, then the others, each in order
   int ntab = 0;
   {
-    int nt_seen = 0;
     for (int b = 0; b < npair; b += 64) {
       const int q = b + lane;
-      const bool valid = q < npair;
-      const bool tab = valid && gload(&a.pairs[u.pbeg + q].kind) == KG_TABLE;
-      const uint64_t tm = __ballot(tab);
-      ntab += __popcll(tm);
+      const bool tab = q < npair && gload(&a.pairs[u.pbeg + q].kind) == KG_TABLE;
+      ntab += __popcll(__ballot(tab));
     }
+    int nt_seen = 0;
     for (int b = 0; b < npair; b += 64) {
       const int q = b + lane;
       const bool valid = q < npair;
@@ -307,14 +318,15 @@ __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandD
   auto issue = [&](int s) {
     const int t = s / nch, c = s - t * nch;
     const int m = (t0 + t) * kAccTile + lane;
-    const int cs = c * CH, nrow = 2 * (min(win, cs + CH) - cs);
+    const int cs = cbase + c * CH;
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
       const int r = w + NW * k;
+      const int j = cs + (r >> 1);
 #pragma unroll
       for (int e = 0; e < MPL; ++e) pre[k][e] = cmake<C>(R(0), R(0));
-      if (r < nrow) {
-        const RowRef rr = rows[2 * cs + r];
+      if (r < 2 * CH && j >= bd.jlo && j <= bd.jhi) {
+        const RowRef rr = rows[2 * (j - bd.jlo) + (r & 1)];
 #pragma unroll
         for (int e = 0; e < MPL; ++e)
           if (m + 64 * e < rr.len) pre[k][e] = gload(spec + rr.off + m + 64 * e);
@@ -323,54 +335,34 @@ __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandD
   };
   issue(0);
   C acc0[MPL], acc1[MPL];
-  ModeAngles<R> ang[MPL];
-  int mm[MPL];
-  int qt = 0, qo = 0, phase = 0;
-  PairLds dA{}, dB{};
-  R bA[kPrefetchCoef], bB[kPrefetchCoef];
-  int m0 = 0, c0 = 0, c1 = 0;
+  ModeConst<R> mc[MPL];
+  int qt = 0, qo = 0;
+  PairU cur{};
+  int m0 = 0, c0 = 0, c1 = 0;  // c0, c1: the staged chunk's rings, relative to jlo
   auto accumulate_pair = [&](int row, const R (&k)[MPL]) {
+    const C* s0 = sa + row * kAccTile + lane;
 #pragma unroll
     for (int e = 0; e < MPL; ++e) {
-      const C s0 = sa[row * kAccTile + 64 * e + lane];
-      acc0[e] = cmake<C>(fma(k[e], s0.x, acc0[e].x), fma(k[e], s0.y, acc0[e].y));
+      const C v = s0[64 * e];
+      acc0[e] = cmake<C>(fma(k[e], v.x, acc0[e].x), fma(k[e], v.y, acc0[e].y));
     }
     if (mirror) {
 #pragma unroll
       for (int e = 0; e < MPL; ++e) {
-        const C s1 = sa[(row + 1) * kAccTile + 64 * e + lane];
-        acc1[e] = cmake<C>(fma(k[e], s1.x, acc1[e].x), fma(k[e], s1.y, acc1[e].y));
+        const C v = s0[kAccTile + 64 * e];
+        acc1[e] = cmake<C>(fma(k[e], v.x, acc1[e].x), fma(k[e], v.y, acc1[e].y));
       }
     }
-  };
-  // evaluates the current on-the-fly pair (cur, cb) and prefetches the next
-  // one into (nx, nb); false at the end of the list or of the staged chunk
-  auto step = [&](const PairLds& cur, const R (&cb)[kPrefetchCoef], PairLds& nx, R (&nb)[kPrefetchCoef]) {
-    if (qo >= npair || pl_row(cur) >= c1) return false;
-    if (qo + 1 < npair) {
-      nx = mine[qo + 1];
-      nx.meta = __builtin_amdgcn_readfirstlane(nx.meta);
-      nx.ncoef = __builtin_amdgcn_readfirstlane(nx.ncoef);
-      nx.band = __builtin_amdgcn_readfirstlane(nx.band);
-      prefetch_coef<R>(nx, a.coef, nb);
-    }
-    if (m0 <= cur.band) {
-      R k[MPL];
-      pair_k<R, MPL>(cur, a.coef, cb, ang, mm, ny_own, ny_fine, k);
-      accumulate_pair(2 * (pl_row(cur) - c0), k);
-    }
-    ++qo;
-    return true;
   };
   for (int s = 0; s < nst; ++s) {
     const int t = s / nch, c = s - t * nch;
     m0 = (t0 + t) * kAccTile;
-    c0 = c * CH;
-    c1 = min(win, c0 + CH);
+    c0 = cbase + c * CH - bd.jlo;
+    c1 = c0 + CH;
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
       const int r = w + NW * k;
-      if (r < 2 * (c1 - c0)) {
+      if (r < 2 * CH) {
 #pragma unroll
         for (int e = 0; e < MPL; ++e) sa[r * kAccTile + 64 * e + lane] = pre[k][e];
       }
@@ -383,12 +375,11 @@ __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandD
       for (int e = 0; e < MPL; ++e) {
         acc0[e] = cmake<C>(R(0), R(0));
         acc1[e] = acc0[e];
-        mm[e] = m0 + 64 * e + lane;
-        if (busy) ang[e] = mode_angles<R>(mm[e], Ni, pl, a.tw, a.TN);
+        if (busy) mc[e] = mode_const<R>(m0 + 64 * e + lane, Ni, pl, a.tw, a.TN);
       }
       qt = 0;
       qo = ntab;
-      phase = 0;
+      if (busy && qo < npair) cur = uniform_pair(mine[qo]);
     }
     if (busy) {
       // table pairs of this chunk, kTableGroup at a time
@@ -398,15 +389,17 @@ __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandD
         int g = 0;
 #pragma unroll
         for (int x = 0; x < kTableGroup; ++x) {
-          rw[x] = -1;
+          rw[x] = 0;
           if (qt + x < ntab && g == x) {
-            PairLds d = mine[qt + x];
-            d.meta = __builtin_amdgcn_readfirstlane(d.meta);
-            if (pl_row(d) < c1) {
-              rw[x] = 2 * (pl_row(d) - c0);
+            const PairU d = uniform_pair(mine[qt + x]);
+            if (pl_row(d.meta) < c1) {
+              rw[x] = 2 * (pl_row(d.meta) - c0);
               g = x + 1;
 #pragma unroll
-              for (int e = 0; e < MPL; ++e) kv[x][e] = mm[e] <= d.band ? gload(a.table + d.off + mm[e]) : R(0);
+              for (int e = 0; e < MPL; ++e) {
+                const int m = m0 + 64 * e + lane;
+                kv[x][e] = m <= d.band ? gload(a.table + d.off + m) : R(0);
+              }
             }
           }
         }
@@ -417,34 +410,27 @@ __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandD
         qt += g;
       }
       // on-the-fly pairs of this chunk
-      if (qo < npair && phase == 0 && (c == 0 || qo == ntab)) {
-        dA = mine[qo];
-        dA.meta = __builtin_amdgcn_readfirstlane(dA.meta);
-        dA.ncoef = __builtin_amdgcn_readfirstlane(dA.ncoef);
-        dA.band = __builtin_amdgcn_readfirstlane(dA.band);
-        prefetch_coef<R>(dA, a.coef, bA);
-      }
-      // the two prefetch buffers alternate; each call site names its own
-      // buffers so that they stay in registers
-      bool more = true;
-      if (phase == 1) {
-        more = step(dB, bB, dA, bA);
-        if (more) phase = 0;
-      }
-      while (more) {
-        if (!step(dA, bA, dB, bB)) break;
-        if (!step(dB, bB, dA, bA)) {
-          phase = 1;
-          break;
+      while (qo < npair && pl_row(cur.meta) < c1) {
+        const PairU d = cur;
+        if (qo + 1 < npair) cur = uniform_pair(mine[qo + 1]);
+        if (m0 <= d.band) {
+          R k[MPL];
+          pair_k<R, MPL>(d, a.coef, mc, m0, lane, ny_own, ny_fine, k);
+          accumulate_pair(2 * (pl_row(d.meta) - c0), k);
         }
+        ++qo;
       }
       if (c == nch - 1) {
+        const int64_t o0 = gload(a.out_off + u.i);
+        const int64_t o1 = mirror ? gload(a.out_off + u.im) : 0;
 #pragma unroll
-        for (int e = 0; e < MPL; ++e)
-          if (mm[e] <= u.band) {
-            gstore(bout + gload(a.out_off + u.i) + mm[e], acc0[e]);
-            if (mirror) gstore(bout + gload(a.out_off + u.im) + mm[e], acc1[e]);
+        for (int e = 0; e < MPL; ++e) {
+          const int m = m0 + 64 * e + lane;
+          if (m <= u.band) {
+            gstore(bout + o0 + m, acc0[e]);
+            if (mirror) gstore(bout + o1 + m, acc1[e]);
           }
+        }
       }
     }
     __syncthreads();
@@ -516,15 +502,15 @@ void fill_acc_args(arkcos_plan_s* P, const BandDev* bands, void* out) {
 }
 
 // LDS of one accumulation block: the staged spectra (2 CH rows of kAccTile
-// complex values, CH = min(window, kRings)), the row table of the whole
-// window, the band's pair descriptors.
+// complex values), the row table of the whole window, the band's pair
+// descriptors.
 static AccLayout acc_layout(arkcos_dtype_t dt, const AccShape& sh) {
   const int32_t win = std::max(sh.max_window, 1);
   size_t tile;
   if (dt == ARKCOS_F32)
-    tile = 2 * (size_t)std::min<int32_t>(win, AccLds<float>::kRings) * kAccTile * sizeof(float2);
+    tile = 2 * (size_t)AccLds<float>::kRings * kAccTile * sizeof(float2);
   else
-    tile = 2 * (size_t)std::min<int32_t>(win, AccLds<double>::kRings) * kAccTile * sizeof(double2);
+    tile = 2 * (size_t)AccLds<double>::kRings * kAccTile * sizeof(double2);
   AccLayout l;
   l.rows_off = (int32_t)tile;
   l.pairs_off = (int32_t)(tile + 2 * (size_t)win * sizeof(RowRef));
@@ -582,12 +568,13 @@ hipError_t launch_accumulate(arkcos_plan_s* P, const void* spec, void* bout, hip
   if (P->h_items.empty()) return hipSuccess;
   const size_t lds = acc_lds_bytes(P->dtype, P->acc_shape);
   const AccLayout lay = acc_layout(P->dtype, P->acc_shape);
+  const unsigned grid = (unsigned)P->h_items.size();
   if (P->dtype == ARKCOS_F32)
-    accumulate_kernel<float><<<(unsigned)P->h_items.size(), kAccThreads, lds, s>>>(
-        make_acc_args<float>(P, P->d_bands), (const float2*)spec, (float2*)bout, lay);
+    accumulate_kernel<float><<<grid, kAccThreads, lds, s>>>(make_acc_args<float>(P, P->d_bands),
+                                                            (const float2*)spec, (float2*)bout, lay);
   else
-    accumulate_kernel<double><<<(unsigned)P->h_items.size(), kAccThreads, lds, s>>>(
-        make_acc_args<double>(P, P->d_bands), (const double2*)spec, (double2*)bout, lay);
+    accumulate_kernel<double><<<grid, kAccThreads, lds, s>>>(make_acc_args<double>(P, P->d_bands),
+                                                             (const double2*)spec, (double2*)bout, lay);
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ constexpr int kDirectMax = 64;         // rings up to this length use a plain DF
 constexpr int kOtfMaxCoef = 48;        // wider kernel rows use a K_ij(m) table (auto mode)
 constexpr int kClenshawMaxCoef = 16;   // longer centred rows use Reinsch's recurrence
 constexpr int kBandUnits = 8;          // output units (ring + mirror) per accumulation work item
-constexpr int kAccTile = 128;          // modes per accumulation tile (two per lane)
+constexpr int kAccTile = 256;          // modes per accumulation tile (four per lane)
 constexpr int kAccThreads = 64 * kBandUnits;  // one wavefront per unit
 
 // FFT strategy of one ring length.
@@ -78,7 +78,7 @@ struct BatchItem {
   int32_t map, band, t0, nt;
 };
 
-constexpr int kTilesPerItem = 8;     // mode tiles per accumulation work item
+constexpr int kTilesPerItem = 4;     // mode tiles per accumulation work item
 
 // A band of up to kBandUnits consecutive units: the input rings they need.
 struct BandDev {

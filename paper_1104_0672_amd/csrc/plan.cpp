@@ -12,6 +12,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 
@@ -184,8 +186,9 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
   if (!first_time && table_total != P->table_total)
     return fail(ARKCOS_ERR_INTERNAL, "table layout changed on knot update");
   // the accumulation addresses samples and tables with 32-bit offsets
-  if (table_total >= (int64_t(1) << 32) || P->coef_total >= (int64_t(1) << 32))
-    return fail(ARKCOS_ERR_NOT_SUPPORTED, "kernel samples or tables beyond 2^32 elements");
+  if (table_total >= (int64_t(1) << 32) ||
+      (P->coef_total + 16) * (int64_t)(P->dtype == ARKCOS_F32 ? 4 : 8) >= (int64_t(1) << 31))
+    return fail(ARKCOS_ERR_NOT_SUPPORTED, "kernel samples beyond 2 GiB or tables beyond 2^32 elements");
   P->n_table_pairs = ntab;
   P->table_total = table_total;
   const size_t rsz = P->dtype == ARKCOS_F32 ? sizeof(float) : sizeof(double);
@@ -566,6 +569,19 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
     arkcos_status_t st = build_kernel_tables(P, true);
     if (st != ARKCOS_OK) return st;
   }
+  if (const char* e = getenv("ARKCOS_PLAN_STATS"); e && *e == '1') {
+    // (pair, mode) products per kernel-generation kind and row length
+    std::map<std::pair<int, int>, int64_t> h;
+    for (int64_t q = 0; q < P->n_pairs; ++q) {
+      const PairDev& pr = P->h_pairs[q];
+      if (pr.band < 0) continue;
+      const int row = pr.kind == KG_TABLE ? 0 : (pr.ncoef + 7) / 8 * 8;
+      h[{pr.kind, row}] += (int64_t)(pr.band + 1);
+    }
+    for (auto& kv : h)
+      fprintf(stderr, "arkcos plan: kind %d row %d: %lld unit-pair modes\n", kv.first.first, kv.first.second,
+              (long long)kv.second);
+  }
 
   // ----------------------------------------- spectra / output layout
   P->h_spec_len.assign(nr, 0);
@@ -609,6 +625,7 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
     std::vector<WorkItem> its;
     std::vector<double> cost;
     accumulation_items(P, P->h_bands, its, cost);
+    // heaviest first, so that the launch does not end on a long item
     std::vector<size_t> ord(its.size());
     for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
     std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });

@@ -310,7 +310,7 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
     for (int32_t i = 0; i < n; ++i) {
       arkcos_plan_s* P = B->plans[i];
       for (int64_t k = 0; k < P->nrings; ++k) {
-        int32_t b = 4096;
+        int32_t b = 32768;  // small rings of every map share one launch
         while (b < P->h_ring_lds[k]) b <<= 1;
         cls[b].push_back(make_int2(i, (int)k));
       }

@@ -454,15 +454,20 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   P->h_fft_len = fft_m;
   for (int64_t k = 0; k < nr; ++k) P->h_ring_lds[k] = (int32_t)((ring_lds[k] + 15) / 16 * 16);
   {
-    // launch classes by LDS size (power-of-two buckets from 4 KiB); a ring
-    // and its mirror stay adjacent so they share cached filters
+    // launch classes by LDS size: power-of-two buckets from 32 KiB, so that
+    // the many small rings share one launch; within a class the longest
+    // rings come first, and a ring and its mirror stay adjacent so they
+    // share cached filters
     std::map<size_t, std::vector<int32_t>> cls;
+    std::vector<int64_t> order((nr + 1) / 2);
+    for (int64_t k = 0; k < (int64_t)order.size(); ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return P->h_n[x] > P->h_n[y]; });
     auto bucket = [&](int64_t k) {
-      size_t b = 4096;
+      size_t b = 32768;
       while (b < ring_lds[k]) b <<= 1;
       cls[b].push_back((int32_t)k);
     };
-    for (int64_t k = 0; k < (nr + 1) / 2; ++k) {
+    for (int64_t k : order) {
       bucket(k);
       if (nr - 1 - k != k) bucket(nr - 1 - k);
     }

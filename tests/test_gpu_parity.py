@@ -118,6 +118,22 @@ def test_healpix_fp32_small(nside):
     assert _frac(y, ref_d) <= 1e-4
 
 
+def test_healpix_fp32_wide_beam_oversample_one():
+    """A beam of five pixels: the automatic kernel grid is the paper's
+    (oversample 1), where an equatorial ring's own grid is also the fine
+    grid."""
+    w = W.scaled_healpix(32, fwhm_arcmin=5.0 * 60 * math.degrees(math.sqrt(math.pi / 3) / 32),
+                         radius_fwhm=3.0, seed=77)
+    _say(f"case {w.name} f32 wide beam")
+    x = W.make_input(w)
+    plan, y = _run(w, x)
+    assert plan.info.oversample == 1
+    ref_m = oracle.hybrid(w.grid, w.profile, w.radius, x, oversample=1)
+    ref_d = oracle.direct(w.grid, w.profile, w.radius, x)
+    assert _frac(y, ref_m) <= 1e-5
+    assert _frac(y, ref_d) <= 1e-4
+
+
 def test_healpix256_30arcmin_full_map():
     w = W.healpix256()
     _say(f"case {w.name}")

@@ -48,33 +48,60 @@ __device__ __forceinline__ double pixel_distance(const PoleArgs& P, int ia, int 
   return 2.0 * asin(r < 1.0 ? r : 1.0);
 }
 
-// Forward: one block per pole pixel (blockIdx.x < 8); `rings` lists the
-// rings within R of either pole ring.
+// The direct sum for pole pixel b (0..3: first ring, 4..7: last ring) with
+// the whole block; `rings` lists the rings within R of either pole ring.
+// The rings of the list (kPoleRings at a time) and their pixel counts are
+// staged in LDS, so the candidate pixels of all rings are spread over the
+// threads at once.  Returns the block's sum on every thread.
+constexpr int kPoleRings = 256;
+
 template <typename R>
-__global__ void __launch_bounds__(kBlock) pole_forward_kernel(PoleArgs P, const int32_t* __restrict__ rings,
-                                                              int32_t nlist, const R* __restrict__ x,
-                                                              R* __restrict__ y) {
-  const int b = blockIdx.x;
+__device__ double pole_pixel_sum(const PoleArgs& P, const int32_t* __restrict__ rings, int nlist, int b,
+                                 const R* __restrict__ x) {
+  __shared__ int32_t rj[kPoleRings], rfirst[kPoleRings + 1];
+  __shared__ double red[kBlock];
   const int ip = b < 4 ? 0 : P.nrings - 1, kp = b & 3;
   double acc = 0.0;
-  for (int t = 0; t < nlist; ++t) {
-    const int j = rings[t];
-    if (fabs(P.theta[j] - P.theta[ip]) > P.radius) continue;
-    const int nj = P.n[j];
-    const double wj = P.w[j];
-    for (int k = threadIdx.x; k < nj; k += blockDim.x) {
-      double t = pixel_distance(P, ip, kp, j, k);
-      acc += pole_profile(P, t) * wj * (double)x[P.start[j] + k];
+  for (int l0 = 0; l0 < nlist; l0 += kPoleRings) {
+    const int cnt = min(kPoleRings, nlist - l0);
+    // pixel counts of the rings in reach (0 for the others), then their prefix sums
+    if (threadIdx.x < cnt) {
+      const int j = rings[l0 + threadIdx.x];
+      rj[threadIdx.x] = j;
+      rfirst[threadIdx.x + 1] = fabs(P.theta[j] - P.theta[ip]) > P.radius ? 0 : P.n[j];
     }
+    if (threadIdx.x == 0) rfirst[0] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int t = 0; t < cnt; ++t) rfirst[t + 1] += rfirst[t];
+    __syncthreads();
+    const int total = rfirst[cnt];
+    int t = 0;
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+      while (rfirst[t + 1] <= q) ++t;
+      const int j = rj[t], k = q - rfirst[t];
+      const double d = pixel_distance(P, ip, kp, j, k);
+      acc += pole_profile(P, d) * P.w[j] * (double)x[P.start[j] + k];
+    }
+    __syncthreads();
   }
-  __shared__ double red[kBlock];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int st = kBlock / 2; st > 0; st >>= 1) {
     if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) y[P.start[ip] + kp] = (R)red[0];
+  return red[0];
+}
+
+// Forward: one block per pole pixel (blockIdx.x < 8).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) pole_forward_kernel(PoleArgs P, const int32_t* __restrict__ rings,
+                                                              int32_t nlist, const R* __restrict__ x,
+                                                              R* __restrict__ y) {
+  const int b = blockIdx.x;
+  const double v = pole_pixel_sum<R>(P, rings, nlist, b, x);
+  if (threadIdx.x == 0) y[P.start[b < 4 ? 0 : P.nrings - 1] + (b & 3)] = (R)v;
 }
 
 // Transpose: one block per ring j within the support of either pole ring.
@@ -156,24 +183,8 @@ __global__ void __launch_bounds__(kBlock) pole_batch_kernel(const PoleMap* __res
   R* y = ys[e.x];
   if (!adjoint) {
     const int b = e.y;
-    const int ip = b < 4 ? 0 : P.nrings - 1, kp = b & 3;
-    double acc = 0.0;
-    for (int t = 0; t < pm.nlist; ++t) {
-      const int j = pm.rings[t];
-      if (fabs(P.theta[j] - P.theta[ip]) > P.radius) continue;
-      const int nj = P.n[j];
-      const double wj = P.w[j];
-      for (int k = threadIdx.x; k < nj; k += blockDim.x)
-        acc += pole_profile(P, pixel_distance(P, ip, kp, j, k)) * wj * (double)x[P.start[j] + k];
-    }
-    __shared__ double red[kBlock];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int st = kBlock / 2; st > 0; st >>= 1) {
-      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) y[P.start[ip] + kp] = (R)red[0];
+    const double v = pole_pixel_sum<R>(P, pm.rings, pm.nlist, b, x);
+    if (threadIdx.x == 0) y[P.start[b < 4 ? 0 : P.nrings - 1] + (b & 3)] = (R)v;
   } else {
     const int j = pm.rings[e.y];
     const int nj = P.n[j];

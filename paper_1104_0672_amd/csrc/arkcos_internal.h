@@ -103,6 +103,7 @@ struct FftClass {
   int32_t count = 0;
   int32_t lds = 0;
   int32_t threads = 256;  // block size: 512 when an FFT is longer than 4096 points
+  int32_t mf = 0;         // the FFT length of every ring of the class, if they share one
 };
 
 }  // namespace arkcos

@@ -245,15 +245,86 @@ __device__ void lds_fft(cx_t<R>* buf, int M, const cx_t<R>* __restrict__ tw, int
   if (n16 > 2) stockham_pass<R, INV, 16, 1, NT>(buf, M, (1 << rest) << 8, w2);
 }
 
+// ---------------------------------------------------------------------------
+// The same FFT for a length M known at compile time (the long rings: M =
+// 16 NT, one radix-16 butterfly per thread and pass).  All LDS addresses of a
+// butterfly are its base address plus compile-time offsets: the reads
+// j + r Q of a pass sit r (Q + Q/32) slots apart (Q a multiple of 32), and
+// the writes o + r Ns (o = (j - j mod Ns) RAD + j mod Ns) a constant distance
+// out_gap(r) apart for the Ns that occur (1, 2, 16 and multiples of 32).
+// ---------------------------------------------------------------------------
+template <int NS, int RAD> __device__ __forceinline__ constexpr int out_gap(int r) {
+  static_assert(NS * RAD <= 32 || NS == 16 || NS % 32 == 0, "pass shape");
+  if constexpr (NS % 32 == 0) return r * (NS + NS / 32);
+  else if constexpr (NS * RAD <= 32) return r * NS;  // the butterfly's outputs share one 32-slot row
+  else return 16 * r + (r >> 1);                      // NS = 16: o mod 32 < 16
+}
+
+template <typename R, bool INV, int RAD, int NT, int M, int NS>
+__device__ __forceinline__ void stockham_ct(cx_t<R>* buf, cx_t<R> w) {
+  using C = cx_t<R>;
+  constexpr int Q = M / RAD;
+  constexpr int MAXB = Q / NT;
+  static_assert(Q % NT == 0 && Q % 32 == 0 && NT % 32 == 0, "pass shape");
+  constexpr int RG = Q + Q / 32;
+  C v[MAXB][RAD];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const C* src = buf + lidx(threadIdx.x + b * NT);
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[b][r] = src[r * RG];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = threadIdx.x + b * NT;
+    const int k = j & (NS - 1);
+    if constexpr (NS > 1) {
+      C p[RAD];
+      twiddle_powers<C, RAD>(INV ? cconj(w) : w, p);
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) v[b][r] = cmul(v[b][r], p[r]);
+    }
+    dft_reg<C, INV, RAD>(v[b]);
+    C* dst = buf + lidx((j - k) * RAD + k);
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) dst[out_gap<NS, RAD>(r)] = v[b][r];
+  }
+  __syncthreads();
+}
+
+template <int M> struct Log2 { static constexpr int value = 1 + Log2<M / 2>::value; };
+template <> struct Log2<1> { static constexpr int value = 0; };
+
+template <typename R, bool INV, int NT, int M>
+__device__ __forceinline__ void lds_fft_ct(cx_t<R>* buf, const cx_t<R>* __restrict__ tw, int TN) {
+  using C = cx_t<R>;
+  constexpr int LG = Log2<M>::value, REST = LG & 3, N16 = LG >> 2;
+  static_assert(M == 16 * NT && N16 <= 3 && N16 >= 1, "length");
+  constexpr int NS0 = 1 << REST, NS1 = NS0 << 4, NS2 = NS0 << 8;
+  const int j = threadIdx.x;
+  auto tw_at = [&](int ns) {
+    return ns > 1 ? tw[(j & (ns - 1)) * (TN / (ns * 16))] : cmake<C>(R(1), R(0));
+  };
+  const C w0 = tw_at(NS0), w1 = tw_at(NS1), w2 = N16 > 2 ? tw_at(NS2) : cmake<C>(R(1), R(0));
+  if constexpr (REST == 1) stockham_ct<R, INV, 2, NT, M, 1>(buf, w0);
+  else if constexpr (REST == 2) stockham_ct<R, INV, 4, NT, M, 1>(buf, w0);
+  else if constexpr (REST == 3) stockham_ct<R, INV, 8, NT, M, 1>(buf, w0);
+  stockham_ct<R, INV, 16, NT, M, NS0>(buf, w0);
+  if constexpr (N16 > 1) stockham_ct<R, INV, 16, NT, M, NS1>(buf, w1);
+  if constexpr (N16 > 2) stockham_ct<R, INV, 16, NT, M, NS2>(buf, w2);
+}
+
 // Bluestein's chirp convolution: the length-n DFT of buf[0..n) (padded
 // layout) through power-of-two FFTs of length M >= 2n - 1, M <= kFftCap<NT>,
 // in place.  filt: FFT_M of the conjugate chirp, followed by the chirp
 // e^{-i pi l^2 / n} for l < n.  INV gives the unnormalised inverse DFT.  The
 // block is synchronised on entry and on exit; the global loads of each phase
 // are issued together before their first use.
-template <typename R, bool INV, int NT>
-__device__ void bluestein(cx_t<R>* buf, int n, int M, const cx_t<R>* __restrict__ filt,
-                          const cx_t<R>* __restrict__ tw, int TN) {
+template <typename R, bool INV, int NT, int MF = 0>
+__device__ __forceinline__ void bluestein(cx_t<R>* buf, int n, int M_, const cx_t<R>* __restrict__ filt,
+                                          const cx_t<R>* __restrict__ tw, int TN) {
+  const int M = MF > 0 ? MF : M_;
   using C = cx_t<R>;
   constexpr int EPT = kFftCap<NT> / NT;
   const int tid = threadIdx.x;
@@ -279,7 +350,8 @@ __device__ void bluestein(cx_t<R>* buf, int n, int M, const cx_t<R>* __restrict_
     }
   }
   __syncthreads();
-  lds_fft<R, false, NT>(buf, M, tw, TN);
+  if constexpr (MF > 0) lds_fft_ct<R, false, NT, MF>(buf, tw, TN);
+  else lds_fft<R, false, NT>(buf, M, tw, TN);
   {
     C f[EPT];
 #pragma unroll
@@ -294,7 +366,8 @@ __device__ void bluestein(cx_t<R>* buf, int n, int M, const cx_t<R>* __restrict_
     }
   }
   __syncthreads();
-  lds_fft<R, true, NT>(buf, M, tw, TN);
+  if constexpr (MF > 0) lds_fft_ct<R, true, NT, MF>(buf, tw, TN);
+  else lds_fft<R, true, NT>(buf, M, tw, TN);
   {
     const R inv = R(1) / R(M);
     C c[EPT];

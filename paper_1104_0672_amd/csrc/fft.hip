@@ -68,7 +68,7 @@ template <typename R> struct PairBatch { static constexpr int value = sizeof(R) 
 
 // Step (a) for ring j of one plan; x and spec are that plan's map and
 // spectrum buffer.  buf: dynamic LDS, nyq: one shared slot.
-template <typename R, int NT>
+template <typename R, int NT, int MF>
 __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, const R* __restrict__ x,
                                          cx_t<R>* __restrict__ spec, cx_t<R>* buf, cx_t<R>& nyq) {
   using C = cx_t<R>;
@@ -123,10 +123,14 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
       }
     }
     __syncthreads();
-    if (kind == FFT_POW2)
-      lds_fft<R, false, NT>(buf, n, a.tw, a.TN);
-    else
-      bluestein<R, false, NT>(buf, n, a.fft_m[j], a.bl + a.bl_off[j], a.tw, a.TN);
+    const int M = a.fft_m[j];
+    if (kind == FFT_POW2) {
+      if (MF > 0 && n == MF) lds_fft_ct<R, false, NT, (MF > 0 ? MF : 16 * NT)>(buf, a.tw, a.TN);
+      else lds_fft<R, false, NT>(buf, n, a.tw, a.TN);
+    } else {
+      if (MF > 0 && M == MF) bluestein<R, false, NT, MF>(buf, n, M, a.bl + a.bl_off[j], a.tw, a.TN);
+      else bluestein<R, false, NT>(buf, n, M, a.bl + a.bl_off[j], a.tw, a.TN);
+    }
     constexpr int kPairBatch = PairBatch<R>::value;
     // split Z into A(r) = E(r) - i exp(-2 pi i r / N) O(r) for the pair
     // (r, n - r), then the phase shift A~(r) = A(r) w_r, w_{n-r} = -i conj(w_r)
@@ -185,7 +189,7 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
 //   G(r) = conj(w_r) (P(r) - conj(P(N - r)))   (offset rings),
 //   G(r) = P(r) + conj(P(N - r))               (others),
 // for 0 <= r <= N/2 (P(N) collects the modes qN, q >= 1).
-template <typename R, int NT>
+template <typename R, int NT, int MF>
 __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, const cx_t<R>* __restrict__ bin,
                                          R* __restrict__ y, cx_t<R>* buf, cx_t<R>& nyq) {
   using C = cx_t<R>;
@@ -279,10 +283,14 @@ __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, cons
     }
     return;
   }
-  if (kind == FFT_POW2)
-    lds_fft<R, true, NT>(buf, n, a.tw, a.TN);
-  else
-    bluestein<R, true, NT>(buf, n, a.fft_m[i], a.bl + a.bl_off[i], a.tw, a.TN);
+  const int M = a.fft_m[i];
+  if (kind == FFT_POW2) {
+    if (MF > 0 && n == MF) lds_fft_ct<R, true, NT, (MF > 0 ? MF : 16 * NT)>(buf, a.tw, a.TN);
+    else lds_fft<R, true, NT>(buf, n, a.tw, a.TN);
+  } else {
+    if (MF > 0 && M == MF) bluestein<R, true, NT, MF>(buf, n, M, a.bl + a.bl_off[i], a.tw, a.TN);
+    else bluestein<R, true, NT>(buf, n, M, a.bl + a.bl_off[i], a.tw, a.TN);
+  }
   cx_t<R>* yc = reinterpret_cast<cx_t<R>*>(yr);
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -296,20 +304,20 @@ __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, cons
 // 256 threads (or two of 512) per CU in FP32, whose LDS also fits four.
 template <typename R> struct FftWaves { static constexpr int value = sizeof(R) == 4 ? 4 : 2; };
 
-template <typename R, int NT>
+template <typename R, int NT, int MF>
 __global__ void __launch_bounds__(NT, FftWaves<R>::value) r2c_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
                                                  const R* __restrict__ x, cx_t<R>* __restrict__ spec) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ cx_t<R> nyq;  // A(N/2), kept outside the padded buffer
-  r2c_ring<R, NT>(a, list[blockIdx.x], x, spec, reinterpret_cast<cx_t<R>*>(smem), nyq);
+  r2c_ring<R, NT, MF>(a, list[blockIdx.x], x, spec, reinterpret_cast<cx_t<R>*>(smem), nyq);
 }
 
-template <typename R, int NT>
+template <typename R, int NT, int MF>
 __global__ void __launch_bounds__(NT, FftWaves<R>::value) c2r_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
                                                  const cx_t<R>* __restrict__ bin, R* __restrict__ y) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ cx_t<R> nyq;  // G(N/2)
-  c2r_ring<R, NT>(a, list[blockIdx.x], bin, y, reinterpret_cast<cx_t<R>*>(smem), nyq);
+  c2r_ring<R, NT, MF>(a, list[blockIdx.x], bin, y, reinterpret_cast<cx_t<R>*>(smem), nyq);
 }
 
 // Batched forms: entry (map, ring); per-map arguments, maps and workspace
@@ -323,7 +331,7 @@ __global__ void __launch_bounds__(NT, FftWaves<R>::value) r2c_batch_kernel(const
   __shared__ cx_t<R> nyq;
   const int2 e = entries[blockIdx.x];
   const RingArgs<R> a = args[e.x];
-  r2c_ring<R, NT>(a, e.y, xs[e.x], ws + base[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
+  r2c_ring<R, NT, 0>(a, e.y, xs[e.x], ws + base[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
 }
 
 template <typename R, int NT>
@@ -335,7 +343,7 @@ __global__ void __launch_bounds__(NT, FftWaves<R>::value) c2r_batch_kernel(const
   __shared__ cx_t<R> nyq;
   const int2 e = entries[blockIdx.x];
   const RingArgs<R> a = args[e.x];
-  c2r_ring<R, NT>(a, e.y, ws + base[e.x], ys[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
+  c2r_ring<R, NT, 0>(a, e.y, ws + base[e.x], ys[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
 }
 
 template <typename R> RingArgs<R> ring_args(arkcos_plan_s* P, bool out_side, int adjoint,
@@ -373,31 +381,63 @@ hipError_t configure_fft_kernels(arkcos_plan_s* P) {
   hipError_t e = hipSuccess;
   const int32_t b = P->max_fft_lds;
   if (P->dtype == ARKCOS_F32) {
-    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 256>, b);
-    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 512>, b);
-    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 256>, b);
-    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 512>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 256, 0>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 512, 0>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 256, 4096>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 512, 8192>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 256, 0>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 512, 0>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 256, 4096>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 512, 8192>, b);
   } else {
-    if (e == hipSuccess) e = allow_lds(r2c_kernel<double, 256>, b);
-    if (e == hipSuccess) e = allow_lds(c2r_kernel<double, 256>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<double, 256, 0>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<double, 256, 0>, b);
   }
   return e;
 }
 
+// The launches of one class: a kernel compiled for the class's FFT length
+// when every ring of the class has the same one (4096 or 8192 points).
 template <typename R>
 static void r2c_class(const FftClass& c, const RingArgs<R>& a, const void* x, void* spec, hipStream_t s) {
-  if (sizeof(R) == 4 && c.threads == 512)
-    r2c_kernel<R, 512><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, (const R*)x, (cx_t<R>*)spec);
-  else
-    r2c_kernel<R, 256><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, (const R*)x, (cx_t<R>*)spec);
+  const R* xi = (const R*)x;
+  cx_t<R>* so = (cx_t<R>*)spec;
+  if constexpr (sizeof(R) == 4) {
+    if (c.threads == 512 && c.mf == 8192) {
+      r2c_kernel<R, 512, 8192><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, xi, so);
+      return;
+    }
+    if (c.threads == 256 && c.mf == 4096) {
+      r2c_kernel<R, 256, 4096><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, xi, so);
+      return;
+    }
+    if (c.threads == 512) {
+      r2c_kernel<R, 512, 0><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, xi, so);
+      return;
+    }
+  }
+  r2c_kernel<R, 256, 0><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, xi, so);
 }
 
 template <typename R>
 static void c2r_class(const FftClass& c, const RingArgs<R>& a, const void* b, void* y, hipStream_t s) {
-  if (sizeof(R) == 4 && c.threads == 512)
-    c2r_kernel<R, 512><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, (const cx_t<R>*)b, (R*)y);
-  else
-    c2r_kernel<R, 256><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, (const cx_t<R>*)b, (R*)y);
+  const cx_t<R>* bi = (const cx_t<R>*)b;
+  R* yo = (R*)y;
+  if constexpr (sizeof(R) == 4) {
+    if (c.threads == 512 && c.mf == 8192) {
+      c2r_kernel<R, 512, 8192><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, bi, yo);
+      return;
+    }
+    if (c.threads == 256 && c.mf == 4096) {
+      c2r_kernel<R, 256, 4096><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, bi, yo);
+      return;
+    }
+    if (c.threads == 512) {
+      c2r_kernel<R, 512, 0><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, bi, yo);
+      return;
+    }
+  }
+  c2r_kernel<R, 256, 0><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, bi, yo);
 }
 
 hipError_t launch_r2c(arkcos_plan_s* P, const void* x, void* spec, int32_t adjoint,

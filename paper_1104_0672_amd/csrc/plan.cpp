@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -475,13 +476,15 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       FftClass c;
       c.count = (int32_t)it->second.size();
       size_t mx = 0;
-      int32_t len = 0;
+      int32_t len = 0, lo = INT32_MAX;
       for (int32_t k : it->second) {
         mx = std::max(mx, ring_lds[k]);
         len = std::max(len, fft_m[k]);
+        lo = std::min(lo, fft_m[k]);
       }
       c.lds = (int32_t)((mx + 15) / 16 * 16);
       c.threads = fft_threads(dtype, len);
+      c.mf = (lo == len && len == 16 * c.threads) ? len : 0;
       HIPCHK(upload(P, &c.d_rings, it->second));
       P->fft_classes.push_back(c);
     }

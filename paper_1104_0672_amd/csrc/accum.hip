@@ -106,16 +106,24 @@ __device__ __forceinline__ PairU uniform_pair(const PairLds& d) {
 }
 
 // Runs STEP over a row of n8 (a multiple of 8) kernel samples from the top
-// down, in chunks of 8 read with wave-uniform (scalar) loads.
+// down, in chunks of 8 read with wave-uniform (scalar) loads; the rows start
+// on whole chunks (the sample array is allocated aligned), so a chunk is one
+// aligned load.  Rows of one chunk, the common case, take no loop.
 template <typename R, typename STEP>
 __device__ __forceinline__ void recur_row(int n8, const R* __restrict__ cf, STEP step) {
-  for (int c = n8 - 8; c >= 0; c -= 8) {
+  auto chunk = [&](int c) {
+    const R* p = static_cast<const R*>(__builtin_assume_aligned(cf + c, 8 * sizeof(R)));
     R cc[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) cc[t] = cf[c + t];
+    for (int t = 0; t < 8; ++t) cc[t] = p[t];
 #pragma unroll
     for (int t = 7; t >= 0; --t) step(cc[t]);
+  };
+  if (n8 == 8) {
+    chunk(0);
+    return;
   }
+  for (int c = n8 - 8; c >= 0; c -= 8) chunk(c);
 }
 
 template <typename R, int MPL, bool OWN>

@@ -261,6 +261,44 @@ def bench_batch(n_maps: int, steps: int, dev):
     return out
 
 
+def bench_spline(steps: int, dev):
+    """The spline-kernel workload (HEALPix nside 1024, 64 knots on [0, 40']):
+    forward convolution and the knot gradient of 1/2 |C x - t|^2 given the
+    residual, each timed over `steps` calls (wall clock, maps resident)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1104_0672_amd import Plan
+
+    w = W.healpix1024_spline()
+    t0 = time.perf_counter()
+    plan = Plan.from_workload(w)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    rng = np.random.default_rng(w.seed)
+    x = torch.tensor(rng.standard_normal(w.grid.npix), dtype=torch.float32, device=dev)
+    r = torch.tensor(rng.standard_normal(w.grid.npix), dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    ws = plan.workspace()
+    out = {"workload": w.name, "npix": plan.npix, "oversample": int(plan.info.oversample),
+           "plan_seconds": round(plan_s, 2)}
+    for name, fn in (("forward", lambda: plan.convolve(x, out=y, ws=ws)),
+                     ("knot_gradient", lambda: plan.kernel_grad(x, r, ws=ws))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        out[name] = {"ms": round(ms, 3), "pixels_per_s": plan.npix / (ms * 1e-3)}
+        log(f"bench: spline {name} {ms:.3f} ms")
+    del plan, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +308,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batch-maps", type=int, default=256, help="maps in the batched form (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--spline-steps", type=int, default=5, help="spline-kernel forward and gradient (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a device copy of this size first (for counter calibration)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -346,6 +385,10 @@ def main():
         forms["adjoint"] = {"pixels_per_s": plan.npix * steps_a / wall_a, "ms": ms_a,
                             "hbm_roofline_frac_24B_per_px": round(total_alg / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                             "stages_ms": dict(zip(STAGES, [round(t, 4) for t in stage_a]))}
+    forms["spline"] = None
+    if args.spline_steps > 0:
+        log("bench: spline kernel, nside 1024")
+        forms["spline"] = bench_spline(args.spline_steps, dev)
     forms["batched"] = None
     if args.batch_maps > 0:
         forms["batched"] = bench_batch(args.batch_maps, args.batch_steps, dev)

@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(kBlock) grad_pairs_kernel(GradArgs g, const cx
   using C = cx_t<R>;
   __shared__ double U[4 * 63];
   __shared__ double Y[kGradMaxCoef];
-  __shared__ double part[kBlock / 64];
+  __shared__ double part[kBlock / 64 * kGradMaxCoef];
   __shared__ double xs[kBlock];
   __shared__ double st[kBlock];
   __shared__ double sw[kBlock];
@@ -156,17 +156,22 @@ __global__ void __launch_bounds__(kBlock) grad_pairs_kernel(GradArgs g, const cx
           c1 = c2;
         }
       }
-      for (int d = 0; d < nc; ++d) {
-        const double v = wave_sum(acc[d]);
-        if (lane == 0) part[wv] = v;
-        __syncthreads();
-        if (tid == 0) {
-          double t = 0.0;
-          for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k];
-          Y[d] = t;
+      // reduce every sample's sums over the wave, then over the waves in
+      // order, with one barrier
+#pragma unroll
+      for (int d = 0; d < kGradMaxCoef; ++d) {
+        if (d < nc) {
+          const double v = wave_sum(acc[d]);
+          if (lane == 0) part[wv * kGradMaxCoef + d] = v;
         }
-        __syncthreads();
       }
+      __syncthreads();
+      if (tid < nc) {
+        double t = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k * kGradMaxCoef + tid];
+        Y[tid] = t;
+      }
+      __syncthreads();
       double t = 0.0, cd = 0.0, wgt = 0.0;
       if (tid < nc) {
         sample(tid, t, cd);
@@ -174,26 +179,29 @@ __global__ void __launch_bounds__(kBlock) grad_pairs_kernel(GradArgs g, const cx
       }
       ordered_scatter(U, g, st, sw, nc, t, wgt);
     } else {
-      // wide rows: threads over samples, modes staged in chunks
+      // wide rows: threads over samples, modes staged in chunks; cos(m nu_d)
+      // by the three-term recurrence in m, restarted from exact values at
+      // every chunk
       for (int d0 = 0; d0 < nc; d0 += blockDim.x) {
         const int d = d0 + tid;
-        double sn = 0.0, cs = 1.0;
-        if (d < nc) sincospi((double)(2 * (int64_t)d + s) / (double)pl, &sn, &cs);  // e^{i nu_d}
+        const int64_t nd = 2 * (int64_t)d + s;  // nu_d = pi nd / (p L)
+        const double step = d < nc ? 2.0 * cospi((double)nd / (double)pl) : 0.0;
         double y = 0.0;
         for (int m0 = 0; m0 <= pr.band; m0 += blockDim.x) {
           const int m = m0 + tid;
           xs[tid] = m <= pr.band ? xcorr(m) : 0.0;
           __syncthreads();
           if (d < nc) {
-            const int64_t ph = ((2 * (int64_t)d + s) * (int64_t)m0) % (2 * pl);
-            double zi, zr;  // e^{i m0 nu_d}
-            sincospi((double)ph / (double)pl, &zi, &zr);
+            // cos((m0 - 1) nu_d) and cos(m0 nu_d), exactly (angles reduced mod 2 pi)
+            const int64_t p0 = (nd * (int64_t)m0) % (2 * pl);
+            const int64_t pm = (nd * (int64_t)(m0 > 0 ? m0 - 1 : 1)) % (2 * pl);
+            double cp = cospi((double)pm / (double)pl), cc = cospi((double)p0 / (double)pl);
             const int mc = min((int)blockDim.x, pr.band - m0 + 1);
             for (int k = 0; k < mc; ++k) {
-              y = fma(xs[k], zr, y);
-              const double nr = zr * cs - zi * sn;
-              zi = zr * sn + zi * cs;
-              zr = nr;
+              y = fma(xs[k], cc, y);
+              const double cn = fma(step, cc, -cp);
+              cp = cc;
+              cc = cn;
             }
           }
           __syncthreads();

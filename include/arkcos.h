@@ -93,9 +93,11 @@ typedef struct {
                                ring: 1, 2, 4, 8 or 16; 0 = choose from the kernel's
                                width (p = next power of two >= 4.3 pixel / FWHM) */
   int32_t kgen;             /* how K_ij(m) is produced per call: 0 = automatic
-                               (recurrence from the kernel samples for narrow pairs,
-                               precomputed table for wide ones), 1 = recurrence for
-                               every pair, 2 = precomputed table for every pair */
+                               (precomputed tables for every pair if they take at
+                               most 1 GiB, otherwise the recurrence from the kernel
+                               samples for narrow pairs and tables for wide ones),
+                               1 = recurrence for every pair (wide rows still use
+                               tables), 2 = precomputed table for every pair */
   int32_t fix_pole_pixels;  /* HEALPix: recompute the 8 pixels of the first and last
                                ring by the direct sum (default 1) */
   double band_tol;          /* modes with |K_ij(m)| below band_tol times the largest
@@ -110,7 +112,8 @@ typedef struct {
   int64_t output_modes;     /* complex coefficients accumulated for the output rings */
   int64_t pair_modes;       /* sum over ring pairs of the modes accumulated */
   int64_t taps;             /* kernel samples held for the recurrence */
-  int64_t table_entries;    /* precomputed K_ij(m) values */
+  int64_t table_entries;    /* precomputed K_ij(m) values (each pair's table
+                               zero-padded to a multiple of 256 modes) */
   int32_t oversample, dtype, n_knots;
   int32_t reserved;
   size_t workspace_bytes, plan_bytes;

@@ -240,7 +240,7 @@ struct AccLayout {
 // issued together, then evaluates its on-the-fly pairs, the next pair's
 // kernel samples loaded while the current one is evaluated.  Every wave of
 // the block must call this; it synchronises the block.
-template <typename R, int NW>
+template <typename R, int NW, bool TAB_ONLY = false>
 __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandDev& bd, const int t0, const int nt,
                                                 const cx_t<R>* __restrict__ spec, cx_t<R>* __restrict__ bout,
                                                 unsigned char* smem, const AccLayout lay) {
@@ -383,40 +383,52 @@ __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandD
       for (int e = 0; e < MPL; ++e) {
         acc0[e] = cmake<C>(R(0), R(0));
         acc1[e] = acc0[e];
-        if (busy) mc[e] = mode_const<R>(m0 + 64 * e + lane, Ni, pl, a.tw, a.TN);
+        if (busy && !TAB_ONLY) mc[e] = mode_const<R>(m0 + 64 * e + lane, Ni, pl, a.tw, a.TN);
       }
       qt = 0;
       qo = ntab;
-      if (busy && qo < npair) cur = uniform_pair(mine[qo]);
+      if (!TAB_ONLY && busy && qo < npair) cur = uniform_pair(mine[qo]);
     }
-    if (busy) {
-      // table pairs of this chunk, kTableGroup at a time
-      while (qt < ntab) {
-        R kv[kTableGroup][MPL];
-        int rw[kTableGroup];
-        int g = 0;
+    // Up to G table pairs of the staged chunk from descriptor qt on: the
+    // descriptors are read together (the descriptor area has CH spare
+    // entries, so reads past a unit's last pair stay inside it), then the
+    // tile of every pair whose band reaches it is loaded without bounds
+    // checks (tables are zero-padded to whole tiles) and with no register
+    // cleared in between, so that the loads overlap each other and the
+    // spectrum prefetch; then they are accumulated.  Returns the pairs used.
+    auto table_group = [&](auto gsize) -> int {
+      constexpr int G = decltype(gsize)::value;
+      PairU d[G];
 #pragma unroll
-        for (int x = 0; x < kTableGroup; ++x) {
-          rw[x] = 0;
-          if (qt + x < ntab && g == x) {
-            const PairU d = uniform_pair(mine[qt + x]);
-            if (pl_row(d.meta) < c1) {
-              rw[x] = 2 * (pl_row(d.meta) - c0);
-              g = x + 1;
+      for (int x = 0; x < G; ++x) d[x] = uniform_pair(mine[qt + x]);
+      int g = 0;
+      uint32_t live = 0;
 #pragma unroll
-              for (int e = 0; e < MPL; ++e) {
-                const int m = m0 + 64 * e + lane;
-                kv[x][e] = m <= d.band ? gload(a.table + d.off + m) : R(0);
-              }
-            }
-          }
+      for (int x = 0; x < G; ++x)
+        if (g == x && qt + x < ntab && pl_row(d[x].meta) < c1) {
+          g = x + 1;
+          if (d[x].band >= m0) live |= 1u << x;
         }
-        if (g == 0) break;
+      R kv[G][MPL];
 #pragma unroll
-        for (int x = 0; x < kTableGroup; ++x)
-          if (x < g) accumulate_pair(rw[x], kv[x]);
-        qt += g;
-      }
+      for (int x = 0; x < G; ++x)
+        if ((live >> x) & 1u) {
+          const R* tb = a.table + d[x].off + m0;
+#pragma unroll
+          for (int e = 0; e < MPL; ++e) kv[x][e] = gload(tb + 64 * e + lane);
+        }
+#pragma unroll
+      for (int x = 0; x < G; ++x)
+        if ((live >> x) & 1u) accumulate_pair(2 * (pl_row(d[x].meta) - c0), kv[x]);
+      qt += g;
+      return g;
+    };
+    if (busy && TAB_ONLY) {
+      // every pair has a table: a unit has at most CH pairs in a chunk
+      table_group(std::integral_constant<int, CH>{});
+    } else if (busy) {
+      while (qt < ntab)
+        if (table_group(std::integral_constant<int, kTableGroup>{}) == 0) break;
       // on-the-fly pairs of this chunk
       while (qo < npair && pl_row(cur.meta) < c1) {
         const PairU d = cur;
@@ -428,16 +440,16 @@ __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandD
         }
         ++qo;
       }
-      if (c == nch - 1) {
-        const int64_t o0 = gload(a.out_off + u.i);
-        const int64_t o1 = mirror ? gload(a.out_off + u.im) : 0;
+    }
+    if (busy && c == nch - 1) {
+      const int64_t o0 = gload(a.out_off + u.i);
+      const int64_t o1 = mirror ? gload(a.out_off + u.im) : 0;
 #pragma unroll
-        for (int e = 0; e < MPL; ++e) {
-          const int m = m0 + 64 * e + lane;
-          if (m <= u.band) {
-            gstore(bout + o0 + m, acc0[e]);
-            if (mirror) gstore(bout + o1 + m, acc1[e]);
-          }
+      for (int e = 0; e < MPL; ++e) {
+        const int m = m0 + 64 * e + lane;
+        if (m <= u.band) {
+          gstore(bout + o0 + m, acc0[e]);
+          if (mirror) gstore(bout + o1 + m, acc1[e]);
         }
       }
     }
@@ -459,12 +471,14 @@ __device__ __forceinline__ BandDev load_band(const BandDev* g) {
   return b;
 }
 
-template <typename R>
+// TAB_ONLY: every pair of the plan has a table of K_ij(m) (no recurrence
+// code, fewer registers, more waves).
+template <typename R, bool TAB_ONLY>
 __global__ void __launch_bounds__(kAccThreads) accumulate_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec,
                                                                  cx_t<R>* __restrict__ bout, AccLayout lay) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WorkItem it = a.items[blockIdx.x];
-  accumulate_band<R, kBandUnits>(a, a.bands[it.band], it.t0, it.nt, spec, bout, smem, lay);
+  accumulate_band<R, kBandUnits, TAB_ONLY>(a, a.bands[it.band], it.t0, it.nt, spec, bout, smem, lay);
 }
 
 // Batched form: one persistent launch drains a queue of (map, band, tiles)
@@ -526,7 +540,8 @@ static AccLayout acc_layout(arkcos_dtype_t dt, const AccShape& sh) {
 }
 
 size_t acc_lds_bytes(arkcos_dtype_t dt, const AccShape& sh) {
-  return (size_t)acc_layout(dt, sh).pairs_off + (size_t)std::max(sh.max_band_pairs, 1) * sizeof(PairLds);
+  // CH spare descriptors: a group of table pairs reads CH descriptors at once
+  return (size_t)acc_layout(dt, sh).pairs_off + (size_t)(std::max(sh.max_band_pairs, 1) + 8) * sizeof(PairLds);
 }
 
 template <typename R, int NW>
@@ -565,11 +580,21 @@ hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const in
 // Modes beyond a unit's band stay zero (B_i has out_len_i = band_i + 1 modes,
 // so nothing is left unwritten).
 
+template <typename K> static hipError_t allow_acc_lds(K* k, size_t bytes) {
+  return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 hipError_t configure_accumulate(arkcos_plan_s* P) {
   const size_t lds = acc_lds_bytes(P->dtype, P->acc_shape);
-  if (P->dtype == ARKCOS_F32)
-    return hipFuncSetAttribute((const void*)accumulate_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  return hipFuncSetAttribute((const void*)accumulate_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e;
+  if (P->dtype == ARKCOS_F32) {
+    e = allow_acc_lds(accumulate_kernel<float, false>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<float, true>, lds);
+  } else {
+    e = allow_acc_lds(accumulate_kernel<double, false>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<double, true>, lds);
+  }
+  return e;
 }
 
 hipError_t launch_accumulate(arkcos_plan_s* P, const void* spec, void* bout, hipStream_t s) {
@@ -577,12 +602,15 @@ hipError_t launch_accumulate(arkcos_plan_s* P, const void* spec, void* bout, hip
   const size_t lds = acc_lds_bytes(P->dtype, P->acc_shape);
   const AccLayout lay = acc_layout(P->dtype, P->acc_shape);
   const unsigned grid = (unsigned)P->h_items.size();
-  if (P->dtype == ARKCOS_F32)
-    accumulate_kernel<float><<<grid, kAccThreads, lds, s>>>(make_acc_args<float>(P, P->d_bands),
-                                                            (const float2*)spec, (float2*)bout, lay);
-  else
-    accumulate_kernel<double><<<grid, kAccThreads, lds, s>>>(make_acc_args<double>(P, P->d_bands),
-                                                             (const double2*)spec, (double2*)bout, lay);
+  const bool tab = P->all_tables;
+  if (P->dtype == ARKCOS_F32) {
+    auto k = tab ? accumulate_kernel<float, true> : accumulate_kernel<float, false>;
+    k<<<grid, kAccThreads, lds, s>>>(make_acc_args<float>(P, P->d_bands), (const float2*)spec, (float2*)bout, lay);
+  } else {
+    auto k = tab ? accumulate_kernel<double, true> : accumulate_kernel<double, false>;
+    k<<<grid, kAccThreads, lds, s>>>(make_acc_args<double>(P, P->d_bands), (const double2*)spec, (double2*)bout,
+                                     lay);
+  }
   return hipGetLastError();
 }
 

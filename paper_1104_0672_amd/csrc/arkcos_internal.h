@@ -79,6 +79,10 @@ struct BatchItem {
 };
 
 constexpr int kTilesPerItem = 4;     // mode tiles per accumulation work item
+// entries of a pair's K_ij(m) table: modes 0..band, zero-padded to whole
+// mode tiles so that a tile is read without bounds checks
+__host__ __device__ constexpr int32_t table_span(int32_t band) { return (band / kAccTile + 1) * kAccTile; }
+constexpr int64_t kAutoTableBytes = int64_t(1) << 30;  // automatic choice: tables for every pair up to this size
 
 // A band of up to kBandUnits consecutive units: the input rings they need.
 struct BandDev {
@@ -153,6 +157,7 @@ struct arkcos_plan_s {
   arkcos::WorkItem* d_items = nullptr;
   arkcos::BandDev* d_bands = nullptr;
   arkcos::AccShape acc_shape;  // LDS needs of the accumulation bands
+  bool all_tables = false;     // every pair reads K_ij(m) from a table
   std::vector<arkcos::BandDev> h_bands;
   void* d_coef = nullptr;       // recurrence coefficients, plan dtype
   double* d_coef64 = nullptr;   // the same in FP64 (plan-time table building, gradient)

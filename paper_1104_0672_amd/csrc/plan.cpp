@@ -158,7 +158,16 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
     for (int64_t q = 0; q < np; ++q) band[q] = P->h_pairs[q].band;
   }
 
-  // table selection and offsets
+  // table selection and offsets: automatic choice = tables for every pair if
+  // they fit in kAutoTableBytes (the accumulation then only streams them),
+  // otherwise tables only for rows too wide for the recurrence
+  bool all_auto = false;
+  if (first_time && P->opts.kgen == 0) {
+    int64_t entries = 0;
+    for (int64_t q = 0; q < np; ++q)
+      if (band[q] >= 0) entries += table_span(band[q]);
+    all_auto = entries * (int64_t)(P->dtype == ARKCOS_F32 ? 4 : 8) <= kAutoTableBytes;
+  }
   int64_t table_total = 0, ntab = 0;
   std::vector<int32_t> tab_list;
   std::vector<int64_t> tab_coef;
@@ -169,13 +178,13 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
     if (!first_time) {
       table = pr.kind == KG_TABLE;
     } else if (pr.band >= 0) {
-      if (P->opts.kgen == 2) table = true;
+      if (P->opts.kgen == 2 || all_auto) table = true;
       else if (P->opts.kgen == 0) table = pr.ncoef > kOtfMaxCoef;
     }
     if (table) {
       pr.kind = KG_TABLE;
       pr.off = table_total;
-      table_total += pr.band + 1;
+      table_total += table_span(pr.band);
       tab_list.push_back((int32_t)q);
       tab_coef.push_back(P->h_coef_off[q]);
       ++ntab;
@@ -192,6 +201,12 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
     return fail(ARKCOS_ERR_NOT_SUPPORTED, "kernel samples beyond 2 GiB or tables beyond 2^32 elements");
   P->n_table_pairs = ntab;
   P->table_total = table_total;
+  {
+    bool all = true;
+    for (int64_t q = 0; q < np && all; ++q)
+      if (P->h_pairs[q].band >= 0 && P->h_pairs[q].kind != KG_TABLE) all = false;
+    P->all_tables = all;
+  }
   const size_t rsz = P->dtype == ARKCOS_F32 ? sizeof(float) : sizeof(double);
   if (first_time) {
     void* t = nullptr;

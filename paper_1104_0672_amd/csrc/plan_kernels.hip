@@ -143,7 +143,8 @@ __global__ void __launch_bounds__(kBlock) band_kernel(
 }
 
 // Tables: K_ij(m) for m <= band of the pairs listed in `list` (their coef64
-// offsets are read from `coef_off`, their table offsets from pairs[].off).
+// offsets are read from `coef_off`, their table offsets from pairs[].off),
+// zero from band + 1 to the end of the last mode tile.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) table_kernel(
     const PairDev* __restrict__ pairs, const int32_t* __restrict__ pair_shift,
@@ -153,8 +154,10 @@ __global__ void __launch_bounds__(kBlock) table_kernel(
   const int q = list[t];
   const PairDev pr = pairs[q];
   const int64_t pl = (int64_t)pr.grid;
-  for (int m = threadIdx.x; m <= pr.band; m += blockDim.x)
-    table[pr.off + m] = (R)k_of_m_fp64(coef64 + coef_off[t], pr.ncoef, m, pair_shift[q], pl, pr.nyq);
+  const int end = table_span(pr.band);
+  for (int m = threadIdx.x; m < end; m += blockDim.x)
+    table[pr.off + m] =
+        m <= pr.band ? (R)k_of_m_fp64(coef64 + coef_off[t], pr.ncoef, m, pair_shift[q], pl, pr.nyq) : R(0);
 }
 
 // Bluestein filter of length n: FFT_M of b_l = exp(+i pi l^2 / n) placed at l

@@ -260,19 +260,22 @@ template <int NS, int RAD> __device__ __forceinline__ constexpr int out_gap(int 
   else return 16 * r + (r >> 1);                      // NS = 16: o mod 32 < 16
 }
 
-template <typename R, bool INV, int RAD, int NT, int M, int NS>
+// HIN (first pass, NS = 1): the points M/2 .. M-1 are zero and not read.
+// HOUT (last pass, NS = M/RAD): only the outputs 0 .. M/2-1 are written.
+template <typename R, bool INV, int RAD, int NT, int M, int NS, bool HIN = false, bool HOUT = false>
 __device__ __forceinline__ void stockham_ct(cx_t<R>* buf, cx_t<R> w) {
   using C = cx_t<R>;
   constexpr int Q = M / RAD;
   constexpr int MAXB = Q / NT;
   static_assert(Q % NT == 0 && Q % 32 == 0 && NT % 32 == 0, "pass shape");
+  static_assert((!HIN || NS == 1) && (!HOUT || NS == Q), "pruned pass");
   constexpr int RG = Q + Q / 32;
   C v[MAXB][RAD];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const C* src = buf + lidx(threadIdx.x + b * NT);
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) v[b][r] = src[r * RG];
+    for (int r = 0; r < RAD; ++r) v[b][r] = (HIN && 2 * r >= RAD) ? cmake<C>(R(0), R(0)) : src[r * RG];
   }
   __syncthreads();
 #pragma unroll
@@ -288,7 +291,8 @@ __device__ __forceinline__ void stockham_ct(cx_t<R>* buf, cx_t<R> w) {
     dft_reg<C, INV, RAD>(v[b]);
     C* dst = buf + lidx((j - k) * RAD + k);
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) dst[out_gap<NS, RAD>(r)] = v[b][r];
+    for (int r = 0; r < RAD; ++r)
+      if (!HOUT || 2 * r < RAD) dst[out_gap<NS, RAD>(r)] = v[b][r];
   }
   __syncthreads();
 }
@@ -296,23 +300,26 @@ __device__ __forceinline__ void stockham_ct(cx_t<R>* buf, cx_t<R> w) {
 template <int M> struct Log2 { static constexpr int value = 1 + Log2<M / 2>::value; };
 template <> struct Log2<1> { static constexpr int value = 0; };
 
-template <typename R, bool INV, int NT, int M>
+// HIN: the input's upper half is zero; HOUT: only the lower half of the
+// output is wanted (the two halves of a Bluestein convolution).
+template <typename R, bool INV, int NT, int M, bool HIN = false, bool HOUT = false>
 __device__ __forceinline__ void lds_fft_ct(cx_t<R>* buf, const cx_t<R>* __restrict__ tw, int TN) {
   using C = cx_t<R>;
   constexpr int LG = Log2<M>::value, REST = LG & 3, N16 = LG >> 2;
   static_assert(M == 16 * NT && N16 <= 3 && N16 >= 1, "length");
   constexpr int NS0 = 1 << REST, NS1 = NS0 << 4, NS2 = NS0 << 8;
+  constexpr bool H16 = HIN && REST == 0;  // the first radix-16 pass is the first pass
   const int j = threadIdx.x;
   auto tw_at = [&](int ns) {
     return ns > 1 ? tw[(j & (ns - 1)) * (TN / (ns * 16))] : cmake<C>(R(1), R(0));
   };
   const C w0 = tw_at(NS0), w1 = tw_at(NS1), w2 = N16 > 2 ? tw_at(NS2) : cmake<C>(R(1), R(0));
-  if constexpr (REST == 1) stockham_ct<R, INV, 2, NT, M, 1>(buf, w0);
-  else if constexpr (REST == 2) stockham_ct<R, INV, 4, NT, M, 1>(buf, w0);
-  else if constexpr (REST == 3) stockham_ct<R, INV, 8, NT, M, 1>(buf, w0);
-  stockham_ct<R, INV, 16, NT, M, NS0>(buf, w0);
-  if constexpr (N16 > 1) stockham_ct<R, INV, 16, NT, M, NS1>(buf, w1);
-  if constexpr (N16 > 2) stockham_ct<R, INV, 16, NT, M, NS2>(buf, w2);
+  if constexpr (REST == 1) stockham_ct<R, INV, 2, NT, M, 1, HIN>(buf, w0);
+  else if constexpr (REST == 2) stockham_ct<R, INV, 4, NT, M, 1, HIN>(buf, w0);
+  else if constexpr (REST == 3) stockham_ct<R, INV, 8, NT, M, 1, HIN>(buf, w0);
+  stockham_ct<R, INV, 16, NT, M, NS0, H16, HOUT && N16 == 1>(buf, w0);
+  if constexpr (N16 > 1) stockham_ct<R, INV, 16, NT, M, NS1, false, HOUT && N16 == 2>(buf, w1);
+  if constexpr (N16 > 2) stockham_ct<R, INV, 16, NT, M, NS2, false, HOUT>(buf, w2);
 }
 
 // Bluestein's chirp convolution: the length-n DFT of buf[0..n) (padded
@@ -335,10 +342,13 @@ __device__ __forceinline__ void bluestein(cx_t<R>* buf, int n, int M_, const cx_
       const int l = tid + e * NT;
       if (l < n) c[e] = filt[M + l];
     }
+    // n <= M/2: the compile-time FFTs skip the zero upper half of the input
+    // and the unused upper half of the output
+    const int lim = MF > 0 ? M / 2 : M;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int l = tid + e * NT;
-      if (l < M) {
+      if (l < lim) {
         C v = cmake<C>(R(0), R(0));
         if (l < n) {
           v = buf[lidx(l)];
@@ -350,7 +360,7 @@ __device__ __forceinline__ void bluestein(cx_t<R>* buf, int n, int M_, const cx_
     }
   }
   __syncthreads();
-  if constexpr (MF > 0) lds_fft_ct<R, false, NT, MF>(buf, tw, TN);
+  if constexpr (MF > 0) lds_fft_ct<R, false, NT, MF, true, false>(buf, tw, TN);
   else lds_fft<R, false, NT>(buf, M, tw, TN);
   {
     C f[EPT];
@@ -366,7 +376,7 @@ __device__ __forceinline__ void bluestein(cx_t<R>* buf, int n, int M_, const cx_
     }
   }
   __syncthreads();
-  if constexpr (MF > 0) lds_fft_ct<R, true, NT, MF>(buf, tw, TN);
+  if constexpr (MF > 0) lds_fft_ct<R, true, NT, MF, false, true>(buf, tw, TN);
   else lds_fft<R, true, NT>(buf, M, tw, TN);
   {
     const R inv = R(1) / R(M);

@@ -48,29 +48,32 @@ template <typename R> struct RingArgs {
 //   A~(m + N) = s A~(m),  A~(N - r) = s conj(A~(r)),  s = -1 (offset), +1,
 // so a ring needs w_r only for r <= N/2, and the split of the half-length
 // complex FFT needs w_r^2 = exp(-2 pi i r / N).  Power-of-two rings read w_r
-// from the twiddle table (TN a multiple of 2N); the others compute it.
+// from the twiddle table (TN a multiple of 2N), Bluestein rings from the
+// table stored after their filter (ph), the short rings compute it.
 template <typename R>
-__device__ __forceinline__ cx_t<R> half_twiddle(int r, int N, bool table, const cx_t<R>* __restrict__ tw, int TN) {
-  if (table) return tw[r * (TN / (2 * N))];
+__device__ __forceinline__ cx_t<R> half_twiddle(int r, int N, int kind, const cx_t<R>* __restrict__ ph,
+                                                const cx_t<R>* __restrict__ tw, int TN) {
+  if (kind == FFT_POW2) return tw[r * (TN / (2 * N))];
+  if (kind == FFT_BLUESTEIN) return ph[r];
   return cconj(expipi<R>(r, N));
 }
 
-// q = m / N, r = m mod N for 0 <= m < 2^20, 0 < N < 2^16 (the rounding
-// error of the float quotient is far below the 1/(2N) margin kept from the
-// integers).
-__device__ __forceinline__ void divmod_small(int m, int N, float invN, int& q, int& r) {
-  q = (int)(((float)m + 0.5f) * invN);
-  r = m - q * N;
+// The half-angle phase table of a Bluestein ring: after its filter (M values)
+// and chirp (n values).
+template <typename R>
+__device__ __forceinline__ const cx_t<R>* phase_table(const RingArgs<R>& a, int ring, int kind, int n) {
+  return kind == FFT_BLUESTEIN ? a.bl + a.bl_off[ring] + a.fft_m[ring] + n : nullptr;
 }
 
 // (r, n - r) pairs per thread per batch of loads
 template <typename R> struct PairBatch { static constexpr int value = sizeof(R) == 4 ? 4 : 2; };
 
 // Step (a) for ring j of one plan; x and spec are that plan's map and
-// spectrum buffer.  buf: dynamic LDS, nyq: one shared slot.
+// spectrum buffer.  buf: dynamic LDS (A(n) is kept in the slot after the n
+// points).
 template <typename R, int NT, int MF>
 __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, const R* __restrict__ x,
-                                         cx_t<R>* __restrict__ spec, cx_t<R>* buf, cx_t<R>& nyq) {
+                                         cx_t<R>* __restrict__ spec, cx_t<R>* buf) {
   using C = cx_t<R>;
   constexpr int EPT = kFftCap<NT> / NT;
   const int N = a.n[j], n = N / 2, kind = a.fft_kind[j];
@@ -84,7 +87,7 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
   }
   const R scale = a.adjoint ? R(1.0 / a.w[j]) : R(1);
   const R* xr = x + a.start[j];
-  const bool table = kind == FFT_POW2;
+  const C* ph = phase_table(a, j, kind, n);
   if (kind == FFT_DIRECT) {
     C* tab = buf + lds_elems(n);
     R* xs = reinterpret_cast<R*>(tab + N);
@@ -101,9 +104,8 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
         idx += m;
         if (idx >= N) idx -= N;
       }
-      if (shifted) acc = cmul(acc, half_twiddle<R>(m, N, false, a.tw, a.TN));
-      if (m < n) buf[lidx(m)] = acc;
-      else nyq = acc;
+      if (shifted) acc = cmul(acc, half_twiddle<R>(m, N, FFT_DIRECT, ph, a.tw, a.TN));
+      buf[lidx(m)] = acc;  // A(n) in the slot after the n points
     }
     __syncthreads();
   } else {
@@ -139,7 +141,7 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
 #pragma unroll
       for (int u = 0; u < kPairBatch; ++u) {
         const int r = base + tid + u * NT;
-        if (r <= n / 2) wr[u] = half_twiddle<R>(r, N, table, a.tw, a.TN);
+        if (r <= n / 2) wr[u] = half_twiddle<R>(r, N, kind, ph, a.tw, a.TN);
       }
 #pragma unroll
       for (int u = 0; u < kPairBatch; ++u) {
@@ -159,28 +161,27 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
             a2 = cmul(a2, w2);
           }
           buf[lidx(r)] = a1;
-          if (r2 == n) nyq = a2;
-          else if (r2 != r) buf[lidx(r2)] = a2;
+          if (r2 != r) buf[lidx(r2)] = a2;  // r = 0: A(n) in the slot after the n points
         }
       }
     }
     __syncthreads();
   }
-  // periodic extension: A~(qN + r) = s^q A~(r), A~(N - r) = s conj(A~(r))
-  const float invN = 1.0f / (float)N;
-  const R s = shifted ? R(-1) : R(1);
+  // periodic extension: A~(qN + r) = s^q A~(r), A~(N - r) = s conj(A~(r)),
+  // m = q N + r advanced by NT per step
+  int q = tid / N, r = tid - q * N;
+  const int dq = NT / N, dr = NT - dq * N;
   for (int m = tid; m < len; m += NT) {
-    int q, r;
-    divmod_small(m, N, invN, q, r);
-    C v;
-    if (r == n) v = nyq;
-    else if (r < n) v = buf[lidx(r)];
-    else {
-      const C c = buf[lidx(N - r)];
-      v = cmake<C>(s * c.x, -s * c.y);
+    const bool up = r > n;
+    const C c = buf[lidx(up ? N - r : r)];
+    const R sg = (shifted && ((q + (up ? 1 : 0)) & 1)) ? R(-1) : R(1);
+    out[m] = cmake<C>(sg * c.x, (up ? -sg : sg) * c.y);
+    r += dr;
+    q += dq;
+    if (r >= N) {
+      r -= N;
+      ++q;
     }
-    if (shifted && (q & 1)) v = cmake<C>(-v.x, -v.y);
-    out[m] = v;
   }
 }
 
@@ -200,7 +201,7 @@ __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, cons
   const C* b = bin + a.off[i];
   const int tid = threadIdx.x;
   const R scale = a.adjoint ? R(a.w[i]) : R(1);
-  const bool table = kind == FFT_POW2;
+  const C* ph = phase_table(a, i, kind, n);
   const bool direct = kind == FFT_DIRECT;
   constexpr int kPairBatch = PairBatch<R>::value;
   const int nq = (len + N - 1) / N;
@@ -235,7 +236,7 @@ __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, cons
       const int r = base + tid + u * NT;
       if (r > n / 2) continue;
       const int r2 = n - r;
-      const C w = half_twiddle<R>(r, N, table, a.tw, a.TN);
+      const C w = half_twiddle<R>(r, N, kind, ph, a.tw, a.TN);
       C g1, g2;
       if (shifted) {
         g1 = cmul(cconj(w), csub(p[u][0], cconj(p[u][1])));
@@ -308,8 +309,7 @@ template <typename R, int NT, int MF>
 __global__ void __launch_bounds__(NT, FftWaves<R>::value) r2c_kernel(RingArgs<R> a, const int32_t* __restrict__ list,
                                                  const R* __restrict__ x, cx_t<R>* __restrict__ spec) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ cx_t<R> nyq;  // A(N/2), kept outside the padded buffer
-  r2c_ring<R, NT, MF>(a, list[blockIdx.x], x, spec, reinterpret_cast<cx_t<R>*>(smem), nyq);
+  r2c_ring<R, NT, MF>(a, list[blockIdx.x], x, spec, reinterpret_cast<cx_t<R>*>(smem));
 }
 
 template <typename R, int NT, int MF>
@@ -328,10 +328,9 @@ __global__ void __launch_bounds__(NT, FftWaves<R>::value) r2c_batch_kernel(const
                                                        const R* const* __restrict__ xs,
                                                        cx_t<R>* __restrict__ ws, const int64_t* __restrict__ base) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ cx_t<R> nyq;
   const int2 e = entries[blockIdx.x];
   const RingArgs<R> a = args[e.x];
-  r2c_ring<R, NT, 0>(a, e.y, xs[e.x], ws + base[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
+  r2c_ring<R, NT, 0>(a, e.y, xs[e.x], ws + base[e.x], reinterpret_cast<cx_t<R>*>(smem));
 }
 
 template <typename R, int NT>

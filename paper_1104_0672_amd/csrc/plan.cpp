@@ -454,7 +454,7 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       if (it == bl_of_len.end()) {
         bl_of_len[(int32_t)N] = P->bl_total;
         bl_off[k] = P->bl_total;
-        P->bl_total += M + n;
+        P->bl_total += M + n + n / 2 + 1;  // filter, chirp, half-angle phases
         bl_rings.push_back((int32_t)k);
         P->max_bl_m = std::max<int32_t>(P->max_bl_m, (int32_t)M);
       } else {

@@ -161,7 +161,9 @@ __global__ void __launch_bounds__(kBlock) table_kernel(
 }
 
 // Bluestein filter of length n: FFT_M of b_l = exp(+i pi l^2 / n) placed at l
-// and M - l for 0 <= l < n, followed by the chirp exp(-i pi l^2 / n), l < n.
+// and M - l for 0 <= l < n, followed by the chirp exp(-i pi l^2 / n), l < n,
+// and the ring's half-angle phases w_r = exp(-i pi r / (2 n)), r <= n / 2
+// (the ring has N = 2 n pixels).
 template <typename R, int NT>
 __global__ void __launch_bounds__(NT) bluestein_filter_kernel(
     const int32_t* __restrict__ rings, const int32_t* __restrict__ ring_n,
@@ -183,6 +185,7 @@ __global__ void __launch_bounds__(NT) bluestein_filter_kernel(
   C* o = out + bl_off[ring];
   for (int l = threadIdx.x; l < M; l += blockDim.x) o[l] = buf[lidx(l)];
   for (int l = threadIdx.x; l < n; l += blockDim.x) o[M + l] = chirp<R>(l, n);
+  for (int r = threadIdx.x; r <= n / 2; r += blockDim.x) o[M + n + r] = cconj(expipi<R>(r, 2 * n));
 }
 
 static ProfileDev make_profile(arkcos_plan_s* P) {

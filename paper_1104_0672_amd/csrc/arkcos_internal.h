@@ -141,6 +141,7 @@ struct arkcos_plan_s {
   std::vector<arkcos::PairDev> h_pairs;
   std::vector<int32_t> h_pair_i;         // output ring of each pair
   std::vector<int32_t> h_pair_shift;     // half-shift flag per pair
+  std::vector<int64_t> h_tab_owner;      // pair whose table a table pair reads (itself, or its transpose)
   std::vector<int64_t> h_coef_off;       // recurrence-coefficient offset per pair
   std::vector<int32_t> h_ncoef_window;   // kernel samples inside each pair's window
   std::vector<arkcos::FftClass> fft_classes;

@@ -158,19 +158,52 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
     for (int64_t q = 0; q < np; ++q) band[q] = P->h_pairs[q].band;
   }
 
+  // A table pair reads the table of its transpose when that one exists:
+  // K_ji(m) = K_ij(m) if rings i and j have equal pixel weights and the two
+  // pairs have the same grid, shift and band (the kernel depends only on the
+  // angular distance, and the grid is symmetric under a change of sign of
+  // the longitude offset).  (j, i) is a pair of the unit of ring j or, for a
+  // southern ring j, the mirror image (mirror j, mirror i) in the unit of
+  // mirror j.  Halves the tables on HEALPix grids (and counts once towards
+  // the automatic choice's budget).
+  std::vector<int64_t> unit_of(P->nrings, -1);
+  for (int64_t u = 0; u < P->n_units; ++u) unit_of[P->h_units[u].i] = u;
+  auto transpose = [&](int64_t q) -> int64_t {
+    const int64_t nr = P->nrings;
+    int64_t i = P->h_pair_i[q], j = P->h_pairs[q].j;
+    if (j > nr - 1 - j) {
+      j = nr - 1 - j;
+      i = nr - 1 - i;
+    }
+    const int64_t u = unit_of[j];
+    if (u < 0) return -1;
+    const PairDev* b = P->h_pairs.data() + P->h_units[u].pbeg;
+    const PairDev* e = P->h_pairs.data() + P->h_units[u].pend;
+    const PairDev* f = std::lower_bound(b, e, (int32_t)i, [](const PairDev& x, int32_t v) { return x.j < v; });
+    return (f != e && f->j == i) ? (int64_t)(f - P->h_pairs.data()) : -1;
+  };
+  auto compatible = [&](int64_t t, int64_t q) {
+    const PairDev &o = P->h_pairs[t], &pr = P->h_pairs[q];
+    return band[t] == band[q] && o.grid == pr.grid && o.nyq == pr.nyq && P->h_pair_shift[t] == P->h_pair_shift[q] &&
+           P->h_w[P->h_pair_i[q]] == P->h_w[pr.j];
+  };
   // table selection and offsets: automatic choice = tables for every pair if
   // they fit in kAutoTableBytes (the accumulation then only streams them),
   // otherwise tables only for rows too wide for the recurrence
   bool all_auto = false;
   if (first_time && P->opts.kgen == 0) {
     int64_t entries = 0;
-    for (int64_t q = 0; q < np; ++q)
-      if (band[q] >= 0) entries += table_span(band[q]);
+    for (int64_t q = 0; q < np; ++q) {
+      if (band[q] < 0) continue;
+      const int64_t t = transpose(q);
+      if (!(t >= 0 && t < q && compatible(t, q))) entries += table_span(band[q]);
+    }
     all_auto = entries * (int64_t)(P->dtype == ARKCOS_F32 ? 4 : 8) <= kAutoTableBytes;
   }
   int64_t table_total = 0, ntab = 0;
   std::vector<int32_t> tab_list;
   std::vector<int64_t> tab_coef;
+  if (first_time) P->h_tab_owner.assign(np, -1);
   for (int64_t q = 0; q < np; ++q) {
     PairDev& pr = P->h_pairs[q];
     pr.band = band[q];
@@ -181,7 +214,17 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
       if (P->opts.kgen == 2 || all_auto) table = true;
       else if (P->opts.kgen == 0) table = pr.ncoef > kOtfMaxCoef;
     }
-    if (table) {
+    if (table && first_time) {
+      P->h_tab_owner[q] = q;
+      const int64_t t = transpose(q);
+      if (t >= 0 && t < q && P->h_pairs[t].kind == KG_TABLE && compatible(t, q))
+        P->h_tab_owner[q] = P->h_tab_owner[t];
+    }
+    if (table && P->h_tab_owner[q] != q) {
+      pr.kind = KG_TABLE;
+      pr.off = P->h_pairs[P->h_tab_owner[q]].off;
+      ++ntab;
+    } else if (table) {
       pr.kind = KG_TABLE;
       pr.off = table_total;
       table_total += table_span(pr.band);
@@ -205,7 +248,7 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
     bool all = true;
     for (int64_t q = 0; q < np && all; ++q)
       if (P->h_pairs[q].band >= 0 && P->h_pairs[q].kind != KG_TABLE) all = false;
-    P->all_tables = all;
+    P->all_tables = all && ntab > 0;
   }
   const size_t rsz = P->dtype == ARKCOS_F32 ? sizeof(float) : sizeof(double);
   if (first_time) {
@@ -216,15 +259,16 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
     P->d_table = t;
   }
   HIPCHK(hipMemcpy(P->d_pairs, P->h_pairs.data(), np * sizeof(PairDev), hipMemcpyHostToDevice));
-  if (ntab > 0) {
+  const int64_t nlist = (int64_t)tab_list.size();  // tables computed (shared ones once)
+  if (nlist > 0) {
     int32_t* d_list = nullptr;
     int64_t* d_co = nullptr;
-    HIPCHK(hipMalloc(&d_list, ntab * sizeof(int32_t)));
-    HIPCHK(hipMalloc(&d_co, ntab * sizeof(int64_t)));
+    HIPCHK(hipMalloc(&d_list, nlist * sizeof(int32_t)));
+    HIPCHK(hipMalloc(&d_co, nlist * sizeof(int64_t)));
     struct Free2 { void* a; void* b; ~Free2() { hipFree(a); hipFree(b); } } f2{d_list, d_co};
-    HIPCHK(hipMemcpy(d_list, tab_list.data(), ntab * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(d_co, tab_coef.data(), ntab * sizeof(int64_t), hipMemcpyHostToDevice));
-    HIPCHK(launch_table_list(P, d_list, d_co, (int32_t)ntab, s));
+    HIPCHK(hipMemcpy(d_list, tab_list.data(), nlist * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_co, tab_coef.data(), nlist * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(launch_table_list(P, d_list, d_co, (int32_t)nlist, s));
     HIPCHK(hipStreamSynchronize(s));
   }
   return ARKCOS_OK;

@@ -484,7 +484,7 @@ __global__ void __launch_bounds__(kAccThreads) accumulate_kernel(AccArgs<R> a, c
 // Batched form: one persistent launch drains a queue of (map, band, tiles)
 // items shared by many plans; every block exits once the queue counter
 // passes the item count.
-template <typename R, int NW>
+template <typename R, int NW, bool TAB_ONLY>
 __global__ void __launch_bounds__(64 * NW) accumulate_batch_kernel(
     const AccArgs<R>* __restrict__ maps, const int64_t* __restrict__ spec_base,
     const int64_t* __restrict__ out_base, const BatchItem* __restrict__ items, int32_t n_items,
@@ -499,8 +499,8 @@ __global__ void __launch_bounds__(64 * NW) accumulate_batch_kernel(
     if (it >= n_items) break;
     const BatchItem bi = items[it];
     const AccArgs<R> a = maps[bi.map];
-    accumulate_band<R, NW>(a, load_band(a.bands + bi.band), bi.t0, bi.nt, spec + spec_base[bi.map],
-                           bout + out_base[bi.map], smem, lay);
+    accumulate_band<R, NW, TAB_ONLY>(a, load_band(a.bands + bi.band), bi.t0, bi.nt, spec + spec_base[bi.map],
+                                     bout + out_base[bi.map], smem, lay);
   }
 }
 
@@ -544,37 +544,46 @@ size_t acc_lds_bytes(arkcos_dtype_t dt, const AccShape& sh) {
   return (size_t)acc_layout(dt, sh).pairs_off + (size_t)(std::max(sh.max_band_pairs, 1) + 8) * sizeof(PairLds);
 }
 
-template <typename R, int NW>
+template <typename R, int NW, bool TAB_ONLY>
 static hipError_t batch_launch(const void* maps, const int64_t* spec_base, const int64_t* out_base,
                                const BatchItem* items, int32_t n_items, int32_t* counter, const void* spec,
                                void* bout, int32_t grid, size_t lds, AccLayout lay, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)accumulate_batch_kernel<R, NW>,
+  hipError_t e = hipFuncSetAttribute((const void*)accumulate_batch_kernel<R, NW, TAB_ONLY>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  accumulate_batch_kernel<R, NW><<<grid, 64 * NW, lds, s>>>((const AccArgs<R>*)maps, spec_base, out_base, items,
-                                                            n_items, counter, (const cx_t<R>*)spec, (cx_t<R>*)bout,
-                                                            lay);
+  accumulate_batch_kernel<R, NW, TAB_ONLY><<<grid, 64 * NW, lds, s>>>(
+      (const AccArgs<R>*)maps, spec_base, out_base, items, n_items, counter, (const cx_t<R>*)spec, (cx_t<R>*)bout,
+      lay);
   return hipGetLastError();
+}
+
+template <typename R, bool TAB_ONLY>
+static hipError_t batch_launch_nw(int32_t units_per_band, const void* maps, const int64_t* spec_base,
+                                  const int64_t* out_base, const BatchItem* items, int32_t n_items, int32_t* counter,
+                                  const void* spec, void* bout, int32_t grid, size_t lds, AccLayout lay,
+                                  hipStream_t s) {
+  return units_per_band == 4 ? batch_launch<R, 4, TAB_ONLY>(maps, spec_base, out_base, items, n_items, counter, spec,
+                                                            bout, grid, lds, lay, s)
+                             : batch_launch<R, 8, TAB_ONLY>(maps, spec_base, out_base, items, n_items, counter, spec,
+                                                            bout, grid, lds, lay, s);
 }
 
 hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const int64_t* spec_base,
                                    const int64_t* out_base, const BatchItem* items, int32_t n_items,
                                    int32_t* counter, const void* spec, void* bout, int32_t grid,
-                                   int32_t units_per_band, const AccShape& shape, hipStream_t s) {
+                                   int32_t units_per_band, bool all_tables, const AccShape& shape, hipStream_t s) {
   reset_counter_kernel<<<1, 64, 0, s>>>(counter);
   const size_t lds = acc_lds_bytes(dt, shape);
   const AccLayout lay = acc_layout(dt, shape);
   if (dt == ARKCOS_F32)
-    return units_per_band == 4
-               ? batch_launch<float, 4>(maps, spec_base, out_base, items, n_items, counter, spec, bout, grid, lds,
-                                        lay, s)
-               : batch_launch<float, 8>(maps, spec_base, out_base, items, n_items, counter, spec, bout, grid, lds,
-                                        lay, s);
-  return units_per_band == 4
-             ? batch_launch<double, 4>(maps, spec_base, out_base, items, n_items, counter, spec, bout, grid, lds,
-                                       lay, s)
-             : batch_launch<double, 8>(maps, spec_base, out_base, items, n_items, counter, spec, bout, grid, lds,
-                                       lay, s);
+    return all_tables ? batch_launch_nw<float, true>(units_per_band, maps, spec_base, out_base, items, n_items,
+                                                     counter, spec, bout, grid, lds, lay, s)
+                      : batch_launch_nw<float, false>(units_per_band, maps, spec_base, out_base, items, n_items,
+                                                      counter, spec, bout, grid, lds, lay, s);
+  return all_tables ? batch_launch_nw<double, true>(units_per_band, maps, spec_base, out_base, items, n_items,
+                                                    counter, spec, bout, grid, lds, lay, s)
+                    : batch_launch_nw<double, false>(units_per_band, maps, spec_base, out_base, items, n_items,
+                                                     counter, spec, bout, grid, lds, lay, s);
 }
 
 // Modes beyond a unit's band stay zero (B_i has out_len_i = band_i + 1 modes,

@@ -205,7 +205,7 @@ size_t acc_lds_bytes(arkcos_dtype_t dt, const AccShape& shape);
 hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const int64_t* spec_base,
                                    const int64_t* out_base, const BatchItem* items, int32_t n_items,
                                    int32_t* counter, const void* spec, void* bout, int32_t grid,
-                                   int32_t units_per_band, const AccShape& shape, hipStream_t s);
+                                   int32_t units_per_band, bool all_tables, const AccShape& shape, hipStream_t s);
 size_t ring_args_size();
 void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out);
 hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, const void* entries, int32_t count,

@@ -41,6 +41,7 @@ struct arkcos_batch_s {
   int32_t n = 0;
   std::vector<arkcos_plan_s*> plans;
   int32_t units_per_band = kBandUnits, grid = 0, tuned = 0;
+  bool all_tables = false;  // every plan reads all its K_ij(m) from tables
   AccShape acc_shape;
   int64_t spec_total = 0, out_total = 0, npix_total = 0;
   std::vector<int64_t> h_spec_base, h_out_base;
@@ -135,7 +136,7 @@ hipError_t build_queue(arkcos_batch_s* B, const std::vector<int32_t>& maps, int3
 
 std::string tune_key(const arkcos_batch_s* B) {
   std::ostringstream k;
-  k << "dt" << (int)B->dtype << "_n" << B->n;
+  k << "dt" << (int)B->dtype << "_n" << B->n << "_t" << (B->all_tables ? 1 : 0);
   uint64_t h = 1469598103934665603ull;
   for (auto* P : B->plans) {
     const int64_t v[3] = {P->npix, P->pair_modes, P->coef_total};
@@ -192,7 +193,8 @@ hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64
     if (r == 1) e = hipEventRecord(e0, nullptr);
     if (e == hipSuccess)
       e = launch_accumulate_batch(B->dtype, dargs, (const int64_t*)dsb, (const int64_t*)dob, (const BatchItem*)ditems,
-                                  (int32_t)Q.items.size(), counter, spec, bout, grid, upb, Q.shape, nullptr);
+                                  (int32_t)Q.items.size(), counter, spec, bout, grid, upb, B->all_tables, Q.shape,
+                                  nullptr);
   }
   if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -279,7 +281,9 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
   B->n = n;
   B->dtype = plans[0]->dtype;
   B->plans.assign(plans, plans + n);
+  B->all_tables = true;
   for (auto* P : B->plans) {
+    B->all_tables = B->all_tables && P->all_tables;
     B->h_spec_base.push_back(B->spec_total);
     B->h_out_base.push_back(B->out_total);
     B->spec_total += P->spec_total;
@@ -443,7 +447,7 @@ arkcos_status_t run_batch(arkcos_batch_s* B, const void* const* x, void* const* 
                               B->d_spec_base, s));
   if (ev) BLAUNCH(hipEventRecord(ev[1], s));
   BLAUNCH(launch_accumulate_batch(B->dtype, B->d_acc_args, B->d_spec_base, B->d_out_base, B->d_items, B->n_items,
-                                  counter, spec, bout, B->grid, B->units_per_band, B->acc_shape, s));
+                                  counter, spec, bout, B->grid, B->units_per_band, B->all_tables, B->acc_shape, s));
   if (ev) BLAUNCH(hipEventRecord(ev[2], s));
   for (const ClassDev& c : B->classes)
     BLAUNCH(launch_ring_batch(B->dtype, true, B->d_rargs[adjoint ? 3 : 2], c.entries, c.count, c.lds, c.threads, B->d_ys, bout,

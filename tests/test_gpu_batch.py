@@ -52,6 +52,23 @@ def test_batch_equals_per_plan_results():
         assert np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-4
 
 
+def test_batch_mixed_kernel_sources_equal_per_plan_results():
+    """Plans whose K_ij(m) come from tables (automatic and kgen=2) and from the
+    recurrence (kgen=1) in one batch: the batch takes its general path, and
+    every map still equals its own plan's result bit for bit."""
+    from paper_1104_0672_amd import Batch, Plan
+    wl = _small_batch(seed=61, n=6)
+    print("case mixed-source batch of", [w.grid.nside for w in wl], flush=True)
+    plans = [Plan.from_workload(w, kgen=k % 3) for k, w in enumerate(wl)]
+    batch = Batch(plans)
+    xs = [torch.tensor(W.make_input(w), dtype=torch.float32, device="cuda") for w in wl]
+    for adjoint in (False, True):
+        ys = batch.convolve(xs, adjoint=adjoint)
+        for p, x, y in zip(plans, xs, ys):
+            ref = p.adjoint(x) if adjoint else p.convolve(x)
+            assert torch.equal(y, ref)
+
+
 def test_batch_graph_capture_replays():
     from paper_1104_0672_amd import Batch, Plan
     wl = _small_batch(seed=41, n=5)

@@ -516,20 +516,28 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   {
     // launch classes by LDS size: power-of-two buckets from 32 KiB, so that
     // the many small rings share one launch; within a class the longest
-    // rings come first, and a ring and its mirror stay adjacent so they
-    // share cached filters
-    std::map<size_t, std::vector<int32_t>> cls;
+    // rings come first.  Workgroups go to the 8 XCDs round-robin, so each
+    // run of 8 northern rings is followed by their 8 mirrors: a ring and its
+    // mirror then run on the same XCD and share its L2 copy of their
+    // Bluestein filter.
+    std::map<size_t, std::vector<std::pair<int32_t, int32_t>>> pairs_of;
     std::vector<int64_t> order((nr + 1) / 2);
     for (int64_t k = 0; k < (int64_t)order.size(); ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return P->h_n[x] > P->h_n[y]; });
-    auto bucket = [&](int64_t k) {
+    for (int64_t k : order) {
       size_t b = 32768;
       while (b < ring_lds[k]) b <<= 1;
-      cls[b].push_back((int32_t)k);
-    };
-    for (int64_t k : order) {
-      bucket(k);
-      if (nr - 1 - k != k) bucket(nr - 1 - k);
+      pairs_of[b].push_back({(int32_t)k, nr - 1 - k != k ? (int32_t)(nr - 1 - k) : -1});
+    }
+    std::map<size_t, std::vector<int32_t>> cls;
+    for (auto& [b, prs] : pairs_of) {
+      std::vector<int32_t>& lst = cls[b];
+      for (size_t c = 0; c < prs.size(); c += 8) {
+        const size_t e = std::min(prs.size(), c + 8);
+        for (size_t a = c; a < e; ++a) lst.push_back(prs[a].first);
+        for (size_t a = c; a < e; ++a)
+          if (prs[a].second >= 0) lst.push_back(prs[a].second);
+      }
     }
     for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
       FftClass c;

@@ -67,6 +67,17 @@ struct UnitDev {
   int32_t pad;
 };
 
+// One work item of the knot gradient: the narrow rows (at most
+// kGradMaxCoef samples) of unit `unit` (pair = -1), or the samples
+// [d0, d0 + cnt) of the wide row `pair` of that unit.
+struct GradItem {
+  int32_t unit, pair, d0, cnt;
+};
+constexpr int kGradMaxCoef = 48;      // rows up to this length: one item per unit, threads over modes
+constexpr int kGradGroup = 32;        // samples of a wide row per pass over its modes
+constexpr int kGradThreads = 512;     // threads per gradient block
+constexpr double kGradItemWork = 16777216.0;  // samples x modes of a wide-row item
+
 // One accumulation work item: band `band`, mode tiles [t0, t0 + nt) of
 // kAccTile modes each.
 struct WorkItem {
@@ -175,6 +186,11 @@ struct arkcos_plan_s {
   int64_t* d_coef_off = nullptr;    // recurrence-coefficient offset of every pair
   int32_t* d_ncoef_window = nullptr;  // kernel samples inside each pair's window
   double* d_basis_mom = nullptr;    // spline basis moments S[a][k], n_knots^2
+  std::vector<arkcos::GradItem> h_grad_items;  // knot-gradient work items, in unit / pair / sample order
+  arkcos::GradItem* d_grad_items = nullptr;
+  int32_t* d_grad_run = nullptr;    // n_grad_runs + 1 item offsets: the items of each gradient block
+  int32_t n_grad_runs = 0;
+  int32_t grad_zcache_bytes = 0;    // LDS of a gradient block for a wide row's correlation
   int32_t* d_pole_rings = nullptr;  // rings within reach of a pole pixel
   int32_t n_pole_rings = 0;
   size_t plan_bytes = 0;

@@ -44,10 +44,12 @@ struct GradArgs {
   int64_t L;
   int32_t nk;
   double h, radius, theta_max;
-  double* slots;  // [slot][4 * (nk - 1)]
+  double* slots;         // [slot][4 * (nk - 1)]
+  int64_t TN;            // length of the twiddle table
+  int32_t zcache_bytes;  // LDS for a wide row's correlation
 };
 
-constexpr int kGradMaxCoef = 48;  // rows up to this length: threads over modes
+constexpr int kGradModes = 4;  // modes per thread at once in the wide rows
 
 __device__ __forceinline__ double grad_distance(double ti, double tj, double si, double sj, int64_t num,
                                                 int64_t den) {
@@ -88,138 +90,222 @@ __device__ __forceinline__ void ordered_scatter(double* U, const GradArgs& g, do
   __syncthreads();
 }
 
+// The same for the samples of one kernel row (count <= kBlock): thread k
+// provides sample d0 + k, whose distance does not decrease with k (it grows with the
+// longitude offset), so the interval index is non-decreasing in k and each
+// interval's samples are a contiguous run.  Thread (a, c) sums piece c over
+// interval a's run in thread order and adds the sum into U: parallel, and
+// still independent of timing.  Samples outside the support get index nk
+// (past every interval), which keeps the order.
+__device__ __forceinline__ void row_scatter(double* U, const GradArgs& g, int* sa, double* sp, int count, double t,
+                                            double wgt) {
+  const int tid = threadIdx.x;
+  int a = g.nk;
+  double pc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (tid < count && !(t > g.radius || t > g.theta_max + kSupportTol)) {
+    a = (int)floor(t / g.h);
+    a = a < 0 ? 0 : (a > g.nk - 2 ? g.nk - 2 : a);
+    const double u = t / g.h - a, v = 1.0 - u, h2 = g.h * g.h / 6.0;
+    pc[0] = wgt * v;
+    pc[1] = wgt * u;
+    pc[2] = wgt * h2 * (v * v * v - v);
+    pc[3] = wgt * h2 * (u * u * u - u);
+  }
+  if (tid < count) {
+    sa[tid] = a;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sp[c * kBlock + tid] = pc[c];
+  }
+  __syncthreads();
+  for (int k = tid; k < 4 * (g.nk - 1); k += blockDim.x) {
+    const int ia = k >> 2, c = k & 3;
+    int lo = 0, hi = count;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sa[mid] < ia) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < count && sa[lo] == ia) {
+      double sum = 0.0;
+      for (int d = lo; d < count && sa[d] == ia; ++d) sum += sp[c * kBlock + d];
+      U[k] += sum;
+    }
+  }
+  __syncthreads();
+}
+
+// cos(pi k / pl) for an integer k: from the twiddle table when 2 pl divides
+// its length (tw[k'] = exp(-2 pi i k' / TN)), otherwise computed.
 template <typename R>
-__global__ void __launch_bounds__(kBlock) grad_pairs_kernel(GradArgs g, const cx_t<R>* __restrict__ aspec,
-                                                            const cx_t<R>* __restrict__ rspec) {
+__device__ __forceinline__ double cos_pi_over(int64_t k, int64_t pl, const cx_t<R>* __restrict__ tw, int64_t TN) {
+  if (TN % (2 * pl) == 0) return (double)tw[(k & (2 * pl - 1)) * (TN / (2 * pl))].x;
+  return cospi((double)(k % (2 * pl)) / (double)pl);
+}
+
+// One block per run of work items (a fixed, cost-balanced partition), its
+// interval sums accumulated over the run in item order and written to the
+// block's slot.  An item is either the narrow rows (at most kGradMaxCoef
+// samples) of one unit, or a range of samples of one wide row.
+//
+// Narrow rows: threads over modes, per-thread sums for every sample, the
+// cosines by the three-term recurrence in the sample index d.
+//
+// Wide rows: the correlation Z(m) = eps_m h(m) (X_ij(m) + X_i'j'(m)) of the
+// pair is staged in LDS once per item (in the plan's precision), then the
+// item's samples are taken kGradGroup at a time: every thread runs over
+// kGradModes of its modes at once, with cos(m nu_d) started at the group's
+// first two samples (twiddle table, or computed) and continued by the
+// recurrence in d; the per-thread sums are reduced over the block (wave
+// shuffles, then the waves in order) and scattered.
+template <typename R>
+__global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, const GradItem* __restrict__ items,
+                                                                  const int32_t* __restrict__ run,
+                                                                  const cx_t<R>* __restrict__ aspec,
+                                                                  const cx_t<R>* __restrict__ rspec,
+                                                                  const cx_t<R>* __restrict__ tw) {
   using C = cx_t<R>;
+  constexpr int NWV = kGradThreads / 64;
+  extern __shared__ __align__(16) unsigned char gsm[];
+  R* zc = reinterpret_cast<R*>(gsm);  // Z(m) of the current wide row
   __shared__ double U[4 * 63];
+  __shared__ double part[NWV * kGradMaxCoef];
   __shared__ double Y[kGradMaxCoef];
-  __shared__ double part[kBlock / 64 * kGradMaxCoef];
-  __shared__ double xs[kBlock];
-  __shared__ double st[kBlock];
-  __shared__ double sw[kBlock];
+  __shared__ double sp[4 * kBlock];
+  __shared__ int sa[kBlock];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nint4 = 4 * (g.nk - 1);
   for (int e = tid; e < nint4; e += blockDim.x) U[e] = 0.0;
-  const UnitDev u = g.units[blockIdx.x];
-  const bool mirror = u.im >= 0;
   __syncthreads();
-  for (int q = u.pbeg; q < u.pend; ++q) {
-    const PairDev pr = g.pairs[q];
-    if (pr.band < 0) continue;
-    const int j = pr.j, jm = g.nrings - 1 - j;
-    const int nc = g.ncoef_window[q], s = g.pair_shift[q];
-    const int64_t pl = (int64_t)pr.grid;
-    const C* ai = aspec + g.spec_off[j];
-    const C* ri = rspec + g.out_off[u.i];
-    const C* am = aspec + g.spec_off[jm];
-    const C* rm = mirror ? rspec + g.out_off[u.im] : ri;
-    const double scale = g.w[j] / (double)pl;
-    auto xcorr = [&](int m) -> double {  // eps_m h(m) (X_ij(m) + X_i'j'(m))
-      const C a0 = ai[m], r0 = ri[m];
-      double X = (double)r0.x * a0.x + (double)r0.y * a0.y;
-      if (mirror) {
-        const C a1 = am[m], r1 = rm[m];
-        X += (double)r1.x * a1.x + (double)r1.y * a1.y;
-      }
-      double wm = m == 0 ? 1.0 : 2.0;
-      if (m == pr.nyq) wm *= 0.5;
-      return X * wm;
-    };
-    auto sample = [&](int d, double& t, double& cd) {
-      t = grad_distance(g.theta[u.i], g.theta[j], g.sint[u.i], g.sint[j], 2 * (int64_t)d + s, pl);
-      cd = (s == 0 && (d == 0 || 2 * (int64_t)d == pl)) ? 1.0 : 2.0;
-    };
-    if (nc <= kGradMaxCoef) {
-      // threads over modes; per-thread sums for every sample d
-      double acc[kGradMaxCoef];
+  // per-thread sums acc[0..cnt) -> Y[0..cnt) (every wave's sums, then the
+  // waves in order), Y ready on return
+  auto reduce = [&](auto& acc, int cnt) {
+    constexpr int NA = sizeof(acc) / sizeof(acc[0]);
 #pragma unroll
-      for (int d = 0; d < kGradMaxCoef; ++d) acc[d] = 0.0;
-      for (int m = tid; m <= pr.band; m += blockDim.x) {
-        const double X = xcorr(m);
-        // cos(m nu_d), nu_d = pi (2d + s) / (p L), by the Chebyshev recurrence in d
-        double c0, c1, step;
-        if (s == 0) {
-          c0 = 1.0;
-          c1 = cospi(2.0 * (double)m / (double)pl);
-          step = 2.0 * c1;
-        } else {
-          c0 = cospi((double)m / (double)pl);
-          c1 = cospi(3.0 * (double)m / (double)pl);
-          step = 2.0 * cospi(2.0 * (double)m / (double)pl);
+    for (int d = 0; d < NA; ++d) {
+      if (d < cnt) {
+        const double v = wave_sum(acc[d]);
+        if (lane == 0) part[wv * kGradMaxCoef + d] = v;
+      }
+    }
+    __syncthreads();
+    if (tid < cnt) {
+      double t = 0.0;
+      for (int k = 0; k < NWV; ++k) t += part[k * kGradMaxCoef + tid];
+      Y[tid] = t;
+    }
+    __syncthreads();
+  };
+  const int it0 = run[blockIdx.x], it1 = run[blockIdx.x + 1];
+  for (int it = it0; it < it1; ++it) {
+    const GradItem item = items[it];
+    const UnitDev u = g.units[item.unit];
+    const bool mirror = u.im >= 0;
+    const int q0 = item.pair < 0 ? u.pbeg : item.pair, q1 = item.pair < 0 ? u.pend : item.pair + 1;
+    for (int q = q0; q < q1; ++q) {
+      const PairDev pr = g.pairs[q];
+      const int nc = g.ncoef_window[q], s = g.pair_shift[q];
+      if (pr.band < 0 || (item.pair < 0) != (nc <= kGradMaxCoef)) continue;
+      const int j = pr.j, jm = g.nrings - 1 - j;
+      const int64_t pl = (int64_t)pr.grid;
+      const C* ai = aspec + g.spec_off[j];
+      const C* ri = rspec + g.out_off[u.i];
+      const C* am = aspec + g.spec_off[jm];
+      const C* rm = mirror ? rspec + g.out_off[u.im] : ri;
+      const double scale = g.w[j] / (double)pl;
+      auto xcorr = [&](int m) -> double {  // eps_m h(m) (X_ij(m) + X_i'j'(m))
+        const C a0 = ai[m], r0 = ri[m];
+        double X = (double)r0.x * a0.x + (double)r0.y * a0.y;
+        if (mirror) {
+          const C a1 = am[m], r1 = rm[m];
+          X += (double)r1.x * a1.x + (double)r1.y * a1.y;
         }
+        double wm = m == 0 ? 1.0 : 2.0;
+        if (m == pr.nyq) wm *= 0.5;
+        return X * wm;
+      };
+      auto sample = [&](int d, double& t, double& cd) {
+        t = grad_distance(g.theta[u.i], g.theta[j], g.sint[u.i], g.sint[j], 2 * (int64_t)d + s, pl);
+        cd = (s == 0 && (d == 0 || 2 * (int64_t)d == pl)) ? 1.0 : 2.0;
+      };
+      if (item.pair < 0) {
+        double acc[kGradMaxCoef];
 #pragma unroll
-        for (int d = 0; d < kGradMaxCoef; ++d) {
-          if (d < nc) acc[d] = fma(X, c0, acc[d]);
-          const double c2 = fma(step, c1, -c0);
-          c0 = c1;
-          c1 = c2;
-        }
-      }
-      // reduce every sample's sums over the wave, then over the waves in
-      // order, with one barrier
+        for (int d = 0; d < kGradMaxCoef; ++d) acc[d] = 0.0;
+        for (int m = tid; m <= pr.band; m += blockDim.x) {
+          const double X = xcorr(m);
+          // cos(m nu_d), nu_d = pi (2d + s) / pl, by the Chebyshev recurrence in d
+          double c0 = cos_pi_over<R>((int64_t)m * s, pl, tw, g.TN);
+          double c1 = cos_pi_over<R>((int64_t)m * (2 + s), pl, tw, g.TN);
+          const double step = 2.0 * cos_pi_over<R>(2 * (int64_t)m, pl, tw, g.TN);
 #pragma unroll
-      for (int d = 0; d < kGradMaxCoef; ++d) {
-        if (d < nc) {
-          const double v = wave_sum(acc[d]);
-          if (lane == 0) part[wv * kGradMaxCoef + d] = v;
+          for (int d = 0; d < kGradMaxCoef; ++d) {
+            acc[d] = fma(X, c0, acc[d]);
+            const double c2 = fma(step, c1, -c0);
+            c0 = c1;
+            c1 = c2;
+          }
         }
+        reduce(acc, nc);
+        double t = 0.0, cd = 0.0, wgt = 0.0;
+        if (tid < nc) {
+          sample(tid, t, cd);
+          wgt = cd * scale * Y[tid];
+        }
+        row_scatter(U, g, sa, sp, nc, t, wgt);
+        continue;
       }
-      __syncthreads();
-      if (tid < nc) {
-        double t = 0.0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k * kGradMaxCoef + tid];
-        Y[tid] = t;
+      // a wide row: stage Z(m) (or evaluate it on the fly when it does not fit)
+      const bool cached = (int64_t)(pr.band + 1) * (int64_t)sizeof(R) <= (int64_t)g.zcache_bytes;
+      if (cached) {
+        for (int m = tid; m <= pr.band; m += blockDim.x) zc[m] = (R)xcorr(m);
+        __syncthreads();
       }
-      __syncthreads();
-      double t = 0.0, cd = 0.0, wgt = 0.0;
-      if (tid < nc) {
-        sample(tid, t, cd);
-        wgt = cd * scale * Y[tid];
-      }
-      ordered_scatter(U, g, st, sw, nc, t, wgt);
-    } else {
-      // wide rows: threads over samples, modes staged in chunks; cos(m nu_d)
-      // by the three-term recurrence in m, restarted from exact values at
-      // every chunk
-      for (int d0 = 0; d0 < nc; d0 += blockDim.x) {
-        const int d = d0 + tid;
-        const int64_t nd = 2 * (int64_t)d + s;  // nu_d = pi nd / (p L)
-        const double step = d < nc ? 2.0 * cospi((double)nd / (double)pl) : 0.0;
-        double y = 0.0;
-        for (int m0 = 0; m0 <= pr.band; m0 += blockDim.x) {
-          const int m = m0 + tid;
-          xs[tid] = m <= pr.band ? xcorr(m) : 0.0;
-          __syncthreads();
-          if (d < nc) {
-            // cos((m0 - 1) nu_d) and cos(m0 nu_d), exactly (angles reduced mod 2 pi)
-            const int64_t p0 = (nd * (int64_t)m0) % (2 * pl);
-            const int64_t pm = (nd * (int64_t)(m0 > 0 ? m0 - 1 : 1)) % (2 * pl);
-            double cp = cospi((double)pm / (double)pl), cc = cospi((double)p0 / (double)pl);
-            const int mc = min((int)blockDim.x, pr.band - m0 + 1);
-            for (int k = 0; k < mc; ++k) {
-              y = fma(xs[k], cc, y);
-              const double cn = fma(step, cc, -cp);
-              cp = cc;
-              cc = cn;
+      const int dend = item.d0 + item.cnt;
+      for (int gd = item.d0; gd < dend; gd += kGradGroup) {
+        const int cnt = min(kGradGroup, dend - gd);
+        double acc[kGradGroup];
+#pragma unroll
+        for (int d = 0; d < kGradGroup; ++d) acc[d] = 0.0;
+        const int64_t k0 = 2 * (int64_t)gd + s;  // nu_gd = pi k0 / pl
+        for (int mb = tid; mb <= pr.band; mb += kGradModes * blockDim.x) {
+          double z[kGradModes], c0[kGradModes], c1[kGradModes], st[kGradModes];
+#pragma unroll
+          for (int k = 0; k < kGradModes; ++k) {
+            const int m = mb + k * blockDim.x;
+            const bool ok = m <= pr.band;
+            const int mm = ok ? m : 0;
+            z[k] = ok ? (cached ? (double)zc[mm] : xcorr(mm)) : 0.0;
+            c0[k] = cos_pi_over<R>((int64_t)mm * k0, pl, tw, g.TN);
+            c1[k] = cos_pi_over<R>((int64_t)mm * (k0 + 2), pl, tw, g.TN);
+            st[k] = 2.0 * cos_pi_over<R>(2 * (int64_t)mm, pl, tw, g.TN);
+          }
+#pragma unroll
+          for (int d = 0; d < kGradGroup; ++d) {
+#pragma unroll
+            for (int k = 0; k < kGradModes; ++k) {
+              acc[d] = fma(z[k], c0[k], acc[d]);
+              const double c2 = fma(st[k], c1[k], -c0[k]);
+              c0[k] = c1[k];
+              c1[k] = c2;
             }
           }
-          __syncthreads();
         }
+        reduce(acc, cnt);
         double t = 0.0, cd = 0.0, wgt = 0.0;
-        if (d < nc) {
-          sample(d, t, cd);
-          wgt = cd * scale * y;
+        if (tid < cnt) {
+          sample(gd + tid, t, cd);
+          wgt = cd * scale * Y[tid];
         }
-        ordered_scatter(U, g, st, sw, min((int)blockDim.x, nc - d0), t, wgt);
+        row_scatter(U, g, sa, sp, cnt, t, wgt);
       }
+      __syncthreads();  // zc is rewritten by the next row
     }
   }
   double* out = g.slots + (size_t)blockIdx.x * nint4;
   for (int e = tid; e < nint4; e += blockDim.x) out[e] = U[e];
 }
 
-// Direct-sum pole rows: one block per pole pixel p, slot n_units + b.
+// Direct-sum pole rows: one block per pole pixel p, slot slot0 + b.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) grad_pole_kernel(GradArgs g, const int32_t* __restrict__ rings,
                                                            int32_t nlist, const R* __restrict__ x,
@@ -310,19 +396,34 @@ arkcos_status_t run_kernel_grad(arkcos_plan_s* P, const void* x, const void* r, 
   g.radius = P->radius + kSupportTol;
   g.theta_max = P->theta_max;
   g.slots = slots;
-  const int32_t nunits = (int32_t)P->n_units;
-  if (P->dtype == ARKCOS_F32)
-    grad_pairs_kernel<float><<<nunits, kBlock, 0, s>>>(g, (const float2*)spec, (const float2*)bout);
-  else
-    grad_pairs_kernel<double><<<nunits, kBlock, 0, s>>>(g, (const double2*)spec, (const double2*)bout);
-  int32_t nslots = nunits;
+  g.TN = P->twiddle_n;
+  g.zcache_bytes = P->grad_zcache_bytes;
+  const int32_t nruns = P->n_grad_runs;
+  const size_t lds = (size_t)P->grad_zcache_bytes;
+  if (P->dtype == ARKCOS_F32) {
+    e = hipFuncSetAttribute((const void*)grad_items_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e == hipSuccess)
+      grad_items_kernel<float><<<nruns, kGradThreads, lds, s>>>(g, P->d_grad_items, P->d_grad_run,
+                                                                (const float2*)spec, (const float2*)bout,
+                                                                (const float2*)P->d_twiddle);
+  } else {
+    e = hipFuncSetAttribute((const void*)grad_items_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e == hipSuccess)
+      grad_items_kernel<double><<<nruns, kGradThreads, lds, s>>>(g, P->d_grad_items, P->d_grad_run,
+                                                                 (const double2*)spec, (const double2*)bout,
+                                                                 (const double2*)P->d_twiddle);
+  }
+  if (e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string("gradient kernels: ") + hipGetErrorString(e));
+  int32_t nslots = nruns;
   if (fix) {
     int32_t count = 0;
     int32_t* list = pole_ring_list(P, &count);
     if (P->dtype == ARKCOS_F32)
-      grad_pole_kernel<float><<<8, kBlock, 0, s>>>(g, list, count, (const float*)x, (const float*)r, nunits);
+      grad_pole_kernel<float><<<8, kBlock, 0, s>>>(g, list, count, (const float*)x, (const float*)r, nruns);
     else
-      grad_pole_kernel<double><<<8, kBlock, 0, s>>>(g, list, count, (const double*)x, (const double*)r, nunits);
+      grad_pole_kernel<double><<<8, kBlock, 0, s>>>(g, list, count, (const double*)x, (const double*)r, nruns);
     nslots += 8;
   }
   grad_final_kernel<<<1, kBlock, 0, s>>>(slots, nslots, g.nk, P->d_basis_mom, grad);

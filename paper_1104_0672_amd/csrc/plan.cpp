@@ -97,6 +97,65 @@ arkcos_status_t upload_knots(arkcos_plan_s* P) {
   return ARKCOS_OK;
 }
 
+// Work items of the knot gradient (spline plans): per unit its narrow rows,
+// and every wide row cut into sample ranges of about kGradItemWork samples x
+// modes; then the items cut into runs of equal estimated cost, one run per
+// gradient block (about four per CU).  Depends only on the pairs' windows and
+// bands, which knot updates keep.
+arkcos_status_t build_grad_items(arkcos_plan_s* P) {
+  std::vector<GradItem> items;
+  std::vector<double> cost;
+  int64_t zmax = 0;
+  for (int64_t u = 0; u < P->n_units; ++u) {
+    const UnitDev& U = P->h_units[u];
+    double narrow = 0.0;
+    for (int32_t q = U.pbeg; q < U.pend; ++q) {
+      const PairDev& pr = P->h_pairs[q];
+      const int64_t nc = P->h_ncoef_window[q];
+      if (pr.band >= 0 && nc <= kGradMaxCoef) narrow += (double)kGradMaxCoef * (pr.band + 1) + 1000.0;
+    }
+    if (narrow > 0.0) {
+      items.push_back(GradItem{(int32_t)u, -1, 0, 0});
+      cost.push_back(narrow);
+    }
+    for (int32_t q = U.pbeg; q < U.pend; ++q) {
+      const PairDev& pr = P->h_pairs[q];
+      const int64_t nc = P->h_ncoef_window[q];
+      if (pr.band < 0 || nc <= kGradMaxCoef) continue;
+      zmax = std::max<int64_t>(zmax, pr.band + 1);
+      int64_t per = (int64_t)(kGradItemWork / (double)(pr.band + 1)) / kGradGroup * kGradGroup;
+      per = std::max<int64_t>(per, kGradGroup);
+      for (int64_t d0 = 0; d0 < nc; d0 += per) {
+        const int64_t cnt = std::min(per, nc - d0);
+        items.push_back(GradItem{(int32_t)u, q, (int32_t)d0, (int32_t)cnt});
+        cost.push_back((double)(cnt + 8) * (pr.band + 1) + 4000.0);
+      }
+    }
+  }
+  int cus = 0;
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device));
+  const int64_t nruns = std::max<int64_t>(1, std::min<int64_t>((int64_t)items.size(), 4 * (int64_t)cus));
+  double total = 0.0;
+  for (double c : cost) total += c;
+  std::vector<int32_t> run(nruns + 1, (int32_t)items.size());
+  run[0] = 0;
+  double acc = 0.0;
+  int64_t r = 1;
+  for (size_t k = 0; k < items.size() && r < nruns; ++k) {
+    acc += cost[k];
+    while (r < nruns && acc >= total * (double)r / (double)nruns) run[r++] = (int32_t)(k + 1);
+  }
+  P->h_grad_items = items;
+  P->n_grad_runs = (int32_t)nruns;
+  // a wide row's correlation is staged in LDS when it fits next to the
+  // block's other arrays (about 18 KB)
+  const int64_t rsz = P->dtype == ARKCOS_F32 ? 4 : 8;
+  P->grad_zcache_bytes = (int32_t)std::min<int64_t>((zmax * rsz + 15) / 16 * 16, 139264);
+  HIPCHK(upload(P, &P->d_grad_items, items));
+  HIPCHK(upload(P, &P->d_grad_run, run));
+  return ARKCOS_OK;
+}
+
 // Kernel samples, bands and tables from the current profile.  Called at plan
 // creation and again by arkcos_set_knots; ring pairs and windows stay fixed.
 arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
@@ -656,6 +715,23 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
     for (auto& kv : h)
       fprintf(stderr, "arkcos plan: kind %d row %d: %lld unit-pair modes\n", kv.first.first, kv.first.second,
               (long long)kv.second);
+    // the knot gradient's per-pair correlation: window samples x modes
+    double sm_narrow = 0.0, sm_wide = 0.0;
+    int64_t n_narrow = 0, n_wide = 0, max_nc = 0;
+    for (int64_t q = 0; q < P->n_pairs; ++q) {
+      const PairDev& pr = P->h_pairs[q];
+      if (pr.band < 0) continue;
+      const int64_t nc = P->h_ncoef_window[q];
+      max_nc = std::max(max_nc, nc);
+      if (nc <= kGradMaxCoef) sm_narrow += (double)nc * (pr.band + 1), ++n_narrow;
+      else sm_wide += (double)nc * (pr.band + 1), ++n_wide;
+    }
+    fprintf(stderr, "arkcos plan: gradient samples x modes: %lld narrow rows %.3g, %lld wide rows %.3g (max %lld samples)\n",
+            (long long)n_narrow, sm_narrow, (long long)n_wide, sm_wide, (long long)max_nc);
+  }
+  if (P->prof_kind == 1) {
+    arkcos_status_t st = build_grad_items(P);
+    if (st != ARKCOS_OK) return st;
   }
 
   // ----------------------------------------- spectra / output layout
@@ -796,7 +872,7 @@ static size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
 static size_t grad_slot_bytes(const arkcos_plan_s* P) {
   if (P->prof_kind != 1) return 0;
-  return al256((size_t)(P->n_units + 8) * 4 * (P->knots.size() - 1) * sizeof(double));
+  return al256((size_t)(P->n_grad_runs + 8) * 4 * (P->knots.size() - 1) * sizeof(double));
 }
 
 size_t workspace_bytes(const arkcos_plan_s* P) {

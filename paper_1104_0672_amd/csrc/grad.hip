@@ -134,12 +134,20 @@ __device__ __forceinline__ void row_scatter(double* U, const GradArgs& g, int* s
   __syncthreads();
 }
 
-// cos(pi k / pl) for an integer k: from the twiddle table when 2 pl divides
-// its length (tw[k'] = exp(-2 pi i k' / TN)), otherwise computed.
+// cos(pi k / pl) for integers k >= 0 on one kernel grid: read from the
+// twiddle table (tw[k'] = exp(-2 pi i k' / TN)) when 2 pl divides its length,
+// otherwise computed.  `table` is fixed per grid, so the loops below are
+// compiled once for each case and the table reads carry no branches.
+template <typename R> struct GridCos {
+  const cx_t<R>* tw;
+  int64_t pl, mask, stride;
+  __device__ __forceinline__ R raw(int64_t k) const { return tw[(k & mask) * stride].x; }
+  __device__ __forceinline__ double exact(int64_t k) const { return cospi((double)(k % (2 * pl)) / (double)pl); }
+};
 template <typename R>
-__device__ __forceinline__ double cos_pi_over(int64_t k, int64_t pl, const cx_t<R>* __restrict__ tw, int64_t TN) {
-  if (TN % (2 * pl) == 0) return (double)tw[(k & (2 * pl - 1)) * (TN / (2 * pl))].x;
-  return cospi((double)(k % (2 * pl)) / (double)pl);
+__device__ __forceinline__ GridCos<R> grid_cos(const cx_t<R>* tw, int64_t pl, int64_t TN, bool& table) {
+  table = TN % (2 * pl) == 0;
+  return GridCos<R>{tw, pl, 2 * pl - 1, table ? TN / (2 * pl) : 0};
 }
 
 // One block per run of work items (a fixed, cost-balanced partition), its
@@ -227,24 +235,39 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
         t = grad_distance(g.theta[u.i], g.theta[j], g.sint[u.i], g.sint[j], 2 * (int64_t)d + s, pl);
         cd = (s == 0 && (d == 0 || 2 * (int64_t)d == pl)) ? 1.0 : 2.0;
       };
+      bool table = false;
+      const GridCos<R> gc = grid_cos<R>(tw, pl, g.TN, table);
       if (item.pair < 0) {
         double acc[kGradMaxCoef];
 #pragma unroll
         for (int d = 0; d < kGradMaxCoef; ++d) acc[d] = 0.0;
-        for (int m = tid; m <= pr.band; m += blockDim.x) {
-          const double X = xcorr(m);
-          // cos(m nu_d), nu_d = pi (2d + s) / pl, by the Chebyshev recurrence in d
-          double c0 = cos_pi_over<R>((int64_t)m * s, pl, tw, g.TN);
-          double c1 = cos_pi_over<R>((int64_t)m * (2 + s), pl, tw, g.TN);
-          const double step = 2.0 * cos_pi_over<R>(2 * (int64_t)m, pl, tw, g.TN);
+        auto modes = [&](auto tab) {
+          constexpr bool TAB = decltype(tab)::value;
+          for (int m = tid; m <= pr.band; m += blockDim.x) {
+            // cos(m nu_d), nu_d = pi (2d + s) / pl, by the Chebyshev recurrence in d
+            double c0, c1, step;
+            if constexpr (TAB) {
+              const R a = gc.raw((int64_t)m * s), b = gc.raw((int64_t)m * (2 + s)), c = gc.raw(2 * (int64_t)m);
+              c0 = a;
+              c1 = b;
+              step = 2.0 * (double)c;
+            } else {
+              c0 = gc.exact((int64_t)m * s);
+              c1 = gc.exact((int64_t)m * (2 + s));
+              step = 2.0 * gc.exact(2 * (int64_t)m);
+            }
+            const double X = xcorr(m);
 #pragma unroll
-          for (int d = 0; d < kGradMaxCoef; ++d) {
-            acc[d] = fma(X, c0, acc[d]);
-            const double c2 = fma(step, c1, -c0);
-            c0 = c1;
-            c1 = c2;
+            for (int d = 0; d < kGradMaxCoef; ++d) {
+              acc[d] = fma(X, c0, acc[d]);
+              const double c2 = fma(step, c1, -c0);
+              c0 = c1;
+              c1 = c2;
+            }
           }
-        }
+        };
+        if (table) modes(std::true_type{});
+        else modes(std::false_type{});
         reduce(acc, nc);
         double t = 0.0, cd = 0.0, wgt = 0.0;
         if (tid < nc) {
@@ -267,29 +290,56 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
 #pragma unroll
         for (int d = 0; d < kGradGroup; ++d) acc[d] = 0.0;
         const int64_t k0 = 2 * (int64_t)gd + s;  // nu_gd = pi k0 / pl
-        for (int mb = tid; mb <= pr.band; mb += kGradModes * blockDim.x) {
-          double z[kGradModes], c0[kGradModes], c1[kGradModes], st[kGradModes];
-#pragma unroll
-          for (int k = 0; k < kGradModes; ++k) {
-            const int m = mb + k * blockDim.x;
-            const bool ok = m <= pr.band;
-            const int mm = ok ? m : 0;
-            z[k] = ok ? (cached ? (double)zc[mm] : xcorr(mm)) : 0.0;
-            c0[k] = cos_pi_over<R>((int64_t)mm * k0, pl, tw, g.TN);
-            c1[k] = cos_pi_over<R>((int64_t)mm * (k0 + 2), pl, tw, g.TN);
-            st[k] = 2.0 * cos_pi_over<R>(2 * (int64_t)mm, pl, tw, g.TN);
-          }
-#pragma unroll
-          for (int d = 0; d < kGradGroup; ++d) {
+        const int step_m = kGradModes * blockDim.x;
+        auto modes = [&](auto tab) {
+          constexpr bool TAB = decltype(tab)::value;
+          // table form: the next step's twiddle reads are issued before the
+          // current step's recurrences (modes past the band read mode 0)
+          R t0[kGradModes], t1[kGradModes], t2[kGradModes];
+          auto fetch = [&](int mb) {
 #pragma unroll
             for (int k = 0; k < kGradModes; ++k) {
-              acc[d] = fma(z[k], c0[k], acc[d]);
-              const double c2 = fma(st[k], c1[k], -c0[k]);
-              c0[k] = c1[k];
-              c1[k] = c2;
+              const int m = mb + k * (int)blockDim.x;
+              const int64_t mm = m <= pr.band ? m : 0;
+              t0[k] = gc.raw(mm * k0);
+              t1[k] = gc.raw(mm * (k0 + 2));
+              t2[k] = gc.raw(2 * mm);
+            }
+          };
+          if constexpr (TAB) fetch(tid);
+          for (int mb = tid; mb <= pr.band; mb += step_m) {
+            double z[kGradModes], c0[kGradModes], c1[kGradModes], st[kGradModes];
+#pragma unroll
+            for (int k = 0; k < kGradModes; ++k) {
+              const int m = mb + k * (int)blockDim.x;
+              const bool ok = m <= pr.band;
+              const int mm = ok ? m : 0;
+              z[k] = ok ? (cached ? (double)zc[mm] : xcorr(mm)) : 0.0;
+              if constexpr (TAB) {
+                c0[k] = t0[k];
+                c1[k] = t1[k];
+                st[k] = 2.0 * (double)t2[k];
+              } else {
+                c0[k] = gc.exact((int64_t)mm * k0);
+                c1[k] = gc.exact((int64_t)mm * (k0 + 2));
+                st[k] = 2.0 * gc.exact(2 * (int64_t)mm);
+              }
+            }
+            if constexpr (TAB) fetch(mb + step_m);
+#pragma unroll
+            for (int d = 0; d < kGradGroup; ++d) {
+#pragma unroll
+              for (int k = 0; k < kGradModes; ++k) {
+                acc[d] = fma(z[k], c0[k], acc[d]);
+                const double c2 = fma(st[k], c1[k], -c0[k]);
+                c0[k] = c1[k];
+                c1[k] = c2;
+              }
             }
           }
-        }
+        };
+        if (table) modes(std::true_type{});
+        else modes(std::false_type{});
         reduce(acc, cnt);
         double t = 0.0, cd = 0.0, wgt = 0.0;
         if (tid < cnt) {

@@ -74,7 +74,7 @@ struct GradItem {
   int32_t unit, pair, d0, cnt;
 };
 constexpr int kGradMaxCoef = 48;      // rows up to this length: one item per unit, threads over modes
-constexpr int kGradGroup = 32;        // samples of a wide row per pass over its modes
+constexpr int kGradPass = 256;        // samples of a wide row per pass over its modes
 constexpr int kGradThreads = 512;     // threads per gradient block
 constexpr double kGradItemWork = 16777216.0;  // samples x modes of a wide-row item
 

@@ -49,7 +49,9 @@ struct GradArgs {
   int32_t zcache_bytes;  // LDS for a wide row's correlation
 };
 
-constexpr int kGradModes = 4;  // modes per thread at once in the wide rows
+constexpr int kGradSpl = kGradPass / 64;  // wide rows: samples per lane in a pass
+constexpr int kGradRestart = 1024;  // wide rows: modes between exact restarts of the cosine recurrence
+static_assert(64 * kGradSpl <= kBlock, "a pass's samples are scattered at once");
 
 __device__ __forceinline__ double grad_distance(double ti, double tj, double si, double sj, int64_t num,
                                                 int64_t den) {
@@ -160,11 +162,10 @@ __device__ __forceinline__ GridCos<R> grid_cos(const cx_t<R>* tw, int64_t pl, in
 //
 // Wide rows: the correlation Z(m) = eps_m h(m) (X_ij(m) + X_i'j'(m)) of the
 // pair is staged in LDS once per item (in the plan's precision), then the
-// item's samples are taken kGradGroup at a time: every thread runs over
-// kGradModes of its modes at once, with cos(m nu_d) started at the group's
-// first two samples (twiddle table, or computed) and continued by the
-// recurrence in d; the per-thread sums are reduced over the block (wave
-// shuffles, then the waves in order) and scattered.
+// item's samples are taken 64 kGradSpl at a time, each lane holding
+// kGradSpl samples and each wave one contiguous range of modes, so every
+// mode's Z is one broadcast LDS read for a whole wave and needs no
+// reduction across lanes; the waves' partial sums are added in wave order.
 template <typename R>
 __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, const GradItem* __restrict__ items,
                                                                   const int32_t* __restrict__ run,
@@ -176,10 +177,14 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
   extern __shared__ __align__(16) unsigned char gsm[];
   R* zc = reinterpret_cast<R*>(gsm);  // Z(m) of the current wide row
   __shared__ double U[4 * 63];
-  __shared__ double part[NWV * kGradMaxCoef];
   __shared__ double Y[kGradMaxCoef];
   __shared__ double sp[4 * kBlock];
   __shared__ int sa[kBlock];
+  // partial sums: a wide-row pass's per-wave sums, or a narrow row's
+  // per-wave reductions (never in use at the same time)
+  __shared__ double red[NWV * 64 * kGradSpl];
+  double* part = red;
+  static_assert(kGradMaxCoef <= 64 * kGradSpl, "narrow reductions fit the pass buffer");
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nint4 = 4 * (g.nk - 1);
   for (int e = tid; e < nint4; e += blockDim.x) U[e] = 0.0;
@@ -283,68 +288,68 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
         for (int m = tid; m <= pr.band; m += blockDim.x) zc[m] = (R)xcorr(m);
         __syncthreads();
       }
+      // passes of 64 x kGradSpl samples: lane l holds samples d + l + 64 k
+      // (k < kGradSpl), wave w the w-th of NWV contiguous mode ranges; per
+      // sample cos(m nu_d) runs by the recurrence in m, restarted from exact
+      // values every kGradRestart modes; the NWV partial sums of a sample are
+      // added in wave order
+      const int nmode = pr.band + 1;
+      const int mlo = (int)((int64_t)nmode * wv / NWV), mhi = (int)((int64_t)nmode * (wv + 1) / NWV);
       const int dend = item.d0 + item.cnt;
-      for (int gd = item.d0; gd < dend; gd += kGradGroup) {
-        const int cnt = min(kGradGroup, dend - gd);
-        double acc[kGradGroup];
+      for (int pd = item.d0; pd < dend; pd += 64 * kGradSpl) {
+        double acc[kGradSpl], st[kGradSpl];
+        int64_t kd[kGradSpl];  // nu_d = pi kd / pl
 #pragma unroll
-        for (int d = 0; d < kGradGroup; ++d) acc[d] = 0.0;
-        const int64_t k0 = 2 * (int64_t)gd + s;  // nu_gd = pi k0 / pl
-        const int step_m = kGradModes * blockDim.x;
-        auto modes = [&](auto tab) {
-          constexpr bool TAB = decltype(tab)::value;
-          // table form: the next step's twiddle reads are issued before the
-          // current step's recurrences (modes past the band read mode 0)
-          R t0[kGradModes], t1[kGradModes], t2[kGradModes];
-          auto fetch = [&](int mb) {
+        for (int k = 0; k < kGradSpl; ++k) {
+          acc[k] = 0.0;
+          kd[k] = 2 * (int64_t)(pd + lane + 64 * k) + s;
+          st[k] = 2.0 * cospi((double)(kd[k] % (2 * pl)) / (double)pl);
+        }
+        for (int mr = mlo; mr < mhi; mr += kGradRestart) {
+          const int me = min(mr + kGradRestart, mhi);
+          double c0[kGradSpl], c1[kGradSpl];
 #pragma unroll
-            for (int k = 0; k < kGradModes; ++k) {
-              const int m = mb + k * (int)blockDim.x;
-              const int64_t mm = m <= pr.band ? m : 0;
-              t0[k] = gc.raw(mm * k0);
-              t1[k] = gc.raw(mm * (k0 + 2));
-              t2[k] = gc.raw(2 * mm);
-            }
-          };
-          if constexpr (TAB) fetch(tid);
-          for (int mb = tid; mb <= pr.band; mb += step_m) {
-            double z[kGradModes], c0[kGradModes], c1[kGradModes], st[kGradModes];
+          for (int k = 0; k < kGradSpl; ++k) {
+            c0[k] = cospi((double)(((int64_t)mr * kd[k]) % (2 * pl)) / (double)pl);
+            c1[k] = cospi((double)(((int64_t)(mr + 1) * kd[k]) % (2 * pl)) / (double)pl);
+          }
+          int m = mr;
+          for (; m + 4 <= me; m += 4) {
+            double z[4];
 #pragma unroll
-            for (int k = 0; k < kGradModes; ++k) {
-              const int m = mb + k * (int)blockDim.x;
-              const bool ok = m <= pr.band;
-              const int mm = ok ? m : 0;
-              z[k] = ok ? (cached ? (double)zc[mm] : xcorr(mm)) : 0.0;
-              if constexpr (TAB) {
-                c0[k] = t0[k];
-                c1[k] = t1[k];
-                st[k] = 2.0 * (double)t2[k];
-              } else {
-                c0[k] = gc.exact((int64_t)mm * k0);
-                c1[k] = gc.exact((int64_t)mm * (k0 + 2));
-                st[k] = 2.0 * gc.exact(2 * (int64_t)mm);
-              }
-            }
-            if constexpr (TAB) fetch(mb + step_m);
+            for (int e = 0; e < 4; ++e) z[e] = cached ? (double)zc[m + e] : xcorr(m + e);
 #pragma unroll
-            for (int d = 0; d < kGradGroup; ++d) {
+            for (int e = 0; e < 4; ++e) {
 #pragma unroll
-              for (int k = 0; k < kGradModes; ++k) {
-                acc[d] = fma(z[k], c0[k], acc[d]);
+              for (int k = 0; k < kGradSpl; ++k) {
+                acc[k] = fma(z[e], c0[k], acc[k]);
                 const double c2 = fma(st[k], c1[k], -c0[k]);
                 c0[k] = c1[k];
                 c1[k] = c2;
               }
             }
           }
-        };
-        if (table) modes(std::true_type{});
-        else modes(std::false_type{});
-        reduce(acc, cnt);
+          for (; m < me; ++m) {
+            const double z = cached ? (double)zc[m] : xcorr(m);
+#pragma unroll
+            for (int k = 0; k < kGradSpl; ++k) {
+              acc[k] = fma(z, c0[k], acc[k]);
+              const double c2 = fma(st[k], c1[k], -c0[k]);
+              c0[k] = c1[k];
+              c1[k] = c2;
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kGradSpl; ++k) red[wv * 64 * kGradSpl + lane + 64 * k] = acc[k];
+        __syncthreads();
+        const int cnt = min(64 * kGradSpl, dend - pd);
         double t = 0.0, cd = 0.0, wgt = 0.0;
         if (tid < cnt) {
-          sample(gd + tid, t, cd);
-          wgt = cd * scale * Y[tid];
+          double y = 0.0;
+          for (int w = 0; w < NWV; ++w) y += red[w * 64 * kGradSpl + tid];
+          sample(pd + tid, t, cd);
+          wgt = cd * scale * y;
         }
         row_scatter(U, g, sa, sp, cnt, t, wgt);
       }

@@ -123,8 +123,8 @@ arkcos_status_t build_grad_items(arkcos_plan_s* P) {
       const int64_t nc = P->h_ncoef_window[q];
       if (pr.band < 0 || nc <= kGradMaxCoef) continue;
       zmax = std::max<int64_t>(zmax, pr.band + 1);
-      int64_t per = (int64_t)(kGradItemWork / (double)(pr.band + 1)) / kGradGroup * kGradGroup;
-      per = std::max<int64_t>(per, kGradGroup);
+      int64_t per = (int64_t)(kGradItemWork / (double)(pr.band + 1)) / kGradPass * kGradPass;
+      per = std::max<int64_t>(per, kGradPass);
       for (int64_t d0 = 0; d0 < nc; d0 += per) {
         const int64_t cnt = std::min(per, nc - d0);
         items.push_back(GradItem{(int32_t)u, q, (int32_t)d0, (int32_t)cnt});
@@ -148,9 +148,9 @@ arkcos_status_t build_grad_items(arkcos_plan_s* P) {
   P->h_grad_items = items;
   P->n_grad_runs = (int32_t)nruns;
   // a wide row's correlation is staged in LDS when it fits next to the
-  // block's other arrays (about 18 KB)
+  // block's other arrays (about 28 KB of 160 KB)
   const int64_t rsz = P->dtype == ARKCOS_F32 ? 4 : 8;
-  P->grad_zcache_bytes = (int32_t)std::min<int64_t>((zmax * rsz + 15) / 16 * 16, 139264);
+  P->grad_zcache_bytes = (int32_t)std::min<int64_t>((zmax * rsz + 15) / 16 * 16, 131088);
   HIPCHK(upload(P, &P->d_grad_items, items));
   HIPCHK(upload(P, &P->d_grad_run, run));
   return ARKCOS_OK;

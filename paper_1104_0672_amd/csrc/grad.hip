@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
   __shared__ double red[NWV * 64 * kGradSpl];
   double* part = red;
   static_assert(kGradMaxCoef <= 64 * kGradSpl, "narrow reductions fit the pass buffer");
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nint4 = 4 * (g.nk - 1);
   for (int e = tid; e < nint4; e += blockDim.x) U[e] = 0.0;
   __syncthreads();
@@ -283,9 +283,10 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
         continue;
       }
       // a wide row: stage Z(m) (or evaluate it on the fly when it does not fit)
-      const bool cached = (int64_t)(pr.band + 1) * (int64_t)sizeof(R) <= (int64_t)g.zcache_bytes;
+      const int band = __builtin_amdgcn_readfirstlane(pr.band);
+      const bool cached = (int64_t)(band + 1) * (int64_t)sizeof(R) <= (int64_t)g.zcache_bytes;
       if (cached) {
-        for (int m = tid; m <= pr.band; m += blockDim.x) zc[m] = (R)xcorr(m);
+        for (int m = tid; m <= band; m += blockDim.x) zc[m] = (R)xcorr(m);
         __syncthreads();
       }
       // passes of 64 x kGradSpl samples: lane l holds samples d + l + 64 k
@@ -293,9 +294,12 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
       // sample cos(m nu_d) runs by the recurrence in m, restarted from exact
       // values every kGradRestart modes; the NWV partial sums of a sample are
       // added in wave order
-      const int nmode = pr.band + 1;
-      const int mlo = (int)((int64_t)nmode * wv / NWV), mhi = (int)((int64_t)nmode * (wv + 1) / NWV);
+      const int nmode = band + 1;
+      const int mlo = __builtin_amdgcn_readfirstlane((int)((int64_t)nmode * wv / NWV));
+      const int mhi = __builtin_amdgcn_readfirstlane((int)((int64_t)nmode * (wv + 1) / NWV));
       const int dend = item.d0 + item.cnt;
+      auto passes = [&](auto cached_tag) {
+      constexpr bool CACHED = decltype(cached_tag)::value;
       for (int pd = item.d0; pd < dend; pd += 64 * kGradSpl) {
         double acc[kGradSpl], st[kGradSpl];
         int64_t kd[kGradSpl];  // nu_d = pi kd / pl
@@ -314,12 +318,12 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
             c1[k] = cospi((double)(((int64_t)(mr + 1) * kd[k]) % (2 * pl)) / (double)pl);
           }
           int m = mr;
-          for (; m + 4 <= me; m += 4) {
-            double z[4];
+          for (; m + 8 <= me; m += 8) {
+            double z[8];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) z[e] = cached ? (double)zc[m + e] : xcorr(m + e);
+            for (int e = 0; e < 8; ++e) z[e] = CACHED ? (double)zc[m + e] : xcorr(m + e);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            for (int e = 0; e < 8; ++e) {
 #pragma unroll
               for (int k = 0; k < kGradSpl; ++k) {
                 acc[k] = fma(z[e], c0[k], acc[k]);
@@ -330,7 +334,7 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
             }
           }
           for (; m < me; ++m) {
-            const double z = cached ? (double)zc[m] : xcorr(m);
+            const double z = CACHED ? (double)zc[m] : xcorr(m);
 #pragma unroll
             for (int k = 0; k < kGradSpl; ++k) {
               acc[k] = fma(z, c0[k], acc[k]);
@@ -353,6 +357,9 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
         }
         row_scatter(U, g, sa, sp, cnt, t, wgt);
       }
+      };
+      if (cached) passes(std::true_type{});
+      else passes(std::false_type{});
       __syncthreads();  // zc is rewritten by the next row
     }
   }

@@ -90,6 +90,7 @@ struct BatchItem {
 };
 
 constexpr int kTilesPerItem = 4;     // mode tiles per accumulation work item
+constexpr int kFoldThreads = 256;    // threads sharing the period sums of a short ring's fold (C2R)
 // entries of a pair's K_ij(m) table: modes 0..band, zero-padded to whole
 // mode tiles so that a tile is read without bounds checks
 __host__ __device__ constexpr int32_t table_span(int32_t band) { return (band / kAccTile + 1) * kAccTile; }

@@ -205,62 +205,104 @@ __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, cons
   const bool direct = kind == FFT_DIRECT;
   constexpr int kPairBatch = PairBatch<R>::value;
   const int nq = (len + N - 1) / N;
-  for (int base = 0; base <= n / 2; base += NT * kPairBatch) {
-    // P at r, N - r, n - r and n + r for each pair (r, n - r)
-    C p[kPairBatch][4];
+  // the fold's results for the pair (r, n - r), from pp = P at r, N - r,
+  // n - r and n + r: G(r), G(n - r), then the split for the half-length FFT
+  auto finish = [&](int r, const C (&pp)[4]) {
+    const int r2 = n - r;
+    const C w = half_twiddle<R>(r, N, kind, ph, a.tw, a.TN);
+    C g1, g2;
+    if (shifted) {
+      g1 = cmul(cconj(w), csub(pp[0], cconj(pp[1])));
+      g2 = cmul(cmake<C>(-w.y, w.x), csub(pp[2], cconj(pp[3])));   // conj(w_{n-r}) = i w_r
+    } else {
+      g1 = cadd(pp[0], cconj(pp[1]));
+      g2 = cadd(pp[2], cconj(pp[3]));
+    }
+    g1 = cscale(g1, scale);
+    g2 = cscale(g2, scale);
+    if (direct) {
+      buf[lidx(r)] = g1;
+      if (r2 == n) nyq = g2;
+      else if (r2 != r) buf[lidx(r2)] = g2;
+      return;
+    }
+    // Z(r) = E(r) + i O(r), E(r) = G(r) + conj(G(n-r)), O(r) = exp(2 pi i r/N) (G(r) - conj(G(n-r)))
+    const C t = cconj(cmul(w, w));                      // exp(2 pi i r / N)
+    const C t2 = cmake<C>(-t.x, t.y);                   // exp(2 pi i (n - r) / N)
+    const C e1 = cadd(g1, cconj(g2)), o1 = cmul(t, csub(g1, cconj(g2)));
+    buf[lidx(r)] = cadd(e1, cmake<C>(-o1.y, o1.x));
+    if (r2 < n && r2 != r) {
+      const C e2 = cadd(g2, cconj(g1)), o2 = cmul(t2, csub(g2, cconj(g1)));
+      buf[lidx(r2)] = cadd(e2, cmake<C>(-o2.y, o2.x));
+    }
+  };
+  const int npr = n / 2 + 1;  // pairs (r, n - r), r <= n / 2
+  if (2 * npr <= kFoldThreads) {
+    // a short ring: the periods q are shared out over G groups of threads
+    // (thread t: pair t mod npr, periods q = t / npr + k G), the groups'
+    // partial sums are added in group order through LDS
+    const int G = kFoldThreads / npr;
+    const int u = tid % npr, grp = tid / npr;
+    C pp[4];
 #pragma unroll
-    for (int u = 0; u < kPairBatch; ++u)
+    for (int c = 0; c < 4; ++c) pp[c] = cmake<C>(R(0), R(0));
+    if (grp < G) {
+      for (int q = grp; q < nq; q += G) {
+        const R sg = (shifted && (q & 1)) ? R(-1) : R(1);
+        const int m0 = q * N;
+        const int ms[4] = {m0 + u, m0 + N - u, m0 + n - u, m0 + n + u};
 #pragma unroll
-      for (int c = 0; c < 4; ++c) p[u][c] = cmake<C>(R(0), R(0));
-    for (int q = 0; q < nq; ++q) {
-      const R sg = (shifted && (q & 1)) ? R(-1) : R(1);
-      const int m0 = q * N;
-      C v[kPairBatch][4];
-#pragma unroll
-      for (int u = 0; u < kPairBatch; ++u) {
-        const int r = base + tid + u * NT;
-        const int ms[4] = {m0 + r, m0 + N - r, m0 + n - r, m0 + n + r};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          v[u][c] = cmake<C>(R(0), R(0));
-          if (r <= n / 2 && ms[c] < len) v[u][c] = b[ms[c]];
-        }
+        for (int c = 0; c < 4; ++c)
+          if (ms[c] < len) pp[c] = cadd(pp[c], cscale(b[ms[c]], sg));
       }
+    }
+    C* scr = buf;  // G npr 4 <= 4 kFoldThreads values: the ring's LDS holds them
+    if (grp < G) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) scr[(grp * npr + u) * 4 + c] = pp[c];
+    }
+    __syncthreads();
+    C fin[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) fin[c] = cmake<C>(R(0), R(0));
+    if (tid < npr) {
+      for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fin[c] = cadd(fin[c], scr[(k * npr + tid) * 4 + c]);
+    }
+    __syncthreads();
+    if (tid < npr) finish(tid, fin);
+  } else {
+    for (int base = 0; base <= n / 2; base += NT * kPairBatch) {
+      // P at r, N - r, n - r and n + r for each pair (r, n - r)
+      C p[kPairBatch][4];
 #pragma unroll
       for (int u = 0; u < kPairBatch; ++u)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) p[u][c] = cadd(p[u][c], cscale(v[u][c], sg));
-    }
+        for (int c = 0; c < 4; ++c) p[u][c] = cmake<C>(R(0), R(0));
+      for (int q = 0; q < nq; ++q) {
+        const R sg = (shifted && (q & 1)) ? R(-1) : R(1);
+        const int m0 = q * N;
+        C v[kPairBatch][4];
 #pragma unroll
-    for (int u = 0; u < kPairBatch; ++u) {
-      const int r = base + tid + u * NT;
-      if (r > n / 2) continue;
-      const int r2 = n - r;
-      const C w = half_twiddle<R>(r, N, kind, ph, a.tw, a.TN);
-      C g1, g2;
-      if (shifted) {
-        g1 = cmul(cconj(w), csub(p[u][0], cconj(p[u][1])));
-        g2 = cmul(cmake<C>(-w.y, w.x), csub(p[u][2], cconj(p[u][3])));   // conj(w_{n-r}) = i w_r
-      } else {
-        g1 = cadd(p[u][0], cconj(p[u][1]));
-        g2 = cadd(p[u][2], cconj(p[u][3]));
+        for (int u = 0; u < kPairBatch; ++u) {
+          const int r = base + tid + u * NT;
+          const int ms[4] = {m0 + r, m0 + N - r, m0 + n - r, m0 + n + r};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            v[u][c] = cmake<C>(R(0), R(0));
+            if (r <= n / 2 && ms[c] < len) v[u][c] = b[ms[c]];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kPairBatch; ++u)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) p[u][c] = cadd(p[u][c], cscale(v[u][c], sg));
       }
-      g1 = cscale(g1, scale);
-      g2 = cscale(g2, scale);
-      if (direct) {
-        buf[lidx(r)] = g1;
-        if (r2 == n) nyq = g2;
-        else if (r2 != r) buf[lidx(r2)] = g2;
-        continue;
-      }
-      // Z(r) = E(r) + i O(r), E(r) = G(r) + conj(G(n-r)), O(r) = exp(2 pi i r/N) (G(r) - conj(G(n-r)))
-      const C t = cconj(cmul(w, w));                      // exp(2 pi i r / N)
-      const C t2 = cmake<C>(-t.x, t.y);                   // exp(2 pi i (n - r) / N)
-      const C e1 = cadd(g1, cconj(g2)), o1 = cmul(t, csub(g1, cconj(g2)));
-      buf[lidx(r)] = cadd(e1, cmake<C>(-o1.y, o1.x));
-      if (r2 < n && r2 != r) {
-        const C e2 = cadd(g2, cconj(g1)), o2 = cmul(t2, csub(g2, cconj(g1)));
-        buf[lidx(r2)] = cadd(e2, cmake<C>(-o2.y, o2.x));
+#pragma unroll
+      for (int u = 0; u < kPairBatch; ++u) {
+        const int r = base + tid + u * NT;
+        if (r <= n / 2) finish(r, p[u]);
       }
     }
   }

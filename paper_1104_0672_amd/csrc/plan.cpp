@@ -567,6 +567,9 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   }
   // the accumulation reads exp(i pi m / (p L)) from the table as well
   if (is_pow2((int64_t)P->oversample * L)) twn = std::max<int64_t>(twn, 2 * (int64_t)P->oversample * L);
+  // a short ring's fold shares its period sums through 4 kFoldThreads values of LDS
+  for (int64_t k = 0; k < nr; ++k) ring_lds[k] = std::max(ring_lds[k], (size_t)4 * kFoldThreads * csz);
+  lds = std::max(lds, (size_t)4 * kFoldThreads * csz);
   P->twiddle_n = (int32_t)twn;
   P->max_fft_lds = (int32_t)((lds + 15) / 16 * 16);
   P->h_ring_lds.resize(nr);

@@ -174,6 +174,40 @@ def summarize_kernels(trace_dir: str, cmd: str, title: str):
     print("\n".join(lines))
 
 
+def summarize_counters(csv_path: str, cmd: str, title: str):
+    """Markdown summary of one rocprofv3 --pmc run of SQ instruction counters
+    (summed over the device, per dispatch): per kernel and launch shape the
+    wave instructions by kind, and the VALU issue fraction = VALU wave
+    instructions x 4 cycles / (1024 SIMDs x 2.4 GHz x dispatch duration under
+    the profiler)."""
+    import collections
+    rows = _counter_rows(csv_path)
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    durs = collections.defaultdict(dict)
+    for r in rows:
+        n = _short(r["Kernel_Name"])
+        if not (n in KERNEL_NAMES.values() or "grad" in n or "batch" in n):
+            continue
+        key = (n, int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"])), int(r["Workgroup_Size"]))
+        per[key][r["Counter_Name"]] += float(r["Counter_Value"])
+        durs[key][r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    names = ["SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR"]
+    lines = [f"# {title}", "", "Command (from the repository root, one MI355X):", "", "```", cmd, "```", "",
+             "Per dispatch (averages over the run's dispatches of each launch shape; wave instructions "
+             "summed over the device); VALU issue = VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x duration):", "",
+             "| kernel | workgroups | threads | dispatches | us (profiled) | VALU | SALU | LDS | VMEM rd | VMEM wr | VALU issue |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for key in sorted(per):
+        nd = len(durs[key])
+        us = sum(durs[key].values()) / nd / 1e3
+        c = {k: v / nd for k, v in per[key].items()}
+        valu = c.get("SQ_INSTS_VALU", 0.0)
+        frac = valu * 4 / (1024 * 2.4e9 * us * 1e-6) if us > 0 else 0.0
+        cells = " | ".join(f"{c.get(k, 0.0) / 1e6:.2f} M" for k in names)
+        lines.append(f"| `{key[0]}` | {key[1]} | {key[2]} | {nd} | {us:.1f} | {cells} | {frac:.2f} |")
+    print("\n".join(lines))
+
+
 def cpu_baseline(w, x, budget_s: float):
     import numpy as np
 
@@ -315,6 +349,8 @@ def main():
                     help="offline: write the per-kernel HBM traffic summary from two counter runs")
     ap.add_argument("--summarize-kernels", metavar="TRACE_DIR",
                     help="offline: print a markdown summary of a kernel-trace run")
+    ap.add_argument("--summarize-counters", metavar="COUNTER_CSV",
+                    help="offline: print a markdown summary of an SQ instruction-counter run")
     ap.add_argument("--summary-command", default="", help="command line recorded in a summary")
     ap.add_argument("--summary-title", default="")
     args = ap.parse_args()
@@ -324,6 +360,9 @@ def main():
         return
     if args.summarize_kernels:
         summarize_kernels(args.summarize_kernels, args.summary_command, args.summary_title)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.summary_command, args.summary_title)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the single-map path "

@@ -262,22 +262,36 @@ template <int NS, int RAD> __device__ __forceinline__ constexpr int out_gap(int 
 
 // HIN (first pass, NS = 1): the points M/2 .. M-1 are zero and not read.
 // HOUT (last pass, NS = M/RAD): only the outputs 0 .. M/2-1 are written.
-template <typename R, bool INV, int RAD, int NT, int M, int NS, bool HIN = false, bool HOUT = false>
-__device__ __forceinline__ void stockham_ct(cx_t<R>* buf, cx_t<R> w) {
+// REGIN (first pass): the inputs come from io instead of LDS, io[e] being
+// point threadIdx.x + e NT (e < 16): thread j's butterfly b takes points
+// j + b NT + r Q = io[b + (16 / RAD) r].  REGOUT (last pass, Q = NT): the
+// outputs j + r NT stay in io[r] instead of going to LDS; the pass then
+// ends without a barrier.
+template <typename R, bool INV, int RAD, int NT, int M, int NS, bool HIN = false, bool HOUT = false,
+          bool REGIN = false, bool REGOUT = false>
+__device__ __forceinline__ void stockham_ct(cx_t<R>* buf, cx_t<R> w, cx_t<R>* io = nullptr) {
   using C = cx_t<R>;
   constexpr int Q = M / RAD;
   constexpr int MAXB = Q / NT;
   static_assert(Q % NT == 0 && Q % 32 == 0 && NT % 32 == 0, "pass shape");
   static_assert((!HIN || NS == 1) && (!HOUT || NS == Q), "pruned pass");
+  static_assert((!REGIN || (NS == 1 && M == 16 * NT)) && (!REGOUT || (NS == Q && MAXB == 1)), "register pass");
   constexpr int RG = Q + Q / 32;
   C v[MAXB][RAD];
+  if constexpr (REGIN) {
 #pragma unroll
-  for (int b = 0; b < MAXB; ++b) {
-    const C* src = buf + lidx(threadIdx.x + b * NT);
+    for (int b = 0; b < MAXB; ++b)
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) v[b][r] = (HIN && 2 * r >= RAD) ? cmake<C>(R(0), R(0)) : src[r * RG];
+      for (int r = 0; r < RAD; ++r) v[b][r] = (HIN && 2 * r >= RAD) ? cmake<C>(R(0), R(0)) : io[b + MAXB * r];
+  } else {
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const C* src = buf + lidx(threadIdx.x + b * NT);
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[b][r] = (HIN && 2 * r >= RAD) ? cmake<C>(R(0), R(0)) : src[r * RG];
+    }
+    __syncthreads();
   }
-  __syncthreads();
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = threadIdx.x + b * NT;
@@ -289,37 +303,49 @@ __device__ __forceinline__ void stockham_ct(cx_t<R>* buf, cx_t<R> w) {
       for (int r = 1; r < RAD; ++r) v[b][r] = cmul(v[b][r], p[r]);
     }
     dft_reg<C, INV, RAD>(v[b]);
-    C* dst = buf + lidx((j - k) * RAD + k);
+    if constexpr (REGOUT) {
 #pragma unroll
-    for (int r = 0; r < RAD; ++r)
-      if (!HOUT || 2 * r < RAD) dst[out_gap<NS, RAD>(r)] = v[b][r];
+      for (int r = 0; r < RAD; ++r)
+        if (!HOUT || 2 * r < RAD) io[r] = v[b][r];
+    } else {
+      C* dst = buf + lidx((j - k) * RAD + k);
+#pragma unroll
+      for (int r = 0; r < RAD; ++r)
+        if (!HOUT || 2 * r < RAD) dst[out_gap<NS, RAD>(r)] = v[b][r];
+    }
   }
-  __syncthreads();
+  if constexpr (!REGOUT) __syncthreads();
 }
 
 template <int M> struct Log2 { static constexpr int value = 1 + Log2<M / 2>::value; };
 template <> struct Log2<1> { static constexpr int value = 0; };
 
 // HIN: the input's upper half is zero; HOUT: only the lower half of the
-// output is wanted (the two halves of a Bluestein convolution).
-template <typename R, bool INV, int NT, int M, bool HIN = false, bool HOUT = false>
-__device__ __forceinline__ void lds_fft_ct(cx_t<R>* buf, const cx_t<R>* __restrict__ tw, int TN) {
+// output is wanted (the two halves of a Bluestein convolution).  REGIN /
+// REGOUT: the input / output point threadIdx.x + e NT is io[e] (e < 16)
+// instead of LDS (see stockham_ct); with REGIN the block need not be
+// synchronised on entry, with REGOUT the call ends without a barrier.
+template <typename R, bool INV, int NT, int M, bool HIN = false, bool HOUT = false, bool REGIN = false,
+          bool REGOUT = false>
+__device__ __forceinline__ void lds_fft_ct(cx_t<R>* buf, const cx_t<R>* __restrict__ tw, int TN,
+                                           cx_t<R>* io = nullptr) {
   using C = cx_t<R>;
   constexpr int LG = Log2<M>::value, REST = LG & 3, N16 = LG >> 2;
   static_assert(M == 16 * NT && N16 <= 3 && N16 >= 1, "length");
   constexpr int NS0 = 1 << REST, NS1 = NS0 << 4, NS2 = NS0 << 8;
   constexpr bool H16 = HIN && REST == 0;  // the first radix-16 pass is the first pass
+  constexpr bool R16 = REGIN && REST == 0;
   const int j = threadIdx.x;
   auto tw_at = [&](int ns) {
     return ns > 1 ? tw[(j & (ns - 1)) * (TN / (ns * 16))] : cmake<C>(R(1), R(0));
   };
   const C w0 = tw_at(NS0), w1 = tw_at(NS1), w2 = N16 > 2 ? tw_at(NS2) : cmake<C>(R(1), R(0));
-  if constexpr (REST == 1) stockham_ct<R, INV, 2, NT, M, 1, HIN>(buf, w0);
-  else if constexpr (REST == 2) stockham_ct<R, INV, 4, NT, M, 1, HIN>(buf, w0);
-  else if constexpr (REST == 3) stockham_ct<R, INV, 8, NT, M, 1, HIN>(buf, w0);
-  stockham_ct<R, INV, 16, NT, M, NS0, H16, HOUT && N16 == 1>(buf, w0);
-  if constexpr (N16 > 1) stockham_ct<R, INV, 16, NT, M, NS1, false, HOUT && N16 == 2>(buf, w1);
-  if constexpr (N16 > 2) stockham_ct<R, INV, 16, NT, M, NS2, false, HOUT>(buf, w2);
+  if constexpr (REST == 1) stockham_ct<R, INV, 2, NT, M, 1, HIN, false, REGIN>(buf, w0, io);
+  else if constexpr (REST == 2) stockham_ct<R, INV, 4, NT, M, 1, HIN, false, REGIN>(buf, w0, io);
+  else if constexpr (REST == 3) stockham_ct<R, INV, 8, NT, M, 1, HIN, false, REGIN>(buf, w0, io);
+  stockham_ct<R, INV, 16, NT, M, NS0, H16, HOUT && N16 == 1, R16, REGOUT && N16 == 1>(buf, w0, io);
+  if constexpr (N16 > 1) stockham_ct<R, INV, 16, NT, M, NS1, false, HOUT && N16 == 2, false, REGOUT && N16 == 2>(buf, w1, io);
+  if constexpr (N16 > 2) stockham_ct<R, INV, 16, NT, M, NS2, false, HOUT, false, REGOUT>(buf, w2, io);
 }
 
 // Bluestein's chirp convolution: the length-n DFT of buf[0..n) (padded
@@ -397,6 +423,59 @@ __device__ __forceinline__ void bluestein(cx_t<R>* buf, int n, int M_, const cx_
     }
   }
   __syncthreads();
+}
+
+// The same for a compile-time length M = MF = 16 NT, with the phases that
+// act point by point kept in registers: io[e] is point threadIdx.x + e NT.
+// The chirp product feeds the forward FFT's first pass, the filter product
+// sits between the forward FFT's last pass and the inverse FFT's first pass,
+// and the final chirp product takes the inverse FFT's last pass.  REGIN:
+// the input is io (points >= n zero) instead of buf; REGOUT: the result is
+// left in io[e] (e < 8, points < M/2 >= n) instead of buf, and the call ends
+// without a barrier.
+template <typename R, bool INV, int NT, int MF, bool REGIN, bool REGOUT>
+__device__ __forceinline__ void bluestein_ct(cx_t<R>* buf, int n, const cx_t<R>* __restrict__ filt,
+                                             const cx_t<R>* __restrict__ tw, int TN, cx_t<R>* io) {
+  using C = cx_t<R>;
+  constexpr int M = MF;
+  constexpr int EPT = 16;
+  static_assert(M == EPT * NT, "length");
+  const int tid = threadIdx.x;
+  C x[EPT];
+  {
+    C c[EPT / 2];
+#pragma unroll
+    for (int e = 0; e < EPT / 2; ++e) {
+      const int l = tid + e * NT;
+      c[e] = l < n ? filt[M + l] : cmake<C>(R(0), R(0));
+    }
+#pragma unroll
+    for (int e = 0; e < EPT / 2; ++e) {
+      const int l = tid + e * NT;
+      C v = cmake<C>(R(0), R(0));
+      if (l < n) v = REGIN ? io[e] : buf[lidx(l)];
+      if (INV) v = cconj(v);
+      x[e] = cmul(v, c[e]);
+      x[e + EPT / 2] = cmake<C>(R(0), R(0));  // n <= M/2: the upper half is zero
+    }
+  }
+  if constexpr (!REGIN) __syncthreads();  // every read of buf done before the first pass writes it
+  lds_fft_ct<R, false, NT, M, true, false, true, true>(buf, tw, TN, x);
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) x[e] = cmul(x[e], filt[tid + e * NT]);
+  lds_fft_ct<R, true, NT, M, false, true, true, true>(buf, tw, TN, x);
+  const R inv = R(1) / R(M);
+#pragma unroll
+  for (int e = 0; e < EPT / 2; ++e) {
+    const int k = tid + e * NT;
+    if (k < n) {
+      C v = cscale(cmul(x[e], filt[M + k]), inv);
+      if (INV) v = cconj(v);
+      if constexpr (REGOUT) io[e] = v;
+      else buf[lidx(k)] = v;
+    }
+  }
+  if constexpr (!REGOUT) __syncthreads();
 }
 
 // Loads and stores through the global address space.  Pointers read from

@@ -109,28 +109,34 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
     }
     __syncthreads();
   } else {
-    // the ring as n complex samples (x_2l, x_2l+1), all loads issued at once
-    {
-      const cx_t<R>* xc = reinterpret_cast<const cx_t<R>*>(xr);
-      C z[EPT];
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int l = tid + e * NT;
-        if (l < n) z[e] = xc[l];
-      }
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int l = tid + e * NT;
-        if (l < n) buf[lidx(l)] = cscale(z[e], scale);
-      }
-    }
-    __syncthreads();
+    // the ring as n complex samples (x_2l, x_2l+1), all loads issued at
+    // once; z[e] is sample tid + e NT.  The compile-time transforms take
+    // them from registers, the others from LDS.
     const int M = a.fft_m[j];
-    if (kind == FFT_POW2) {
-      if (MF > 0 && n == MF) lds_fft_ct<R, false, NT, (MF > 0 ? MF : 16 * NT)>(buf, a.tw, a.TN);
-      else lds_fft<R, false, NT>(buf, n, a.tw, a.TN);
+    const cx_t<R>* xc = reinterpret_cast<const cx_t<R>*>(xr);
+    C z[EPT];
+    auto load = [&](int e0, int e1) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int l = tid + e * NT;
+        if (e >= e0 && e < e1) z[e] = l < n ? cscale(xc[l], scale) : cmake<C>(R(0), R(0));
+      }
+    };
+    if (MF > 0 && kind == FFT_POW2 && n == MF) {
+      load(0, EPT);
+      lds_fft_ct<R, false, NT, (MF > 0 ? MF : 16 * NT), false, false, true, false>(buf, a.tw, a.TN, z);
+    } else if (MF > 0 && kind == FFT_BLUESTEIN && M == MF) {
+      load(0, EPT / 2);  // n <= M/2
+      bluestein_ct<R, false, NT, (MF > 0 ? MF : 16 * NT), true, false>(buf, n, a.bl + a.bl_off[j], a.tw, a.TN, z);
     } else {
-      if (MF > 0 && M == MF) bluestein<R, false, NT, MF>(buf, n, M, a.bl + a.bl_off[j], a.tw, a.TN);
+      load(0, EPT);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int l = tid + e * NT;
+        if (l < n) buf[lidx(l)] = z[e];
+      }
+      __syncthreads();
+      if (kind == FFT_POW2) lds_fft<R, false, NT>(buf, n, a.tw, a.TN);
       else bluestein<R, false, NT>(buf, n, M, a.bl + a.bl_off[j], a.tw, a.TN);
     }
     constexpr int kPairBatch = PairBatch<R>::value;
@@ -327,14 +333,26 @@ __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, cons
     return;
   }
   const int M = a.fft_m[i];
-  if (kind == FFT_POW2) {
-    if (MF > 0 && n == MF) lds_fft_ct<R, true, NT, (MF > 0 ? MF : 16 * NT)>(buf, a.tw, a.TN);
-    else lds_fft<R, true, NT>(buf, n, a.tw, a.TN);
-  } else {
-    if (MF > 0 && M == MF) bluestein<R, true, NT, MF>(buf, n, M, a.bl + a.bl_off[i], a.tw, a.TN);
-    else bluestein<R, true, NT>(buf, n, M, a.bl + a.bl_off[i], a.tw, a.TN);
-  }
   cx_t<R>* yc = reinterpret_cast<cx_t<R>*>(yr);
+  // the compile-time transforms leave point tid + e NT in z[e]
+  C z[EPT];
+  if (MF > 0 && kind == FFT_POW2 && n == MF) {
+    lds_fft_ct<R, true, NT, (MF > 0 ? MF : 16 * NT), false, false, false, true>(buf, a.tw, a.TN, z);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) yc[tid + e * NT] = z[e];
+    return;
+  }
+  if (MF > 0 && kind == FFT_BLUESTEIN && M == MF) {
+    bluestein_ct<R, true, NT, (MF > 0 ? MF : 16 * NT), false, true>(buf, n, a.bl + a.bl_off[i], a.tw, a.TN, z);
+#pragma unroll
+    for (int e = 0; e < EPT / 2; ++e) {
+      const int l = tid + e * NT;
+      if (l < n) yc[l] = z[e];
+    }
+    return;
+  }
+  if (kind == FFT_POW2) lds_fft<R, true, NT>(buf, n, a.tw, a.TN);
+  else bluestein<R, true, NT>(buf, n, M, a.bl + a.bl_off[i], a.tw, a.TN);
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int l = tid + e * NT;

@@ -290,7 +290,28 @@ def bench_batch(n_maps: int, steps: int, dev):
                      "hbm_roofline_frac_24B_per_px": round(total_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "stages_ms": dict(zip(STAGES, [round(t / max(calls, 1), 3) for t in st]))}
         log(f"bench: batch {name} {ms:.2f} ms, {npix * steps / wall:.3e} px/s")
-    del xs, ys, ws, batch, plans
+    # the forward call captured once in a hipGraph (through torch.cuda.CUDAGraph) and replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch.convolve(xs, outs=ys, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.convolve(xs, outs=ys, ws=ws)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = 1e3 * wall / steps
+    out["graph_forward"] = {"pixels_per_s": npix * steps / wall, "ms": ms,
+                            "hbm_roofline_frac_24B_per_px": round(total_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"bench: batch forward as a replayed hipGraph {ms:.2f} ms, {npix * steps / wall:.3e} px/s")
+    del graph, xs, ys, ws, batch, plans
     torch.cuda.empty_cache()
     return out
 

@@ -115,25 +115,32 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
     const int M = a.fft_m[j];
     const cx_t<R>* xc = reinterpret_cast<const cx_t<R>*>(xr);
     C z[EPT];
-    auto load = [&](int e0, int e1) {
+    if constexpr (MF > 0) {
+      auto load = [&](int e0, int e1) {
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int l = tid + e * NT;
-        if (e >= e0 && e < e1) z[e] = l < n ? cscale(xc[l], scale) : cmake<C>(R(0), R(0));
+        for (int e = 0; e < EPT; ++e) {
+          const int l = tid + e * NT;
+          if (e >= e0 && e < e1) z[e] = l < n ? cscale(xc[l], scale) : cmake<C>(R(0), R(0));
+        }
+      };
+      if (kind == FFT_POW2) {  // n == MF
+        load(0, EPT);
+        lds_fft_ct<R, false, NT, (MF > 0 ? MF : 16 * NT), false, false, true, false>(buf, a.tw, a.TN, z);
+      } else {  // Bluestein, M == MF >= 2 n
+        load(0, EPT / 2);
+        bluestein_ct<R, false, NT, (MF > 0 ? MF : 16 * NT), true, false>(buf, n, a.bl + a.bl_off[j], a.tw, a.TN,
+                                                                            z);
       }
-    };
-    if (MF > 0 && kind == FFT_POW2 && n == MF) {
-      load(0, EPT);
-      lds_fft_ct<R, false, NT, (MF > 0 ? MF : 16 * NT), false, false, true, false>(buf, a.tw, a.TN, z);
-    } else if (MF > 0 && kind == FFT_BLUESTEIN && M == MF) {
-      load(0, EPT / 2);  // n <= M/2
-      bluestein_ct<R, false, NT, (MF > 0 ? MF : 16 * NT), true, false>(buf, n, a.bl + a.bl_off[j], a.tw, a.TN, z);
     } else {
-      load(0, EPT);
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const int l = tid + e * NT;
-        if (l < n) buf[lidx(l)] = z[e];
+        if (l < n) z[e] = xc[l];
+      }
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int l = tid + e * NT;
+        if (l < n) buf[lidx(l)] = cscale(z[e], scale);
       }
       __syncthreads();
       if (kind == FFT_POW2) lds_fft<R, false, NT>(buf, n, a.tw, a.TN);
@@ -334,20 +341,20 @@ __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, cons
   }
   const int M = a.fft_m[i];
   cx_t<R>* yc = reinterpret_cast<cx_t<R>*>(yr);
-  // the compile-time transforms leave point tid + e NT in z[e]
-  C z[EPT];
-  if (MF > 0 && kind == FFT_POW2 && n == MF) {
-    lds_fft_ct<R, true, NT, (MF > 0 ? MF : 16 * NT), false, false, false, true>(buf, a.tw, a.TN, z);
+  if constexpr (MF > 0) {
+    // the compile-time transforms leave point tid + e NT in z[e]
+    C z[EPT];
+    if (kind == FFT_POW2) {  // n == MF
+      lds_fft_ct<R, true, NT, (MF > 0 ? MF : 16 * NT), false, false, false, true>(buf, a.tw, a.TN, z);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) yc[tid + e * NT] = z[e];
-    return;
-  }
-  if (MF > 0 && kind == FFT_BLUESTEIN && M == MF) {
-    bluestein_ct<R, true, NT, (MF > 0 ? MF : 16 * NT), false, true>(buf, n, a.bl + a.bl_off[i], a.tw, a.TN, z);
+      for (int e = 0; e < EPT; ++e) yc[tid + e * NT] = z[e];
+    } else {  // Bluestein, M == MF >= 2 n
+      bluestein_ct<R, true, NT, (MF > 0 ? MF : 16 * NT), false, true>(buf, n, a.bl + a.bl_off[i], a.tw, a.TN, z);
 #pragma unroll
-    for (int e = 0; e < EPT / 2; ++e) {
-      const int l = tid + e * NT;
-      if (l < n) yc[l] = z[e];
+      for (int e = 0; e < EPT / 2; ++e) {
+        const int l = tid + e * NT;
+        if (l < n) yc[l] = z[e];
+      }
     }
     return;
   }

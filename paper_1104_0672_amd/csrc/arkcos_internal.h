@@ -226,8 +226,8 @@ hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const in
 size_t ring_args_size();
 void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out);
 hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, const void* entries, int32_t count,
-                             int32_t lds, int32_t threads, const void* maps, void* ws, const int64_t* base,
-                             hipStream_t s);
+                             int32_t lds, int32_t threads, int32_t mf, const void* maps, void* ws,
+                             const int64_t* base, hipStream_t s);
 int fft_threads(arkcos_dtype_t dt, int32_t fft_len);
 size_t pole_map_size();
 void fill_pole_map(arkcos_plan_s* P, void* out);

@@ -31,6 +31,7 @@ struct ClassDev {
   int32_t count = 0;
   int32_t lds = 0;
   int32_t threads = 256;
+  int32_t mf = 0;  // the FFT length of every ring of the class, if they share one of 16 x threads
 };
 
 }  // namespace
@@ -322,13 +323,16 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
     for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
       ClassDev c;
       c.count = (int32_t)it->second.size();
-      int32_t mx = 0, len = 0;
+      int32_t mx = 0, len = 0, lo = INT32_MAX;
       for (const int2& e : it->second) {
         mx = std::max(mx, B->plans[e.x]->h_ring_lds[e.y]);
         len = std::max(len, B->plans[e.x]->h_fft_len[e.y]);
+        lo = std::min(lo, B->plans[e.x]->h_fft_len[e.y]);
       }
       c.lds = mx;
       c.threads = fft_threads(B->dtype, len);
+      // one FFT length of 16 x (the threads) for the whole class: compile-time transforms
+      c.mf = (lo == len && len == 16 * c.threads) ? len : 0;
       BCHK(bupload(B, &c.entries, it->second));
       B->classes.push_back(c);
     }
@@ -443,14 +447,14 @@ arkcos_status_t run_batch(arkcos_batch_s* B, const void* const* x, void* const* 
   if (B->timing_used < B->timing_slots) ev = &B->timing_events[5 * B->timing_used++];
   if (ev) BLAUNCH(hipEventRecord(ev[0], s));
   for (const ClassDev& c : B->classes)
-    BLAUNCH(launch_ring_batch(B->dtype, false, B->d_rargs[adjoint ? 1 : 0], c.entries, c.count, c.lds, c.threads, B->d_xs, spec,
+    BLAUNCH(launch_ring_batch(B->dtype, false, B->d_rargs[adjoint ? 1 : 0], c.entries, c.count, c.lds, c.threads, c.mf, B->d_xs, spec,
                               B->d_spec_base, s));
   if (ev) BLAUNCH(hipEventRecord(ev[1], s));
   BLAUNCH(launch_accumulate_batch(B->dtype, B->d_acc_args, B->d_spec_base, B->d_out_base, B->d_items, B->n_items,
                                   counter, spec, bout, B->grid, B->units_per_band, B->all_tables, B->acc_shape, s));
   if (ev) BLAUNCH(hipEventRecord(ev[2], s));
   for (const ClassDev& c : B->classes)
-    BLAUNCH(launch_ring_batch(B->dtype, true, B->d_rargs[adjoint ? 3 : 2], c.entries, c.count, c.lds, c.threads, B->d_ys, bout,
+    BLAUNCH(launch_ring_batch(B->dtype, true, B->d_rargs[adjoint ? 3 : 2], c.entries, c.count, c.lds, c.threads, c.mf, B->d_ys, bout,
                               B->d_out_base, s));
   if (ev) BLAUNCH(hipEventRecord(ev[3], s));
   if (!adjoint)

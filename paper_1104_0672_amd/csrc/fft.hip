@@ -389,7 +389,7 @@ __global__ void __launch_bounds__(NT, FftWaves<R>::value) c2r_kernel(RingArgs<R>
 
 // Batched forms: entry (map, ring); per-map arguments, maps and workspace
 // offsets in device arrays.
-template <typename R, int NT>
+template <typename R, int NT, int MF>
 __global__ void __launch_bounds__(NT, FftWaves<R>::value) r2c_batch_kernel(const RingArgs<R>* __restrict__ args,
                                                        const int2* __restrict__ entries,
                                                        const R* const* __restrict__ xs,
@@ -397,10 +397,10 @@ __global__ void __launch_bounds__(NT, FftWaves<R>::value) r2c_batch_kernel(const
   extern __shared__ __align__(16) unsigned char smem[];
   const int2 e = entries[blockIdx.x];
   const RingArgs<R> a = args[e.x];
-  r2c_ring<R, NT, 0>(a, e.y, xs[e.x], ws + base[e.x], reinterpret_cast<cx_t<R>*>(smem));
+  r2c_ring<R, NT, MF>(a, e.y, xs[e.x], ws + base[e.x], reinterpret_cast<cx_t<R>*>(smem));
 }
 
-template <typename R, int NT>
+template <typename R, int NT, int MF>
 __global__ void __launch_bounds__(NT, FftWaves<R>::value) c2r_batch_kernel(const RingArgs<R>* __restrict__ args,
                                                        const int2* __restrict__ entries,
                                                        const cx_t<R>* __restrict__ ws,
@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(NT, FftWaves<R>::value) c2r_batch_kernel(const
   __shared__ cx_t<R> nyq;
   const int2 e = entries[blockIdx.x];
   const RingArgs<R> a = args[e.x];
-  c2r_ring<R, NT, 0>(a, e.y, ws + base[e.x], ys[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
+  c2r_ring<R, NT, MF>(a, e.y, ws + base[e.x], ys[e.x], reinterpret_cast<cx_t<R>*>(smem), nyq);
 }
 
 template <typename R> RingArgs<R> ring_args(arkcos_plan_s* P, bool out_side, int adjoint,
@@ -528,32 +528,37 @@ void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t ze
 
 // Batched ring transforms: forward (R2C of maps[m] into ws + base[m]) or
 // inverse (C2R of ws + base[m] into maps[m]).
-template <typename R, int NT>
+template <typename R, int NT, int MF>
 static hipError_t ring_batch(bool inverse, const void* args, const void* entries, int32_t count, int32_t lds,
                              const void* maps, void* ws, const int64_t* base, hipStream_t s) {
   hipError_t e;
   if (!inverse) {
-    e = allow_lds(r2c_batch_kernel<R, NT>, lds);
+    e = allow_lds(r2c_batch_kernel<R, NT, MF>, lds);
     if (e != hipSuccess) return e;
-    r2c_batch_kernel<R, NT><<<count, NT, lds, s>>>((const RingArgs<R>*)args, (const int2*)entries,
-                                                   (const R* const*)maps, (cx_t<R>*)ws, base);
+    r2c_batch_kernel<R, NT, MF><<<count, NT, lds, s>>>((const RingArgs<R>*)args, (const int2*)entries,
+                                                       (const R* const*)maps, (cx_t<R>*)ws, base);
   } else {
-    e = allow_lds(c2r_batch_kernel<R, NT>, lds);
+    e = allow_lds(c2r_batch_kernel<R, NT, MF>, lds);
     if (e != hipSuccess) return e;
-    c2r_batch_kernel<R, NT><<<count, NT, lds, s>>>((const RingArgs<R>*)args, (const int2*)entries,
-                                                   (const cx_t<R>*)ws, base, (R* const*)maps);
+    c2r_batch_kernel<R, NT, MF><<<count, NT, lds, s>>>((const RingArgs<R>*)args, (const int2*)entries,
+                                                       (const cx_t<R>*)ws, base, (R* const*)maps);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, const void* entries, int32_t count,
-                             int32_t lds, int32_t threads, const void* maps, void* ws, const int64_t* base,
-                             hipStream_t s) {
+                             int32_t lds, int32_t threads, int32_t mf, const void* maps, void* ws,
+                             const int64_t* base, hipStream_t s) {
   if (count == 0) return hipSuccess;
-  if (dt == ARKCOS_F32)
-    return threads == 512 ? ring_batch<float, 512>(inverse, args, entries, count, lds, maps, ws, base, s)
-                          : ring_batch<float, 256>(inverse, args, entries, count, lds, maps, ws, base, s);
-  return ring_batch<double, 256>(inverse, args, entries, count, lds, maps, ws, base, s);
+  if (dt == ARKCOS_F32) {
+    if (threads == 512 && mf == 8192)
+      return ring_batch<float, 512, 8192>(inverse, args, entries, count, lds, maps, ws, base, s);
+    if (threads == 256 && mf == 4096)
+      return ring_batch<float, 256, 4096>(inverse, args, entries, count, lds, maps, ws, base, s);
+    return threads == 512 ? ring_batch<float, 512, 0>(inverse, args, entries, count, lds, maps, ws, base, s)
+                          : ring_batch<float, 256, 0>(inverse, args, entries, count, lds, maps, ws, base, s);
+  }
+  return ring_batch<double, 256, 0>(inverse, args, entries, count, lds, maps, ws, base, s);
 }
 
 // Step (a) into the output-ring layout (lengths out_len): the extended

@@ -229,6 +229,13 @@ hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, 
                              int32_t lds, int32_t threads, int32_t mf, const void* maps, void* ws,
                              const int64_t* base, hipStream_t s);
 int fft_threads(arkcos_dtype_t dt, int32_t fft_len);
+// FFT lengths with compile-time ring kernels (16 points per thread): the
+// length itself if fft_len is one of them for the dtype, else 0.  The
+// 1024- and 2048-point kernels (64 and 128 threads) pay off only in launches
+// of many rings: they are used when `rings` (the rings of that length in
+// the launch set) reaches kCtMinRings.
+constexpr int64_t kCtMinRings = 8192;
+int32_t ct_fft_length(arkcos_dtype_t dt, int32_t fft_len, int64_t rings);
 size_t pole_map_size();
 void fill_pole_map(arkcos_plan_s* P, void* out);
 hipError_t launch_pole_batch(arkcos_dtype_t dt, const void* maps, const int2* entries, int32_t count, int32_t adjoint,

@@ -31,7 +31,7 @@ struct ClassDev {
   int32_t count = 0;
   int32_t lds = 0;
   int32_t threads = 256;
-  int32_t mf = 0;  // the FFT length of every ring of the class, if they share one of 16 x threads
+  int32_t mf = 0;  // the compile-time FFT length of every ring of the class, if they share one
 };
 
 }  // namespace
@@ -311,12 +311,18 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
     B->d_rargs[v] = d;
   }
   {
-    std::map<int32_t, std::vector<int2>> cls;
+    std::map<int64_t, std::vector<int2>> cls;
+    std::map<int32_t, int64_t> per_len;
+    for (int32_t i = 0; i < n; ++i)
+      for (int64_t k = 0; k < B->plans[i]->nrings; ++k) ++per_len[B->plans[i]->h_fft_len[k]];
     for (int32_t i = 0; i < n; ++i) {
       arkcos_plan_s* P = B->plans[i];
       for (int64_t k = 0; k < P->nrings; ++k) {
-        int32_t b = 32768;  // small rings of every map share one launch
+        int64_t b = 32768;  // small rings of every map share one launch
         while (b < P->h_ring_lds[k]) b <<= 1;
+        // a compile-time FFT length: one class per length
+        const int32_t ct = ct_fft_length(B->dtype, P->h_fft_len[k], per_len[P->h_fft_len[k]]);
+        if (ct > 0) b = (int64_t(1) << 40) + ct;
         cls[b].push_back(make_int2(i, (int)k));
       }
     }
@@ -330,9 +336,9 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
         lo = std::min(lo, B->plans[e.x]->h_fft_len[e.y]);
       }
       c.lds = mx;
-      c.threads = fft_threads(B->dtype, len);
-      // one FFT length of 16 x (the threads) for the whole class: compile-time transforms
-      c.mf = (lo == len && len == 16 * c.threads) ? len : 0;
+      // one compile-time FFT length for the whole class: compile-time transforms
+      c.mf = (lo == len) ? ct_fft_length(B->dtype, len, per_len[len]) : 0;
+      c.threads = c.mf > 0 ? c.mf / 16 : fft_threads(B->dtype, len);
       BCHK(bupload(B, &c.entries, it->second));
       B->classes.push_back(c);
     }

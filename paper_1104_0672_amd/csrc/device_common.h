@@ -251,13 +251,15 @@ __device__ void lds_fft(cx_t<R>* buf, int M, const cx_t<R>* __restrict__ tw, int
 // butterfly are its base address plus compile-time offsets: the reads
 // j + r Q of a pass sit r (Q + Q/32) slots apart (Q a multiple of 32), and
 // the writes o + r Ns (o = (j - j mod Ns) RAD + j mod Ns) a constant distance
-// out_gap(r) apart for the Ns that occur (1, 2, 16 and multiples of 32).
+// out_gap(r) apart (Ns and RAD powers of two).
 // ---------------------------------------------------------------------------
 template <int NS, int RAD> __device__ __forceinline__ constexpr int out_gap(int r) {
-  static_assert(NS * RAD <= 32 || NS == 16 || NS % 32 == 0, "pass shape");
-  if constexpr (NS % 32 == 0) return r * (NS + NS / 32);
-  else if constexpr (NS * RAD <= 32) return r * NS;  // the butterfly's outputs share one 32-slot row
-  else return 16 * r + (r >> 1);                      // NS = 16: o mod 32 < 16
+  // o = (j - k) RAD + k with k < NS and j - k a multiple of NS: if NS RAD >= 32,
+  // o mod 32 = k mod 32 and o + r NS crosses exactly the 32-slot rows r NS
+  // does; if NS RAD <= 32, o mod 32 is a multiple of NS RAD plus k and the
+  // RAD outputs stay in one row
+  static_assert((NS & (NS - 1)) == 0 && (RAD & (RAD - 1)) == 0, "pass shape");
+  return r * NS + ((r * NS) >> 5);
 }
 
 // HIN (first pass, NS = 1): the points M/2 .. M-1 are zero and not read.

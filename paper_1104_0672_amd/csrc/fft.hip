@@ -250,7 +250,7 @@ __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, cons
     }
   };
   const int npr = n / 2 + 1;  // pairs (r, n - r), r <= n / 2
-  if (2 * npr <= kFoldThreads) {
+  if (NT >= kFoldThreads && 2 * npr <= kFoldThreads) {
     // a short ring: the periods q are shared out over G groups of threads
     // (thread t: pair t mod npr, periods q = t / npr + k G), the groups'
     // partial sums are added in group order through LDS
@@ -438,6 +438,13 @@ int fft_threads(arkcos_dtype_t dt, int32_t fft_len) {
   return (dt == ARKCOS_F32 && fft_len > kFftCap<256>) ? 512 : 256;
 }
 
+int32_t ct_fft_length(arkcos_dtype_t dt, int32_t fft_len, int64_t rings) {
+  if (dt != ARKCOS_F32) return 0;
+  if (fft_len == 4096 || fft_len == 8192) return fft_len;
+  if ((fft_len == 1024 || fft_len == 2048) && rings >= kCtMinRings) return fft_len;
+  return 0;
+}
+
 template <typename K> static hipError_t allow_lds(K* k, int32_t bytes) {
   return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
@@ -451,10 +458,14 @@ hipError_t configure_fft_kernels(arkcos_plan_s* P) {
     if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 512, 0>, b);
     if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 256, 4096>, b);
     if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 512, 8192>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 128, 2048>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 64, 1024>, b);
     if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 256, 0>, b);
     if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 512, 0>, b);
     if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 256, 4096>, b);
     if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 512, 8192>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 128, 2048>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 64, 1024>, b);
   } else {
     if (e == hipSuccess) e = allow_lds(r2c_kernel<double, 256, 0>, b);
     if (e == hipSuccess) e = allow_lds(c2r_kernel<double, 256, 0>, b);
@@ -477,6 +488,14 @@ static void r2c_class(const FftClass& c, const RingArgs<R>& a, const void* x, vo
       r2c_kernel<R, 256, 4096><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, xi, so);
       return;
     }
+    if (c.threads == 128 && c.mf == 2048) {
+      r2c_kernel<R, 128, 2048><<<(unsigned)c.count, 128, c.lds, s>>>(a, c.d_rings, xi, so);
+      return;
+    }
+    if (c.threads == 64 && c.mf == 1024) {
+      r2c_kernel<R, 64, 1024><<<(unsigned)c.count, 64, c.lds, s>>>(a, c.d_rings, xi, so);
+      return;
+    }
     if (c.threads == 512) {
       r2c_kernel<R, 512, 0><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, xi, so);
       return;
@@ -496,6 +515,14 @@ static void c2r_class(const FftClass& c, const RingArgs<R>& a, const void* b, vo
     }
     if (c.threads == 256 && c.mf == 4096) {
       c2r_kernel<R, 256, 4096><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, bi, yo);
+      return;
+    }
+    if (c.threads == 128 && c.mf == 2048) {
+      c2r_kernel<R, 128, 2048><<<(unsigned)c.count, 128, c.lds, s>>>(a, c.d_rings, bi, yo);
+      return;
+    }
+    if (c.threads == 64 && c.mf == 1024) {
+      c2r_kernel<R, 64, 1024><<<(unsigned)c.count, 64, c.lds, s>>>(a, c.d_rings, bi, yo);
       return;
     }
     if (c.threads == 512) {
@@ -555,6 +582,10 @@ hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, 
       return ring_batch<float, 512, 8192>(inverse, args, entries, count, lds, maps, ws, base, s);
     if (threads == 256 && mf == 4096)
       return ring_batch<float, 256, 4096>(inverse, args, entries, count, lds, maps, ws, base, s);
+    if (threads == 128 && mf == 2048)
+      return ring_batch<float, 128, 2048>(inverse, args, entries, count, lds, maps, ws, base, s);
+    if (threads == 64 && mf == 1024)
+      return ring_batch<float, 64, 1024>(inverse, args, entries, count, lds, maps, ws, base, s);
     return threads == 512 ? ring_batch<float, 512, 0>(inverse, args, entries, count, lds, maps, ws, base, s)
                           : ring_batch<float, 256, 0>(inverse, args, entries, count, lds, maps, ws, base, s);
   }

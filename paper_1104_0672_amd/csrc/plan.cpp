@@ -582,13 +582,19 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
     // run of 8 northern rings is followed by their 8 mirrors: a ring and its
     // mirror then run on the same XCD and share its L2 copy of their
     // Bluestein filter.
+    // Rings whose FFT length has a compile-time kernel (ct_fft_length) get a
+    // class of their own per length.
     std::map<size_t, std::vector<std::pair<int32_t, int32_t>>> pairs_of;
     std::vector<int64_t> order((nr + 1) / 2);
     for (int64_t k = 0; k < (int64_t)order.size(); ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return P->h_n[x] > P->h_n[y]; });
+    std::map<int32_t, int64_t> per_len;
+    for (int64_t k = 0; k < nr; ++k) ++per_len[fft_m[k]];
     for (int64_t k : order) {
       size_t b = 32768;
       while (b < ring_lds[k]) b <<= 1;
+      const int32_t ct = ct_fft_length(dtype, fft_m[k], per_len[fft_m[k]]);
+      if (ct > 0) b = (size_t(1) << 40) + (size_t)ct;
       pairs_of[b].push_back({(int32_t)k, nr - 1 - k != k ? (int32_t)(nr - 1 - k) : -1});
     }
     std::map<size_t, std::vector<int32_t>> cls;
@@ -612,8 +618,8 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
         lo = std::min(lo, fft_m[k]);
       }
       c.lds = (int32_t)((mx + 15) / 16 * 16);
-      c.threads = fft_threads(dtype, len);
-      c.mf = (lo == len && len == 16 * c.threads) ? len : 0;
+      c.mf = (lo == len) ? ct_fft_length(dtype, len, per_len[len]) : 0;
+      c.threads = c.mf > 0 ? c.mf / 16 : fft_threads(dtype, len);
       HIPCHK(upload(P, &c.d_rings, it->second));
       P->fft_classes.push_back(c);
     }

@@ -69,6 +69,31 @@ def test_batch_mixed_kernel_sources_equal_per_plan_results():
             assert torch.equal(y, ref)
 
 
+def test_batch_many_rings_equals_per_plan_results():
+    """Seven nside-512 maps: the batch holds more than 8192 rings of each of
+    the 1024- and 2048-point FFT lengths, so it runs them through the
+    compile-time ring kernels that a single plan of this size does not use.
+    Those kernels keep the FFT passes in registers and round differently
+    from the LDS kernels, so every map equals its own plan's result to a few
+    FP32 ulps rather than bit for bit."""
+    from paper_1104_0672_amd import Batch, Plan
+    w0 = W.scaled_healpix(512, 2.5 * 60 * math.degrees(math.sqrt(math.pi / 3) / 512), 3.0, seed=71)
+    plan = Plan.from_workload(w0)
+    batch = Batch([plan] * 7)
+    print("case seven nside-512 maps", flush=True)
+    xs = []
+    for k in range(7):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(100 + k)
+        xs.append(torch.randn(w0.grid.npix, generator=g, device="cuda", dtype=torch.float32))
+    for adjoint in (False, True):
+        ys = batch.convolve(xs, adjoint=adjoint)
+        for x, y in zip(xs, ys):
+            ref = plan.adjoint(x) if adjoint else plan.convolve(x)
+            err = float((y - ref).abs().max()) / float(ref.abs().max())
+            assert err <= 1e-6, err
+
+
 def test_batch_graph_capture_replays():
     from paper_1104_0672_amd import Batch, Plan
     wl = _small_batch(seed=41, n=5)

@@ -474,7 +474,7 @@ hipError_t configure_fft_kernels(arkcos_plan_s* P) {
 }
 
 // The launches of one class: a kernel compiled for the class's FFT length
-// when every ring of the class has the same one (4096 or 8192 points).
+// when every ring of the class has the same one (a compile-time length).
 template <typename R>
 static void r2c_class(const FftClass& c, const RingArgs<R>& a, const void* x, void* spec, hipStream_t s) {
   const R* xi = (const R*)x;

@@ -147,8 +147,18 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
       else bluestein<R, false, NT>(buf, n, M, a.bl + a.bl_off[j], a.tw, a.TN);
     }
     constexpr int kPairBatch = PairBatch<R>::value;
+    // A~(k), 0 <= k <= n, to every mode of the periodic extension:
+    // A~(qN + k) = s^q A~(k) and, for 0 < k < n, A~(qN + N - k) = s^(q+1) conj(A~(k))
+    auto emit = [&](int k, C v) {
+      for (int m = k, q = 0; m < len; m += N, ++q) out[m] = (shifted && (q & 1)) ? cscale(v, R(-1)) : v;
+      if (k > 0 && k < n) {
+        const C vc = cconj(v);
+        for (int m = N - k, q = 1; m < len; m += N, ++q) out[m] = (shifted && (q & 1)) ? cscale(vc, R(-1)) : vc;
+      }
+    };
     // split Z into A(r) = E(r) - i exp(-2 pi i r / N) O(r) for the pair
-    // (r, n - r), then the phase shift A~(r) = A(r) w_r, w_{n-r} = -i conj(w_r)
+    // (r, n - r), then the phase shift A~(r) = A(r) w_r, w_{n-r} = -i conj(w_r),
+    // and the results straight to the spectrum
     for (int base = 0; base <= n / 2; base += NT * kPairBatch) {
       C wr[kPairBatch];
 #pragma unroll
@@ -173,15 +183,15 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
             const C w2 = cmake<C>(-wr[u].y, -wr[u].x);    // -i conj(w_r)
             a2 = cmul(a2, w2);
           }
-          buf[lidx(r)] = a1;
-          if (r2 != r) buf[lidx(r2)] = a2;  // r = 0: A(n) in the slot after the n points
+          emit(r, a1);
+          if (r2 != r) emit(r2, a2);  // r = 0: A(n)
         }
       }
     }
-    __syncthreads();
+    return;
   }
-  // periodic extension: A~(qN + r) = s^q A~(r), A~(N - r) = s conj(A~(r)),
-  // m = q N + r advanced by NT per step
+  // (short rings) periodic extension: A~(qN + r) = s^q A~(r),
+  // A~(N - r) = s conj(A~(r)), m = q N + r advanced by NT per step
   int q = tid / N, r = tid - q * N;
   const int dq = NT / N, dr = NT - dq * N;
   for (int m = tid; m < len; m += NT) {

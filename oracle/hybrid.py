@@ -27,6 +27,13 @@ Sect. 4.3):
 (e) optionally, the first and last ring (8 pixels on HEALPix) recomputed by
     the direct sum (Sect. 4.2).
 
+``mode="default"`` is the paper's plain mode of Sect. 4.1, without the
+artifact suppression of Sect. 4.3: every pair uses the ``p L`` kernel grid
+(no pair is sampled at its true pixel offsets), step (a) zero-pads each
+ring's spectrum beyond its own Nyquist mode instead of repeating it, and
+step (d) keeps only the output ring's modes |m| <= N_i / 2 instead of folding
+the higher ones onto them.
+
 Readings taken where the paper is silent (each listed in the design doc):
 
 * Kernel grids: pairs of equal-length rings sample the kernel at their true
@@ -37,6 +44,10 @@ Readings taken where the paper is silent (each listed in the design doc):
   so every pair contributes the real trigonometric interpolant of its kernel
   row, evaluated at the true pixel offsets.
 * The 1 / (grid length) normalisation of the kernel FFT is applied per pair.
+* Default mode: the zero-padded spectrum keeps the ring's DFT at 0 <= m <= N/2
+  (the Nyquist coefficient included once, as the paper's rectangular array
+  holds it), and the truncated synthesis is the two-sided real sum over
+  |m| <= N_i / 2 (both +N_i/2 and -N_i/2 kept).
 """
 from __future__ import annotations
 
@@ -59,7 +70,7 @@ def _grid_length(grid):
     return 4 * grid.nside if grid.kind == "healpix" else grid.nphi
 
 
-def pair_plan(grid, radius, oversample):
+def pair_plan(grid, radius, oversample, mode="suppressed"):
     """For each output ring i: list of (j, G, s) -- input ring, number of
     kernel-grid longitudes and half-shift flag of the grid.
 
@@ -67,7 +78,8 @@ def pair_plan(grid, radius, oversample):
     equatorial rings, any ECP pair) are sampled at their true pixel offsets on
     a grid of their own length (the equatorial modification of Sect. 4.3,
     applied to every equal-length pair); the rest use oversample * L
-    longitudes (L = 4 nside: the paper's kernel grid when oversample = 1)."""
+    longitudes (L = 4 nside: the paper's kernel grid when oversample = 1).
+    In the default mode every pair uses the oversample * L grid."""
     th, ph0, w, n, st = rings(grid)
     L = _grid_length(grid)
     out = []
@@ -77,7 +89,7 @@ def pair_plan(grid, radius, oversample):
             if abs(th[j] - th[i]) > radius + 1e-6:
                 continue
             e = (ph0[i] - ph0[j]) * n[i] / np.pi
-            aligned = n[i] == n[j] and abs(e - round(e)) < 1e-9
+            aligned = mode == "suppressed" and n[i] == n[j] and abs(e - round(e)) < 1e-9
             if aligned:
                 lst.append((j, int(n[i]), int(round(e)) % 2))
             else:
@@ -86,9 +98,14 @@ def pair_plan(grid, radius, oversample):
     return out
 
 
-def _extended_spectrum(a, phi0, nring, mmax):
-    """Physical-longitude spectrum A_j(m mod N_j) exp(-i m phi0), m = 0..mmax."""
+def _extended_spectrum(a, phi0, nring, mmax, mode="suppressed"):
+    """Physical-longitude spectrum A_j(m mod N_j) exp(-i m phi0), m = 0..mmax;
+    in the default mode A_j(m) exp(-i m phi0) up to m = N_j / 2 and zero
+    beyond."""
     m = np.arange(mmax + 1)
+    if mode == "default":
+        base = np.where(m <= nring // 2, a[np.minimum(m, nring // 2)], 0.0)
+        return base * np.exp(-1j * m * phi0)
     r = m % nring
     lower = r <= nring // 2
     base = np.where(lower, a[np.minimum(r, nring // 2)], np.conj(a[np.minimum(nring - r, nring // 2)]))
@@ -110,8 +127,11 @@ def _kernel_row_spectrum(profile, radius, th_i, th_j, w_j, nn, s, values=None):
     return kf
 
 
-def _fold_inverse(bm, phi0, nring):
-    """Reverse phase shift, alias every mode onto m mod N, inverse real FFT."""
+def _fold_inverse(bm, phi0, nring, mode="suppressed"):
+    """Reverse phase shift, alias every mode onto m mod N, inverse real FFT;
+    the default mode first drops the modes above N / 2 (truncation)."""
+    if mode == "default":
+        bm = bm[: nring // 2 + 1]
     m = np.arange(bm.size)
     bp = bm * np.exp(1j * m * phi0)
     half = nring // 2
@@ -125,20 +145,22 @@ def _fold_inverse(bm, phi0, nring):
     return np.fft.irfft(g, nring) * nring
 
 
-def _hybrid_core(grid, profile, radius, x, oversample, values=None):
+def _hybrid_core(grid, profile, radius, x, oversample, values=None, mode="suppressed"):
+    if mode not in ("suppressed", "default"):
+        raise ValueError(mode)
     th, ph0, w, n, st = rings(grid)
     L = _grid_length(grid)
     x = np.asarray(x, dtype=np.float64)
     spec = [np.fft.rfft(x[st[j]: st[j] + n[j]]) for j in range(len(th))]      # step (a)
-    plan = pair_plan(grid, radius, oversample)
+    plan = pair_plan(grid, radius, oversample, mode)
     y = np.empty(grid.npix)
     for i, pairs in enumerate(plan):
         mmax = max(nn // 2 for (_, nn, _) in pairs)
         b = np.zeros(mmax + 1, complex)
         for (j, nn, s) in pairs:
             kf = _kernel_row_spectrum(profile, radius, th[i], th[j], w[j], nn, s, values)  # (b)
-            b[: kf.size] += kf * _extended_spectrum(spec[j], ph0[j], n[j], kf.size - 1)     # (c)
-        y[st[i]: st[i] + n[i]] = _fold_inverse(b, ph0[i], n[i])                             # (d)
+            b[: kf.size] += kf * _extended_spectrum(spec[j], ph0[j], n[j], kf.size - 1, mode)  # (c)
+        y[st[i]: st[i] + n[i]] = _fold_inverse(b, ph0[i], n[i], mode)                          # (d)
     return y
 
 
@@ -149,17 +171,18 @@ def _pole_pixels(grid):
     return np.array([0, 1, 2, 3, npix - 4, npix - 3, npix - 2, npix - 1], np.int64)
 
 
-def hybrid(grid, profile, radius, x, oversample=2, fix_poles=True):
+def hybrid(grid, profile, radius, x, oversample=2, fix_poles=True, mode="suppressed"):
     """The method's output map (FP64).  ``fix_poles`` recomputes the first and
-    last HEALPix ring by the direct sum (step (e))."""
-    y = _hybrid_core(grid, profile, radius, x, oversample)
+    last HEALPix ring by the direct sum (step (e)); ``mode`` is "suppressed"
+    (Sect. 4.3) or "default" (Sect. 4.1 alone)."""
+    y = _hybrid_core(grid, profile, radius, x, oversample, mode=mode)
     idx = _pole_pixels(grid)
     if fix_poles and idx.size:
         y[idx] = direct(grid, profile, radius, x, idx=idx)
     return y
 
 
-def hybrid_adjoint(grid, profile, radius, r, oversample=2, fix_poles=True):
+def hybrid_adjoint(grid, profile, radius, r, oversample=2, fix_poles=True, mode="suppressed"):
     """Transpose of ``hybrid`` as a linear map of x.  Ring pairs use symmetric
     kernel grids, so the transpose of the ring pipeline is
     ``w * pipeline(r / w)``; the direct-sum rows of step (e) transpose into
@@ -172,14 +195,14 @@ def hybrid_adjoint(grid, profile, radius, r, oversample=2, fix_poles=True):
     if fix_poles and idx.size:
         rfix[idx] = r[idx]
         r[idx] = 0.0
-    out = wpix * _hybrid_core(grid, profile, radius, r / wpix, oversample)
+    out = wpix * _hybrid_core(grid, profile, radius, r / wpix, oversample, mode=mode)
     if fix_poles and idx.size:
         from . import adjoint
         out += adjoint(grid, profile, radius, rfix)
     return out
 
 
-def hybrid_knot_grad(grid, profile, radius, x, r, oversample=2, fix_poles=True):
+def hybrid_knot_grad(grid, profile, radius, x, r, oversample=2, fix_poles=True, mode="suppressed"):
     """Gradient of 1/2 |hybrid(x) - t|^2 with respect to the spline knots,
     given r = hybrid(x) - t: the method is linear in the kernel, so
     g_k = <r, hybrid_k(x)> with hybrid_k the method run with kernel phi_k."""
@@ -189,7 +212,7 @@ def hybrid_knot_grad(grid, profile, radius, x, r, oversample=2, fix_poles=True):
     r = np.asarray(r, dtype=np.float64)
     for k in range(nk):
         yk = _hybrid_core(grid, profile, radius, x, oversample,
-                          values=lambda t, k=k: basis(profile, radius, t)[:, k])
+                          values=lambda t, k=k: basis(profile, radius, t)[:, k], mode=mode)
         if fix_poles and idx.size:
             from . import knot_grad
             rr = r.copy()

@@ -13,7 +13,12 @@ not against the oracle's own formulas.
   exact up to rounding;
 * the step-by-step hybrid reference: it equals the direct sum where the
   method is exact (ECP grids, equatorial HEALPix rings; Sect. 4.3) and
-  converges to it with kernel oversampling elsewhere.
+  converges to it with kernel oversampling elsewhere;
+* its default mode (Sect. 4.1 without Sect. 4.3): the zero-padded spectrum
+  and the truncated synthesis against explicit trigonometric sums, equality
+  with the suppressed mode where nothing is padded or truncated (ECP), the
+  truncation error vanishing as the kernel becomes band-limited, and the
+  cap and equator artifacts that the suppression removes (Sect. 4.3).
 """
 import math
 import os
@@ -399,3 +404,100 @@ def test_hybrid_knot_gradient_equals_central_differences():
         e[k] = h
         fd = (loss(c + e) - loss(c - e)) / (2 * h)
         assert abs(fd - grad[k]) <= 1e-8 * max(1.0, abs(grad[k])), (k, fd, grad[k])
+
+
+# ------------------------------------------- the paper's default mode (4.1)
+
+def test_default_mode_steps_by_explicit_sums():
+    """Zero-padded spectrum: A(m) = sum_k x_k exp(-i m (phi0 + 2 pi k / N))
+    for m <= N/2, zero beyond; truncated synthesis: the real two-sided sum
+    y_k = sum_{|m| <= N/2} B(m) exp(i m (phi0 + 2 pi k / N)), B(-m) = conj B(m)."""
+    from oracle.hybrid import _extended_spectrum, _fold_inverse
+    rng = np.random.default_rng(41)
+    for N, phi0 in ((12, math.pi / 12), (8, 0.0), (20, math.pi / 20)):
+        x = rng.standard_normal(N)
+        mmax = 2 * N + 3
+        got = _extended_spectrum(np.fft.rfft(x), phi0, N, mmax, mode="default")
+        for m in range(mmax + 1):
+            want = 0j
+            if m <= N // 2:
+                for k in range(N):
+                    ang = m * (phi0 + 2 * math.pi * k / N)
+                    want += x[k] * complex(math.cos(ang), -math.sin(ang))
+            assert abs(got[m] - want) < 1e-12 * N, (N, m)
+        b = rng.standard_normal(mmax + 1) + 1j * rng.standard_normal(mmax + 1)
+        b[0] = b[0].real
+        y = _fold_inverse(b, phi0, N, mode="default")
+        for k in range(N):
+            t = 0.0
+            for m in range(-(N // 2), N // 2 + 1):
+                bm = b[m] if m >= 0 else np.conj(b[-m])
+                ang = m * (phi0 + 2 * math.pi * k / N)
+                t += (bm * complex(math.cos(ang), math.sin(ang))).real
+            assert abs(y[k] - t) < 1e-11 * N, (N, k)
+
+
+def test_default_mode_equals_suppressed_mode_on_ecp():
+    """ECP rings all have the grid's length and no offset: nothing is padded
+    or truncated, so both modes are the exact direct sum."""
+    w = W.ecp_64x128()
+    x = W.make_input(w)
+    yd = oracle.direct(w.grid, w.profile, w.radius, x)
+    ya = oracle.hybrid(w.grid, w.profile, w.radius, x, oversample=1, mode="default")
+    yb = oracle.hybrid(w.grid, w.profile, w.radius, x, oversample=1)
+    assert np.abs(ya - yb).max() < 1e-13 * np.abs(yd).max()
+    assert np.abs(ya - yd).max() < 1e-12 * np.abs(yd).max()
+
+
+def test_default_mode_truncation_error_vanishes_for_band_limited_kernels():
+    """On rings whose whole support lies in the equatorial belt only the
+    truncation at the ring's Nyquist mode separates the default mode from the
+    direct sum: the error falls by orders of magnitude as the beam widens."""
+    nside = 32
+    g = W.Grid("healpix", nside=nside)
+    pix = math.sqrt(math.pi / 3) / nside
+    th, ph0, w, n, st = oracle.rings(g)
+    x = np.random.default_rng(12).standard_normal(g.npix)
+    err = []
+    for fw in (5.0, 6.0):
+        prof, R = _gauss(fw * pix), 3 * fw * pix
+        yd = oracle.direct(g, prof, R, x)
+        eq = [i for i in range(len(th)) if np.all(n[np.abs(th - th[i]) <= R + 1e-6] == 4 * nside)]
+        sel = np.concatenate([st[i] + np.arange(n[i]) for i in eq])
+        yh = oracle.hybrid(g, prof, R, x, oversample=2, fix_poles=False, mode="default")
+        err.append(np.abs(yh[sel] - yd[sel]).max() / np.abs(yd).max())
+    assert err[1] < 1e-6 and err[1] < err[0] / 30, err
+
+
+def test_suppression_removes_default_mode_artifacts():
+    """Point sources under a 2.5-pixel beam: the default mode rings in the caps
+    and on the equator (percent level), the suppressed mode with the same
+    kernel grid does not (Sect. 4.3)."""
+    nside = 16
+    g = W.Grid("healpix", nside=nside)
+    pix = math.sqrt(math.pi / 3) / nside
+    th, ph0, w, n, st = oracle.rings(g)
+    prof, R = _gauss(2.5 * pix), 7.5 * pix
+    rng = np.random.default_rng(5)
+    x = np.zeros(g.npix)
+    x[rng.choice(g.npix, 40, replace=False)] = 1.0
+    yd = oracle.direct(g, prof, R, x)
+    for ring_sel in ([i for i in range(len(th)) if n[i] < 4 * nside], [i for i in range(len(th)) if n[i] == 4 * nside]):
+        sel = np.concatenate([st[i] + np.arange(n[i]) for i in ring_sel])
+        e = {}
+        for mode in ("suppressed", "default"):
+            yh = oracle.hybrid(g, prof, R, x, oversample=4, fix_poles=False, mode=mode)
+            e[mode] = np.linalg.norm(yh[sel] - yd[sel]) / np.linalg.norm(yd[sel])
+        assert e["default"] > 3e-3 and e["suppressed"] < 1e-9, e
+
+
+def test_default_mode_adjoint_is_transpose():
+    g = W.Grid("healpix", nside=8)
+    pix = math.sqrt(math.pi / 3) / 8
+    prof, R = _gauss(2 * pix), 6 * pix
+    rng = np.random.default_rng(17)
+    x, y = rng.standard_normal(g.npix), rng.standard_normal(g.npix)
+    for fix in (False, True):
+        a = np.dot(oracle.hybrid(g, prof, R, x, oversample=2, fix_poles=fix, mode="default"), y)
+        b = np.dot(x, oracle.hybrid_adjoint(g, prof, R, y, oversample=2, fix_poles=fix, mode="default"))
+        assert abs(a - b) < 1e-12 * abs(a), (fix, a, b)

@@ -25,6 +25,10 @@
  * shift, with the kernel sampled at the true pixel offsets (Sect. 4.3); this
  * makes them exact.  Pairs involving a polar ring sample the kernel on
  * `oversample * 4 nside` longitudes instead of 4 nside.
+ * The option `mode = 1` selects the paper's plain algorithm of Sect. 4.1
+ * instead: every pair on the `oversample * 4 nside` grid, each ring's
+ * spectrum zero-padded past its Nyquist mode in (a), and in (d) only the
+ * output ring's modes |m| <= N_i / 2 kept (truncation instead of aliasing).
  *
  * Conventions shared by every entry point:
  *   - Maps are device buffers in RING order: HEALPix with npix = 12 nside^2,
@@ -103,6 +107,12 @@ typedef struct {
   double band_tol;          /* modes with |K_ij(m)| below band_tol times the largest
                                kernel-row magnitude are dropped; < 0 = default
                                (1e-9 for F32, 0 for F64) */
+  int32_t mode;             /* 0 = with the artifact suppression of Sect. 4.3
+                               (default); 1 = the plain algorithm of Sect. 4.1
+                               (zero-padded spectra, truncated output modes, no
+                               pair on its own grid), for comparisons of the
+                               two; on ECP grids both give the same result */
+  int32_t reserved;         /* must be 0 */
 } arkcos_options_t;
 
 /* Summary of a plan (sizes, chosen parameters), for callers and tooling. */
@@ -120,7 +130,7 @@ typedef struct {
 } arkcos_plan_info_t;
 
 /* Fill *opts with the defaults (oversample 0, kgen 0, fix_pole_pixels 1,
- * band_tol -1). */
+ * band_tol -1, mode 0). */
 void arkcos_default_options(arkcos_options_t* opts);
 
 /* Build a plan on the current device: ring and pair tables, the FP64 kernel

@@ -37,7 +37,8 @@ class ProfileC(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("oversample", ctypes.c_int32), ("kgen", ctypes.c_int32),
-                ("fix_pole_pixels", ctypes.c_int32), ("band_tol", ctypes.c_double)]
+                ("fix_pole_pixels", ctypes.c_int32), ("band_tol", ctypes.c_double),
+                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -130,7 +131,7 @@ class Plan:
     def __init__(self, grid: str, radius: float, *, nside: int = 0, ntheta: int = 0, nphi: int = 0,
                  fwhm: float = 0.0, knots: Optional[Sequence[float]] = None, theta_max: float = 0.0,
                  dtype: str = "f32", oversample: int = 0, kgen: int = 0, fix_pole_pixels: bool = True,
-                 band_tol: float = -1.0):
+                 band_tol: float = -1.0, mode: str = "suppressed"):
         lib = load_library()
         self._lib = lib
         self.handle = ctypes.c_void_p()
@@ -142,7 +143,10 @@ class Plan:
                             ctypes.cast(self._knots, ctypes.POINTER(ctypes.c_double)))
         else:
             prof = ProfileC(GAUSSIAN, float(fwhm), 0, 0.0, None)
-        opts = Options(int(oversample), int(kgen), int(bool(fix_pole_pixels)), float(band_tol))
+        if mode not in ("suppressed", "default"):
+            raise ArkcosError(f"mode must be 'suppressed' or 'default', not {mode!r}")
+        opts = Options(int(oversample), int(kgen), int(bool(fix_pole_pixels)), float(band_tol),
+                       1 if mode == "default" else 0, 0)
         self.dtype = torch.float32 if dtype == "f32" else torch.float64
         self.grid = grid
         _check(lib.arkcos_plan(ctypes.byref(geom), ctypes.byref(prof), float(radius),

@@ -99,6 +99,8 @@ void arkcos_default_options(arkcos_options_t* o) {
   o->kgen = 0;
   o->fix_pole_pixels = 1;
   o->band_tol = -1.0;
+  o->mode = 0;
+  o->reserved = 0;
 }
 
 arkcos_status_t arkcos_plan(const arkcos_geometry_t* geom, const arkcos_profile_t* profile,

@@ -212,6 +212,16 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
   } else {
     for (int64_t q = 0; q < np; ++q) band[q] = abs_sum[q] > 0 ? P->h_pairs[q].nyq : -1;
   }
+  if (first_time && P->opts.mode == 1) {
+    // the plain mode of Sect. 4.1: input spectra zero-padded past N_j / 2
+    // and output coefficients truncated at N_i / 2, i.e. a pair contributes
+    // only its modes m <= min(N_i, N_j) / 2 (both rings of a mirrored pair
+    // have the lengths of the northern one)
+    for (int64_t q = 0; q < np; ++q) {
+      const int32_t top = (int32_t)(std::min(P->h_n[P->h_pair_i[q]], P->h_n[P->h_pairs[q].j]) / 2);
+      band[q] = std::min(band[q], top);
+    }
+  }
   if (!first_time) {
     // the memory layout was sized for the original bands and table choices: keep them
     for (int64_t q = 0; q < np; ++q) band[q] = P->h_pairs[q].band;
@@ -345,6 +355,8 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   if (opts.oversample != 0 && !(is_pow2(opts.oversample) && opts.oversample <= 16))
     return fail(ARKCOS_ERR_INVALID_VALUE, "oversample must be 0, 1, 2, 4, 8 or 16");
   if (opts.kgen < 0 || opts.kgen > 2) return fail(ARKCOS_ERR_INVALID_VALUE, "kgen must be 0, 1 or 2");
+  if (opts.mode < 0 || opts.mode > 1) return fail(ARKCOS_ERR_INVALID_VALUE, "mode must be 0 or 1");
+  if (opts.reserved != 0) return fail(ARKCOS_ERR_INVALID_VALUE, "reserved option field must be 0");
   if (g->kind == 0) {
     if (g->n_theta < 1 || g->n_phi < 4 || (g->n_phi & 1) || g->n_theta > (1 << 20) || g->n_phi > (1 << 20))
       return fail(ARKCOS_ERR_INVALID_VALUE, "ECP needs n_theta >= 1 and an even n_phi >= 4");
@@ -474,8 +486,9 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       PairDev pr{};
       pr.j = (int32_t)j;
       // rings of equal length (with offsets 0 or pi/N) are sampled at their
-      // true pixel offsets on a grid of their own length: exact
-      const bool aligned = P->h_n[i] == P->h_n[j] &&
+      // true pixel offsets on a grid of their own length: exact (Sect. 4.3;
+      // the plain mode of Sect. 4.1 puts every pair on the p L grid)
+      const bool aligned = opts.mode == 0 && P->h_n[i] == P->h_n[j] &&
                            (P->h_phase_den[i] == 0 || P->h_phase_den[i] == P->h_n[i]) &&
                            (P->h_phase_den[j] == 0 || P->h_phase_den[j] == P->h_n[j]);
       int32_t shift = 0;

@@ -5,14 +5,16 @@ Workload: HEALPix nside 2048 (50,331,648 pixels), FP32, Gaussian beam of
 5' FWHM truncated at 20' (Planck-HFI-like channel); input 1e-4 N(0,1) white
 noise plus 2000 point sources with log-uniform amplitudes in [1e-3, 1]
 (synthetic, seeded).  A step is one full forward convolution (ring R2C,
-ring-pair accumulation with on-the-fly kernel coefficients, fold + C2R,
+ring-pair accumulation streaming precomputed K_ij(m) tables, fold + C2R,
 pole-ring fix) of the map already resident in HBM.  The plan (geometry,
 kernel samples, bands) is built once before timing and reported separately.
 
 Prints one JSON line: output pixels/s of the plain forward form, the
 roofline of the dominant kernel (HIP events on the library's stream), the
-adjoint form's throughput, and the FP64 oracle timed on the host cores on a
-bounded sample of output pixels.
+adjoint form's throughput, the same forward without the artifact
+suppression (the paper's Sect. 4.1 algorithm alone), the spline-kernel and
+batched forms, and the FP64 oracle timed on the host cores on a bounded
+sample of output pixels.
 """
 from __future__ import annotations
 
@@ -445,6 +447,18 @@ def main():
         forms["adjoint"] = {"pixels_per_s": plan.npix * steps_a / wall_a, "ms": ms_a,
                             "hbm_roofline_frac_24B_per_px": round(total_alg / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                             "stages_ms": dict(zip(STAGES, [round(t, 4) for t in stage_a]))}
+        # the paper's plain algorithm of Sect. 4.1 on the same map (plan
+        # option mode = 1), for the A/B comparison with the suppressed mode
+        log("bench: plain mode of Sect. 4.1 (no artifact suppression)")
+        plan_d = Plan.from_workload(w, mode="default")
+        plan_d.workspace()
+        wall_d, stage_d = time_form(plan_d, plan_d.convolve, x, y, steps_a, 1)
+        ms_d = 1e3 * wall_d / steps_a
+        log(f"bench: plain mode forward {ms_d:.3f} ms/step")
+        forms["forward_sect4_1_without_suppression"] = {"pixels_per_s": plan.npix * steps_a / wall_d, "ms": ms_d,
+                                       "pair_modes": int(plan_d.info.pair_modes),
+                                       "stages_ms": dict(zip(STAGES, [round(t, 4) for t in stage_d]))}
+        del plan_d
     forms["spline"] = None
     if args.spline_steps > 0:
         log("bench: spline kernel, nside 1024")

@@ -50,6 +50,7 @@ struct GradArgs {
 };
 
 constexpr int kGradSpl = kGradPass / 64;  // wide rows: samples per lane in a pass
+constexpr int kNarrowChunk = 16;           // narrow rows: samples summed per pass over the modes
 constexpr int kGradRestart = 1024;  // wide rows: modes between exact restarts of the cosine recurrence
 static_assert(64 * kGradSpl <= kBlock, "a pass's samples are scattered at once");
 
@@ -189,9 +190,9 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
   const int nint4 = 4 * (g.nk - 1);
   for (int e = tid; e < nint4; e += blockDim.x) U[e] = 0.0;
   __syncthreads();
-  // per-thread sums acc[0..cnt) -> Y[0..cnt) (every wave's sums, then the
-  // waves in order), Y ready on return
-  auto reduce = [&](auto& acc, int cnt) {
+  // per-thread sums acc[0..cnt) -> Y[y0..y0 + cnt) (every wave's sums, then
+  // the waves in order), Y ready on return
+  auto reduce = [&](auto& acc, int cnt, int y0) {
     constexpr int NA = sizeof(acc) / sizeof(acc[0]);
 #pragma unroll
     for (int d = 0; d < NA; ++d) {
@@ -204,7 +205,7 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
     if (tid < cnt) {
       double t = 0.0;
       for (int k = 0; k < NWV; ++k) t += part[k * kGradMaxCoef + tid];
-      Y[tid] = t;
+      Y[y0 + tid] = t;
     }
     __syncthreads();
   };
@@ -243,37 +244,44 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
       bool table = false;
       const GridCos<R> gc = grid_cos<R>(tw, pl, g.TN, table);
       if (item.pair < 0) {
-        double acc[kGradMaxCoef];
+        // the samples in chunks of kNarrowChunk, each chunk's cosines started
+        // from their exact values at its first two samples (a row's sums
+        // for all 48 samples at once would hold 96 registers per thread,
+        // and the kernel's wide-row passes would lose half their waves)
+        for (int dc = 0; dc < nc; dc += kNarrowChunk) {
+          double acc[kNarrowChunk];
 #pragma unroll
-        for (int d = 0; d < kGradMaxCoef; ++d) acc[d] = 0.0;
-        auto modes = [&](auto tab) {
-          constexpr bool TAB = decltype(tab)::value;
-          for (int m = tid; m <= pr.band; m += blockDim.x) {
-            // cos(m nu_d), nu_d = pi (2d + s) / pl, by the Chebyshev recurrence in d
-            double c0, c1, step;
-            if constexpr (TAB) {
-              const R a = gc.raw((int64_t)m * s), b = gc.raw((int64_t)m * (2 + s)), c = gc.raw(2 * (int64_t)m);
-              c0 = a;
-              c1 = b;
-              step = 2.0 * (double)c;
-            } else {
-              c0 = gc.exact((int64_t)m * s);
-              c1 = gc.exact((int64_t)m * (2 + s));
-              step = 2.0 * gc.exact(2 * (int64_t)m);
-            }
-            const double X = xcorr(m);
+          for (int d = 0; d < kNarrowChunk; ++d) acc[d] = 0.0;
+          auto modes = [&](auto tab) {
+            constexpr bool TAB = decltype(tab)::value;
+            const int64_t e0 = 2 * (int64_t)dc + s, e1 = e0 + 2;
+            for (int m = tid; m <= pr.band; m += blockDim.x) {
+              // cos(m nu_d), nu_d = pi (2d + s) / pl, by the Chebyshev recurrence in d
+              double c0, c1, step;
+              if constexpr (TAB) {
+                const R a = gc.raw((int64_t)m * e0), b = gc.raw((int64_t)m * e1), c = gc.raw(2 * (int64_t)m);
+                c0 = a;
+                c1 = b;
+                step = 2.0 * (double)c;
+              } else {
+                c0 = gc.exact((int64_t)m * e0);
+                c1 = gc.exact((int64_t)m * e1);
+                step = 2.0 * gc.exact(2 * (int64_t)m);
+              }
+              const double X = xcorr(m);
 #pragma unroll
-            for (int d = 0; d < kGradMaxCoef; ++d) {
-              acc[d] = fma(X, c0, acc[d]);
-              const double c2 = fma(step, c1, -c0);
-              c0 = c1;
-              c1 = c2;
+              for (int d = 0; d < kNarrowChunk; ++d) {
+                acc[d] = fma(X, c0, acc[d]);
+                const double c2 = fma(step, c1, -c0);
+                c0 = c1;
+                c1 = c2;
+              }
             }
-          }
-        };
-        if (table) modes(std::true_type{});
-        else modes(std::false_type{});
-        reduce(acc, nc);
+          };
+          if (table) modes(std::true_type{});
+          else modes(std::false_type{});
+          reduce(acc, min(kNarrowChunk, nc - dc), dc);
+        }
         double t = 0.0, cd = 0.0, wgt = 0.0;
         if (tid < nc) {
           sample(tid, t, cd);
@@ -318,7 +326,10 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
             c1[k] = cospi((double)(((int64_t)(mr + 1) * kd[k]) % (2 * pl)) / (double)pl);
           }
           int m = mr;
-          for (; m + 8 <= me; m += 8) {
+          // (rows whose Z(m) is not staged evaluate it one mode at a time:
+          // eight on-the-fly correlations in flight would cost the whole
+          // kernel registers and occupancy)
+          for (; CACHED && m + 8 <= me; m += 8) {
             double z[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) z[e] = CACHED ? (double)zc[m + e] : xcorr(m + e);

@@ -113,3 +113,32 @@ def test_suppressed_mode_removes_default_mode_artifacts():
         err[mode] = [_frac(y[s], ref[s]) for s in (caps, belt)]
     print(f"  fractional RMS (caps, belt): {err}", flush=True)
     assert min(err["default"]) > 3e-3 and max(err["suppressed"]) < 1e-5, err
+
+
+def test_default_mode_batch_equals_per_plan_results():
+    """A batch of plain-mode plans (uneven nside and beams, FP32)
+    gives every map its own plan's result bit for bit, forward and transpose."""
+    from paper_1104_0672_amd import Batch, Plan
+    ws = [W.scaled_healpix(ns, f * _pix(ns), 3.0, seed=60 + k)
+          for k, (ns, f) in enumerate(((8, 1.5), (32, 2.5), (16, 3.0), (64, 2.0)))]
+    print("case default-mode batch of", [w.grid.nside for w in ws], flush=True)
+    plans = [Plan.from_workload(w, mode="default") for w in ws]
+    batch = Batch(plans)
+    xs = [_t(W.make_input(w), w) for w in ws]
+    for adjoint in (False, True):
+        ys = batch.convolve(xs, adjoint=adjoint)
+        for p, x, y in zip(plans, xs, ys):
+            ref = p.adjoint(x) if adjoint else p.convolve(x)
+            assert torch.equal(y, ref)
+
+
+@pytest.mark.parametrize("nside", [1, 2])
+def test_default_mode_smallest_grids_fp64(nside):
+    from paper_1104_0672_amd import Plan
+    w = W.scaled_healpix(nside, 0.6 * 60 * math.degrees(1.0), 3.0, dtype="f64", seed=nside)
+    print(f"case default mode {w.name} f64", flush=True)
+    x = W.make_input(w)
+    for p in (1, 2):
+        y = Plan.from_workload(w, oversample=p, mode="default").convolve(_t(x, w)).cpu().numpy()
+        ref = oracle.hybrid(w.grid, w.profile, w.radius, x, oversample=p, mode="default")
+        assert _frac(y, ref) <= 1e-11, p

@@ -69,14 +69,16 @@ struct UnitDev {
 
 // One work item of the knot gradient: the narrow rows (at most
 // kGradMaxCoef samples) of unit `unit` (pair = -1), or the samples
-// [d0, d0 + cnt) of the wide row `pair` of that unit.
+// [d0, d0 + cnt) of the wide row `pair` of that unit over its modes [m0, m1).
 struct GradItem {
-  int32_t unit, pair, d0, cnt;
+  int32_t unit, pair, d0, cnt, m0, m1;
 };
 constexpr int kGradMaxCoef = 48;      // rows up to this length: one item per unit, threads over modes
 constexpr int kGradPass = 256;        // samples of a wide row per pass over its modes
-constexpr int kGradThreads = 512;     // threads per gradient block
+constexpr int kGradThreads = 256;     // threads per gradient block
 constexpr double kGradItemWork = 16777216.0;  // samples x modes of a wide-row item
+constexpr int kGradZBytes = 32768;    // LDS for a wide-row item's correlation: its modes come in chunks of this
+constexpr int kGradBlocksPerCU = 3;   // gradient blocks resident per CU (LDS and registers)
 
 // One accumulation work item: band `band`, mode tiles [t0, t0 + nt) of
 // kAccTile modes each.

@@ -162,7 +162,9 @@ __device__ __forceinline__ GridCos<R> grid_cos(const cx_t<R>* tw, int64_t pl, in
 // cosines by the three-term recurrence in the sample index d.
 //
 // Wide rows: the correlation Z(m) = eps_m h(m) (X_ij(m) + X_i'j'(m)) of the
-// pair is staged in LDS once per item (in the plan's precision), then the
+// pair over the item's mode chunk is staged in LDS once per item (in the
+// plan's precision; the chunks' partial sums of a sample add up linearly in
+// the interval sums), then the
 // item's samples are taken 64 kGradSpl at a time, each lane holding
 // kGradSpl samples and each wave one contiguous range of modes, so every
 // mode's Z is one broadcast LDS read for a whole wave and needs no
@@ -290,11 +292,14 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
         row_scatter(U, g, sa, sp, nc, t, wgt);
         continue;
       }
-      // a wide row: stage Z(m) (or evaluate it on the fly when it does not fit)
+      // a wide row's mode chunk [m0, m1): stage Z(m) (or evaluate it on the
+      // fly when it does not fit)
       const int band = __builtin_amdgcn_readfirstlane(pr.band);
-      const bool cached = (int64_t)(band + 1) * (int64_t)sizeof(R) <= (int64_t)g.zcache_bytes;
+      const int m0 = __builtin_amdgcn_readfirstlane(item.m0);
+      const int m1 = __builtin_amdgcn_readfirstlane(min(item.m1, band + 1));
+      const bool cached = (int64_t)(m1 - m0) * (int64_t)sizeof(R) <= (int64_t)g.zcache_bytes;
       if (cached) {
-        for (int m = tid; m <= band; m += blockDim.x) zc[m] = (R)xcorr(m);
+        for (int m = m0 + tid; m < m1; m += blockDim.x) zc[m - m0] = (R)xcorr(m);
         __syncthreads();
       }
       // passes of 64 x kGradSpl samples: lane l holds samples d + l + 64 k
@@ -302,9 +307,9 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
       // sample cos(m nu_d) runs by the recurrence in m, restarted from exact
       // values every kGradRestart modes; the NWV partial sums of a sample are
       // added in wave order
-      const int nmode = band + 1;
-      const int mlo = __builtin_amdgcn_readfirstlane((int)((int64_t)nmode * wv / NWV));
-      const int mhi = __builtin_amdgcn_readfirstlane((int)((int64_t)nmode * (wv + 1) / NWV));
+      const int nmode = m1 - m0;
+      const int mlo = __builtin_amdgcn_readfirstlane(m0 + (int)((int64_t)nmode * wv / NWV));
+      const int mhi = __builtin_amdgcn_readfirstlane(m0 + (int)((int64_t)nmode * (wv + 1) / NWV));
       const int dend = item.d0 + item.cnt;
       auto passes = [&](auto cached_tag) {
       constexpr bool CACHED = decltype(cached_tag)::value;
@@ -332,7 +337,7 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
           for (; CACHED && m + 8 <= me; m += 8) {
             double z[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) z[e] = CACHED ? (double)zc[m + e] : xcorr(m + e);
+            for (int e = 0; e < 8; ++e) z[e] = CACHED ? (double)zc[m - m0 + e] : xcorr(m + e);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
 #pragma unroll
@@ -345,7 +350,7 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
             }
           }
           for (; m < me; ++m) {
-            const double z = CACHED ? (double)zc[m] : xcorr(m);
+            const double z = CACHED ? (double)zc[m - m0] : xcorr(m);
 #pragma unroll
             for (int k = 0; k < kGradSpl; ++k) {
               acc[k] = fma(z, c0[k], acc[k]);

@@ -98,14 +98,17 @@ arkcos_status_t upload_knots(arkcos_plan_s* P) {
 }
 
 // Work items of the knot gradient (spline plans): per unit its narrow rows,
-// and every wide row cut into sample ranges of about kGradItemWork samples x
-// modes; then the items cut into runs of equal estimated cost, one run per
-// gradient block (about four per CU).  Depends only on the pairs' windows and
-// bands, which knot updates keep.
+// and every wide row cut into mode chunks whose correlation fits
+// kGradZBytes of LDS, each chunk into sample ranges of about kGradItemWork
+// samples x modes; then the items cut into runs of equal estimated cost, one
+// run per gradient block (two rounds of the resident blocks).  Depends only
+// on the pairs' windows and bands, which knot updates keep.
 arkcos_status_t build_grad_items(arkcos_plan_s* P) {
   std::vector<GradItem> items;
   std::vector<double> cost;
   int64_t zmax = 0;
+  const int64_t rsz = P->dtype == ARKCOS_F32 ? 4 : 8;
+  const int64_t chunk = kGradZBytes / rsz;
   for (int64_t u = 0; u < P->n_units; ++u) {
     const UnitDev& U = P->h_units[u];
     double narrow = 0.0;
@@ -115,26 +118,31 @@ arkcos_status_t build_grad_items(arkcos_plan_s* P) {
       if (pr.band >= 0 && nc <= kGradMaxCoef) narrow += (double)kGradMaxCoef * (pr.band + 1) + 1000.0;
     }
     if (narrow > 0.0) {
-      items.push_back(GradItem{(int32_t)u, -1, 0, 0});
+      items.push_back(GradItem{(int32_t)u, -1, 0, 0, 0, 0});
       cost.push_back(narrow);
     }
     for (int32_t q = U.pbeg; q < U.pend; ++q) {
       const PairDev& pr = P->h_pairs[q];
       const int64_t nc = P->h_ncoef_window[q];
       if (pr.band < 0 || nc <= kGradMaxCoef) continue;
-      zmax = std::max<int64_t>(zmax, pr.band + 1);
-      int64_t per = (int64_t)(kGradItemWork / (double)(pr.band + 1)) / kGradPass * kGradPass;
-      per = std::max<int64_t>(per, kGradPass);
-      for (int64_t d0 = 0; d0 < nc; d0 += per) {
-        const int64_t cnt = std::min(per, nc - d0);
-        items.push_back(GradItem{(int32_t)u, q, (int32_t)d0, (int32_t)cnt});
-        cost.push_back((double)(cnt + 8) * (pr.band + 1) + 4000.0);
+      const int64_t nm = pr.band + 1;
+      for (int64_t m0 = 0; m0 < nm; m0 += chunk) {
+        const int64_t len = std::min(chunk, nm - m0);
+        zmax = std::max<int64_t>(zmax, len);
+        int64_t per = (int64_t)(kGradItemWork / (double)len) / kGradPass * kGradPass;
+        per = std::max<int64_t>(per, kGradPass);
+        for (int64_t d0 = 0; d0 < nc; d0 += per) {
+          const int64_t cnt = std::min(per, nc - d0);
+          items.push_back(GradItem{(int32_t)u, q, (int32_t)d0, (int32_t)cnt, (int32_t)m0, (int32_t)(m0 + len)});
+          cost.push_back((double)(cnt + 8) * len + 4000.0);
+        }
       }
     }
   }
   int cus = 0;
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device));
-  const int64_t nruns = std::max<int64_t>(1, std::min<int64_t>((int64_t)items.size(), 4 * (int64_t)cus));
+  const int64_t nruns =
+      std::max<int64_t>(1, std::min<int64_t>((int64_t)items.size(), 2 * kGradBlocksPerCU * (int64_t)cus));
   double total = 0.0;
   for (double c : cost) total += c;
   std::vector<int32_t> run(nruns + 1, (int32_t)items.size());
@@ -147,10 +155,8 @@ arkcos_status_t build_grad_items(arkcos_plan_s* P) {
   }
   P->h_grad_items = items;
   P->n_grad_runs = (int32_t)nruns;
-  // a wide row's correlation is staged in LDS when it fits next to the
-  // block's other arrays (about 28 KB of 160 KB)
-  const int64_t rsz = P->dtype == ARKCOS_F32 ? 4 : 8;
-  P->grad_zcache_bytes = (int32_t)std::min<int64_t>((zmax * rsz + 15) / 16 * 16, 131088);
+  // a wide-row item's correlation (one mode chunk) is staged in LDS
+  P->grad_zcache_bytes = (int32_t)((std::max<int64_t>(zmax, 1) * rsz + 15) / 16 * 16);
   HIPCHK(upload(P, &P->d_grad_items, items));
   HIPCHK(upload(P, &P->d_grad_run, run));
   return ARKCOS_OK;

@@ -101,8 +101,9 @@ arkcos_status_t upload_knots(arkcos_plan_s* P) {
 // and every wide row cut into mode chunks whose correlation fits
 // kGradZBytes of LDS, each chunk into sample ranges of about kGradItemWork
 // samples x modes; then the items cut into runs of equal estimated cost, one
-// run per gradient block (two rounds of the resident blocks).  Depends only
-// on the pairs' windows and bands, which knot updates keep.
+// run per gradient block, eight times as many runs as resident blocks so that
+// the estimate's errors even out (a block that drew cheap runs takes more).
+// Depends only on the pairs' windows and bands, which knot updates keep.
 arkcos_status_t build_grad_items(arkcos_plan_s* P) {
   std::vector<GradItem> items;
   std::vector<double> cost;
@@ -142,7 +143,7 @@ arkcos_status_t build_grad_items(arkcos_plan_s* P) {
   int cus = 0;
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device));
   const int64_t nruns =
-      std::max<int64_t>(1, std::min<int64_t>((int64_t)items.size(), 2 * kGradBlocksPerCU * (int64_t)cus));
+      std::max<int64_t>(1, std::min<int64_t>((int64_t)items.size(), 8 * kGradBlocksPerCU * (int64_t)cus));
   double total = 0.0;
   for (double c : cost) total += c;
   std::vector<int32_t> run(nruns + 1, (int32_t)items.size());

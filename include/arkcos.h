@@ -228,6 +228,35 @@ arkcos_status_t arkcos_plan_timing(arkcos_plan_t plan, int32_t max_calls);
  * Waits for the recorded events; then starts a new recording window. */
 arkcos_status_t arkcos_stage_times(arkcos_plan_t plan, double* ms, int64_t* calls);
 
+/* ---------------------------------------------------------------------------
+ * Support radius from the truncation error (paper Sect. 4).  Host-only: these
+ * two calls touch no device and may run without a GPU.
+ *
+ * Cutting the kernel at radius R changes its Legendre coefficients
+ * (K_l = 2 pi int_{-1}^{1} K(z) P_l(z) dz, Sect. 2) by
+ *     dK_l(R) = -2 pi int_R^pi K(theta) P_l(cos theta) sin theta dtheta,
+ * and for a signal with angular power spectrum C_l the convolved map then
+ * has an error of variance
+ *     sigma^2(R) = sum_{l=0}^{lmax} (2l + 1) / (4 pi) dK_l(R)^2 C_l.
+ * The Gaussian is taken as zero beyond 40 sigma, the spline beyond
+ * theta_max.  Quadrature: 16-point Gauss-Legendre panels in theta with at
+ * least eight nodes per period of P_lmax.
+ *
+ * arkcos_truncation_variance: profile as for arkcos_plan; radius_rad in
+ * [0, pi]; cl: host array of lmax + 1 values (lmax 0 .. 1e6); *sigma2
+ * receives sigma^2(R); dk: optional host array of lmax + 1 values that
+ * receives dK_l(R) (may be NULL).
+ *
+ * arkcos_choose_radius: the smallest radius, to 1e-12 of the support, whose
+ * sigma^2 is at most target_sigma2, searched from the end of the support
+ * inwards on 256 radii then refined by bisection (so the answer also holds
+ * for kernels whose sigma^2 is not monotone in R); 0 if no radius exceeds
+ * the target.  Errors: ARKCOS_ERR_INVALID_VALUE for bad arguments. */
+arkcos_status_t arkcos_truncation_variance(const arkcos_profile_t* profile, double radius_rad, const double* cl,
+                                           int32_t lmax, double* sigma2, double* dk);
+arkcos_status_t arkcos_choose_radius(const arkcos_profile_t* profile, const double* cl, int32_t lmax,
+                                     double target_sigma2, double* radius_rad);
+
 const char* arkcos_status_string(arkcos_status_t status);
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* arkcos_last_error(void);

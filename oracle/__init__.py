@@ -15,6 +15,8 @@ Two references live here:
   FFTs as library primitives.  It is the oracle where the method is an
   approximation (HEALPix pairs that involve a polar ring) and must equal the
   direct sum where the method is exact (ECP grids, equatorial HEALPix pairs).
+* ``truncation_variance`` -- the truncation error of the support radius of
+  Sect. 4 from its definition (``truncation.py``).
 """
 from __future__ import annotations
 
@@ -198,3 +200,4 @@ def neighbour_stats(grid, radius, idx):
 
 
 from .hybrid import hybrid, hybrid_adjoint, hybrid_knot_grad, pair_plan  # noqa: E402,F401
+from .truncation import truncation_variance  # noqa: E402,F401

@@ -11,6 +11,7 @@ import math
 import os
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -61,7 +62,8 @@ EXPORTED = ["arkcos_default_options", "arkcos_plan", "arkcos_plan_destroy", "ark
             "arkcos_workspace_size", "arkcos_convolve", "arkcos_convolve_adjoint", "arkcos_kernel_grad",
             "arkcos_set_knots", "arkcos_batch_plan", "arkcos_batch_get_info", "arkcos_batch_workspace_size",
             "arkcos_batch_convolve", "arkcos_batch_timing", "arkcos_batch_stage_times", "arkcos_batch_destroy",
-            "arkcos_plan_timing", "arkcos_stage_times", "arkcos_status_string", "arkcos_last_error"]
+            "arkcos_plan_timing", "arkcos_stage_times", "arkcos_status_string", "arkcos_last_error",
+            "arkcos_truncation_variance", "arkcos_choose_radius"]
 
 _lib = None
 
@@ -96,6 +98,9 @@ def load_library(path: str = LIB_PATH):
     lib.arkcos_batch_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.arkcos_plan_timing.argtypes = [vp, i32]
     lib.arkcos_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    pd = ctypes.POINTER(ctypes.c_double)
+    lib.arkcos_truncation_variance.argtypes = [ctypes.POINTER(ProfileC), dbl, pd, i32, pd, pd]
+    lib.arkcos_choose_radius.argtypes = [ctypes.POINTER(ProfileC), pd, i32, dbl, pd]
     lib.arkcos_status_string.argtypes = [st]
     lib.arkcos_status_string.restype = ctypes.c_char_p
     lib.arkcos_last_error.argtypes = []
@@ -251,6 +256,45 @@ class Plan:
     def set_knots(self, knots: Sequence[float]):
         arr = (ctypes.c_double * self.n_knots)(*[float(v) for v in knots])
         _check(self._lib.arkcos_set_knots(self.handle, arr), "arkcos_set_knots")
+
+
+def _profile(fwhm: float, knots, theta_max: float):
+    """A ProfileC (and the knot array it points to, which must stay alive)."""
+    if knots is not None:
+        arr = (ctypes.c_double * len(knots))(*[float(v) for v in knots])
+        ptr = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+        return ProfileC(SPLINE, 0.0, len(knots), float(theta_max), ptr), arr
+    return ProfileC(GAUSSIAN, float(fwhm), 0, 0.0, None), None
+
+
+def truncation_variance(radius: float, cl, *, fwhm: float = 0.0, knots=None, theta_max: float = 0.0):
+    """sigma^2(R) of the kernel cut at `radius` for a signal of power spectrum
+    cl[0..lmax] (paper Sect. 4), and the Legendre coefficient changes dK_l.
+    Host computation in libarkcos (no GPU needed)."""
+    lib = load_library()
+    c = np.ascontiguousarray(cl, dtype=np.float64)
+    prof, keep = _profile(fwhm, knots, theta_max)
+    out = ctypes.c_double()
+    dk = np.empty(c.size, dtype=np.float64)
+    _check(lib.arkcos_truncation_variance(ctypes.byref(prof), float(radius),
+                                          c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), c.size - 1,
+                                          ctypes.byref(out), dk.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "arkcos_truncation_variance")
+    del keep
+    return out.value, dk
+
+
+def choose_radius(cl, target_sigma2: float, *, fwhm: float = 0.0, knots=None, theta_max: float = 0.0) -> float:
+    """Smallest support radius whose truncation variance is at most
+    target_sigma2 (paper Sect. 4).  Host computation in libarkcos."""
+    lib = load_library()
+    c = np.ascontiguousarray(cl, dtype=np.float64)
+    prof, keep = _profile(fwhm, knots, theta_max)
+    out = ctypes.c_double()
+    _check(lib.arkcos_choose_radius(ctypes.byref(prof), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    c.size - 1, float(target_sigma2), ctypes.byref(out)), "arkcos_choose_radius")
+    del keep
+    return out.value
 
 
 def pixel_bytes(plan: Plan) -> int:

@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libarkcos.so")
 
 SOURCES = ["plan_kernels.hip", "fft.hip", "accum.hip", "pole.hip", "grad.hip", "batch.hip",
-           "plan.cpp", "capi.cpp"]
+           "plan.cpp", "capi.cpp", "truncation.cpp"]
 
 ARCH = os.environ.get("ARKCOS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

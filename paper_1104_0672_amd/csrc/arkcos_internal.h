@@ -238,6 +238,10 @@ int fft_threads(arkcos_dtype_t dt, int32_t fft_len);
 // the launch set) reaches kCtMinRings.
 constexpr int64_t kCtMinRings = 8192;
 int32_t ct_fft_length(arkcos_dtype_t dt, int32_t fft_len, int64_t rings);
+
+// Clamped cubic spline moments (second derivatives at the knots) for
+// equispaced knots with spacing h; end slopes zero.
+void spline_moments(const std::vector<double>& c, double h, std::vector<double>& M);
 size_t pole_map_size();
 void fill_pole_map(arkcos_plan_s* P, void* out);
 hipError_t launch_pole_batch(arkcos_dtype_t dt, const void* maps, const int2* entries, int32_t count, int32_t adjoint,

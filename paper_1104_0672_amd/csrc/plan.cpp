@@ -56,6 +56,8 @@ int64_t next_pow2(int64_t v) {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+}  // namespace
+
 // Clamped cubic spline moments (second derivatives at the knots) for
 // equispaced knots with spacing h; end slopes zero.
 void spline_moments(const std::vector<double>& c, double h, std::vector<double>& M) {
@@ -76,8 +78,6 @@ void spline_moments(const std::vector<double>& c, double h, std::vector<double>&
   M[n - 1] = rhs[n - 1] / diag[n - 1];
   for (int k = n - 2; k >= 0; --k) M[k] = (rhs[k] - sup[k] * M[k + 1]) / diag[k];
 }
-
-}  // namespace
 
 #define HIPCHK(expr)                                                                      \
   do {                                                                                    \

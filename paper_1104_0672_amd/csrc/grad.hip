@@ -423,16 +423,30 @@ __global__ void __launch_bounds__(kBlock) grad_pole_kernel(GradArgs g, const int
 }
 
 // Sum of the slots in a fixed order, then the map onto the knots.
-__global__ void __launch_bounds__(kBlock) grad_final_kernel(const double* __restrict__ slots, int32_t nslots,
-                                                            int32_t nk, const double* __restrict__ basis_mom,
+// The slots' interval sums: block e adds column e (thread t the slots t,
+// t + kBlock, ...), then the threads' sums in a fixed tree.
+__global__ void __launch_bounds__(kBlock) grad_sum_kernel(const double* __restrict__ slots, int32_t nslots,
+                                                          int32_t nint4, double* __restrict__ sums) {
+  static_assert((kBlock & (kBlock - 1)) == 0, "tree reduction over a power-of-two block");
+  __shared__ double part[kBlock];
+  const int e = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nslots; k += kBlock) s += slots[(size_t)k * nint4 + e];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[e] = part[0];
+}
+
+__global__ void __launch_bounds__(kBlock) grad_final_kernel(const double* __restrict__ sums, int32_t nk,
+                                                            const double* __restrict__ basis_mom,
                                                             double* __restrict__ grad) {
   __shared__ double Us[4 * 63];
   const int nint4 = 4 * (nk - 1);
-  for (int e = threadIdx.x; e < nint4; e += blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < nslots; ++k) s += slots[(size_t)k * nint4 + e];
-    Us[e] = s;
-  }
+  for (int e = threadIdx.x; e < nint4; e += blockDim.x) Us[e] = sums[e];
   __syncthreads();
   for (int k = threadIdx.x; k < nk; k += blockDim.x) {
     double gk = 0.0;
@@ -504,7 +518,10 @@ arkcos_status_t run_kernel_grad(arkcos_plan_s* P, const void* x, const void* r, 
       grad_pole_kernel<double><<<8, kBlock, 0, s>>>(g, list, count, (const double*)x, (const double*)r, nruns);
     nslots += 8;
   }
-  grad_final_kernel<<<1, kBlock, 0, s>>>(slots, nslots, g.nk, P->d_basis_mom, grad);
+  // (the workspace holds n_grad_runs + 8 slots and then the sums)
+  double* sums = slots + (size_t)(nruns + 8) * (size_t)(4 * (g.nk - 1));
+  grad_sum_kernel<<<(unsigned)(4 * (g.nk - 1)), kBlock, 0, s>>>(slots, nslots, 4 * (g.nk - 1), sums);
+  grad_final_kernel<<<1, kBlock, 0, s>>>(sums, g.nk, P->d_basis_mom, grad);
   e = hipGetLastError();
   if (e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string("gradient kernels: ") + hipGetErrorString(e));
   return ARKCOS_OK;

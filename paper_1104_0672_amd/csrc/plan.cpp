@@ -901,7 +901,8 @@ static size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
 static size_t grad_slot_bytes(const arkcos_plan_s* P) {
   if (P->prof_kind != 1) return 0;
-  return al256((size_t)(P->n_grad_runs + 8) * 4 * (P->knots.size() - 1) * sizeof(double));
+  // one slot per run, eight for the pole rows, one for their sum
+  return al256((size_t)(P->n_grad_runs + 9) * 4 * (P->knots.size() - 1) * sizeof(double));
 }
 
 size_t workspace_bytes(const arkcos_plan_s* P) {

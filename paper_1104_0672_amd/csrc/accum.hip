@@ -472,9 +472,11 @@ __device__ __forceinline__ BandDev load_band(const BandDev* g) {
 }
 
 // TAB_ONLY: every pair of the plan has a table of K_ij(m) (no recurrence
-// code, fewer registers, more waves).
+// code, fewer registers, more waves: the FP32 form is held to 80 VGPRs, so
+// that three blocks share a CU instead of two).
 template <typename R, bool TAB_ONLY>
-__global__ void __launch_bounds__(kAccThreads) accumulate_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec,
+__global__ void __launch_bounds__(kAccThreads)
+    __attribute__((amdgpu_waves_per_eu((TAB_ONLY && sizeof(R) == 4) ? 6 : 1))) accumulate_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec,
                                                                  cx_t<R>* __restrict__ bout, AccLayout lay) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WorkItem it = a.items[blockIdx.x];

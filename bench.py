@@ -170,9 +170,11 @@ def summarize_kernels(trace_dir: str, cmd: str, title: str):
                    int(r["LDS_Block_Size"]))
             agg[key].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     lines += ["", "Per launch shape, from `run_kernel_trace.csv`:", "",
-              "| kernel | workgroups | threads | LDS bytes | launches | average us |", "|---|---:|---:|---:|---:|---:|"]
+              "| kernel | workgroups | threads | LDS bytes | launches | average us | average us after the first launch |",
+              "|---|---:|---:|---:|---:|---:|---:|"]
     for k, v in sorted(agg.items()):
-        lines.append(f"| `{k[0]}` | {k[1]} | {k[2]} | {k[3]} | {len(v)} | {sum(v) / len(v) / 1e3:.1f} |")
+        warm = f"{sum(v[1:]) / (len(v) - 1) / 1e3:.1f}" if len(v) > 1 else "-"
+        lines.append(f"| `{k[0]}` | {k[1]} | {k[2]} | {k[3]} | {len(v)} | {sum(v) / len(v) / 1e3:.1f} | {warm} |")
     print("\n".join(lines))
 
 

@@ -104,15 +104,34 @@ typedef struct {
                                tables), 2 = precomputed table for every pair */
   int32_t fix_pole_pixels;  /* HEALPix: recompute the 8 pixels of the first and last
                                ring by the direct sum (default 1) */
-  double band_tol;          /* modes with |K_ij(m)| below band_tol times the largest
-                               kernel-row magnitude are dropped; < 0 = default
-                               (1e-9 for F32, 0 for F64) */
+  double band_tol;          /* Gaussian plans: modes with |K_ij(m)| below band_tol
+                               times the largest kernel-row magnitude are dropped;
+                               < 0 = default (1e-9 for F32, 0 for F64).  Spline
+                               plans keep every mode up to each grid's Nyquist mode
+                               and every kernel sample of a pair's window, so that
+                               any later knot values fit the plan's layout */
   int32_t mode;             /* 0 = with the artifact suppression of Sect. 4.3
                                (default); 1 = the plain algorithm of Sect. 4.1
                                (zero-padded spectra, truncated output modes, no
                                pair on its own grid), for comparisons of the
                                two; on ECP grids both give the same result */
-  int32_t reserved;         /* must be 0 */
+  int32_t own_grid;         /* mode 0: which ring pairs skip the phase shift and
+                               sample the kernel at the true pixel offsets on a grid
+                               of their own length (exact, like the direct sum).
+                               0 = every pair of equal-length rings: the equatorial
+                               pairs plus a polar ring with itself and with its
+                               mirror (an extension of Sect. 4.3; default);
+                               1 = equatorial pairs only, the scheme as Sect. 4.3
+                               states it (with oversample = 1 the paper's method) */
+  int32_t kernel_eval;      /* how the plan evaluates K at each kernel sample:
+                               0 = K(theta) in FP64 from the haversine distance
+                               (default); 1 = linear interpolation in the squared
+                               chord u = 2(1 - cos theta) from a table of
+                               K(2 asin(sqrt(u)/2)) (the biased table of Sect. 4.1,
+                               eq. "kernel_angle"), nodes uniform in u over [0, u(R)] */
+  int32_t table_nodes;      /* kernel_eval 1: nodes of that table, 2 .. 2^24;
+                               0 = 65536 */
+  int32_t reserved[4];      /* must be 0 */
 } arkcos_options_t;
 
 /* Summary of a plan (sizes, chosen parameters), for callers and tooling. */
@@ -127,10 +146,18 @@ typedef struct {
   int32_t oversample, dtype, n_knots;
   int32_t reserved;
   size_t workspace_bytes, plan_bytes;
+  int64_t pairs_by_kind[4]; /* ring pairs (north units) by how K_ij(m) is produced:
+                               [0] Clenshaw recurrence on the centred grid,
+                               [1] Clenshaw on the half-shifted own grid,
+                               [2] precomputed table, [3] Reinsch's recurrence */
+  int32_t acc_seg_units;    /* accumulation: output units per work item */
+  int32_t acc_group;        /* units summed at a time (wavefronts per workgroup) */
+  int32_t acc_window;       /* input rings held in the LDS window (0: read from memory) */
+  int32_t acc_tuned;        /* 1: chosen by timing at plan creation */
 } arkcos_plan_info_t;
 
 /* Fill *opts with the defaults (oversample 0, kgen 0, fix_pole_pixels 1,
- * band_tol -1, mode 0). */
+ * band_tol -1, mode 0, own_grid 0, kernel_eval 0, table_nodes 0). */
 void arkcos_default_options(arkcos_options_t* opts);
 
 /* Build a plan on the current device: ring and pair tables, the FP64 kernel
@@ -166,35 +193,47 @@ arkcos_status_t arkcos_convolve_adjoint(arkcos_plan_t plan, const void* r, void*
 /* Gradient of L = 1/2 |C x - t|^2 with respect to the spline knot values,
  * given r = C x - t:  g_k = <r, (dC/dc_k) x>, a per-ring-pair Fourier-space
  * correlation of the spectra of r and x reduced over modes and kernel samples
- * in FP64.  grad: device, n_knots doubles, overwritten.  Spline plans only.
+ * in FP64.  grad: device, n_knots doubles, overwritten.  Spline plans with
+ * kernel_eval 0 only (ARKCOS_ERR_NOT_SUPPORTED otherwise).
  * flags bit 0: the workspace still holds the spectra of x from the last
  * arkcos_convolve(x) on it (skips their recomputation). */
 arkcos_status_t arkcos_kernel_grad(arkcos_plan_t plan, const void* x, const void* r,
                                    double* grad, void* ws, uint32_t flags, hipStream_t stream);
 
 /* Replace the spline knot values (host array of n_knots doubles) and rebuild
- * the kernel samples and tables in place.  Blocks the host; must not overlap
- * with any call using the plan. */
+ * the kernel samples and K_ij(m) tables in place, with the plan's layout
+ * (ring pairs, sample windows, bands, table choices are fixed at plan
+ * creation and hold for any knot values).  Waits for all work on the device
+ * first and returns once the new tables are ready. */
 arkcos_status_t arkcos_set_knots(arkcos_plan_t plan, const double* knot_values);
+
+/* The same with the knot values in device memory (n_knots doubles), enqueued
+ * on `stream`: a few kernels, no allocation and no host synchronisation, so
+ * it can be captured in a graph.  Calls on other streams that use the plan
+ * must be ordered against it by the caller. */
+arkcos_status_t arkcos_set_knots_async(arkcos_plan_t plan, const double* knot_values, hipStream_t stream);
 
 /* ---- batched form: many maps of uneven size, each with its own plan ---- */
 
 typedef struct {
   int32_t n_maps;
-  int32_t units_per_band;   /* output rings (with mirrors) per work item, autotuned */
+  int32_t seg_units;        /* output units (rings with mirrors) per work item, autotuned */
+  int32_t group;            /* units summed at a time (wavefronts per workgroup), autotuned */
   int32_t grid;             /* workgroups of the persistent accumulation launch, autotuned */
   int32_t tuned;            /* 1: measured now, 2: read from the autotune cache */
+  int32_t reserved;
   int64_t n_items;          /* work items in the queue */
   int64_t npix_total;
   size_t workspace_bytes;
 } arkcos_batch_info_t;
 
 /* Group n plans (same dtype, same device) into one batch: one work queue of
- * (map, band of output rings, mode tile) items over all maps, ordered
- * heaviest first.  The band size and the persistent grid are chosen by an
- * autotuner that times the accumulation on a representative subset of the
- * maps (results cached in the file named by ARKCOS_AUTOTUNE_CACHE, if set).
- * Blocks the host.  The plans must outlive the batch. */
+ * (map, segment of output rings, mode tile) items over all maps, ordered
+ * heaviest first.  The segment length, the rings summed at a time and the
+ * persistent grid are chosen by an autotuner that times the accumulation on
+ * a representative subset of the maps (results cached in the file named by
+ * ARKCOS_AUTOTUNE_CACHE, if set).  Blocks the host.  The plans must outlive
+ * the batch. */
 arkcos_status_t arkcos_batch_plan(int32_t n, const arkcos_plan_t* plans, arkcos_batch_t* out);
 arkcos_status_t arkcos_batch_get_info(arkcos_batch_t batch, arkcos_batch_info_t* info);
 arkcos_status_t arkcos_batch_workspace_size(arkcos_batch_t batch, size_t* bytes);
@@ -202,10 +241,11 @@ arkcos_status_t arkcos_batch_workspace_size(arkcos_batch_t batch, size_t* bytes)
  * y[i] = C_i x[i].  x, y: host arrays of n device pointers (maps as for
  * arkcos_convolve; no x[i] may overlap any y[k]).  ws: arkcos_batch_workspace_size
  * bytes, 256-byte aligned.  Ring transforms run batched over all rings of all
- * maps; one persistent launch performs step (c) for every map.  When the set
- * of map pointers differs from the previous call's, it is uploaded first
- * (a small synchronous copy); with unchanged pointers the call only enqueues
- * kernels, allocates nothing and can be captured in a hipGraph. */
+ * maps; one persistent launch performs step (c) for every map.  The call's
+ * map pointers are written into its workspace by kernels on the stream, so
+ * the call only enqueues kernels, allocates nothing, never waits on the host
+ * and can be captured in a hipGraph (several calls with different maps, e.g.
+ * a forward and a transpose, in one graph). */
 arkcos_status_t arkcos_batch_convolve(arkcos_batch_t batch, const void* const* x, void* const* y,
                                       int32_t adjoint, void* ws, hipStream_t stream);
 /* Stage timing of batch calls, as arkcos_plan_timing / arkcos_stage_times

@@ -7,7 +7,6 @@ library is missing the import-time loader raises; there is no fallback.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 from typing import Optional, Sequence
 
@@ -39,7 +38,8 @@ class ProfileC(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("oversample", ctypes.c_int32), ("kgen", ctypes.c_int32),
                 ("fix_pole_pixels", ctypes.c_int32), ("band_tol", ctypes.c_double),
-                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("own_grid", ctypes.c_int32), ("kernel_eval", ctypes.c_int32),
+                ("table_nodes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -49,18 +49,21 @@ class PlanInfo(ctypes.Structure):
                 ("taps", ctypes.c_int64), ("table_entries", ctypes.c_int64),
                 ("oversample", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n_knots", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t),
-                ("plan_bytes", ctypes.c_size_t)]
+                ("plan_bytes", ctypes.c_size_t), ("pairs_by_kind", ctypes.c_int64 * 4),
+                ("acc_seg_units", ctypes.c_int32), ("acc_group", ctypes.c_int32), ("acc_window", ctypes.c_int32),
+                ("acc_tuned", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
-    _fields_ = [("n_maps", ctypes.c_int32), ("units_per_band", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("tuned", ctypes.c_int32), ("n_items", ctypes.c_int64), ("npix_total", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_size_t)]
+    _fields_ = [("n_maps", ctypes.c_int32), ("seg_units", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("tuned", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_items", ctypes.c_int64), ("npix_total", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t)]
 
 
 EXPORTED = ["arkcos_default_options", "arkcos_plan", "arkcos_plan_destroy", "arkcos_plan_get_info",
-            "arkcos_workspace_size", "arkcos_convolve", "arkcos_convolve_adjoint", "arkcos_kernel_grad",
-            "arkcos_set_knots", "arkcos_batch_plan", "arkcos_batch_get_info", "arkcos_batch_workspace_size",
+            "arkcos_workspace_size", "arkcos_convolve", "arkcos_convolve_adjoint",
+            "arkcos_kernel_grad",
+            "arkcos_set_knots", "arkcos_set_knots_async", "arkcos_batch_plan", "arkcos_batch_get_info", "arkcos_batch_workspace_size",
             "arkcos_batch_convolve", "arkcos_batch_timing", "arkcos_batch_stage_times", "arkcos_batch_destroy",
             "arkcos_plan_timing", "arkcos_stage_times", "arkcos_status_string", "arkcos_last_error",
             "arkcos_truncation_variance", "arkcos_choose_radius"]
@@ -89,6 +92,7 @@ def load_library(path: str = LIB_PATH):
     lib.arkcos_convolve_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.arkcos_kernel_grad.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint32, vp]
     lib.arkcos_set_knots.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.arkcos_set_knots_async.argtypes = [vp, vp, vp]
     lib.arkcos_batch_plan.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     lib.arkcos_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.arkcos_batch_convolve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, vp]
@@ -136,7 +140,8 @@ class Plan:
     def __init__(self, grid: str, radius: float, *, nside: int = 0, ntheta: int = 0, nphi: int = 0,
                  fwhm: float = 0.0, knots: Optional[Sequence[float]] = None, theta_max: float = 0.0,
                  dtype: str = "f32", oversample: int = 0, kgen: int = 0, fix_pole_pixels: bool = True,
-                 band_tol: float = -1.0, mode: str = "suppressed"):
+                 band_tol: float = -1.0, mode: str = "suppressed", own_grid: str = "equal_length",
+                 kernel_eval: str = "exact", table_nodes: int = 0):
         lib = load_library()
         self._lib = lib
         self.handle = ctypes.c_void_p()
@@ -150,8 +155,13 @@ class Plan:
             prof = ProfileC(GAUSSIAN, float(fwhm), 0, 0.0, None)
         if mode not in ("suppressed", "default"):
             raise ArkcosError(f"mode must be 'suppressed' or 'default', not {mode!r}")
+        if own_grid not in ("equal_length", "equatorial"):
+            raise ArkcosError(f"own_grid must be 'equal_length' or 'equatorial', not {own_grid!r}")
+        if kernel_eval not in ("exact", "table"):
+            raise ArkcosError(f"kernel_eval must be 'exact' or 'table', not {kernel_eval!r}")
         opts = Options(int(oversample), int(kgen), int(bool(fix_pole_pixels)), float(band_tol),
-                       1 if mode == "default" else 0, 0)
+                       1 if mode == "default" else 0, 1 if own_grid == "equatorial" else 0,
+                       1 if kernel_eval == "table" else 0, int(table_nodes))
         self.dtype = torch.float32 if dtype == "f32" else torch.float64
         self.grid = grid
         _check(lib.arkcos_plan(ctypes.byref(geom), ctypes.byref(prof), float(radius),
@@ -254,8 +264,18 @@ class Plan:
         return list(ms), int(calls.value)
 
     def set_knots(self, knots: Sequence[float]):
+        """New knot values from the host (waits for the device)."""
         arr = (ctypes.c_double * self.n_knots)(*[float(v) for v in knots])
         _check(self._lib.arkcos_set_knots(self.handle, arr), "arkcos_set_knots")
+
+    def set_knots_async(self, knots: torch.Tensor, stream=None):
+        """New knot values from a device tensor of n_knots doubles, enqueued
+        on the stream (no host synchronisation)."""
+        if not isinstance(knots, torch.Tensor) or not knots.is_cuda or knots.dtype != torch.float64 \
+                or knots.numel() != self.n_knots or not knots.is_contiguous():
+            raise ArkcosError(f"knots must be a contiguous CUDA float64 tensor of {self.n_knots} values")
+        _check(self._lib.arkcos_set_knots_async(self.handle, ctypes.c_void_p(knots.data_ptr()),
+                                                _stream_ptr(stream)), "arkcos_set_knots_async")
 
 
 def _profile(fwhm: float, knots, theta_max: float):
@@ -295,14 +315,6 @@ def choose_radius(cl, target_sigma2: float, *, fwhm: float = 0.0, knots=None, th
                                     c.size - 1, float(target_sigma2), ctypes.byref(out)), "arkcos_choose_radius")
     del keep
     return out.value
-
-
-def pixel_bytes(plan: Plan) -> int:
-    return torch.tensor([], dtype=plan.dtype).element_size()
-
-
-def fwhm_to_sigma(fwhm: float) -> float:
-    return fwhm / math.sqrt(8.0 * math.log(2.0))
 
 
 class Batch:

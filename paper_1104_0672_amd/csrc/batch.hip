@@ -3,11 +3,12 @@
 // transforms, one persistent accumulation launch over a shared work queue,
 // and one pass of batched inverse transforms.
 //
-// The queue holds (map, band of output rings, 64-mode tile) items of every
-// map, ordered by decreasing estimated cost so the persistent workgroups end
-// together.  The band size (output rings per item) and the number of
-// persistent workgroups are chosen by timing the accumulation on a subset of
-// the maps (one to four maps of each ring count).
+// The queue holds (map, segment of output units, 64-mode tile) items of
+// every map, ordered by decreasing estimated cost so the persistent
+// workgroups end together.  The segment length, the units swept at a time
+// (waves per workgroup) and the number of persistent workgroups are chosen by
+// timing the accumulation on a subset of the maps (up to four maps of each
+// ring count).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +22,7 @@
 #include <vector>
 
 #include "arkcos_internal.h"
+#include "device_common.h"
 
 using namespace arkcos;
 
@@ -41,9 +43,9 @@ struct arkcos_batch_s {
   arkcos_dtype_t dtype = ARKCOS_F32;
   int32_t n = 0;
   std::vector<arkcos_plan_s*> plans;
-  int32_t units_per_band = kBandUnits, grid = 0, tuned = 0;
+  int32_t seg_units = 64, group = 4, grid = 0, tuned = 0;
   bool all_tables = false;  // every plan reads all its K_ij(m) from tables
-  AccShape acc_shape;
+  int32_t cap = 0;          // LDS window slots of the accumulation (0: spectra read from memory)
   int64_t spec_total = 0, out_total = 0, npix_total = 0;
   std::vector<int64_t> h_spec_base, h_out_base;
   // device
@@ -58,9 +60,6 @@ struct arkcos_batch_s {
   int2* d_pole_fwd = nullptr;
   int2* d_pole_adj = nullptr;
   int32_t n_pole_fwd = 0, n_pole_adj = 0;
-  void** d_xs = nullptr;
-  void** d_ys = nullptr;
-  std::vector<const void*> h_xs, h_ys;  // last uploaded map pointers
   std::vector<void*> allocations;
   std::vector<hipEvent_t> timing_events;
   int32_t timing_slots = 0, timing_used = 0;
@@ -91,38 +90,43 @@ template <typename T> hipError_t bupload(arkcos_batch_s* B, T** p, const std::ve
   return hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
-// Queue of one batch configuration: per-map bands on the device, the AccArgs
-// pointing at them, and the items sorted by decreasing estimated cost.
+// Queue of one batch configuration: per-map segments on the device, the
+// AccArgs pointing at them, and the items sorted by decreasing estimated cost.
 struct Queue {
-  std::vector<BandDev*> d_bands;
   std::vector<char> acc_args;
   std::vector<BatchItem> items;
-  AccShape shape;
+  int32_t cap = 0;
 };
 
-hipError_t build_queue(arkcos_batch_s* B, const std::vector<int32_t>& maps, int32_t upb, Queue& Q,
-                       std::vector<void*>& owned) {
+// Largest LDS window of the batched accumulation (as for single plans).
+constexpr size_t kMaxBatchWindowBytes = 96 * 1024;
+
+hipError_t build_queue(arkcos_batch_s* B, const std::vector<int32_t>& maps, int32_t seg_units, int32_t group,
+                       Queue& Q, std::vector<void*>& owned) {
   const size_t asz = acc_args_size();
   Q.acc_args.assign(asz * maps.size(), 0);
   std::vector<std::pair<double, BatchItem>> costed;
+  std::vector<std::vector<SegDev>> segs(maps.size());
+  std::vector<int32_t> caps(maps.size());
+  Q.cap = 1;
+  for (size_t mi = 0; mi < maps.size(); ++mi) {
+    build_segments(B->plans[maps[mi]], seg_units, group, segs[mi], &caps[mi]);
+    Q.cap = std::max(Q.cap, caps[mi]);
+  }
+  const bool window = acc_lds_bytes(B->dtype, Q.cap) <= kMaxBatchWindowBytes;
+  if (!window) Q.cap = 0;
   for (size_t mi = 0; mi < maps.size(); ++mi) {
     arkcos_plan_s* P = B->plans[maps[mi]];
-    std::vector<BandDev> bands;
-    AccShape sh;
-    build_bands(P, upb, bands, &sh);
-    Q.shape.max_window = std::max(Q.shape.max_window, sh.max_window);
-    Q.shape.max_band_pairs = std::max(Q.shape.max_band_pairs, sh.max_band_pairs);
     void* d = nullptr;
-    hipError_t e = hipMalloc(&d, std::max<size_t>(bands.size(), 1) * sizeof(BandDev));
+    hipError_t e = hipMalloc(&d, std::max<size_t>(segs[mi].size(), 1) * sizeof(SegDev));
     if (e != hipSuccess) return e;
     owned.push_back(d);
-    e = hipMemcpy(d, bands.data(), bands.size() * sizeof(BandDev), hipMemcpyHostToDevice);
+    e = hipMemcpy(d, segs[mi].data(), segs[mi].size() * sizeof(SegDev), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
-    Q.d_bands.push_back((BandDev*)d);
-    fill_acc_args(P, (const BandDev*)d, Q.acc_args.data() + asz * mi);
+    fill_acc_args(P, (const SegDev*)d, window ? caps[mi] : 0, Q.acc_args.data() + asz * mi);
     std::vector<WorkItem> its;
     std::vector<double> cost;
-    accumulation_items(P, bands, its, cost);
+    accumulation_items(P, segs[mi], its, cost);
     for (size_t k = 0; k < its.size(); ++k)
       costed.push_back({cost[k], BatchItem{(int32_t)mi, its[k].band, its[k].t0, its[k].nt}});
   }
@@ -150,32 +154,33 @@ std::string tune_key(const arkcos_batch_s* B) {
   return k.str();
 }
 
-bool read_cache(const std::string& key, int32_t* upb, int32_t* bpc) {
+bool read_cache(const std::string& key, int32_t* su, int32_t* grp, int32_t* bpc) {
   const char* path = getenv("ARKCOS_AUTOTUNE_CACHE");
   if (!path || !*path) return false;
   std::ifstream f(path);
   std::string k;
-  int32_t a, b;
-  while (f >> k >> a >> b)
-    if (k == key) {
-      *upb = a;
-      *bpc = b;
+  int32_t a, b, c;
+  while (f >> k >> a >> b >> c)
+    if (k == key && a > 0 && (b == 4 || b == 8) && c > 0) {
+      *su = a;
+      *grp = b;
+      *bpc = c;
       return true;
     }
   return false;
 }
 
-void write_cache(const std::string& key, int32_t upb, int32_t bpc) {
+void write_cache(const std::string& key, int32_t su, int32_t grp, int32_t bpc) {
   const char* path = getenv("ARKCOS_AUTOTUNE_CACHE");
   if (!path || !*path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << " " << upb << " " << bpc << "\n";
+  f << key << " " << su << " " << grp << " " << bpc << "\n";
 }
 
 // Times the accumulation of one queue on the subset's workspace (zero
 // spectra); returns milliseconds per launch.
 hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64_t>& sb,
-                      const std::vector<int64_t>& ob, void* spec, void* bout, int32_t* counter, int32_t upb,
+                      const std::vector<int64_t>& ob, void* spec, void* bout, int32_t* counter, int32_t group,
                       int32_t grid, float* ms) {
   void *dargs = nullptr, *ditems = nullptr, *dsb = nullptr, *dob = nullptr;
   hipError_t e = hipMalloc(&dargs, Q.acc_args.size());
@@ -194,7 +199,7 @@ hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64
     if (r == 1) e = hipEventRecord(e0, nullptr);
     if (e == hipSuccess)
       e = launch_accumulate_batch(B->dtype, dargs, (const int64_t*)dsb, (const int64_t*)dob, (const BatchItem*)ditems,
-                                  (int32_t)Q.items.size(), counter, spec, bout, grid, upb, B->all_tables, Q.shape,
+                                  (int32_t)Q.items.size(), counter, spec, bout, grid, group, B->all_tables, Q.cap,
                                   nullptr);
   }
   if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
@@ -211,7 +216,7 @@ hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64
   return e;
 }
 
-arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out) {
+arkcos_status_t autotune(arkcos_batch_s* B, int32_t* su_out, int32_t* grp_out, int32_t* bpc_out) {
   // subset: up to four maps per ring count
   std::map<int64_t, int> seen;
   std::vector<int32_t> sub;
@@ -237,24 +242,28 @@ arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out) 
   int cus = 0;
   BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
   float best = 1e30f;
-  int32_t bu = kBandUnits, bb = 2;
-  for (int32_t upb : {4, 8}) {
-    Queue Q;
-    std::vector<void*> owned;
-    hipError_t e = build_queue(B, sub, upb, Q, owned);
-    for (int32_t bpc : {1, 2, 4}) {
-      float ms = 0.f;
-      if (e == hipSuccess) e = time_queue(B, Q, sb, ob, spec, bout, (int32_t*)ctr, upb, cus * bpc, &ms);
-      if (e == hipSuccess && ms < best) {
-        best = ms;
-        bu = upb;
-        bb = bpc;
+  int32_t bs = 64, bg = 4, bb = 2;
+  for (int32_t su : {32, 64, 128}) {
+    for (int32_t grp : {4, 8}) {
+      Queue Q;
+      std::vector<void*> owned;
+      hipError_t e = build_queue(B, sub, su, grp, Q, owned);
+      for (int32_t bpc : {1, 2, 3, 4}) {
+        float ms = 0.f;
+        if (e == hipSuccess) e = time_queue(B, Q, sb, ob, spec, bout, (int32_t*)ctr, grp, cus * bpc, &ms);
+        if (e == hipSuccess && ms < best) {
+          best = ms;
+          bs = su;
+          bg = grp;
+          bb = bpc;
+        }
       }
+      for (void* p : owned) hipFree(p);
+      if (e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
     }
-    for (void* p : owned) hipFree(p);
-    if (e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
   }
-  *upb_out = bu;
+  *su_out = bs;
+  *grp_out = bg;
   *bpc_out = bb;
   return ARKCOS_OK;
 }
@@ -366,32 +375,31 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
     B->n_pole_fwd = (int32_t)fwd.size();
     B->n_pole_adj = (int32_t)adj.size();
   }
-  BCHK(balloc(B, &B->d_xs, n));
-  BCHK(balloc(B, &B->d_ys, n));
 
-  // band size and grid: cached, else measured
-  int32_t upb = kBandUnits, bpc = 2;
+  // segment length, group and grid: cached, else measured
+  int32_t su = 64, grp = 4, bpc = 2;
   const std::string key = tune_key(B);
-  if (read_cache(key, &upb, &bpc)) {
+  if (read_cache(key, &su, &grp, &bpc)) {
     B->tuned = 2;
   } else {
-    arkcos_status_t st = autotune(B, &upb, &bpc);
+    arkcos_status_t st = autotune(B, &su, &grp, &bpc);
     if (st != ARKCOS_OK) return st;
-    write_cache(key, upb, bpc);
+    write_cache(key, su, grp, bpc);
     B->tuned = 1;
   }
   int cus = 0;
   BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  B->units_per_band = upb;
+  B->seg_units = su;
+  B->group = grp;
   B->grid = cus * bpc;
   std::vector<int32_t> all(n);
   for (int32_t i = 0; i < n; ++i) all[i] = i;
   Queue Q;
   std::vector<void*> owned;
-  hipError_t e = build_queue(B, all, upb, Q, owned);
+  hipError_t e = build_queue(B, all, su, grp, Q, owned);
   for (void* p : owned) B->allocations.push_back(p);
   BCHK(e);
-  B->acc_shape = Q.shape;
+  B->cap = Q.cap;
   void* d = nullptr;
   BCHK(hipMalloc(&d, Q.acc_args.size()));
   B->allocations.push_back(d);
@@ -405,10 +413,39 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
   return ARKCOS_OK;
 }
 
+// Workspace: queue counter (256 bytes) | the call's map pointers (x then y,
+// n each) | spectra | output coefficients, each part 256-byte aligned.
+size_t ptr_table_bytes(const arkcos_batch_s* B) { return ((size_t)2 * B->n * sizeof(void*) + 255) / 256 * 256; }
+
 size_t batch_ws_bytes(const arkcos_batch_s* B) {
   const size_t csz = B->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-  return 256 + al(std::max<int64_t>(B->spec_total, 1) * csz) + al(std::max<int64_t>(B->out_total, 1) * csz);
+  return 256 + ptr_table_bytes(B) + al(std::max<int64_t>(B->spec_total, 1) * csz) +
+         al(std::max<int64_t>(B->out_total, 1) * csz);
+}
+
+// Map pointers of one call, passed by value to a kernel that writes them into
+// the call's region of the workspace (so every call, eager or captured in a
+// graph, reads its own pointers; nothing is uploaded from the host).
+constexpr int kPtrChunk = 64;
+struct PtrChunk {
+  const void* p[kPtrChunk];
+};
+
+__global__ void fill_ptrs_kernel(PtrChunk c, int32_t count, const void** __restrict__ dst) {
+  if ((int32_t)threadIdx.x < count) gstore(dst + threadIdx.x, c.p[threadIdx.x]);
+}
+
+hipError_t write_ptrs(const void* const* src, int32_t n, const void** dst, hipStream_t s) {
+  for (int32_t b = 0; b < n; b += kPtrChunk) {
+    PtrChunk c{};
+    const int32_t cnt = std::min(kPtrChunk, n - b);
+    for (int32_t k = 0; k < cnt; ++k) c.p[k] = src[b + k];
+    fill_ptrs_kernel<<<1, kPtrChunk, 0, s>>>(c, cnt, dst + b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 #define BLAUNCH(expr)                                                                              \
@@ -434,39 +471,34 @@ arkcos_status_t run_batch(arkcos_batch_s* B, const void* const* x, void* const* 
       if (px < py + bk && py < px + bi) return fail(ARKCOS_ERR_INVALID_VALUE, "an input map overlaps an output map");
     }
   }
-  // map pointers: upload when they changed since the last call
-  if (B->h_xs.size() != (size_t)B->n || !std::equal(x, x + B->n, B->h_xs.begin()) ||
-      !std::equal(y, y + B->n, B->h_ys.begin())) {
-    B->h_xs.assign(x, x + B->n);
-    B->h_ys.assign(y, y + B->n);
-    BLAUNCH(hipStreamSynchronize(s));
-    BLAUNCH(hipMemcpy(B->d_xs, x, B->n * sizeof(void*), hipMemcpyHostToDevice));
-    BLAUNCH(hipMemcpy(B->d_ys, y, B->n * sizeof(void*), hipMemcpyHostToDevice));
-  }
   const size_t csz = B->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
   char* base = static_cast<char*>(ws);
   int32_t* counter = reinterpret_cast<int32_t*>(base);
-  void* spec = base + 256;
-  void* bout = base + 256 + al(std::max<int64_t>(B->spec_total, 1) * csz);
+  const void** d_xs = reinterpret_cast<const void**>(base + 256);
+  const void** d_ys = d_xs + B->n;
+  void* spec = base + 256 + ptr_table_bytes(B);
+  void* bout = static_cast<char*>(spec) + al(std::max<int64_t>(B->spec_total, 1) * csz);
   hipEvent_t* ev = nullptr;
   if (B->timing_used < B->timing_slots) ev = &B->timing_events[5 * B->timing_used++];
   if (ev) BLAUNCH(hipEventRecord(ev[0], s));
+  BLAUNCH(write_ptrs(x, B->n, d_xs, s));
+  BLAUNCH(write_ptrs(y, B->n, d_ys, s));
   for (const ClassDev& c : B->classes)
-    BLAUNCH(launch_ring_batch(B->dtype, false, B->d_rargs[adjoint ? 1 : 0], c.entries, c.count, c.lds, c.threads, c.mf, B->d_xs, spec,
+    BLAUNCH(launch_ring_batch(B->dtype, false, B->d_rargs[adjoint ? 1 : 0], c.entries, c.count, c.lds, c.threads, c.mf, d_xs, spec,
                               B->d_spec_base, s));
   if (ev) BLAUNCH(hipEventRecord(ev[1], s));
   BLAUNCH(launch_accumulate_batch(B->dtype, B->d_acc_args, B->d_spec_base, B->d_out_base, B->d_items, B->n_items,
-                                  counter, spec, bout, B->grid, B->units_per_band, B->all_tables, B->acc_shape, s));
+                                  counter, spec, bout, B->grid, B->group, B->all_tables, B->cap, s));
   if (ev) BLAUNCH(hipEventRecord(ev[2], s));
   for (const ClassDev& c : B->classes)
-    BLAUNCH(launch_ring_batch(B->dtype, true, B->d_rargs[adjoint ? 3 : 2], c.entries, c.count, c.lds, c.threads, c.mf, B->d_ys, bout,
+    BLAUNCH(launch_ring_batch(B->dtype, true, B->d_rargs[adjoint ? 3 : 2], c.entries, c.count, c.lds, c.threads, c.mf, d_ys, bout,
                               B->d_out_base, s));
   if (ev) BLAUNCH(hipEventRecord(ev[3], s));
   if (!adjoint)
-    BLAUNCH(launch_pole_batch(B->dtype, B->d_pole_maps, B->d_pole_fwd, B->n_pole_fwd, 0, B->d_xs, B->d_ys, s));
+    BLAUNCH(launch_pole_batch(B->dtype, B->d_pole_maps, B->d_pole_fwd, B->n_pole_fwd, 0, d_xs, d_ys, s));
   else
-    BLAUNCH(launch_pole_batch(B->dtype, B->d_pole_maps, B->d_pole_adj, B->n_pole_adj, 1, B->d_xs, B->d_ys, s));
+    BLAUNCH(launch_pole_batch(B->dtype, B->d_pole_maps, B->d_pole_adj, B->n_pole_adj, 1, d_xs, d_ys, s));
   if (ev) BLAUNCH(hipEventRecord(ev[4], s));
   return ARKCOS_OK;
 }
@@ -489,7 +521,8 @@ arkcos_status_t arkcos_batch_get_info(arkcos_batch_t B, arkcos_batch_info_t* inf
   if (!B || !info) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
   std::memset(info, 0, sizeof(*info));
   info->n_maps = B->n;
-  info->units_per_band = B->units_per_band;
+  info->seg_units = B->seg_units;
+  info->group = B->group;
   info->grid = B->grid;
   info->tuned = B->tuned;
   info->n_items = B->n_items;

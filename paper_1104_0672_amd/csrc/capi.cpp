@@ -21,8 +21,7 @@ arkcos_status_t fail(arkcos_status_t st, const std::string& msg) {
 
 arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* prof, double R,
                            arkcos_dtype_t dtype, const arkcos_options_t* o, arkcos_plan_s** out);
-arkcos_status_t upload_knots(arkcos_plan_s* P);
-arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time);
+hipError_t update_knots(arkcos_plan_s* P, const double* d_src, hipStream_t s);
 arkcos_status_t run_kernel_grad(arkcos_plan_s* P, const void* x, const void* r, double* grad,
                                 void* ws, uint32_t flags, hipStream_t s);
 
@@ -100,7 +99,10 @@ void arkcos_default_options(arkcos_options_t* o) {
   o->fix_pole_pixels = 1;
   o->band_tol = -1.0;
   o->mode = 0;
-  o->reserved = 0;
+  o->own_grid = 0;
+  o->kernel_eval = 0;
+  o->table_nodes = 0;
+  for (int32_t& r : o->reserved) r = 0;
 }
 
 arkcos_status_t arkcos_plan(const arkcos_geometry_t* geom, const arkcos_profile_t* profile,
@@ -145,6 +147,12 @@ arkcos_status_t arkcos_plan_get_info(arkcos_plan_t P, arkcos_plan_info_t* info) 
   info->n_knots = (int32_t)P->knots.size();
   info->workspace_bytes = workspace_bytes(P);
   info->plan_bytes = P->plan_bytes;
+  for (const auto& pr : P->h_pairs)
+    if (pr.band >= 0 && pr.kind >= 0 && pr.kind < 4) ++info->pairs_by_kind[pr.kind];
+  info->acc_seg_units = P->acc.seg_units;
+  info->acc_group = P->acc.group;
+  info->acc_window = P->acc.cap;
+  info->acc_tuned = P->acc.tuned;
   return ARKCOS_OK;
 }
 
@@ -173,6 +181,8 @@ arkcos_status_t arkcos_kernel_grad(arkcos_plan_t plan, const void* x, const void
                                    void* ws, uint32_t flags, hipStream_t stream) {
   if (!plan) return fail(ARKCOS_ERR_INVALID_VALUE, "null plan");
   if (plan->prof_kind != 1) return fail(ARKCOS_ERR_NOT_SUPPORTED, "knot gradient needs a spline profile");
+  if (plan->opts.kernel_eval != 0)
+    return fail(ARKCOS_ERR_NOT_SUPPORTED, "knot gradient needs the exact kernel evaluation (kernel_eval 0)");
   if (!grad) return fail(ARKCOS_ERR_INVALID_VALUE, "null gradient pointer");
   if (!x || !r || !ws) return fail(ARKCOS_ERR_INVALID_VALUE, "null map or workspace pointer");
   const size_t bytes = (size_t)plan->npix * elem_size(plan);
@@ -191,14 +201,21 @@ arkcos_status_t arkcos_set_knots(arkcos_plan_t plan, const double* knot_values) 
   if (plan->prof_kind != 1) return fail(ARKCOS_ERR_NOT_SUPPORTED, "plan has no spline profile");
   arkcos_status_t st = check_device(plan);
   if (st != ARKCOS_OK) return st;
-  try {
-    plan->knots.assign(knot_values, knot_values + plan->knots.size());
-    st = upload_knots(plan);
-    if (st != ARKCOS_OK) return st;
-    return build_kernel_tables(plan, false);
-  } catch (...) {
-    return fail(ARKCOS_ERR_INTERNAL, "unexpected exception in knot update");
-  }
+  // every call already enqueued (on any stream) finishes with the old knots
+  LAUNCH(hipDeviceSynchronize());
+  LAUNCH(hipMemcpy(plan->d_knots, knot_values, plan->knots.size() * sizeof(double), hipMemcpyHostToDevice));
+  LAUNCH(update_knots(plan, plan->d_knots, nullptr));
+  LAUNCH(hipStreamSynchronize(nullptr));
+  return ARKCOS_OK;
+}
+
+arkcos_status_t arkcos_set_knots_async(arkcos_plan_t plan, const double* knot_values, hipStream_t stream) {
+  if (!plan || !knot_values) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
+  if (plan->prof_kind != 1) return fail(ARKCOS_ERR_NOT_SUPPORTED, "plan has no spline profile");
+  arkcos_status_t st = check_device(plan);
+  if (st != ARKCOS_OK) return st;
+  LAUNCH(update_knots(plan, knot_values, stream));
+  return ARKCOS_OK;
 }
 
 arkcos_status_t arkcos_plan_timing(arkcos_plan_t plan, int32_t max_calls) {

@@ -163,9 +163,12 @@ arkcos_status_t build_grad_items(arkcos_plan_s* P) {
   return ARKCOS_OK;
 }
 
-// Kernel samples, bands and tables from the current profile.  Called at plan
-// creation and again by arkcos_set_knots; ring pairs and windows stay fixed.
-arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
+// Kernel samples, bands and tables from the profile, at plan creation.
+// Spline plans keep every kernel sample of a pair's window and every mode
+// up to the grid's Nyquist mode (no band truncation), so that the layout
+// fixed here holds for any later knot values (update_knots).
+arkcos_status_t build_kernel_tables(arkcos_plan_s* P) {
+  const bool spline = P->prof_kind == 1;
   hipStream_t s = nullptr;
   HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
   struct Guard { hipStream_t s; ~Guard() { hipStreamDestroy(s); } } guard{s};
@@ -182,12 +185,7 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
   struct Free { void* a; void* b; ~Free() { if (a) hipFree(a); if (b) hipFree(b); } } fr{d_abs, d_band};
 
   // kernel samples over each pair's full window, indexed by coefficient offsets
-  std::vector<arkcos::PairDev> pcoef = P->h_pairs;
-  for (int64_t q = 0; q < np; ++q) {
-    pcoef[q].off = P->h_coef_off[q];
-    pcoef[q].ncoef = P->h_ncoef_window[q];
-  }
-  HIPCHK(hipMemcpy(P->d_pairs, pcoef.data(), np * sizeof(PairDev), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(P->d_pairs, P->h_pairs.data(), np * sizeof(PairDev), hipMemcpyHostToDevice));
   HIPCHK(launch_kernel_rows(P, d_abs, s));
   HIPCHK(hipStreamSynchronize(s));
   if (np > 0) HIPCHK(hipMemcpy(abs_sum.data(), d_abs, np * sizeof(double), hipMemcpyDeviceToHost));
@@ -198,7 +196,7 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
   // tolerance: |K_ij(m)| then changes by less than 0.1 band_tol times the
   // largest kernel-row magnitude at every m, so the row is not cut off with a
   // step that would widen its spectrum
-  if (np > 0) {
+  if (np > 0 && !spline) {
     std::vector<double> c64(P->coef_total);
     HIPCHK(hipMemcpy(c64.data(), P->d_coef64, P->coef_total * sizeof(double), hipMemcpyDeviceToHost));
     const double cut = 0.1 * P->band_tol * scale;
@@ -207,19 +205,18 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
       const double* a = c64.data() + P->h_coef_off[q];
       double dropped = 0.0;
       while (n > 1 && dropped + fabs(a[n - 1]) <= cut) dropped += fabs(a[--n]);
-      pcoef[q].ncoef = n;
       P->h_pairs[q].ncoef = n;
     }
-    HIPCHK(hipMemcpy(P->d_pairs, pcoef.data(), np * sizeof(PairDev), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(P->d_pairs, P->h_pairs.data(), np * sizeof(PairDev), hipMemcpyHostToDevice));
   }
-  if (first_time && P->band_tol > 0 && np > 0) {
+  if (P->band_tol > 0 && np > 0 && !spline) {
     HIPCHK(launch_band(P, P->band_tol * scale, d_band, s));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemcpy(band.data(), d_band, np * sizeof(int32_t), hipMemcpyDeviceToHost));
   } else {
-    for (int64_t q = 0; q < np; ++q) band[q] = abs_sum[q] > 0 ? P->h_pairs[q].nyq : -1;
+    for (int64_t q = 0; q < np; ++q) band[q] = (spline || abs_sum[q] > 0) ? P->h_pairs[q].nyq : -1;
   }
-  if (first_time && P->opts.mode == 1) {
+  if (P->opts.mode == 1) {
     // the plain mode of Sect. 4.1: input spectra zero-padded past N_j / 2
     // and output coefficients truncated at N_i / 2, i.e. a pair contributes
     // only its modes m <= min(N_i, N_j) / 2 (both rings of a mirrored pair
@@ -228,10 +225,6 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
       const int32_t top = (int32_t)(std::min(P->h_n[P->h_pair_i[q]], P->h_n[P->h_pairs[q].j]) / 2);
       band[q] = std::min(band[q], top);
     }
-  }
-  if (!first_time) {
-    // the memory layout was sized for the original bands and table choices: keep them
-    for (int64_t q = 0; q < np; ++q) band[q] = P->h_pairs[q].band;
   }
 
   // A table pair reads the table of its transpose when that one exists:
@@ -267,7 +260,7 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
   // they fit in kAutoTableBytes (the accumulation then only streams them),
   // otherwise tables only for rows too wide for the recurrence
   bool all_auto = false;
-  if (first_time && P->opts.kgen == 0) {
+  if (P->opts.kgen == 0) {
     int64_t entries = 0;
     for (int64_t q = 0; q < np; ++q) {
       if (band[q] < 0) continue;
@@ -279,18 +272,16 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
   int64_t table_total = 0, ntab = 0;
   std::vector<int32_t> tab_list;
   std::vector<int64_t> tab_coef;
-  if (first_time) P->h_tab_owner.assign(np, -1);
+  P->h_tab_owner.assign(np, -1);
   for (int64_t q = 0; q < np; ++q) {
     PairDev& pr = P->h_pairs[q];
     pr.band = band[q];
     bool table = false;
-    if (!first_time) {
-      table = pr.kind == KG_TABLE;
-    } else if (pr.band >= 0) {
+    if (pr.band >= 0) {
       if (P->opts.kgen == 2 || all_auto) table = true;
       else if (P->opts.kgen == 0) table = pr.ncoef > kOtfMaxCoef;
     }
-    if (table && first_time) {
+    if (table) {
       P->h_tab_owner[q] = q;
       const int64_t t = transpose(q);
       if (t >= 0 && t < q && P->h_pairs[t].kind == KG_TABLE && compatible(t, q))
@@ -312,8 +303,6 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
       pr.off = P->h_coef_off[q];
     }
   }
-  if (!first_time && table_total != P->table_total)
-    return fail(ARKCOS_ERR_INTERNAL, "table layout changed on knot update");
   // the accumulation addresses samples and tables with 32-bit offsets
   if (table_total >= (int64_t(1) << 32) ||
       (P->coef_total + 16) * (int64_t)(P->dtype == ARKCOS_F32 ? 4 : 8) >= (int64_t(1) << 31))
@@ -327,7 +316,7 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
     P->all_tables = all && ntab > 0;
   }
   const size_t rsz = P->dtype == ARKCOS_F32 ? sizeof(float) : sizeof(double);
-  if (first_time) {
+  {
     void* t = nullptr;
     HIPCHK(hipMalloc(&t, std::max<int64_t>(table_total, 1) * rsz));
     P->allocations.push_back(t);
@@ -335,20 +324,58 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P, bool first_time) {
     P->d_table = t;
   }
   HIPCHK(hipMemcpy(P->d_pairs, P->h_pairs.data(), np * sizeof(PairDev), hipMemcpyHostToDevice));
-  const int64_t nlist = (int64_t)tab_list.size();  // tables computed (shared ones once)
-  if (nlist > 0) {
-    int32_t* d_list = nullptr;
-    int64_t* d_co = nullptr;
-    HIPCHK(hipMalloc(&d_list, nlist * sizeof(int32_t)));
-    HIPCHK(hipMalloc(&d_co, nlist * sizeof(int64_t)));
-    struct Free2 { void* a; void* b; ~Free2() { hipFree(a); hipFree(b); } } f2{d_list, d_co};
-    HIPCHK(hipMemcpy(d_list, tab_list.data(), nlist * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(d_co, tab_coef.data(), nlist * sizeof(int64_t), hipMemcpyHostToDevice));
-    HIPCHK(launch_table_list(P, d_list, d_co, (int32_t)nlist, s));
-    HIPCHK(hipStreamSynchronize(s));
-  }
+  // the pairs whose tables are computed (shared ones once), kept for knot updates
+  P->n_tab_list = (int32_t)tab_list.size();
+  HIPCHK(upload(P, &P->d_tab_list, tab_list));
+  HIPCHK(upload(P, &P->d_tab_coef, tab_coef));
+  HIPCHK(launch_table_list(P, P->d_tab_list, P->d_tab_coef, P->n_tab_list, s));
+  HIPCHK(hipStreamSynchronize(s));
   return ARKCOS_OK;
 }
+
+// Clamped-spline moments of the knot values src (n of them, spacing h),
+// solved on the device by the tridiagonal (Thomas) recurrence; the knots are
+// copied to knots first (src may equal knots).  One thread: n <= 64.
+__global__ void spline_update_kernel(const double* __restrict__ src, int n, double h, double* knots, double* mom) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double c[64], diag[64], rhs[64];
+  for (int k = 0; k < n; ++k) c[k] = src[k];
+  for (int k = 0; k < n; ++k) knots[k] = c[k];
+  const double s6 = 6.0 / (h * h);
+  for (int k = 0; k < n; ++k) {
+    if (k == 0) { diag[k] = 2; rhs[k] = s6 * (c[1] - c[0]); }
+    else if (k == n - 1) { diag[k] = 2; rhs[k] = -s6 * (c[n - 1] - c[n - 2]); }
+    else { diag[k] = 4; rhs[k] = s6 * (c[k + 1] - 2 * c[k] + c[k - 1]); }
+  }
+  // sub- and super-diagonals are 1 everywhere they exist
+  for (int k = 1; k < n; ++k) {
+    const double f = 1.0 / diag[k - 1];
+    diag[k] -= f;
+    rhs[k] -= f * rhs[k - 1];
+  }
+  double next = rhs[n - 1] / diag[n - 1];
+  mom[n - 1] = next;
+  for (int k = n - 2; k >= 0; --k) {
+    next = (rhs[k] - next) / diag[k];
+    mom[k] = next;
+  }
+}
+
+// New spline knots (device array of n_knots doubles) applied on stream s:
+// moments, kernel samples and K_ij(m) tables recomputed in place with the
+// layout of plan creation.  Enqueues kernels only (no allocation, no host
+// synchronisation), so it can be captured in a graph.
+hipError_t update_knots(arkcos_plan_s* P, const double* d_src, hipStream_t s) {
+  const int n = (int)P->knots.size();
+  spline_update_kernel<<<1, 64, 0, s>>>(d_src, n, P->theta_max / (n - 1), P->d_knots, P->d_spline_mom);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_kernel_rows(P, nullptr, s);
+  if (e != hipSuccess) return e;
+  return launch_table_list(P, P->d_tab_list, P->d_tab_coef, P->n_tab_list, s);
+}
+
+arkcos_status_t choose_acc_config(arkcos_plan_s* P);
 
 arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* prof, double R,
                            arkcos_dtype_t dtype, const arkcos_options_t* o, arkcos_plan_s** out) {
@@ -363,7 +390,13 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
     return fail(ARKCOS_ERR_INVALID_VALUE, "oversample must be 0, 1, 2, 4, 8 or 16");
   if (opts.kgen < 0 || opts.kgen > 2) return fail(ARKCOS_ERR_INVALID_VALUE, "kgen must be 0, 1 or 2");
   if (opts.mode < 0 || opts.mode > 1) return fail(ARKCOS_ERR_INVALID_VALUE, "mode must be 0 or 1");
-  if (opts.reserved != 0) return fail(ARKCOS_ERR_INVALID_VALUE, "reserved option field must be 0");
+  if (opts.own_grid < 0 || opts.own_grid > 1) return fail(ARKCOS_ERR_INVALID_VALUE, "own_grid must be 0 or 1");
+  if (opts.kernel_eval < 0 || opts.kernel_eval > 1)
+    return fail(ARKCOS_ERR_INVALID_VALUE, "kernel_eval must be 0 or 1");
+  if (opts.table_nodes != 0 && (opts.table_nodes < 2 || opts.table_nodes > (1 << 24)))
+    return fail(ARKCOS_ERR_INVALID_VALUE, "table_nodes must be 0 or in 2 .. 2^24");
+  for (int32_t r : opts.reserved)
+    if (r != 0) return fail(ARKCOS_ERR_INVALID_VALUE, "reserved option fields must be 0");
   if (g->kind == 0) {
     if (g->n_theta < 1 || g->n_phi < 4 || (g->n_phi & 1) || g->n_theta > (1 << 20) || g->n_phi > (1 << 20))
       return fail(ARKCOS_ERR_INVALID_VALUE, "ECP needs n_theta >= 1 and an even n_phi >= 4");
@@ -494,8 +527,12 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       pr.j = (int32_t)j;
       // rings of equal length (with offsets 0 or pi/N) are sampled at their
       // true pixel offsets on a grid of their own length: exact (Sect. 4.3;
-      // the plain mode of Sect. 4.1 puts every pair on the p L grid)
+      // the plain mode of Sect. 4.1 puts every pair on the p L grid).  With
+      // own_grid = 1 only equatorial pairs (rings of L pixels) do so, as
+      // Sect. 4.3 states it; a polar ring with itself or its mirror then
+      // takes the p L grid like the other cap pairs.
       const bool aligned = opts.mode == 0 && P->h_n[i] == P->h_n[j] &&
+                           (opts.own_grid == 0 || P->h_n[i] == L) &&
                            (P->h_phase_den[i] == 0 || P->h_phase_den[i] == P->h_n[i]) &&
                            (P->h_phase_den[j] == 0 || P->h_phase_den[j] == P->h_n[j]);
       int32_t shift = 0;
@@ -684,6 +721,11 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
     P->d_coef = c;
   }
   HIPCHK(dev_alloc(P, &P->d_knots, std::max<size_t>(P->knots.size(), 1)));
+  if (opts.kernel_eval == 1) {
+    // the biased linear table of Sect. 4.1 (filled with the kernel samples)
+    P->utable_n = opts.table_nodes > 0 ? opts.table_nodes : 65536;
+    HIPCHK(dev_alloc(P, &P->d_utable, (size_t)P->utable_n));
+  }
   HIPCHK(dev_alloc(P, &P->d_spline_mom, std::max<size_t>(P->knots.size(), 1)));
   {
     arkcos_status_t st = upload_knots(P);
@@ -729,7 +771,7 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
 
   // ------------------------------------------- kernel samples and bands
   {
-    arkcos_status_t st = build_kernel_tables(P, true);
+    arkcos_status_t st = build_kernel_tables(P);
     if (st != ARKCOS_OK) return st;
   }
   if (const char* e = getenv("ARKCOS_PLAN_STATS"); e && *e == '1') {
@@ -782,6 +824,8 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       }
     }
     U.band = ub;
+    U.jlo = P->h_pairs[U.pbeg].j;
+    U.jhi = P->h_pairs[U.pend - 1].j;
     P->h_out_len[U.i] = ub + 1;
     if (U.im >= 0) P->h_out_len[U.im] = ub + 1;
   }
@@ -799,22 +843,11 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   HIPCHK(upload(P, &P->rt.out_len, P->h_out_len));
   HIPCHK(upload(P, &P->d_units, P->h_units));
 
-  // bands of consecutive units, and work items: (band, first mode) tiles
-  build_bands(P, kBandUnits, P->h_bands, &P->acc_shape);
+  // segments of consecutive units and their (segment, mode tile) items
   {
-    std::vector<WorkItem> its;
-    std::vector<double> cost;
-    accumulation_items(P, P->h_bands, its, cost);
-    // heaviest first, so that the launch does not end on a long item
-    std::vector<size_t> ord(its.size());
-    for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
-    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-    P->h_items.clear();
-    for (size_t k : ord) P->h_items.push_back(its[k]);
+    arkcos_status_t st = choose_acc_config(P);
+    if (st != ARKCOS_OK) return st;
   }
-  HIPCHK(upload(P, &P->d_items, P->h_items));
-  HIPCHK(upload(P, &P->d_bands, P->h_bands));
-  HIPCHK(configure_accumulate(P));
 
   // rings whose pixels can lie within R of a pole pixel (direct-sum columns)
   if (g->kind == 1) {
@@ -832,62 +865,168 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   return ARKCOS_OK;
 }
 
-// Work items of the accumulation: each band's mode tiles in runs of
-// kTilesPerItem, with an estimate of their cost (recurrence length of the
-// pairs still inside their band, summed over the tiles).
-void accumulation_items(const arkcos_plan_s* P, const std::vector<BandDev>& bands, std::vector<WorkItem>& items,
+// Work items of the accumulation: every (segment, mode tile) that some unit
+// of the segment reaches, with an estimate of its cost (table pairs, or the
+// recurrence length of the others, still inside their band at that tile).
+void accumulation_items(const arkcos_plan_s* P, const std::vector<SegDev>& segs, std::vector<WorkItem>& items,
                         std::vector<double>& cost) {
   items.clear();
   cost.clear();
-  for (int32_t b = 0; b < (int32_t)bands.size(); ++b) {
-    const BandDev& bd = bands[b];
-    if (bd.band < 0) continue;
-    const int32_t ntile = bd.band / kAccTile + 1;
-    for (int32_t t0 = 0; t0 < ntile; t0 += kTilesPerItem) {
-      const int32_t nt = std::min(kTilesPerItem, ntile - t0);
+  for (int32_t s = 0; s < (int32_t)segs.size(); ++s) {
+    const SegDev& sg = segs[s];
+    if (sg.band < 0) continue;
+    for (int32_t t = 0; t <= sg.band / kSweepTile; ++t) {
+      const int32_t m0 = t * kSweepTile;
       double c = 0.0;
-      for (int32_t u = bd.u0; u < bd.u0 + bd.nu; ++u) {
+      for (int32_t u = sg.u0; u < sg.u0 + sg.nu; ++u) {
         const UnitDev& U = P->h_units[u];
+        if (U.band < m0) continue;
+        c += 4.0;
         for (int32_t q = U.pbeg; q < U.pend; ++q) {
           const PairDev& pr = P->h_pairs[q];
-          const int32_t live = std::min(nt, pr.band / kAccTile + 1 - t0);
-          if (live <= 0) continue;
-          c += live * (pr.kind == KG_TABLE ? 3.0 : (double)((pr.ncoef + 3) / 4 * 4) + 4.0);
+          if (pr.band < m0) continue;
+          c += pr.kind == KG_TABLE ? 1.0 : (double)((pr.ncoef + 7) / 8) * 4.0;
         }
       }
-      items.push_back(WorkItem{b, t0, nt, 0});
-      cost.push_back(c + 8.0 * nt);
+      items.push_back(WorkItem{s, t, 1, 0});
+      cost.push_back(c);
     }
   }
 }
 
-// Groups consecutive units into bands of units_per_band, with the input-ring
-// window of each band and the largest window.
-void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<BandDev>& bands, AccShape* shape) {
-  bands.clear();
-  *shape = AccShape{};
-  const int64_t nunits = P->n_units, nr = P->nrings;
-  for (int64_t u0 = 0; u0 < nunits; u0 += units_per_band) {
-    BandDev B{};
-    B.u0 = (int32_t)u0;
-    B.nu = (int32_t)std::min<int64_t>(units_per_band, nunits - u0);
-    B.jlo = (int32_t)nr;
-    B.jhi = -1;
-    B.band = -1;
-    B.pbeg = P->h_units[u0].pbeg;
-    B.npair = P->h_units[u0 + B.nu - 1].pend - B.pbeg;
-    for (int64_t u = u0; u < u0 + B.nu; ++u) {
-      const UnitDev& U = P->h_units[u];
-      if (U.pend > U.pbeg) {
-        B.jlo = std::min(B.jlo, P->h_pairs[U.pbeg].j);
-        B.jhi = std::max(B.jhi, P->h_pairs[U.pend - 1].j);
-      }
-      B.band = std::max(B.band, U.band);
+// Segments of seg_units consecutive units, swept `group` units at a time;
+// *cap receives the ring slots the LDS window needs: the input rings of two
+// consecutive groups (the current one and the one whose rows are loaded
+// while it is summed).
+void build_segments(const arkcos_plan_s* P, int32_t seg_units, int32_t group, std::vector<SegDev>& segs,
+                    int32_t* cap) {
+  segs.clear();
+  int32_t c = 1;
+  const int64_t nunits = P->n_units;
+  for (int64_t u0 = 0; u0 < nunits; u0 += seg_units) {
+    SegDev S{};
+    S.u0 = (int32_t)u0;
+    S.nu = (int32_t)std::min<int64_t>(seg_units, nunits - u0);
+    S.jlo = P->h_units[u0].jlo;
+    S.band = -1;
+    for (int64_t u = u0; u < u0 + S.nu; ++u) S.band = std::max(S.band, P->h_units[u].band);
+    for (int64_t g = u0; g < u0 + S.nu; g += group) {
+      const int64_t last = std::min<int64_t>(g + 2 * group, u0 + S.nu) - 1;
+      c = std::max(c, P->h_units[last].jhi - P->h_units[g].jlo + 1);
     }
-    if (B.jhi >= B.jlo) shape->max_window = std::max(shape->max_window, B.jhi - B.jlo + 1);
-    shape->max_band_pairs = std::max(shape->max_band_pairs, B.npair);
-    bands.push_back(B);
+    segs.push_back(S);
   }
+  *cap = c;
+}
+
+namespace {
+
+// Largest LDS window the accumulation uses (bytes); wider windows make the
+// kernel read the spectra straight from memory instead (cap = 0).
+constexpr size_t kMaxWindowBytes = 96 * 1024;
+
+hipError_t make_acc_config(arkcos_plan_s* P, int32_t seg_units, int32_t group, AccConfig& c,
+                           std::vector<void*>& owned) {
+  std::vector<SegDev> segs;
+  int32_t cap = 0;
+  build_segments(P, seg_units, group, segs, &cap);
+  if (acc_lds_bytes(P->dtype, cap) > kMaxWindowBytes) cap = 0;
+  std::vector<WorkItem> its;
+  std::vector<double> cost;
+  accumulation_items(P, segs, its, cost);
+  // heaviest first, so that the launch does not end on a long item
+  std::vector<size_t> ord(its.size());
+  for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+  std::vector<WorkItem> sorted;
+  for (size_t k : ord) sorted.push_back(its[k]);
+  c = AccConfig{};
+  c.seg_units = seg_units;
+  c.group = group;
+  c.cap = cap;
+  c.n_items = (int32_t)sorted.size();
+  void *ds = nullptr, *di = nullptr;
+  hipError_t e = hipMalloc(&ds, std::max<size_t>(segs.size(), 1) * sizeof(SegDev));
+  if (e != hipSuccess) return e;
+  owned.push_back(ds);
+  e = hipMalloc(&di, std::max<size_t>(sorted.size(), 1) * sizeof(WorkItem));
+  if (e != hipSuccess) return e;
+  owned.push_back(di);
+  if (!segs.empty()) e = hipMemcpy(ds, segs.data(), segs.size() * sizeof(SegDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !sorted.empty())
+    e = hipMemcpy(di, sorted.data(), sorted.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+  c.d_segs = (SegDev*)ds;
+  c.d_items = (WorkItem*)di;
+  return e;
+}
+
+}  // namespace
+
+// The accumulation's segment length and group size.  Large plans time each
+// candidate on a scratch workspace (the kernel's control flow does not depend
+// on the data) and keep the fastest; small plans take 64 units in groups of
+// 4.  ARKCOS_ACC_CONFIG="S,G" forces a choice.  The result does not depend on
+// the choice: every unit sums its pairs in the same order.
+arkcos_status_t choose_acc_config(arkcos_plan_s* P) {
+  std::vector<std::pair<int32_t, int32_t>> cand;
+  if (const char* e = getenv("ARKCOS_ACC_CONFIG"); e && *e) {
+    int a = 0, b = 0;
+    if (sscanf(e, "%d,%d", &a, &b) == 2 && a > 0 && (b == 4 || b == 8)) cand.push_back({a, b});
+  }
+  if (cand.empty()) {
+    if (P->npix >= (int64_t(1) << 20))
+      cand = {{32, 4}, {64, 4}, {128, 4}, {32, 8}, {64, 8}, {128, 8}};
+    else
+      cand = {{64, 4}};
+  }
+  std::vector<void*> owned;
+  struct Free {
+    std::vector<void*>* v;
+    ~Free() { for (void* a : *v) hipFree(a); }
+  } fr{&owned};
+  if (cand.size() == 1) {
+    HIPCHK(make_acc_config(P, cand[0].first, cand[0].second, P->acc, owned));
+    for (void* a : owned) P->allocations.push_back(a);
+    owned.clear();
+    return ARKCOS_OK;
+  }
+  void* ws = nullptr;
+  const size_t wsb = workspace_bytes(P);
+  HIPCHK(hipMalloc(&ws, wsb));
+  owned.push_back(ws);
+  HIPCHK(hipMemset(ws, 0, wsb));
+  void *spec = nullptr, *bout = nullptr;
+  workspace_split(P, ws, &spec, &bout);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { hipEventDestroy(a); hipEventDestroy(b); }
+  } ev{e0, e1};
+  float best = 1e30f;
+  size_t best_k = 0;
+  std::vector<AccConfig> cfg(cand.size());
+  std::vector<std::vector<void*>> mem(cand.size());
+  for (size_t k = 0; k < cand.size(); ++k) {
+    HIPCHK(make_acc_config(P, cand[k].first, cand[k].second, cfg[k], mem[k]));
+    HIPCHK(launch_accumulate_config(P, cfg[k], spec, bout, nullptr));
+    HIPCHK(hipEventRecord(e0, nullptr));
+    for (int r = 0; r < 3; ++r) HIPCHK(launch_accumulate_config(P, cfg[k], spec, bout, nullptr));
+    HIPCHK(hipEventRecord(e1, nullptr));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_k = k;
+    }
+  }
+  for (size_t k = 0; k < cand.size(); ++k)
+    for (void* a : mem[k]) (k == best_k ? P->allocations : owned).push_back(a);
+  P->acc = cfg[best_k];
+  P->acc.tuned = 1;
+  return ARKCOS_OK;
 }
 
 int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count) {

@@ -21,6 +21,11 @@ struct ProfileDev {
   double h, theta_max;
   const double* knots;
   const double* mom;
+  // the biased linear table of Sect. 4.1 (kernel_eval = 1): T[k] =
+  // K(2 asin(sqrt(u_k) / 2)) at u_k = k du, k < tn, du = u(radius) / (tn - 1)
+  const double* utab;
+  int32_t tn;
+  double du, umax;
 };
 
 __device__ __forceinline__ double profile_eval(const ProfileDev& P, double t) {
@@ -34,32 +39,60 @@ __device__ __forceinline__ double profile_eval(const ProfileDev& P, double t) {
          h2 * ((v * v * v - v) * P.mom[a] + (u * u * u - u) * P.mom[a + 1]);
 }
 
-// Distance between (theta_i, 0) and (theta_j, nu) with nu = pi * num / den.
-__device__ __forceinline__ double ring_distance(double ti, double tj, double si, double sj,
-                                                int64_t num, int64_t den) {
+// Haversine of the distance between (theta_i, 0) and (theta_j, nu) with
+// nu = pi * num / den: hav = sin^2(theta / 2).
+__device__ __forceinline__ double ring_hav(double ti, double tj, double si, double sj, int64_t num, int64_t den) {
   double a = sin(0.5 * (ti - tj));
   double b = sinpi(0.5 * (double)num / (double)den);
-  double hav = a * a + si * sj * b * b;
-  double r = sqrt(hav);
-  return 2.0 * asin(r < 1.0 ? r : 1.0);
+  return a * a + si * sj * b * b;
+}
+
+// K at the sample of haversine hav: from the exact distance
+// theta = 2 asin(sqrt(hav)), or, with the table of Sect. 4.1, by linear
+// interpolation in the squared chord u = 2 (1 - cos theta) = 4 hav.
+__device__ __forceinline__ double kernel_at(const ProfileDev& P, double hav) {
+  if (P.utab) {
+    const double u = 4.0 * hav;
+    if (u > P.umax) return 0.0;
+    const double x = u / P.du;
+    int k = (int)floor(x);
+    k = k < 0 ? 0 : (k > P.tn - 2 ? P.tn - 2 : k);
+    const double f = x - (double)k;
+    return fma(f, P.utab[k + 1] - P.utab[k], P.utab[k]);
+  }
+  const double r = sqrt(hav);
+  return profile_eval(P, 2.0 * asin(r < 1.0 ? r : 1.0));
+}
+
+// Fills the table of the biased kernel evaluation (kernel_eval = 1).
+__global__ void __launch_bounds__(kBlock) utable_kernel(ProfileDev prof, double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= prof.tn) return;
+  // the last node sits at the support radius itself
+  const double r = 0.5 * sqrt((double)k * prof.du);
+  out[k] = profile_eval(prof, k == prof.tn - 1 ? prof.radius : 2.0 * asin(r < 1.0 ? r : 1.0));
 }
 
 // Node d of pair q: nu_d / pi = 2 (d + s/2) / (p L) = (2d + s) / (p L).
+// Every sample of the pair's window is written (at coef_off[q]); abs_sum
+// (optional) receives the sum of their magnitudes.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) kernel_rows_kernel(
     const PairDev* __restrict__ pairs, const int32_t* __restrict__ pair_i,
-    const int32_t* __restrict__ pair_shift, const double* __restrict__ theta,
+    const int32_t* __restrict__ pair_shift, const int64_t* __restrict__ coef_off,
+    const int32_t* __restrict__ ncoef_window, const double* __restrict__ theta,
     const double* __restrict__ sint, const double* __restrict__ w, int64_t L, ProfileDev prof,
     double* __restrict__ coef64, R* __restrict__ coef, double* __restrict__ abs_sum) {
   const int q = blockIdx.x;
-  const PairDev pr = pairs[q];
+  PairDev pr = pairs[q];
+  pr.off = coef_off[q];
+  pr.ncoef = ncoef_window[q];
   const int i = pair_i[q], j = pr.j, s = pair_shift[q];
   const int64_t pl = (int64_t)pr.grid;
   const double ti = theta[i], tj = theta[j], si = sint[i], sj = sint[j];
   double part = 0.0;
   for (int d = threadIdx.x; d < pr.ncoef; d += blockDim.x) {
-    double t = ring_distance(ti, tj, si, sj, 2 * (int64_t)d + s, pl);
-    double g = w[j] * profile_eval(prof, t);
+    double g = w[j] * kernel_at(prof, ring_hav(ti, tj, si, sj, 2 * (int64_t)d + s, pl));
     double c = 2.0;
     if (s == 0 && (d == 0 || 2 * (int64_t)d == pl)) c = 1.0;
     double a = c * g / (double)pl;
@@ -67,6 +100,7 @@ __global__ void __launch_bounds__(kBlock) kernel_rows_kernel(
     coef[pr.off + d] = (R)a;
     part += fabs(a);
   }
+  if (!abs_sum) return;
   __shared__ double red[kBlock];
   red[threadIdx.x] = part;
   __syncthreads();
@@ -199,20 +233,33 @@ static ProfileDev make_profile(arkcos_plan_s* P) {
   pd.h = pd.nk > 1 ? P->theta_max / (pd.nk - 1) : 0.0;
   pd.knots = P->d_knots;
   pd.mom = P->d_spline_mom;
+  if (P->d_utable) {
+    pd.utab = P->d_utable;
+    pd.tn = P->utable_n;
+    const double sh = sin(0.5 * pd.radius);
+    pd.umax = 4.0 * sh * sh;
+    pd.du = pd.umax / (double)(pd.tn - 1);
+  }
   return pd;
 }
 
 hipError_t launch_kernel_rows(arkcos_plan_s* P, double* abs_sum, hipStream_t s) {
   if (P->n_pairs == 0) return hipSuccess;
   ProfileDev pd = make_profile(P);
+  if (P->d_utable) {
+    // the table from the current profile first (same stream)
+    ProfileDev tp = pd;
+    tp.utab = nullptr;
+    utable_kernel<<<(unsigned)((pd.tn + kBlock - 1) / kBlock), kBlock, 0, s>>>(tp, P->d_utable);
+  }
   if (P->dtype == ARKCOS_F32)
     kernel_rows_kernel<float><<<(unsigned)P->n_pairs, kBlock, 0, s>>>(
-        P->d_pairs, P->d_pair_i, P->d_pair_shift, P->d_theta, P->d_sin, P->rt.w, P->L, pd,
-        P->d_coef64, (float*)P->d_coef, abs_sum);
+        P->d_pairs, P->d_pair_i, P->d_pair_shift, P->d_coef_off, P->d_ncoef_window, P->d_theta, P->d_sin,
+        P->rt.w, P->L, pd, P->d_coef64, (float*)P->d_coef, abs_sum);
   else
     kernel_rows_kernel<double><<<(unsigned)P->n_pairs, kBlock, 0, s>>>(
-        P->d_pairs, P->d_pair_i, P->d_pair_shift, P->d_theta, P->d_sin, P->rt.w, P->L, pd,
-        P->d_coef64, (double*)P->d_coef, abs_sum);
+        P->d_pairs, P->d_pair_i, P->d_pair_shift, P->d_coef_off, P->d_ncoef_window, P->d_theta, P->d_sin,
+        P->rt.w, P->L, pd, P->d_coef64, (double*)P->d_coef, abs_sum);
   return hipGetLastError();
 }
 

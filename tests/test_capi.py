@@ -68,7 +68,10 @@ def test_host_argument_checks(lib):
         (good_g, good_p, 0.1, 0, ak.Options(3, 0, 1, -1.0), "oversample"),
         (good_g, good_p, 0.1, 0, ak.Options(2, 5, 1, -1.0), "kgen"),
         (good_g, good_p, 0.1, 0, ak.Options(2, 0, 1, -1.0, 2, 0), "mode"),
-        (good_g, good_p, 0.1, 0, ak.Options(2, 0, 1, -1.0, 0, 1), "reserved"),
+        (good_g, good_p, 0.1, 0, ak.Options(2, 0, 1, -1.0, 0, 2), "own_grid"),
+        (good_g, good_p, 0.1, 0, ak.Options(2, 0, 1, -1.0, 0, 0, 3), "kernel_eval"),
+        (good_g, good_p, 0.1, 0, ak.Options(2, 0, 1, -1.0, 0, 0, 1, 1), "table_nodes"),
+        (good_g, good_p, 0.1, 0, ak.Options(2, 0, 1, -1.0, 0, 0, 0, 0, (0, 0, 1, 0)), "reserved"),
     ]
     for g, p, r, dt, o, word in cases:
         st, msg, h = _plan_status(lib, g, p, r, dt, o)
@@ -82,6 +85,7 @@ def test_host_argument_checks(lib):
 
 def test_default_options(lib):
     from paper_1104_0672_amd import arkcos as ak
-    o = ak.Options(9, 9, 9, 9.0, 9, 9)
+    o = ak.Options(9, 9, 9, 9.0, 9, 9, 9, 9, (9, 9, 9, 9))
     lib.arkcos_default_options(ctypes.byref(o))
-    assert (o.oversample, o.kgen, o.fix_pole_pixels, o.band_tol, o.mode, o.reserved) == (0, 0, 1, -1.0, 0, 0)
+    assert (o.oversample, o.kgen, o.fix_pole_pixels, o.band_tol, o.mode, o.own_grid, o.kernel_eval,
+            o.table_nodes, tuple(o.reserved)) == (0, 0, 1, -1.0, 0, 0, 0, 0, (0, 0, 0, 0))

@@ -135,4 +135,4 @@ def test_batch_autotune_cache(tmp_path):
     finally:
         del os.environ["ARKCOS_AUTOTUNE_CACHE"]
     assert b1.info.tuned == 1 and b2.info.tuned == 2
-    assert (b1.info.units_per_band, b1.info.grid) == (b2.info.units_per_band, b2.info.grid)
+    assert (b1.info.seg_units, b1.info.group, b1.info.grid) == (b2.info.seg_units, b2.info.group, b2.info.grid)

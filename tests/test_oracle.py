@@ -501,3 +501,97 @@ def test_default_mode_adjoint_is_transpose():
         a = np.dot(oracle.hybrid(g, prof, R, x, oversample=2, fix_poles=fix, mode="default"), y)
         b = np.dot(x, oracle.hybrid_adjoint(g, prof, R, y, oversample=2, fix_poles=fix, mode="default"))
         assert abs(a - b) < 1e-12 * abs(a), (fix, a, b)
+
+
+# --------------------------- the suppression as Sect. 4.3 states it (equatorial own grid)
+
+def test_equatorial_own_grid_is_exact_in_the_belt_and_converges_in_caps():
+    """own_grid="equatorial": only pairs of equatorial rings use the true
+    pixel offsets (Sect. 4.3 as stated).  Output rings of the belt keep the
+    same pairs as the equal-length extension (identical values, exact where
+    their support stays in the belt); polar rings pair with themselves on the
+    p L grid instead, which converges to the direct sum as p grows."""
+    nside = 16
+    g = W.Grid("healpix", nside=nside)
+    pix = math.sqrt(math.pi / 3) / nside
+    prof, R = _gauss(2.5 * pix), 7.5 * pix
+    x = np.random.default_rng(51).standard_normal(g.npix)
+    yd = oracle.direct(g, prof, R, x)
+    th, ph0, w, n, st = oracle.rings(g)
+    belt = np.concatenate([st[i] + np.arange(n[i]) for i in range(len(th)) if n[i] == 4 * nside])
+    caps = np.setdiff1d(np.arange(g.npix), belt)
+    eq_sup = [i for i in range(len(th)) if np.all(n[np.abs(th - th[i]) <= R + 1e-6] == 4 * nside)]
+    sel = np.concatenate([st[i] + np.arange(n[i]) for i in eq_sup])
+    err = []
+    for p in (1, 2, 4, 8):
+        ye = oracle.hybrid(g, prof, R, x, oversample=p, fix_poles=False, own_grid="equatorial")
+        yl = oracle.hybrid(g, prof, R, x, oversample=p, fix_poles=False, own_grid="equal_length")
+        assert np.abs(ye[belt] - yl[belt]).max() <= 1e-15 * np.abs(yd).max()
+        assert np.abs(ye[sel] - yd[sel]).max() < 1e-13 * np.abs(yd).max()
+        if p == 1:
+            # the self pair of a polar ring is the only difference, and it shows
+            assert np.abs(ye[caps] - yl[caps]).max() > 1e-6 * np.abs(yd).max()
+        err.append(np.linalg.norm(ye[caps] - yd[caps]) / np.linalg.norm(yd[caps]))
+    assert err[0] > 1e-5 and err[1] < 1e-2 * err[0] and err[3] < 1e-10, err
+    # the transpose and the pairing agree with the plan's listing
+    plan = oracle.pair_plan(g, R, 2, own_grid="equatorial")
+    for i, pairs in enumerate(plan):
+        for (j, G, s) in pairs:
+            assert (G == n[i]) == (n[i] == n[j] == 4 * nside)
+    rng = np.random.default_rng(52)
+    a, b = rng.standard_normal(g.npix), rng.standard_normal(g.npix)
+    lhs = np.dot(oracle.hybrid(g, prof, R, a, oversample=2, own_grid="equatorial"), b)
+    rhs = np.dot(a, oracle.hybrid_adjoint(g, prof, R, b, oversample=2, own_grid="equatorial"))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+# ------------------------------------ the biased linear kernel table (Sect. 4.1)
+
+def test_chord_table_kernel_nodes_linearity_and_error_bound():
+    """The table of Sect. 4.1 holds K at nodes uniform in the squared chord
+    u = 2 (1 - cos t); between nodes it is linear in u.  Its error is at most
+    du^2 / 8 max |d^2 K / du^2| (linear interpolation), checked on a Gaussian
+    whose u-derivatives follow from K = exp(-t^2 / 2 s^2), t = 2 asin(sqrt(u) / 2)."""
+    from oracle.hybrid import chord_table_kernel
+    fwhm = 0.02
+    s = fwhm / math.sqrt(8 * math.log(2))
+    R = 3 * fwhm
+    prof = _gauss(fwhm)
+    nodes = 257
+    f = chord_table_kernel(prof, R, nodes)
+    umax = 4 * math.sin(0.5 * (R + 1e-9)) ** 2
+    du = umax / (nodes - 1)
+    uk = np.arange(nodes - 1) * du
+    tk = 2 * np.arcsin(0.5 * np.sqrt(uk))
+    assert np.abs(f(tk) - np.exp(-tk ** 2 / (2 * s * s))).max() < 1e-14
+    # midpoints in u: the average of the neighbouring nodes
+    um = (np.arange(nodes - 1) + 0.5) * du
+    tm = 2 * np.arcsin(0.5 * np.sqrt(um))
+    kn = np.exp(-(2 * np.arcsin(0.5 * np.sqrt(np.arange(nodes) * du))) ** 2 / (2 * s * s))
+    kn[-1] = math.exp(-(R + 1e-9) ** 2 / (2 * s * s))
+    assert np.abs(f(tm) - 0.5 * (kn[:-1] + kn[1:])).max() < 1e-14
+    # error bound from the second derivative in u (finite differences of the
+    # closed form on a fine grid)
+    uf = np.linspace(0, umax, 200001)
+    kf = np.exp(-(2 * np.arcsin(0.5 * np.sqrt(uf))) ** 2 / (2 * s * s))
+    d2 = np.abs(np.diff(kf, 2)).max() / (uf[1] - uf[0]) ** 2
+    tf = 2 * np.arcsin(0.5 * np.sqrt(uf))
+    err = np.abs(f(tf) - kf).max()
+    assert err <= 1.01 * du * du / 8 * d2 and err > 0.05 * du * du / 8 * d2
+    assert f(np.array([R + 1e-6]))[0] == 0.0
+
+
+def test_hybrid_with_chord_table_converges_at_second_order():
+    g = W.Grid("healpix", nside=8)
+    pix = math.sqrt(math.pi / 3) / 8
+    prof, R = _gauss(2.5 * pix), 7.5 * pix
+    x = np.random.default_rng(53).standard_normal(g.npix)
+    ye = oracle.hybrid(g, prof, R, x, oversample=2)
+    errs = []
+    nodes = (256, 1024, 4096)
+    for n in nodes:
+        yt = oracle.hybrid(g, prof, R, x, oversample=2, kernel_eval="table", table_nodes=n)
+        errs.append(np.linalg.norm(yt - ye) / np.linalg.norm(ye))
+    # error ~ nodes^-2: a factor 16 per factor 4 in nodes (12 .. 20 allowed)
+    for a, b in zip(errs, errs[1:]):
+        assert 12.0 < a / b < 20.0, errs

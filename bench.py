@@ -226,9 +226,17 @@ def cpu_baseline(w, x, budget_s: float):
         if dt >= budget_s / 4 or n >= w.grid.npix:
             break
         n = min(w.grid.npix, int(n * max(2.0, min(16.0, budget_s / 4 / max(dt, 1e-3)))))
+    # the same oracle on one core, beside the paper's one-core figures
+    n1 = max(64, n // max(threads, 1))
+    idx1 = np.sort(np.random.default_rng(98).choice(w.grid.npix, size=n1, replace=False))
+    t0 = time.perf_counter()
+    oracle.direct(w.grid, w.profile, w.radius, x, idx=idx1, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": n / dt, "unit": "pixels/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} random output pixels of the nside-2048 map (FP64 direct sum, "
-                      f"{dt:.1f} s wall), throughput extrapolated per pixel"}
+                      f"{dt:.1f} s wall), throughput extrapolated per pixel",
+            "single_core": {"value": n1 / dt1, "unit": "pixels/s", "cores": 1,
+                            "sample": f"{n1} random output pixels, {dt1:.1f} s wall"}}
 
 
 def time_form(plan, fn, x, y, steps, warmup):
@@ -266,7 +274,7 @@ def bench_batch(n_maps: int, steps: int, dev):
     plan_s = time.perf_counter() - t0
     info = batch.info
     npix = int(info.npix_total)
-    log(f"bench: batch plans {plan_s:.1f} s, {info.n_items} items, {info.seg_units} units/segment in groups of {info.group}, "
+    log(f"bench: batch plans {plan_s:.1f} s, {info.n_items} items, {info.seg_units} units per band, "
         f"grid {info.grid}, {npix / 1e9:.2f} Gpix, workspace {info.workspace_bytes / 2**30:.1f} GiB")
     xs = []
     for w in wl:
@@ -358,6 +366,53 @@ def bench_spline(steps: int, dev):
     return out
 
 
+def bench_shared(n_kernels: int, steps: int, dev):
+    """Shared-input form (an asymmetric beam split into symmetric kernels):
+    the nside-2048 input map convolved with n_kernels Gaussian kernels of
+    FWHM 4' .. 13' (each cut at 3 FWHM) through one set of input spectra,
+    against the same n_kernels convolutions run one plan at a time."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1104_0672_amd import Batch, Plan
+
+    w = W.healpix2048()
+    fwhms = np.linspace(4.0, 13.0, n_kernels)
+    t0 = time.perf_counter()
+    plans = [Plan("healpix", 3.0 * f * W.ARCMIN, nside=2048, fwhm=f * W.ARCMIN) for f in fwhms]
+    batch = Batch(plans, shared_input=True)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    x = torch.tensor(W.make_input(w), dtype=torch.float32, device=dev)
+    ys = [torch.empty_like(x) for _ in plans]
+    ws = batch.workspace()
+    out = {"workload": f"healpix2048, {n_kernels} Gaussian kernels FWHM {fwhms[0]:g}'..{fwhms[-1]:g}', R = 3 FWHM",
+           "n_kernels": n_kernels, "plan_seconds": round(plan_s, 2),
+           "workspace_bytes": int(batch.workspace_bytes)}
+
+    def run_shared():
+        batch.convolve_shared(x, outs=ys, ws=ws)
+
+    def run_separate():
+        for p, y in zip(plans, ys):
+            p.convolve(x, out=y)
+
+    for name, fn in (("shared_input", run_shared), ("one_plan_at_a_time", run_separate)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        out[name] = {"ms": round(ms, 3), "output_pixels_per_s": n_kernels * x.numel() / (ms * 1e-3)}
+        log(f"bench: {n_kernels} kernels, {name}: {ms:.3f} ms")
+    del batch, plans, ws, ys
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,6 +423,8 @@ def main():
     ap.add_argument("--batch-maps", type=int, default=256, help="maps in the batched form (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--spline-steps", type=int, default=5, help="spline-kernel forward and gradient (0: skip)")
+    ap.add_argument("--shared-kernels", type=int, default=10,
+                    help="kernels of the shared-input form (an asymmetric beam's components; 0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a device copy of this size first (for counter calibration)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -465,6 +522,10 @@ def main():
     if args.spline_steps > 0:
         log("bench: spline kernel, nside 1024")
         forms["spline"] = bench_spline(args.spline_steps, dev)
+    forms["shared_input"] = None
+    if args.shared_kernels > 0:
+        log(f"bench: shared-input form, {args.shared_kernels} kernels")
+        forms["shared_input"] = bench_shared(args.shared_kernels, max(3, args.steps // 4), dev)
     forms["batched"] = None
     if args.batch_maps > 0:
         forms["batched"] = bench_batch(args.batch_maps, args.batch_steps, dev)

@@ -150,10 +150,11 @@ typedef struct {
                                [0] Clenshaw recurrence on the centred grid,
                                [1] Clenshaw on the half-shifted own grid,
                                [2] precomputed table, [3] Reinsch's recurrence */
-  int32_t acc_seg_units;    /* accumulation: output units per work item */
-  int32_t acc_group;        /* units summed at a time (wavefronts per workgroup) */
-  int32_t acc_window;       /* input rings held in the LDS window (0: read from memory) */
-  int32_t acc_tuned;        /* 1: chosen by timing at plan creation */
+  int32_t acc_seg_units;    /* accumulation: output units (rings with their mirrors) per work item */
+  int32_t acc_group;        /* wavefronts per accumulation workgroup (one per unit) */
+  int32_t acc_window;       /* widest input-ring window of a work item's units */
+  int32_t acc_tuned;        /* 1: shape chosen by timing at plan creation, 0: fixed */
+  double support_radius_rad; /* R of the plan (given, or chosen by arkcos_plan_for_error) */
 } arkcos_plan_info_t;
 
 /* Fill *opts with the defaults (oversample 0, kgen 0, fix_pole_pixels 1,
@@ -167,6 +168,21 @@ void arkcos_default_options(arkcos_options_t* opts);
 arkcos_status_t arkcos_plan(const arkcos_geometry_t* geom, const arkcos_profile_t* profile,
                             double support_radius_rad, arkcos_dtype_t dtype,
                             const arkcos_options_t* opts, arkcos_plan_t* out);
+
+/* arkcos_plan with the support radius chosen from a bound on the truncation
+ * error instead of given (paper Sect. 4: the error of cutting the kernel at
+ * R, sigma^2(R) below, is what fixes R).  R is the radius
+ * arkcos_choose_radius(profile, cl, lmax, target_sigma2) returns: the
+ * smallest radius whose truncation variance for the power spectrum cl[0..lmax]
+ * (host array) is at most target_sigma2.  The plan is then built exactly as
+ * arkcos_plan(geom, profile, R, dtype, opts) builds it.  radius_rad (host,
+ * may be NULL) receives R.  Errors: those of the two calls; and
+ * ARKCOS_ERR_NOT_SUPPORTED when the target holds without any support (R = 0),
+ * since an empty kernel needs no plan.  Blocks the host like arkcos_plan. */
+arkcos_status_t arkcos_plan_for_error(const arkcos_geometry_t* geom, const arkcos_profile_t* profile,
+                                      const double* cl, int32_t lmax, double target_sigma2,
+                                      arkcos_dtype_t dtype, const arkcos_options_t* opts,
+                                      arkcos_plan_t* out, double* radius_rad);
 
 arkcos_status_t arkcos_plan_destroy(arkcos_plan_t plan);
 arkcos_status_t arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info_t* info);
@@ -248,6 +264,24 @@ arkcos_status_t arkcos_batch_workspace_size(arkcos_batch_t batch, size_t* bytes)
  * a forward and a transpose, in one graph). */
 arkcos_status_t arkcos_batch_convolve(arkcos_batch_t batch, const void* const* x, void* const* y,
                                       int32_t adjoint, void* ws, hipStream_t stream);
+/* Shared-input form: one map convolved with n kernels on one geometry,
+ * y[i] = C_i x.  This is how an asymmetric beam is applied when it is split
+ * into a few symmetric kernels (paper Sect. 5, on the ASYMFAST approach):
+ * the input's extended spectra (step a) are computed once and every kernel's
+ * ring-pair accumulation (steps b, c) reads them; the accumulation runs as
+ * one persistent launch over all kernels and the inverse transforms (step d)
+ * batched over them.  The plans must share dtype, device, geometry and
+ * fix_pole_pixels (kernels, radii, oversampling and the other options may
+ * differ).  Each y[i] equals arkcos_convolve of plan i on x bit for bit.
+ * Created like arkcos_batch_plan (autotuned, blocks the host); its workspace
+ * holds one set of input spectra.  The batch is used with
+ * arkcos_batch_convolve_shared only (arkcos_batch_convolve rejects it).
+ * x: device, the one input map; y: host array of n device pointers; no y[i]
+ * may overlap x.  Forward only: the transpose of the stacked map is the sum
+ * of the per-kernel transposes, available through an ordinary batch. */
+arkcos_status_t arkcos_batch_plan_shared_input(int32_t n, const arkcos_plan_t* plans, arkcos_batch_t* out);
+arkcos_status_t arkcos_batch_convolve_shared(arkcos_batch_t batch, const void* x, void* const* y, void* ws,
+                                             hipStream_t stream);
 /* Stage timing of batch calls, as arkcos_plan_timing / arkcos_stage_times
  * (stage 1 is the persistent accumulation launch). */
 arkcos_status_t arkcos_batch_timing(arkcos_batch_t batch, int32_t max_calls);

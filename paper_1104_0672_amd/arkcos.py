@@ -51,7 +51,7 @@ class PlanInfo(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t),
                 ("plan_bytes", ctypes.c_size_t), ("pairs_by_kind", ctypes.c_int64 * 4),
                 ("acc_seg_units", ctypes.c_int32), ("acc_group", ctypes.c_int32), ("acc_window", ctypes.c_int32),
-                ("acc_tuned", ctypes.c_int32)]
+                ("acc_tuned", ctypes.c_int32), ("support_radius_rad", ctypes.c_double)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -66,7 +66,8 @@ EXPORTED = ["arkcos_default_options", "arkcos_plan", "arkcos_plan_destroy", "ark
             "arkcos_set_knots", "arkcos_set_knots_async", "arkcos_batch_plan", "arkcos_batch_get_info", "arkcos_batch_workspace_size",
             "arkcos_batch_convolve", "arkcos_batch_timing", "arkcos_batch_stage_times", "arkcos_batch_destroy",
             "arkcos_plan_timing", "arkcos_stage_times", "arkcos_status_string", "arkcos_last_error",
-            "arkcos_truncation_variance", "arkcos_choose_radius"]
+            "arkcos_truncation_variance", "arkcos_choose_radius", "arkcos_plan_for_error",
+            "arkcos_batch_plan_shared_input", "arkcos_batch_convolve_shared"]
 
 _lib = None
 
@@ -85,6 +86,10 @@ def load_library(path: str = LIB_PATH):
     lib.arkcos_default_options.restype = None
     lib.arkcos_plan.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(ProfileC), dbl, i32,
                                 ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    lib.arkcos_plan_for_error.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(ProfileC),
+                                          ctypes.POINTER(ctypes.c_double), i32, dbl, i32,
+                                          ctypes.POINTER(Options), ctypes.POINTER(vp),
+                                          ctypes.POINTER(ctypes.c_double)]
     lib.arkcos_plan_destroy.argtypes = [vp]
     lib.arkcos_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.arkcos_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -96,6 +101,8 @@ def load_library(path: str = LIB_PATH):
     lib.arkcos_batch_plan.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     lib.arkcos_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.arkcos_batch_convolve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, vp]
+    lib.arkcos_batch_plan_shared_input.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.arkcos_batch_convolve_shared.argtypes = [vp, vp, ctypes.POINTER(vp), vp, vp]
     lib.arkcos_batch_destroy.argtypes = [vp]
     lib.arkcos_batch_get_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
     lib.arkcos_batch_timing.argtypes = [vp, i32]
@@ -111,7 +118,7 @@ def load_library(path: str = LIB_PATH):
     lib.arkcos_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         f = getattr(lib, name)
-        if f.restype is ctypes.c_int or name in ("arkcos_plan", "arkcos_plan_destroy"):
+        if f.restype is ctypes.c_int or name in ("arkcos_plan", "arkcos_plan_destroy", "arkcos_plan_for_error"):
             f.restype = st
     _lib = lib
     return lib
@@ -134,14 +141,17 @@ class Plan:
     """A convolution plan: geometry, kernel profile, support radius, dtype.
 
     Maps are 1-D torch tensors on the plan's device with npix elements
-    (RING order) of the plan's dtype.
+    (RING order) of the plan's dtype.  With radius=None the support radius
+    is chosen from a truncation-error target instead (arkcos_plan_for_error):
+    the smallest R whose error variance for the power spectrum `cl` is at
+    most `target_sigma2`; it is then `info.support_radius_rad`.
     """
 
-    def __init__(self, grid: str, radius: float, *, nside: int = 0, ntheta: int = 0, nphi: int = 0,
+    def __init__(self, grid: str, radius: Optional[float], *, nside: int = 0, ntheta: int = 0, nphi: int = 0,
                  fwhm: float = 0.0, knots: Optional[Sequence[float]] = None, theta_max: float = 0.0,
                  dtype: str = "f32", oversample: int = 0, kgen: int = 0, fix_pole_pixels: bool = True,
                  band_tol: float = -1.0, mode: str = "suppressed", own_grid: str = "equal_length",
-                 kernel_eval: str = "exact", table_nodes: int = 0):
+                 kernel_eval: str = "exact", table_nodes: int = 0, cl=None, target_sigma2: Optional[float] = None):
         lib = load_library()
         self._lib = lib
         self.handle = ctypes.c_void_p()
@@ -164,9 +174,19 @@ class Plan:
                        1 if kernel_eval == "table" else 0, int(table_nodes))
         self.dtype = torch.float32 if dtype == "f32" else torch.float64
         self.grid = grid
-        _check(lib.arkcos_plan(ctypes.byref(geom), ctypes.byref(prof), float(radius),
-                               F32 if dtype == "f32" else F64, ctypes.byref(opts),
-                               ctypes.byref(self.handle)), "arkcos_plan")
+        if radius is None:
+            if cl is None or target_sigma2 is None:
+                raise ArkcosError("radius=None needs cl and target_sigma2")
+            c = np.ascontiguousarray(cl, dtype=np.float64)
+            _check(lib.arkcos_plan_for_error(ctypes.byref(geom), ctypes.byref(prof),
+                                             c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), c.size - 1,
+                                             float(target_sigma2), F32 if dtype == "f32" else F64,
+                                             ctypes.byref(opts), ctypes.byref(self.handle), None),
+                   "arkcos_plan_for_error")
+        else:
+            _check(lib.arkcos_plan(ctypes.byref(geom), ctypes.byref(prof), float(radius),
+                                   F32 if dtype == "f32" else F64, ctypes.byref(opts),
+                                   ctypes.byref(self.handle)), "arkcos_plan")
         self.device = torch.device("cuda", torch.cuda.current_device())
         info = PlanInfo()
         _check(lib.arkcos_plan_get_info(self.handle, ctypes.byref(info)), "arkcos_plan_get_info")
@@ -319,15 +339,22 @@ def choose_radius(cl, target_sigma2: float, *, fwhm: float = 0.0, knots=None, th
 
 class Batch:
     """Many plans (same dtype) convolved together: batched ring transforms and
-    one persistent accumulation launch over a shared work queue."""
+    one persistent accumulation launch over a shared work queue.  With
+    shared_input=True the plans share one geometry and one input map
+    (convolve_shared): its spectra are computed once for every kernel."""
 
-    def __init__(self, plans: Sequence[Plan]):
+    def __init__(self, plans: Sequence[Plan], shared_input: bool = False):
         lib = load_library()
         self._lib = lib
         self.plans = list(plans)
+        self.shared_input = bool(shared_input)
         arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
         self.handle = ctypes.c_void_p()
-        _check(lib.arkcos_batch_plan(len(self.plans), arr, ctypes.byref(self.handle)), "arkcos_batch_plan")
+        if self.shared_input:
+            _check(lib.arkcos_batch_plan_shared_input(len(self.plans), arr, ctypes.byref(self.handle)),
+                   "arkcos_batch_plan_shared_input")
+        else:
+            _check(lib.arkcos_batch_plan(len(self.plans), arr, ctypes.byref(self.handle)), "arkcos_batch_plan")
         info = BatchInfo()
         _check(lib.arkcos_batch_get_info(self.handle, ctypes.byref(info)), "arkcos_batch_get_info")
         self.info = info
@@ -367,6 +394,22 @@ class Batch:
         ya = (ctypes.c_void_p * len(ys))(*[y.data_ptr() for y in ys])
         _check(self._lib.arkcos_batch_convolve(self.handle, xa, ya, 1 if adjoint else 0, ctypes.c_void_p(addr),
                                                _stream_ptr(stream)), "arkcos_batch_convolve")
+        return ys
+
+    def convolve_shared(self, x: torch.Tensor, outs: Optional[Sequence[torch.Tensor]] = None, ws=None,
+                        stream=None):
+        """y[i] = C_i x for every plan i of a shared-input batch."""
+        x = self.plans[0]._map(x, "x")
+        ys = [torch.empty_like(x) for _ in self.plans] if outs is None else \
+            [p._map(y, f"out[{i}]") for i, (p, y) in enumerate(zip(self.plans, outs))]
+        wst = self.workspace() if ws is None else ws
+        addr = (wst.data_ptr() + 255) // 256 * 256
+        if addr + self.workspace_bytes > wst.data_ptr() + wst.numel():
+            raise ArkcosError("workspace too small")
+        ya = (ctypes.c_void_p * len(ys))(*[y.data_ptr() for y in ys])
+        _check(self._lib.arkcos_batch_convolve_shared(self.handle, ctypes.c_void_p(x.data_ptr()), ya,
+                                                      ctypes.c_void_p(addr), _stream_ptr(stream)),
+               "arkcos_batch_convolve_shared")
         return ys
 
     def start_timing(self, max_calls: int):

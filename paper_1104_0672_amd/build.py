@@ -1,7 +1,8 @@
 """Builds libarkcos.so (HIP for gfx950) in-tree with hipcc.
 
-Every HIP translation unit is compiled with packed-FP32 instructions turned
-off; host code goes through the same hipcc driver.  Objects land in
+Every source, .hip and .cpp alike, is compiled as HIP for gfx950 with
+packed-FP32 instructions turned off (a .cpp file compiled without the target
+would carry device code for hipcc's default target only).  Objects land in
 ``paper_1104_0672_amd/_build`` and the shared library next to this file.
 """
 from __future__ import annotations
@@ -34,10 +35,10 @@ def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
     cmd = [HIPCC] + COMMON
-    if src.endswith(".hip"):
-        cmd += ["-x", "hip"] + HIP_FLAGS
-    else:
-        cmd += ["-D__HIP_PLATFORM_AMD__"]
+    # every source as HIP for gfx950: hipcc would otherwise build the device
+    # code of a .cpp file (kernels, device helpers it includes) for its
+    # default target, which has no code object on the MI355X
+    cmd += ["-x", "hip"] + HIP_FLAGS
     cmd += ["-c", path, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

@@ -1,22 +1,14 @@
 // Step (c) of the hybrid method (paper Sect. 4.1): for every output ring i
 //   B_i(m) = sum_{j in support(i)} K_ij(m) A~_j(m)
-// with K_ij(m) (step b) read from the plan's precomputed tables or produced
-// on the fly from the FP64-derived kernel samples of the pair by a
-// Chebyshev recurrence.  An output unit is a ring together with its
+// with K_ij(m) produced on the fly from the FP64-derived kernel samples of
+// the pair by a Chebyshev recurrence (step b), or read from a precomputed
+// table for wide pairs.  An output unit is a ring together with its
 // north/south mirror (the mirrored pair has the same K_ij(m), as in the
-// paper's ring-reduction kernel that treats both hemispheres at once).
-//
-// Sweep: a work item owns one tile of kSweepTile modes (one per lane) and a
-// segment of consecutive units, which it sweeps G units at a time (one
-// wavefront per unit).  The input rings inside the support of the current
-// units sit in an LDS ring buffer (slot j mod cap: the spectrum tile of ring
-// j and of its mirror); moving to the next group only loads the rings that
-// enter the support, so a spectrum tile is read about once per segment, not
-// once per unit.  The rows of the next group are loaded into registers while
-// the current group is summed.  Each unit sums its pairs in list order
-// (table pairs first, their loads issued in batches, then the recurrence
-// pairs), one lane per mode, with no atomics: the result does not depend on
-// the segment or group size, and it is deterministic.
+// paper's ring-reduction kernel that treats both hemispheres at once).  A
+// work item is a band of consecutive units (one wavefront each) and a run of
+// mode tiles; a lane owns kModesPerLane modes of a tile, so spectrum loads
+// and B stores are coalesced and no atomics are needed: the sum over j runs
+// in a fixed order, so results are deterministic.
 #include "arkcos_internal.h"
 #include "device_common.h"
 
@@ -28,7 +20,7 @@ template <typename R> struct AccArgs {
   const UnitDev* units;
   const PairDev* pairs;
   const WorkItem* items;
-  const SegDev* segs;
+  const BandDev* bands;
   const int64_t* spec_off;
   const int32_t* spec_len;
   const int64_t* out_off;
@@ -40,7 +32,6 @@ template <typename R> struct AccArgs {
   int32_t nrings;
   int32_t L;
   int32_t p;
-  int32_t cap;         // ring slots of the LDS window
 };
 
 // (cos, sin) of pi m / den: from the twiddle table when 2 den divides its
@@ -55,6 +46,9 @@ __device__ __forceinline__ cx_t<R> half_angle(int m, int den, const cx_t<R>* __r
   const int r = (int)((uint32_t)m % (2u * (uint32_t)den));
   return expipi<R>(r, den);
 }
+
+constexpr int kModesPerLane = kAccTile / 64;
+constexpr int kTableGroup = 2;     // table pairs whose values are loaded together
 
 // Per-mode constants of the two kernel grids a unit's pairs use at mode m
 // (the output ring's own length N_i for equal-length pairs, the fine grid
@@ -83,16 +77,33 @@ __device__ __forceinline__ ModeConst<R> mode_const(int m, int Ni, int pl, const 
   return k;
 }
 
-// A pair's descriptor with wave-uniform fields: meta = kind << 24 | own
-// grid << 26.
+// A pair as staged in LDS for one work item.
+struct PairLds {
+  uint32_t meta;   // row (j - jlo) | kind << 24 | own grid << 26
+  int32_t band;
+  int32_t ncoef;
+  uint32_t off;    // coefficient or table offset
+};
+
+__device__ __forceinline__ int pl_row(uint32_t meta) { return (int)(meta & 0xffffff); }
+__device__ __forceinline__ int pl_kind(uint32_t meta) { return (int)((meta >> 24) & 3); }
+__device__ __forceinline__ bool pl_own(uint32_t meta) { return (meta >> 26) & 1; }
+
+// A pair's descriptor with wave-uniform fields.
 struct PairU {
   uint32_t meta;
   int32_t band, ncoef;
   uint32_t off;
 };
 
-__device__ __forceinline__ int pl_kind(uint32_t meta) { return (int)((meta >> 24) & 3); }
-__device__ __forceinline__ bool pl_own(uint32_t meta) { return (meta >> 26) & 1; }
+__device__ __forceinline__ PairU uniform_pair(const PairLds& d) {
+  PairU p;
+  p.meta = __builtin_amdgcn_readfirstlane(d.meta);
+  p.band = __builtin_amdgcn_readfirstlane(d.band);
+  p.ncoef = __builtin_amdgcn_readfirstlane(d.ncoef);
+  p.off = __builtin_amdgcn_readfirstlane(d.off);
+  return p;
+}
 
 // Runs STEP over a row of n8 (a multiple of 8) kernel samples from the top
 // down, in chunks of 8 read with wave-uniform (scalar) loads; the rows start
@@ -203,186 +214,295 @@ __device__ __forceinline__ void pair_k(const PairU& d, const R* __restrict__ coe
   }
 }
 
+template <typename R> struct AccLds { static constexpr int kRings = 8; };
+template <> struct AccLds<double> { static constexpr int kRings = 4; };
 
-constexpr int kTableBatch = 32;   // table pairs whose loads are issued together
-constexpr int kPrefetchRows = 4;  // next-group spectrum rows held in registers per wave
+// Spectrum row of one staged input ring: offset and length in the workspace.
+struct RowRef {
+  int64_t off;
+  int32_t len, pad;
+};
 
-// Input-ring window of the segment in LDS: slot s holds the tile of ring j
-// (row 0) and of its mirror nr - 1 - j (row 1) for j = s mod cap.
-template <typename R>
-__device__ __forceinline__ cx_t<R>* win_row(cx_t<R>* win, int cap, int j, int half) {
-  return win + ((j % cap) * 2 + half) * kSweepTile;
-}
+// Byte offsets of the row table and the pair descriptors in the LDS of an
+// accumulation block (the staged spectra come first).
+struct AccLayout {
+  int32_t rows_off, pairs_off;
+};
 
-// One work item: units [seg.u0, seg.u0 + seg.nu) over the modes
-// [tile kSweepTile, (tile + 1) kSweepTile).  Every wave of the block must
-// call this; it synchronises the block.  WIN = false (supports too wide for
-// the LDS window, cap = 0): the spectra are read from memory at each pair.
-template <typename R, int G, bool TAB_ONLY, bool WIN>
-__device__ __forceinline__ void sweep_item(const AccArgs<R>& a, const SegDev seg, const int tile,
-                                           const cx_t<R>* __restrict__ spec, cx_t<R>* __restrict__ bout,
-                                           cx_t<R>* win) {
+// One work item: the units of band bd (one wavefront each) over the tiles
+// [t0, t0 + nt) of kAccTile modes; lane l holds modes m0 + l + 64 e.  The
+// band's pair descriptors are staged into LDS once, each unit's list split
+// (in input-ring order) into table pairs and on-the-fly pairs.  The input
+// rings of the window are staged in chunks of CH rings (a ring and its
+// mirror per row pair), the spectra of the next (tile, chunk) stage loaded
+// into registers while the current stage is accumulated.  Per stage a wave
+// first streams its table pairs, kTableGroup at a time with all their loads
+// issued together, then evaluates its on-the-fly pairs, the next pair's
+// kernel samples loaded while the current one is evaluated.  Every wave of
+// the block must call this; it synchronises the block.
+template <typename R, int NW, bool TAB_ONLY = false>
+__device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandDev& bd, const int t0, const int nt,
+                                                const cx_t<R>* __restrict__ spec, cx_t<R>* __restrict__ bout,
+                                                unsigned char* smem, const AccLayout lay) {
   using C = cx_t<R>;
+  constexpr int CH = AccLds<R>::kRings;        // input rings staged at a time
+  constexpr int RPW = (2 * CH + NW - 1) / NW;  // staged rows per wave
+  constexpr int MPL = kModesPerLane;
+  C* sa = reinterpret_cast<C*>(smem);
+  RowRef* rows = reinterpret_cast<RowRef*>(smem + lay.rows_off);
+  PairLds* dsc = reinterpret_cast<PairLds*>(smem + lay.pairs_off);
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int m0 = tile * kSweepTile, m = m0 + lane;
-  const int uend = seg.u0 + seg.nu;
-  const int cap = a.cap, nr = a.nrings;
-  // the spectrum row of ring j (half 0) or of its mirror (half 1), this lane's mode
-  auto row_value = [&](int j, int half) -> C {
-    const int ring = half ? nr - 1 - j : j;
-    const int64_t off = __builtin_amdgcn_readfirstlane(gload(a.spec_off + ring));
-    const int len = __builtin_amdgcn_readfirstlane(gload(a.spec_len + ring));
-    return m < len ? gload(spec + off + m) : cmake<C>(R(0), R(0));
-  };
-  // rows of rings [jl, jh] straight into the window, wave by wave
-  auto load_rows = [&](int jl, int jh, int first_row) {
-    const int nrow = 2 * (jh - jl + 1);
-    for (int r = first_row + w; r < nrow; r += G) {
-      const int j = jl + (r >> 1);
-      win_row<R>(win, cap, j, r & 1)[lane] = row_value(j, r & 1);
+  const int win = max(bd.jhi - bd.jlo + 1, 0);
+  // chunks are fixed ranges of CH input rings [cbase + c CH, cbase + (c + 1) CH),
+  // the same for every band layout, so that the order of the sum over a
+  // unit's pairs (by chunk, then tables before the rest, each by ring) does
+  // not depend on how units are grouped into bands
+  const int cbase = win > 0 ? bd.jlo / CH * CH : 0;
+  const int nch = win > 0 ? (bd.jhi + 1 - cbase + CH - 1) / CH : 1;
+  const int pl = a.p * a.L;
+  for (int r = threadIdx.x; r < 2 * win; r += NW * 64) {
+    int j = bd.jlo + (r >> 1);
+    if (r & 1) j = a.nrings - 1 - j;
+    rows[r].off = gload(a.spec_off + j);
+    rows[r].len = gload(a.spec_len + j);
+  }
+  const bool active = w < bd.nu;
+  UnitDev u{};
+  if (active) {
+    u.i = gload(&a.units[bd.u0 + w].i);
+    u.im = gload(&a.units[bd.u0 + w].im);
+    u.pbeg = gload(&a.units[bd.u0 + w].pbeg);
+    u.pend = gload(&a.units[bd.u0 + w].pend);
+    u.band = gload(&a.units[bd.u0 + w].band);
+  }
+  const bool mirror = u.im >= 0;
+  const int npair = active ? u.pend - u.pbeg : 0;
+  PairLds* mine = dsc + (active ? u.pbeg - bd.pbeg : 0);
+  // this unit's descriptors: table pairs first, then the others, each in order
+  int ntab = 0;
+  {
+    for (int b = 0; b < npair; b += 64) {
+      const int q = b + lane;
+      const bool tab = q < npair && gload(&a.pairs[u.pbeg + q].kind) == KG_TABLE;
+      ntab += __popcll(__ballot(tab));
     }
-  };
-  auto unit_hi = [&](int u) { return __builtin_amdgcn_readfirstlane(gload(&a.units[u].jhi)); };
+    int nt_seen = 0;
+    for (int b = 0; b < npair; b += 64) {
+      const int q = b + lane;
+      const bool valid = q < npair;
+      PairDev pr{};
+      if (valid) {
+        const PairDev* g = a.pairs + u.pbeg + q;
+        pr.j = gload(&g->j);
+        pr.kind = gload(&g->kind);
+        pr.band = gload(&g->band);
+        pr.ncoef = gload(&g->ncoef);
+        pr.grid = gload(&g->grid);
+        pr.off = gload(&g->off);
+      }
+      const bool tab = valid && pr.kind == KG_TABLE;
+      const uint64_t tm = __ballot(tab), vm = __ballot(valid);
+      const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+      const int tb = __popcll(tm & below);
+      const int ob = __popcll(vm & ~tm & below);
+      if (valid) {
+        PairLds d;
+        d.meta = (uint32_t)(pr.j - bd.jlo) | ((uint32_t)pr.kind << 24) | ((pr.grid != pl ? 1u : 0u) << 26);
+        d.band = pr.band;
+        d.ncoef = pr.ncoef;
+        d.off = (uint32_t)pr.off;
+        mine[tab ? nt_seen + tb : ntab + (b - nt_seen) + ob] = d;
+      }
+      nt_seen += __popcll(tm);
+    }
+  }
+  const int Ni = active ? gload(a.ring_n + u.i) : a.L;
+  const int ny_own = Ni / 2, ny_fine = pl / 2;
+  __syncthreads();  // row table and descriptors ready
 
-  int hi = WIN ? unit_hi(min(seg.u0 + G, uend) - 1) : 0;
-  if (WIN) load_rows(seg.jlo, hi, 0);
-  for (int u = seg.u0; u < uend; u += G) {
-    if (WIN) __syncthreads();  // the window holds every ring of this group's supports
-    // the next group's new rows: the first kPrefetchRows G into registers now
-    const bool more = WIN && u + G < uend;
-    const int nhi = more ? unit_hi(min(u + 2 * G, uend) - 1) : hi;
-    C pf[kPrefetchRows];
+  const int nst = nt * nch;
+  C pre[RPW][MPL];
+  auto issue = [&](int s) {
+    const int t = s / nch, c = s - t * nch;
+    const int m = (t0 + t) * kAccTile + lane;
+    const int cs = cbase + c * CH;
 #pragma unroll
-    for (int k = 0; k < kPrefetchRows; ++k) {
-      const int r = w + G * k;
-      if (r < 2 * (nhi - hi)) pf[k] = row_value(hi + 1 + (r >> 1), r & 1);
+    for (int k = 0; k < RPW; ++k) {
+      const int r = w + NW * k;
+      const int j = cs + (r >> 1);
+#pragma unroll
+      for (int e = 0; e < MPL; ++e) pre[k][e] = cmake<C>(R(0), R(0));
+      if (r < 2 * CH && j >= bd.jlo && j <= bd.jhi) {
+        const RowRef rr = rows[2 * (j - bd.jlo) + (r & 1)];
+#pragma unroll
+        for (int e = 0; e < MPL; ++e)
+          if (m + 64 * e < rr.len) pre[k][e] = gload(spec + rr.off + m + 64 * e);
+      }
     }
-    const int uu = u + w;
-    if (uu < uend) {
-      const UnitDev* U = a.units + uu;
-      const int band = __builtin_amdgcn_readfirstlane(gload(&U->band));
-      if (m0 <= band) {
-        const int i = __builtin_amdgcn_readfirstlane(gload(&U->i));
-        const int im = __builtin_amdgcn_readfirstlane(gload(&U->im));
-        const int pbeg = __builtin_amdgcn_readfirstlane(gload(&U->pbeg));
-        const int pend = __builtin_amdgcn_readfirstlane(gload(&U->pend));
-        const bool mirror = im >= 0;
-        C acc0 = cmake<C>(R(0), R(0)), acc1 = acc0;
-        auto add = [&](int j, R k) {
-          const C v0 = WIN ? win_row<R>(win, cap, j, 0)[lane] : row_value(j, 0);
-          acc0 = cmake<C>(fma(k, v0.x, acc0.x), fma(k, v0.y, acc0.y));
-          if (mirror) {
-            const C v1 = WIN ? win_row<R>(win, cap, j, 1)[lane] : row_value(j, 1);
-            acc1 = cmake<C>(fma(k, v1.x, acc1.x), fma(k, v1.y, acc1.y));
-          }
-        };
-        // table pairs, kTableBatch at a time with all their loads in flight
-        for (int qb = pbeg; qb < pend; qb += kTableBatch) {
-          R kv[kTableBatch];
-          int jj[kTableBatch];
-          uint32_t live = 0;
+  };
+  issue(0);
+  C acc0[MPL], acc1[MPL];
+  ModeConst<R> mc[MPL];
+  int qt = 0, qo = 0;
+  PairU cur{};
+  int m0 = 0, c0 = 0, c1 = 0;  // c0, c1: the staged chunk's rings, relative to jlo
+  auto accumulate_pair = [&](int row, const R (&k)[MPL]) {
+    const C* s0 = sa + row * kAccTile + lane;
 #pragma unroll
-          for (int x = 0; x < kTableBatch; ++x) {
-            const int q = qb + x;
-            jj[x] = 0;
-            if (q < pend) {
-              const PairDev* pr = a.pairs + q;
-              const int kind = __builtin_amdgcn_readfirstlane(gload(&pr->kind));
-              const int pb = __builtin_amdgcn_readfirstlane(gload(&pr->band));
-              if ((TAB_ONLY || kind == KG_TABLE) && pb >= m0) {
-                const uint32_t off = __builtin_amdgcn_readfirstlane((uint32_t)gload(&pr->off));
-                jj[x] = __builtin_amdgcn_readfirstlane(gload(&pr->j));
-                kv[x] = gload(a.table + off + m);
-                live |= 1u << x;
-              }
-            }
-          }
+    for (int e = 0; e < MPL; ++e) {
+      const C v = s0[64 * e];
+      acc0[e] = cmake<C>(fma(k[e], v.x, acc0[e].x), fma(k[e], v.y, acc0[e].y));
+    }
+    if (mirror) {
 #pragma unroll
-          for (int x = 0; x < kTableBatch; ++x)
-            if ((live >> x) & 1u) add(jj[x], kv[x]);
+      for (int e = 0; e < MPL; ++e) {
+        const C v = s0[kAccTile + 64 * e];
+        acc1[e] = cmake<C>(fma(k[e], v.x, acc1[e].x), fma(k[e], v.y, acc1[e].y));
+      }
+    }
+  };
+  for (int s = 0; s < nst; ++s) {
+    const int t = s / nch, c = s - t * nch;
+    m0 = (t0 + t) * kAccTile;
+    c0 = cbase + c * CH - bd.jlo;
+    c1 = c0 + CH;
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int r = w + NW * k;
+      if (r < 2 * CH) {
+#pragma unroll
+        for (int e = 0; e < MPL; ++e) sa[r * kAccTile + 64 * e + lane] = pre[k][e];
+      }
+    }
+    __syncthreads();
+    if (s + 1 < nst) issue(s + 1);
+    const bool busy = active && m0 <= u.band;
+    if (c == 0) {
+#pragma unroll
+      for (int e = 0; e < MPL; ++e) {
+        acc0[e] = cmake<C>(R(0), R(0));
+        acc1[e] = acc0[e];
+        if (busy && !TAB_ONLY) mc[e] = mode_const<R>(m0 + 64 * e + lane, Ni, pl, a.tw, a.TN);
+      }
+      qt = 0;
+      qo = ntab;
+      if (!TAB_ONLY && busy && qo < npair) cur = uniform_pair(mine[qo]);
+    }
+    // Up to G table pairs of the staged chunk from descriptor qt on: the
+    // descriptors are read together (the descriptor area has CH spare
+    // entries, so reads past a unit's last pair stay inside it), then the
+    // tile of every pair whose band reaches it is loaded without bounds
+    // checks (tables are zero-padded to whole tiles) and with no register
+    // cleared in between, so that the loads overlap each other and the
+    // spectrum prefetch; then they are accumulated.  Returns the pairs used.
+    auto table_group = [&](auto gsize) -> int {
+      constexpr int G = decltype(gsize)::value;
+      PairU d[G];
+#pragma unroll
+      for (int x = 0; x < G; ++x) d[x] = uniform_pair(mine[qt + x]);
+      int g = 0;
+      uint32_t live = 0;
+#pragma unroll
+      for (int x = 0; x < G; ++x)
+        if (g == x && qt + x < ntab && pl_row(d[x].meta) < c1) {
+          g = x + 1;
+          if (d[x].band >= m0) live |= 1u << x;
         }
-        if (!TAB_ONLY) {
-          // pairs whose K_ij(m) comes from the recurrence
-          const int pl = a.p * a.L;
-          const int Ni = __builtin_amdgcn_readfirstlane(gload(a.ring_n + i));
-          ModeConst<R> mc[1];
-          mc[0] = mode_const<R>(m, Ni, pl, a.tw, a.TN);
-          for (int q = pbeg; q < pend; ++q) {
-            const PairDev* pr = a.pairs + q;
-            const int kind = __builtin_amdgcn_readfirstlane(gload(&pr->kind));
-            const int pb = __builtin_amdgcn_readfirstlane(gload(&pr->band));
-            if (kind == KG_TABLE || pb < m0) continue;
-            PairU d;
-            const int grid = __builtin_amdgcn_readfirstlane(gload(&pr->grid));
-            d.meta = ((uint32_t)kind << 24) | ((grid != pl ? 1u : 0u) << 26);
-            d.band = pb;
-            d.ncoef = __builtin_amdgcn_readfirstlane(gload(&pr->ncoef));
-            d.off = __builtin_amdgcn_readfirstlane((uint32_t)gload(&pr->off));
-            R k[1];
-            pair_k<R, 1>(d, a.coef, mc, m0, lane, Ni / 2, pl / 2, k);
-            add(__builtin_amdgcn_readfirstlane(gload(&pr->j)), k[0]);
-          }
+      R kv[G][MPL];
+#pragma unroll
+      for (int x = 0; x < G; ++x)
+        if ((live >> x) & 1u) {
+          const R* tb = a.table + d[x].off + m0;
+#pragma unroll
+          for (int e = 0; e < MPL; ++e) kv[x][e] = gload(tb + 64 * e + lane);
         }
-        if (m <= band) {
-          gstore(bout + gload(a.out_off + i) + m, acc0);
-          if (mirror) gstore(bout + gload(a.out_off + im) + m, acc1);
+#pragma unroll
+      for (int x = 0; x < G; ++x)
+        if ((live >> x) & 1u) accumulate_pair(2 * (pl_row(d[x].meta) - c0), kv[x]);
+      qt += g;
+      return g;
+    };
+    if (busy && TAB_ONLY) {
+      // every pair has a table: a unit has at most CH pairs in a chunk
+      table_group(std::integral_constant<int, CH>{});
+    } else if (busy) {
+      while (qt < ntab)
+        if (table_group(std::integral_constant<int, kTableGroup>{}) == 0) break;
+      // on-the-fly pairs of this chunk
+      while (qo < npair && pl_row(cur.meta) < c1) {
+        const PairU d = cur;
+        if (qo + 1 < npair) cur = uniform_pair(mine[qo + 1]);
+        if (m0 <= d.band) {
+          R k[MPL];
+          pair_k<R, MPL>(d, a.coef, mc, m0, lane, ny_own, ny_fine, k);
+          accumulate_pair(2 * (pl_row(d.meta) - c0), k);
+        }
+        ++qo;
+      }
+    }
+    if (busy && c == nch - 1) {
+      const int64_t o0 = gload(a.out_off + u.i);
+      const int64_t o1 = mirror ? gload(a.out_off + u.im) : 0;
+#pragma unroll
+      for (int e = 0; e < MPL; ++e) {
+        const int m = m0 + 64 * e + lane;
+        if (m <= u.band) {
+          gstore(bout + o0 + m, acc0[e]);
+          if (mirror) gstore(bout + o1 + m, acc1[e]);
         }
       }
     }
-    if (more) {
-      // the next group's rows: the prefetched ones, then any beyond them
-      // (their slots held rings below this group's supports: nobody reads them)
-#pragma unroll
-      for (int k = 0; k < kPrefetchRows; ++k) {
-        const int r = w + G * k;
-        if (r < 2 * (nhi - hi)) win_row<R>(win, cap, hi + 1 + (r >> 1), r & 1)[lane] = pf[k];
-      }
-      if (2 * (nhi - hi) > kPrefetchRows * G) load_rows(hi + 1, nhi, kPrefetchRows * G);
-      hi = nhi;
-    }
+    __syncthreads();
   }
 }
 
-// A segment descriptor read with wave-uniform (scalar) values.
-__device__ __forceinline__ SegDev load_seg(const SegDev* g) {
-  SegDev s;
-  s.u0 = __builtin_amdgcn_readfirstlane(gload(&g->u0));
-  s.nu = __builtin_amdgcn_readfirstlane(gload(&g->nu));
-  s.jlo = __builtin_amdgcn_readfirstlane(gload(&g->jlo));
-  s.band = __builtin_amdgcn_readfirstlane(gload(&g->band));
-  return s;
+// A band descriptor read with wave-uniform (scalar) values.
+__device__ __forceinline__ BandDev load_band(const BandDev* g) {
+  BandDev b;
+  b.u0 = __builtin_amdgcn_readfirstlane(gload(&g->u0));
+  b.nu = __builtin_amdgcn_readfirstlane(gload(&g->nu));
+  b.jlo = __builtin_amdgcn_readfirstlane(gload(&g->jlo));
+  b.jhi = __builtin_amdgcn_readfirstlane(gload(&g->jhi));
+  b.band = __builtin_amdgcn_readfirstlane(gload(&g->band));
+  b.pbeg = __builtin_amdgcn_readfirstlane(gload(&g->pbeg));
+  b.npair = __builtin_amdgcn_readfirstlane(gload(&g->npair));
+  b.pad = 0;
+  return b;
 }
 
-template <typename R, int G, bool TAB_ONLY, bool WIN>
-__global__ void __launch_bounds__(64 * G) accumulate_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec,
-                                                            cx_t<R>* __restrict__ bout) {
+// TAB_ONLY: every pair of the plan has a table of K_ij(m) (no recurrence
+// code, fewer registers, more waves: the FP32 form is held to 80 VGPRs, so
+// that three blocks share a CU instead of two).
+template <typename R, bool TAB_ONLY>
+__global__ void __launch_bounds__(kAccThreads)
+    __attribute__((amdgpu_waves_per_eu((TAB_ONLY && sizeof(R) == 4) ? 6 : 1))) accumulate_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec,
+                                                                 cx_t<R>* __restrict__ bout, AccLayout lay) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WorkItem it = a.items[blockIdx.x];
-  sweep_item<R, G, TAB_ONLY, WIN>(a, load_seg(a.segs + it.band), it.t0, spec, bout,
-                                  reinterpret_cast<cx_t<R>*>(smem));
+  accumulate_band<R, kBandUnits, TAB_ONLY>(a, a.bands[it.band], it.t0, it.nt, spec, bout, smem, lay);
 }
 
-// Batched form: one persistent launch drains a queue of (map, segment, tile)
+// Batched form: one persistent launch drains a queue of (map, band, tiles)
 // items shared by many plans; every block exits once the queue counter
 // passes the item count.
-template <typename R, int G, bool TAB_ONLY, bool WIN>
-__global__ void __launch_bounds__(64 * G) accumulate_batch_kernel(
+template <typename R, int NW, bool TAB_ONLY>
+__global__ void __launch_bounds__(64 * NW) accumulate_batch_kernel(
     const AccArgs<R>* __restrict__ maps, const int64_t* __restrict__ spec_base,
     const int64_t* __restrict__ out_base, const BatchItem* __restrict__ items, int32_t n_items,
-    int32_t* __restrict__ counter, const cx_t<R>* __restrict__ spec, cx_t<R>* __restrict__ bout) {
+    int32_t* __restrict__ counter, const cx_t<R>* __restrict__ spec, cx_t<R>* __restrict__ bout, AccLayout lay) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int cur;
   for (;;) {
-    __syncthreads();  // the previous item is done with `cur` and the window
+    __syncthreads();  // the previous item is done with `cur` and the LDS tiles
     if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(cur);
     if (it >= n_items) break;
     const BatchItem bi = items[it];
     const AccArgs<R> a = maps[bi.map];
-    sweep_item<R, G, TAB_ONLY, WIN>(a, load_seg(a.segs + bi.band), bi.t0, spec + spec_base[bi.map],
-                                    bout + out_base[bi.map], reinterpret_cast<cx_t<R>*>(smem));
+    accumulate_band<R, NW, TAB_ONLY>(a, load_band(a.bands + bi.band), bi.t0, bi.nt, spec + spec_base[bi.map],
+                                     bout + out_base[bi.map], smem, lay);
   }
 }
 
@@ -392,104 +512,125 @@ __global__ void reset_counter_kernel(int32_t* counter) {
 
 size_t acc_args_size() { return sizeof(AccArgs<float>); }
 
-template <typename R>
-static AccArgs<R> make_acc_args(const arkcos_plan_s* P, const SegDev* segs, const WorkItem* items, int32_t cap) {
-  return AccArgs<R>{P->d_units, P->d_pairs, items, segs, P->rt.spec_off, P->rt.spec_len,
+template <typename R> static AccArgs<R> make_acc_args(const arkcos_plan_s* P, const BandDev* bands) {
+  return AccArgs<R>{P->d_units, P->d_pairs, P->d_items, bands, P->rt.spec_off, P->rt.spec_len,
                     P->rt.out_off, (const R*)P->d_coef, (const R*)P->d_table, P->rt.n,
-                    (const cx_t<R>*)P->d_twiddle, P->twiddle_n, (int32_t)P->nrings, (int32_t)P->L, P->oversample,
-                    cap};
+                    (const cx_t<R>*)P->d_twiddle, P->twiddle_n, (int32_t)P->nrings, (int32_t)P->L, P->oversample};
 }
 
-void fill_acc_args(arkcos_plan_s* P, const SegDev* segs, int32_t cap, void* out) {
-  if (P->dtype == ARKCOS_F32)
-    *reinterpret_cast<AccArgs<float>*>(out) = make_acc_args<float>(P, segs, nullptr, cap);
+void fill_acc_args(arkcos_plan_s* P, const BandDev* bands, void* out, const int64_t* spec_off,
+                   const int32_t* spec_len) {
+  if (P->dtype == ARKCOS_F32) {
+    AccArgs<float> a = make_acc_args<float>(P, bands);
+    if (spec_off) a.spec_off = spec_off;
+    if (spec_len) a.spec_len = spec_len;
+    *reinterpret_cast<AccArgs<float>*>(out) = a;
+  } else {
+    AccArgs<double> a = make_acc_args<double>(P, bands);
+    if (spec_off) a.spec_off = spec_off;
+    if (spec_len) a.spec_len = spec_len;
+    *reinterpret_cast<AccArgs<double>*>(out) = a;
+  }
+}
+
+// LDS of one accumulation block: the staged spectra (2 CH rows of kAccTile
+// complex values), the row table of the whole window, the band's pair
+// descriptors.
+static AccLayout acc_layout(arkcos_dtype_t dt, const AccShape& sh) {
+  const int32_t win = std::max(sh.max_window, 1);
+  size_t tile;
+  if (dt == ARKCOS_F32)
+    tile = 2 * (size_t)AccLds<float>::kRings * kAccTile * sizeof(float2);
   else
-    *reinterpret_cast<AccArgs<double>*>(out) = make_acc_args<double>(P, segs, nullptr, cap);
+    tile = 2 * (size_t)AccLds<double>::kRings * kAccTile * sizeof(double2);
+  AccLayout l;
+  l.rows_off = (int32_t)tile;
+  l.pairs_off = (int32_t)(tile + 2 * (size_t)win * sizeof(RowRef));
+  return l;
 }
 
-// LDS of one block: cap slots of two rows of kSweepTile complex values.
-size_t acc_lds_bytes(arkcos_dtype_t dt, int32_t cap) {
-  return (size_t)std::max(cap, 1) * 2 * kSweepTile * (dt == ARKCOS_F32 ? sizeof(float2) : sizeof(double2));
+size_t acc_lds_bytes(arkcos_dtype_t dt, const AccShape& sh) {
+  // CH spare descriptors: a group of table pairs reads CH descriptors at once
+  return (size_t)acc_layout(dt, sh).pairs_off + (size_t)(std::max(sh.max_band_pairs, 1) + 8) * sizeof(PairLds);
 }
+
+template <typename R, int NW, bool TAB_ONLY>
+static hipError_t batch_launch(const void* maps, const int64_t* spec_base, const int64_t* out_base,
+                               const BatchItem* items, int32_t n_items, int32_t* counter, const void* spec,
+                               void* bout, int32_t grid, size_t lds, AccLayout lay, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)accumulate_batch_kernel<R, NW, TAB_ONLY>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  accumulate_batch_kernel<R, NW, TAB_ONLY><<<grid, 64 * NW, lds, s>>>(
+      (const AccArgs<R>*)maps, spec_base, out_base, items, n_items, counter, (const cx_t<R>*)spec, (cx_t<R>*)bout,
+      lay);
+  return hipGetLastError();
+}
+
+template <typename R, bool TAB_ONLY>
+static hipError_t batch_launch_nw(int32_t units_per_band, const void* maps, const int64_t* spec_base,
+                                  const int64_t* out_base, const BatchItem* items, int32_t n_items, int32_t* counter,
+                                  const void* spec, void* bout, int32_t grid, size_t lds, AccLayout lay,
+                                  hipStream_t s) {
+  return units_per_band == 4 ? batch_launch<R, 4, TAB_ONLY>(maps, spec_base, out_base, items, n_items, counter, spec,
+                                                            bout, grid, lds, lay, s)
+                             : batch_launch<R, 8, TAB_ONLY>(maps, spec_base, out_base, items, n_items, counter, spec,
+                                                            bout, grid, lds, lay, s);
+}
+
+hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const int64_t* spec_base,
+                                   const int64_t* out_base, const BatchItem* items, int32_t n_items,
+                                   int32_t* counter, const void* spec, void* bout, int32_t grid,
+                                   int32_t units_per_band, bool all_tables, const AccShape& shape, hipStream_t s) {
+  reset_counter_kernel<<<1, 64, 0, s>>>(counter);
+  const size_t lds = acc_lds_bytes(dt, shape);
+  const AccLayout lay = acc_layout(dt, shape);
+  if (dt == ARKCOS_F32)
+    return all_tables ? batch_launch_nw<float, true>(units_per_band, maps, spec_base, out_base, items, n_items,
+                                                     counter, spec, bout, grid, lds, lay, s)
+                      : batch_launch_nw<float, false>(units_per_band, maps, spec_base, out_base, items, n_items,
+                                                      counter, spec, bout, grid, lds, lay, s);
+  return all_tables ? batch_launch_nw<double, true>(units_per_band, maps, spec_base, out_base, items, n_items,
+                                                    counter, spec, bout, grid, lds, lay, s)
+                    : batch_launch_nw<double, false>(units_per_band, maps, spec_base, out_base, items, n_items,
+                                                     counter, spec, bout, grid, lds, lay, s);
+}
+
+// Modes beyond a unit's band stay zero (B_i has out_len_i = band_i + 1 modes,
+// so nothing is left unwritten).
 
 template <typename K> static hipError_t allow_acc_lds(K* k, size_t bytes) {
   return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename R, int G, bool TAB_ONLY, bool WIN>
-static hipError_t batch_launch(const void* maps, const int64_t* spec_base, const int64_t* out_base,
-                               const BatchItem* items, int32_t n_items, int32_t* counter, const void* spec,
-                               void* bout, int32_t grid, size_t lds, hipStream_t s) {
-  hipError_t e = allow_acc_lds(accumulate_batch_kernel<R, G, TAB_ONLY, WIN>, lds);
-  if (e != hipSuccess) return e;
-  accumulate_batch_kernel<R, G, TAB_ONLY, WIN><<<grid, 64 * G, lds, s>>>(
-      (const AccArgs<R>*)maps, spec_base, out_base, items, n_items, counter, (const cx_t<R>*)spec, (cx_t<R>*)bout);
-  return hipGetLastError();
-}
-
-template <typename R, bool TAB_ONLY>
-static hipError_t batch_launch_g(int32_t group, int32_t cap, const void* maps, const int64_t* spec_base,
-                                 const int64_t* out_base, const BatchItem* items, int32_t n_items, int32_t* counter,
-                                 const void* spec, void* bout, int32_t grid, size_t lds, hipStream_t s) {
-  if (cap == 0)
-    return batch_launch<R, 4, TAB_ONLY, false>(maps, spec_base, out_base, items, n_items, counter, spec, bout, grid,
-                                               0, s);
-  return group == 4 ? batch_launch<R, 4, TAB_ONLY, true>(maps, spec_base, out_base, items, n_items, counter, spec,
-                                                         bout, grid, lds, s)
-                    : batch_launch<R, 8, TAB_ONLY, true>(maps, spec_base, out_base, items, n_items, counter, spec,
-                                                         bout, grid, lds, s);
-}
-
-// cap: the largest window of the batch's maps, or 0 when some map reads its
-// spectra from memory (then every map does, with groups of 4).
-hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const int64_t* spec_base,
-                                   const int64_t* out_base, const BatchItem* items, int32_t n_items,
-                                   int32_t* counter, const void* spec, void* bout, int32_t grid, int32_t group,
-                                   bool all_tables, int32_t cap, hipStream_t s) {
-  reset_counter_kernel<<<1, 64, 0, s>>>(counter);
-  const size_t lds = acc_lds_bytes(dt, cap);
-  if (dt == ARKCOS_F32)
-    return all_tables ? batch_launch_g<float, true>(group, cap, maps, spec_base, out_base, items, n_items, counter,
-                                                    spec, bout, grid, lds, s)
-                      : batch_launch_g<float, false>(group, cap, maps, spec_base, out_base, items, n_items, counter,
-                                                     spec, bout, grid, lds, s);
-  return all_tables ? batch_launch_g<double, true>(group, cap, maps, spec_base, out_base, items, n_items, counter,
-                                                   spec, bout, grid, lds, s)
-                    : batch_launch_g<double, false>(group, cap, maps, spec_base, out_base, items, n_items, counter,
-                                                    spec, bout, grid, lds, s);
-}
-
-// Modes beyond a unit's band stay unwritten: B_i has out_len_i = band_i + 1
-// modes.
-
-template <typename R, int G, bool TAB_ONLY, bool WIN>
-static hipError_t launch_one(const arkcos_plan_s* P, const AccConfig& c, const void* spec, void* bout, hipStream_t s) {
-  const size_t lds = WIN ? acc_lds_bytes(P->dtype, c.cap) : 0;
-  hipError_t e = allow_acc_lds(accumulate_kernel<R, G, TAB_ONLY, WIN>, lds);
-  if (e != hipSuccess) return e;
-  accumulate_kernel<R, G, TAB_ONLY, WIN><<<(unsigned)c.n_items, 64 * G, lds, s>>>(
-      make_acc_args<R>(P, c.d_segs, c.d_items, c.cap), (const cx_t<R>*)spec, (cx_t<R>*)bout);
-  return hipGetLastError();
-}
-
-template <typename R, bool TAB_ONLY>
-static hipError_t launch_tab(const arkcos_plan_s* P, const AccConfig& c, const void* spec, void* bout,
-                             hipStream_t s) {
-  if (c.cap == 0) return launch_one<R, 4, TAB_ONLY, false>(P, c, spec, bout, s);
-  return c.group == 4 ? launch_one<R, 4, TAB_ONLY, true>(P, c, spec, bout, s)
-                      : launch_one<R, 8, TAB_ONLY, true>(P, c, spec, bout, s);
-}
-
-hipError_t launch_accumulate_config(const arkcos_plan_s* P, const AccConfig& c, const void* spec, void* bout,
-                                    hipStream_t s) {
-  if (c.n_items == 0) return hipSuccess;
-  if (P->dtype == ARKCOS_F32)
-    return P->all_tables ? launch_tab<float, true>(P, c, spec, bout, s) : launch_tab<float, false>(P, c, spec, bout, s);
-  return P->all_tables ? launch_tab<double, true>(P, c, spec, bout, s) : launch_tab<double, false>(P, c, spec, bout, s);
+hipError_t configure_accumulate(arkcos_plan_s* P) {
+  const size_t lds = acc_lds_bytes(P->dtype, P->acc_shape);
+  hipError_t e;
+  if (P->dtype == ARKCOS_F32) {
+    e = allow_acc_lds(accumulate_kernel<float, false>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<float, true>, lds);
+  } else {
+    e = allow_acc_lds(accumulate_kernel<double, false>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<double, true>, lds);
+  }
+  return e;
 }
 
 hipError_t launch_accumulate(arkcos_plan_s* P, const void* spec, void* bout, hipStream_t s) {
-  return launch_accumulate_config(P, P->acc, spec, bout, s);
+  if (P->h_items.empty()) return hipSuccess;
+  const size_t lds = acc_lds_bytes(P->dtype, P->acc_shape);
+  const AccLayout lay = acc_layout(P->dtype, P->acc_shape);
+  const unsigned grid = (unsigned)P->h_items.size();
+  const bool tab = P->all_tables;
+  if (P->dtype == ARKCOS_F32) {
+    auto k = tab ? accumulate_kernel<float, true> : accumulate_kernel<float, false>;
+    k<<<grid, kAccThreads, lds, s>>>(make_acc_args<float>(P, P->d_bands), (const float2*)spec, (float2*)bout, lay);
+  } else {
+    auto k = tab ? accumulate_kernel<double, true> : accumulate_kernel<double, false>;
+    k<<<grid, kAccThreads, lds, s>>>(make_acc_args<double>(P, P->d_bands), (const double2*)spec, (double2*)bout,
+                                     lay);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace arkcos

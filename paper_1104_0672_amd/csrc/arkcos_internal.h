@@ -18,8 +18,9 @@ constexpr int kModeTile = 256;         // modes per accumulation work item
 constexpr int kDirectMax = 64;         // rings up to this length use a plain DFT
 constexpr int kOtfMaxCoef = 48;        // wider kernel rows use a K_ij(m) table (auto mode)
 constexpr int kClenshawMaxCoef = 16;   // longer centred rows use Reinsch's recurrence
-constexpr int kAccTile = 256;          // K_ij(m) tables are zero-padded to multiples of this
-constexpr int kSweepTile = 64;         // modes per accumulation work item (one per lane)
+constexpr int kBandUnits = 8;          // output units (ring + mirror) per accumulation work item
+constexpr int kAccTile = 256;          // modes per accumulation tile (four per lane)
+constexpr int kAccThreads = 64 * kBandUnits;  // one wavefront per unit
 
 // FFT strategy of one ring length.
 enum FftKind : int32_t { FFT_DIRECT = 0, FFT_POW2 = 1, FFT_BLUESTEIN = 2 };
@@ -80,8 +81,8 @@ constexpr double kGradItemWork = 16777216.0;  // samples x modes of a wide-row i
 constexpr int kGradZBytes = 32768;    // LDS for a wide-row item's correlation: its modes come in chunks of this
 constexpr int kGradBlocksPerCU = 3;   // gradient blocks resident per CU (LDS and registers)
 
-// One accumulation work item: segment `band` (an index into the segment
-// table) over the modes [t0 kSweepTile, (t0 + 1) kSweepTile).
+// One accumulation work item: band `band`, mode tiles [t0, t0 + nt) of
+// kAccTile modes each.
 struct WorkItem {
   int32_t band, t0, nt, pad;
 };
@@ -91,26 +92,28 @@ struct BatchItem {
   int32_t map, band, t0, nt;
 };
 
-// A segment of consecutive output units swept by one accumulation item.
-struct SegDev {
-  int32_t u0, nu;   // units [u0, u0 + nu)
-  int32_t jlo;      // first input ring of its first unit
-  int32_t band;     // largest band of its units
-};
-
-// How a plan's accumulation is launched: segment length, units per group
-// (waves per block), ring slots of the LDS window, the items and segments.
-struct AccConfig {
-  int32_t seg_units = 64, group = 4, cap = 1, n_items = 0;
-  int32_t tuned = 0;
-  SegDev* d_segs = nullptr;
-  WorkItem* d_items = nullptr;
-};
+constexpr int kTilesPerItem = 4;     // mode tiles per accumulation work item
 constexpr int kFoldThreads = 256;    // threads sharing the period sums of a short ring's fold (C2R)
 // entries of a pair's K_ij(m) table: modes 0..band, zero-padded to whole
 // mode tiles so that a tile is read without bounds checks
 __host__ __device__ constexpr int32_t table_span(int32_t band) { return (band / kAccTile + 1) * kAccTile; }
 constexpr int64_t kAutoTableBytes = int64_t(1) << 30;  // automatic choice: tables for every pair up to this size
+
+// A band of up to kBandUnits consecutive units: the input rings they need.
+struct BandDev {
+  int32_t u0, nu;       // units [u0, u0 + nu)
+  int32_t jlo, jhi;     // input rings [jlo, jhi]
+  int32_t band;         // max band over the units
+  int32_t pbeg, npair;  // the units' pairs [pbeg, pbeg + npair) (contiguous)
+  int32_t pad;
+};
+
+// What sizes the LDS of an accumulation block: the widest input-ring window
+// and the most pairs of any band.
+struct AccShape {
+  int32_t max_window = 0;
+  int32_t max_band_pairs = 0;
+};
 
 
 // Rings whose FFTs share one launch: similar LDS needs, so small rings are
@@ -167,7 +170,11 @@ struct arkcos_plan_s {
   arkcos::RingTables rt;
   arkcos::UnitDev* d_units = nullptr;
   arkcos::PairDev* d_pairs = nullptr;
-  arkcos::AccConfig acc;        // accumulation launch (segments, items, window)
+  std::vector<arkcos::WorkItem> h_items;
+  arkcos::WorkItem* d_items = nullptr;
+  arkcos::BandDev* d_bands = nullptr;
+  arkcos::AccShape acc_shape;  // LDS needs of the accumulation bands
+  std::vector<arkcos::BandDev> h_bands;
   bool all_tables = false;     // every pair reads K_ij(m) from a table
   void* d_coef = nullptr;       // recurrence coefficients, plan dtype
   double* d_coef64 = nullptr;   // the same in FP64 (plan-time table building, gradient)
@@ -212,22 +219,28 @@ arkcos_status_t fail(arkcos_status_t st, const std::string& msg);
 
 // Kernel launchers (defined next to their kernels).
 hipError_t launch_kernel_rows(arkcos_plan_s* P, double* coef_abs_sum, hipStream_t s);
+// new spline knots (device, n_knots doubles) and their clamped-spline moments
+hipError_t launch_spline_update(arkcos_plan_s* P, const double* d_src, hipStream_t s);
 hipError_t launch_band(arkcos_plan_s* P, double threshold, int32_t* band_out, hipStream_t s);
 hipError_t launch_table_list(arkcos_plan_s* P, const int32_t* d_list, const int64_t* d_coef_off,
                              int32_t count, hipStream_t s);
 hipError_t configure_fft_kernels(arkcos_plan_s* P);
 // batched form
 size_t acc_args_size();
-void fill_acc_args(arkcos_plan_s* P, const SegDev* segs, int32_t cap, void* out);
-size_t acc_lds_bytes(arkcos_dtype_t dt, int32_t cap);
+// spec_off / spec_len (device, may be null): a spectrum layout to read instead
+// of the plan's own (a shared-input batch's union layout, which holds at
+// least every mode the plan's pairs read).
+void fill_acc_args(arkcos_plan_s* P, const BandDev* bands, void* out, const int64_t* spec_off = nullptr,
+                   const int32_t* spec_len = nullptr);
+size_t acc_lds_bytes(arkcos_dtype_t dt, const AccShape& shape);
 hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const int64_t* spec_base,
                                    const int64_t* out_base, const BatchItem* items, int32_t n_items,
                                    int32_t* counter, const void* spec, void* bout, int32_t grid,
-                                   int32_t group, bool all_tables, int32_t cap, hipStream_t s);
-hipError_t launch_accumulate_config(const arkcos_plan_s* P, const AccConfig& c, const void* spec, void* bout,
-                                    hipStream_t s);
+                                   int32_t units_per_band, bool all_tables, const AccShape& shape, hipStream_t s);
+hipError_t configure_accumulate(arkcos_plan_s* P);
 size_t ring_args_size();
-void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out);
+void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out,
+                    const int64_t* off = nullptr, const int32_t* len = nullptr);
 hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, const void* entries, int32_t count,
                              int32_t lds, int32_t threads, int32_t mf, const void* maps, void* ws,
                              const int64_t* base, hipStream_t s);
@@ -247,9 +260,8 @@ size_t pole_map_size();
 void fill_pole_map(arkcos_plan_s* P, void* out);
 hipError_t launch_pole_batch(arkcos_dtype_t dt, const void* maps, const int2* entries, int32_t count, int32_t adjoint,
                              const void* xs, const void* ys, hipStream_t s);
-void build_segments(const arkcos_plan_s* P, int32_t seg_units, int32_t group, std::vector<SegDev>& segs,
-                    int32_t* cap);
-void accumulation_items(const arkcos_plan_s* P, const std::vector<SegDev>& segs, std::vector<WorkItem>& items,
+void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<BandDev>& bands, AccShape* shape);
+void accumulation_items(const arkcos_plan_s* P, const std::vector<BandDev>& bands, std::vector<WorkItem>& items,
                         std::vector<double>& cost);
 int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count);
 void workspace_split(const arkcos_plan_s* P, void* ws, void** spec, void** bout);

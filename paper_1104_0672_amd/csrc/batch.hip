@@ -3,12 +3,18 @@
 // transforms, one persistent accumulation launch over a shared work queue,
 // and one pass of batched inverse transforms.
 //
-// The queue holds (map, segment of output units, 64-mode tile) items of
-// every map, ordered by decreasing estimated cost so the persistent
-// workgroups end together.  The segment length, the units swept at a time
-// (waves per workgroup) and the number of persistent workgroups are chosen by
-// timing the accumulation on a subset of the maps (up to four maps of each
-// ring count).
+// Shared-input form: one map convolved with many kernels on one geometry
+// (e.g. the symmetric components an asymmetric beam is split into, paper
+// Sect. 5).  The input's extended spectra are computed once, in the union of
+// the plans' spectrum layouts (every ring as long as the longest any plan
+// needs), and every plan's accumulation reads them from there; the
+// accumulation and the inverse transforms run batched over the kernels.
+//
+// The queue holds (map, band of output rings, mode tiles) items of every
+// map, ordered by decreasing estimated cost so the persistent workgroups end
+// together.  The band size (output rings per item) and the number of
+// persistent workgroups are chosen by timing the accumulation on a subset of
+// the maps (up to four maps of each ring count).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,9 +49,9 @@ struct arkcos_batch_s {
   arkcos_dtype_t dtype = ARKCOS_F32;
   int32_t n = 0;
   std::vector<arkcos_plan_s*> plans;
-  int32_t seg_units = 64, group = 4, grid = 0, tuned = 0;
+  int32_t units_per_band = kBandUnits, grid = 0, tuned = 0;
   bool all_tables = false;  // every plan reads all its K_ij(m) from tables
-  int32_t cap = 0;          // LDS window slots of the accumulation (0: spectra read from memory)
+  AccShape acc_shape;
   int64_t spec_total = 0, out_total = 0, npix_total = 0;
   std::vector<int64_t> h_spec_base, h_out_base;
   // device
@@ -56,6 +62,12 @@ struct arkcos_batch_s {
   int32_t n_items = 0;
   void* d_rargs[4] = {nullptr, nullptr, nullptr, nullptr};  // R2C fwd, R2C adj, C2R fwd, C2R adj
   std::vector<ClassDev> classes;
+  // shared-input form: the R2C classes of the one input map, and the union
+  // spectrum layout every plan reads
+  bool shared = false;
+  std::vector<ClassDev> in_classes;
+  int64_t* d_union_off = nullptr;
+  int32_t* d_union_len = nullptr;
   void* d_pole_maps = nullptr;
   int2* d_pole_fwd = nullptr;
   int2* d_pole_adj = nullptr;
@@ -90,43 +102,38 @@ template <typename T> hipError_t bupload(arkcos_batch_s* B, T** p, const std::ve
   return hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
-// Queue of one batch configuration: per-map segments on the device, the
-// AccArgs pointing at them, and the items sorted by decreasing estimated cost.
+// Queue of one batch configuration: per-map bands on the device, the AccArgs
+// pointing at them, and the items sorted by decreasing estimated cost.
 struct Queue {
+  std::vector<BandDev*> d_bands;
   std::vector<char> acc_args;
   std::vector<BatchItem> items;
-  int32_t cap = 0;
+  AccShape shape;
 };
 
-// Largest LDS window of the batched accumulation (as for single plans).
-constexpr size_t kMaxBatchWindowBytes = 96 * 1024;
-
-hipError_t build_queue(arkcos_batch_s* B, const std::vector<int32_t>& maps, int32_t seg_units, int32_t group,
-                       Queue& Q, std::vector<void*>& owned) {
+hipError_t build_queue(arkcos_batch_s* B, const std::vector<int32_t>& maps, int32_t upb, Queue& Q,
+                       std::vector<void*>& owned) {
   const size_t asz = acc_args_size();
   Q.acc_args.assign(asz * maps.size(), 0);
   std::vector<std::pair<double, BatchItem>> costed;
-  std::vector<std::vector<SegDev>> segs(maps.size());
-  std::vector<int32_t> caps(maps.size());
-  Q.cap = 1;
-  for (size_t mi = 0; mi < maps.size(); ++mi) {
-    build_segments(B->plans[maps[mi]], seg_units, group, segs[mi], &caps[mi]);
-    Q.cap = std::max(Q.cap, caps[mi]);
-  }
-  const bool window = acc_lds_bytes(B->dtype, Q.cap) <= kMaxBatchWindowBytes;
-  if (!window) Q.cap = 0;
   for (size_t mi = 0; mi < maps.size(); ++mi) {
     arkcos_plan_s* P = B->plans[maps[mi]];
+    std::vector<BandDev> bands;
+    AccShape sh;
+    build_bands(P, upb, bands, &sh);
+    Q.shape.max_window = std::max(Q.shape.max_window, sh.max_window);
+    Q.shape.max_band_pairs = std::max(Q.shape.max_band_pairs, sh.max_band_pairs);
     void* d = nullptr;
-    hipError_t e = hipMalloc(&d, std::max<size_t>(segs[mi].size(), 1) * sizeof(SegDev));
+    hipError_t e = hipMalloc(&d, std::max<size_t>(bands.size(), 1) * sizeof(BandDev));
     if (e != hipSuccess) return e;
     owned.push_back(d);
-    e = hipMemcpy(d, segs[mi].data(), segs[mi].size() * sizeof(SegDev), hipMemcpyHostToDevice);
+    e = hipMemcpy(d, bands.data(), bands.size() * sizeof(BandDev), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
-    fill_acc_args(P, (const SegDev*)d, window ? caps[mi] : 0, Q.acc_args.data() + asz * mi);
+    Q.d_bands.push_back((BandDev*)d);
+    fill_acc_args(P, (const BandDev*)d, Q.acc_args.data() + asz * mi, B->d_union_off, B->d_union_len);
     std::vector<WorkItem> its;
     std::vector<double> cost;
-    accumulation_items(P, segs[mi], its, cost);
+    accumulation_items(P, bands, its, cost);
     for (size_t k = 0; k < its.size(); ++k)
       costed.push_back({cost[k], BatchItem{(int32_t)mi, its[k].band, its[k].t0, its[k].nt}});
   }
@@ -141,7 +148,7 @@ hipError_t build_queue(arkcos_batch_s* B, const std::vector<int32_t>& maps, int3
 
 std::string tune_key(const arkcos_batch_s* B) {
   std::ostringstream k;
-  k << "dt" << (int)B->dtype << "_n" << B->n << "_t" << (B->all_tables ? 1 : 0);
+  k << "dt" << (int)B->dtype << "_n" << B->n << "_t" << (B->all_tables ? 1 : 0) << (B->shared ? "_s" : "");
   uint64_t h = 1469598103934665603ull;
   for (auto* P : B->plans) {
     const int64_t v[3] = {P->npix, P->pair_modes, P->coef_total};
@@ -154,33 +161,32 @@ std::string tune_key(const arkcos_batch_s* B) {
   return k.str();
 }
 
-bool read_cache(const std::string& key, int32_t* su, int32_t* grp, int32_t* bpc) {
+bool read_cache(const std::string& key, int32_t* upb, int32_t* bpc) {
   const char* path = getenv("ARKCOS_AUTOTUNE_CACHE");
   if (!path || !*path) return false;
   std::ifstream f(path);
   std::string k;
-  int32_t a, b, c;
-  while (f >> k >> a >> b >> c)
-    if (k == key && a > 0 && (b == 4 || b == 8) && c > 0) {
-      *su = a;
-      *grp = b;
-      *bpc = c;
+  int32_t a, b;
+  while (f >> k >> a >> b)
+    if (k == key) {
+      *upb = a;
+      *bpc = b;
       return true;
     }
   return false;
 }
 
-void write_cache(const std::string& key, int32_t su, int32_t grp, int32_t bpc) {
+void write_cache(const std::string& key, int32_t upb, int32_t bpc) {
   const char* path = getenv("ARKCOS_AUTOTUNE_CACHE");
   if (!path || !*path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << " " << su << " " << grp << " " << bpc << "\n";
+  f << key << " " << upb << " " << bpc << "\n";
 }
 
 // Times the accumulation of one queue on the subset's workspace (zero
 // spectra); returns milliseconds per launch.
 hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64_t>& sb,
-                      const std::vector<int64_t>& ob, void* spec, void* bout, int32_t* counter, int32_t group,
+                      const std::vector<int64_t>& ob, void* spec, void* bout, int32_t* counter, int32_t upb,
                       int32_t grid, float* ms) {
   void *dargs = nullptr, *ditems = nullptr, *dsb = nullptr, *dob = nullptr;
   hipError_t e = hipMalloc(&dargs, Q.acc_args.size());
@@ -199,7 +205,7 @@ hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64
     if (r == 1) e = hipEventRecord(e0, nullptr);
     if (e == hipSuccess)
       e = launch_accumulate_batch(B->dtype, dargs, (const int64_t*)dsb, (const int64_t*)dob, (const BatchItem*)ditems,
-                                  (int32_t)Q.items.size(), counter, spec, bout, grid, group, B->all_tables, Q.cap,
+                                  (int32_t)Q.items.size(), counter, spec, bout, grid, upb, B->all_tables, Q.shape,
                                   nullptr);
   }
   if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
@@ -216,7 +222,7 @@ hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64
   return e;
 }
 
-arkcos_status_t autotune(arkcos_batch_s* B, int32_t* su_out, int32_t* grp_out, int32_t* bpc_out) {
+arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out) {
   // subset: up to four maps per ring count
   std::map<int64_t, int> seen;
   std::vector<int32_t> sub;
@@ -225,11 +231,12 @@ arkcos_status_t autotune(arkcos_batch_s* B, int32_t* su_out, int32_t* grp_out, i
   std::vector<int64_t> sb, ob;
   int64_t st = 0, ot = 0;
   for (int32_t i : sub) {
-    sb.push_back(st);
+    sb.push_back(B->shared ? 0 : st);
     ob.push_back(ot);
-    st += B->plans[i]->spec_total;
+    st += B->shared ? 0 : B->plans[i]->spec_total;
     ot += B->plans[i]->out_total;
   }
+  if (B->shared) st = B->spec_total;  // every plan reads the one union layout
   const size_t csz = B->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
   void *spec = nullptr, *bout = nullptr, *ctr = nullptr;
   BCHK(hipMalloc(&spec, std::max<int64_t>(st, 1) * csz));
@@ -242,33 +249,65 @@ arkcos_status_t autotune(arkcos_batch_s* B, int32_t* su_out, int32_t* grp_out, i
   int cus = 0;
   BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
   float best = 1e30f;
-  int32_t bs = 64, bg = 4, bb = 2;
-  for (int32_t su : {32, 64, 128}) {
-    for (int32_t grp : {4, 8}) {
-      Queue Q;
-      std::vector<void*> owned;
-      hipError_t e = build_queue(B, sub, su, grp, Q, owned);
-      for (int32_t bpc : {1, 2, 3, 4}) {
-        float ms = 0.f;
-        if (e == hipSuccess) e = time_queue(B, Q, sb, ob, spec, bout, (int32_t*)ctr, grp, cus * bpc, &ms);
-        if (e == hipSuccess && ms < best) {
-          best = ms;
-          bs = su;
-          bg = grp;
-          bb = bpc;
-        }
+  int32_t bu = kBandUnits, bb = 2;
+  for (int32_t upb : {4, 8}) {
+    Queue Q;
+    std::vector<void*> owned;
+    hipError_t e = build_queue(B, sub, upb, Q, owned);
+    for (int32_t bpc : {1, 2, 4}) {
+      float ms = 0.f;
+      if (e == hipSuccess) e = time_queue(B, Q, sb, ob, spec, bout, (int32_t*)ctr, upb, cus * bpc, &ms);
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        bu = upb;
+        bb = bpc;
       }
-      for (void* p : owned) hipFree(p);
-      if (e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
     }
+    for (void* p : owned) hipFree(p);
+    if (e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
   }
-  *su_out = bs;
-  *grp_out = bg;
+  *upb_out = bu;
   *bpc_out = bb;
   return ARKCOS_OK;
 }
 
-arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_t* out) {
+// Rings of the given (map, ring) entries grouped into ring-transform
+// classes: rings of similar LDS needs share a launch, and rings of a length
+// with a compile-time transform get a class of their own.
+hipError_t make_classes(arkcos_batch_s* B, const std::vector<int2>& entries, std::vector<ClassDev>& out) {
+  std::map<int64_t, std::vector<int2>> cls;
+  std::map<int32_t, int64_t> per_len;
+  for (const int2& e : entries) ++per_len[B->plans[e.x]->h_fft_len[e.y]];
+  for (const int2& e : entries) {
+    arkcos_plan_s* P = B->plans[e.x];
+    int64_t b = 32768;  // small rings of every map share one launch
+    while (b < P->h_ring_lds[e.y]) b <<= 1;
+    // a compile-time FFT length: one class per length
+    const int32_t ct = ct_fft_length(B->dtype, P->h_fft_len[e.y], per_len[P->h_fft_len[e.y]]);
+    if (ct > 0) b = (int64_t(1) << 40) + ct;
+    cls[b].push_back(e);
+  }
+  for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
+    ClassDev c;
+    c.count = (int32_t)it->second.size();
+    int32_t mx = 0, len = 0, lo = INT32_MAX;
+    for (const int2& e : it->second) {
+      mx = std::max(mx, B->plans[e.x]->h_ring_lds[e.y]);
+      len = std::max(len, B->plans[e.x]->h_fft_len[e.y]);
+      lo = std::min(lo, B->plans[e.x]->h_fft_len[e.y]);
+    }
+    c.lds = mx;
+    // one compile-time FFT length for the whole class: compile-time transforms
+    c.mf = (lo == len) ? ct_fft_length(B->dtype, len, per_len[len]) : 0;
+    c.threads = c.mf > 0 ? c.mf / 16 : fft_threads(B->dtype, len);
+    hipError_t e = bupload(B, &c.entries, it->second);
+    if (e != hipSuccess) return e;
+    out.push_back(c);
+  }
+  return hipSuccess;
+}
+
+arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, bool shared, arkcos_batch_t* out) {
   if (n < 1 || !plans || !out) return fail(ARKCOS_ERR_INVALID_VALUE, "need n >= 1 plans and an output handle");
   int dev = -1;
   BCHK(hipGetDevice(&dev));
@@ -276,6 +315,13 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
     if (!plans[i]) return fail(ARKCOS_ERR_INVALID_VALUE, "null plan in batch");
     if (plans[i]->device != dev) return fail(ARKCOS_ERR_INVALID_VALUE, "plans live on another device");
     if (plans[i]->dtype != plans[0]->dtype) return fail(ARKCOS_ERR_INVALID_VALUE, "plans of mixed dtype");
+    if (shared) {
+      const arkcos_geometry_t &a = plans[i]->geom, &b = plans[0]->geom;
+      if (a.kind != b.kind || (a.kind == 1 ? a.nside != b.nside : (a.n_theta != b.n_theta || a.n_phi != b.n_phi)))
+        return fail(ARKCOS_ERR_INVALID_VALUE, "a shared-input batch needs plans of one geometry");
+      if (plans[i]->opts.fix_pole_pixels != plans[0]->opts.fix_pole_pixels)
+        return fail(ARKCOS_ERR_INVALID_VALUE, "a shared-input batch needs one fix_pole_pixels setting");
+    }
   }
   auto* B = new arkcos_batch_s();
   struct Owner {
@@ -291,14 +337,29 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
   B->n = n;
   B->dtype = plans[0]->dtype;
   B->plans.assign(plans, plans + n);
+  B->shared = shared;
   B->all_tables = true;
   for (auto* P : B->plans) {
     B->all_tables = B->all_tables && P->all_tables;
-    B->h_spec_base.push_back(B->spec_total);
+    B->h_spec_base.push_back(shared ? 0 : B->spec_total);
     B->h_out_base.push_back(B->out_total);
-    B->spec_total += P->spec_total;
+    B->spec_total += shared ? 0 : P->spec_total;
     B->out_total += P->out_total;
     B->npix_total += P->npix;
+  }
+  if (shared) {
+    // union spectrum layout: each ring as long as the longest any plan reads
+    const int64_t nr = B->plans[0]->nrings;
+    std::vector<int32_t> len(nr, 0);
+    std::vector<int64_t> off(nr, 0);
+    for (auto* P : B->plans)
+      for (int64_t k = 0; k < nr; ++k) len[k] = std::max(len[k], P->h_spec_len[k]);
+    for (int64_t k = 0; k < nr; ++k) {
+      off[k] = B->spec_total;
+      B->spec_total += len[k];
+    }
+    BCHK(bupload(B, &B->d_union_off, off));
+    BCHK(bupload(B, &B->d_union_len, len));
   }
   BCHK(bupload(B, &B->d_spec_base, B->h_spec_base));
   BCHK(bupload(B, &B->d_out_base, B->h_out_base));
@@ -311,7 +372,11 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
       arkcos_plan_s* P = B->plans[i];
       const bool fix = P->geom.kind == 1 && P->opts.fix_pole_pixels;
       const bool outl = v >= 2, adj = (v & 1) != 0;
-      fill_ring_args(P, outl, adj ? 1 : 0, (!outl && adj && fix) ? 1 : 0, h.data() + rsz * i);
+      if (shared && !outl)  // the one input map, in the union layout
+        fill_ring_args(B->plans[0], false, adj ? 1 : 0, (adj && fix) ? 1 : 0, h.data() + rsz * i, B->d_union_off,
+                       B->d_union_len);
+      else
+        fill_ring_args(P, outl, adj ? 1 : 0, (!outl && adj && fix) ? 1 : 0, h.data() + rsz * i);
     }
     void* d = nullptr;
     BCHK(hipMalloc(&d, h.size()));
@@ -320,36 +385,13 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
     B->d_rargs[v] = d;
   }
   {
-    std::map<int64_t, std::vector<int2>> cls;
-    std::map<int32_t, int64_t> per_len;
+    std::vector<int2> all_rings, in_rings;
     for (int32_t i = 0; i < n; ++i)
-      for (int64_t k = 0; k < B->plans[i]->nrings; ++k) ++per_len[B->plans[i]->h_fft_len[k]];
-    for (int32_t i = 0; i < n; ++i) {
-      arkcos_plan_s* P = B->plans[i];
-      for (int64_t k = 0; k < P->nrings; ++k) {
-        int64_t b = 32768;  // small rings of every map share one launch
-        while (b < P->h_ring_lds[k]) b <<= 1;
-        // a compile-time FFT length: one class per length
-        const int32_t ct = ct_fft_length(B->dtype, P->h_fft_len[k], per_len[P->h_fft_len[k]]);
-        if (ct > 0) b = (int64_t(1) << 40) + ct;
-        cls[b].push_back(make_int2(i, (int)k));
-      }
-    }
-    for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
-      ClassDev c;
-      c.count = (int32_t)it->second.size();
-      int32_t mx = 0, len = 0, lo = INT32_MAX;
-      for (const int2& e : it->second) {
-        mx = std::max(mx, B->plans[e.x]->h_ring_lds[e.y]);
-        len = std::max(len, B->plans[e.x]->h_fft_len[e.y]);
-        lo = std::min(lo, B->plans[e.x]->h_fft_len[e.y]);
-      }
-      c.lds = mx;
-      // one compile-time FFT length for the whole class: compile-time transforms
-      c.mf = (lo == len) ? ct_fft_length(B->dtype, len, per_len[len]) : 0;
-      c.threads = c.mf > 0 ? c.mf / 16 : fft_threads(B->dtype, len);
-      BCHK(bupload(B, &c.entries, it->second));
-      B->classes.push_back(c);
+      for (int64_t k = 0; k < B->plans[i]->nrings; ++k) all_rings.push_back(make_int2(i, (int)k));
+    BCHK(make_classes(B, all_rings, B->classes));
+    if (shared) {
+      for (int64_t k = 0; k < B->plans[0]->nrings; ++k) in_rings.push_back(make_int2(0, (int)k));
+      BCHK(make_classes(B, in_rings, B->in_classes));
     }
   }
   // pole rows
@@ -376,30 +418,29 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, arkcos_batch_
     B->n_pole_adj = (int32_t)adj.size();
   }
 
-  // segment length, group and grid: cached, else measured
-  int32_t su = 64, grp = 4, bpc = 2;
+  // band size and grid: cached, else measured
+  int32_t upb = kBandUnits, bpc = 2;
   const std::string key = tune_key(B);
-  if (read_cache(key, &su, &grp, &bpc)) {
+  if (read_cache(key, &upb, &bpc)) {
     B->tuned = 2;
   } else {
-    arkcos_status_t st = autotune(B, &su, &grp, &bpc);
+    arkcos_status_t st = autotune(B, &upb, &bpc);
     if (st != ARKCOS_OK) return st;
-    write_cache(key, su, grp, bpc);
+    write_cache(key, upb, bpc);
     B->tuned = 1;
   }
   int cus = 0;
   BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  B->seg_units = su;
-  B->group = grp;
+  B->units_per_band = upb;
   B->grid = cus * bpc;
   std::vector<int32_t> all(n);
   for (int32_t i = 0; i < n; ++i) all[i] = i;
   Queue Q;
   std::vector<void*> owned;
-  hipError_t e = build_queue(B, all, su, grp, Q, owned);
+  hipError_t e = build_queue(B, all, upb, Q, owned);
   for (void* p : owned) B->allocations.push_back(p);
   BCHK(e);
-  B->cap = Q.cap;
+  B->acc_shape = Q.shape;
   void* d = nullptr;
   BCHK(hipMalloc(&d, Q.acc_args.size()));
   B->allocations.push_back(d);
@@ -454,9 +495,11 @@ hipError_t write_ptrs(const void* const* src, int32_t n, const void** dst, hipSt
     if (_e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
   } while (0)
 
+// x: n input pointers (a shared-input batch: n copies of its one input).
 arkcos_status_t run_batch(arkcos_batch_s* B, const void* const* x, void* const* y, int32_t adjoint, void* ws,
                           hipStream_t s) {
   if (!x || !y || !ws) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
+  if (B->shared && adjoint) return fail(ARKCOS_ERR_NOT_SUPPORTED, "a shared-input batch runs the forward map only");
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(ARKCOS_ERR_INVALID_VALUE, "workspace must be 256-byte aligned");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != B->device)
@@ -484,12 +527,12 @@ arkcos_status_t run_batch(arkcos_batch_s* B, const void* const* x, void* const* 
   if (ev) BLAUNCH(hipEventRecord(ev[0], s));
   BLAUNCH(write_ptrs(x, B->n, d_xs, s));
   BLAUNCH(write_ptrs(y, B->n, d_ys, s));
-  for (const ClassDev& c : B->classes)
+  for (const ClassDev& c : (B->shared ? B->in_classes : B->classes))
     BLAUNCH(launch_ring_batch(B->dtype, false, B->d_rargs[adjoint ? 1 : 0], c.entries, c.count, c.lds, c.threads, c.mf, d_xs, spec,
                               B->d_spec_base, s));
   if (ev) BLAUNCH(hipEventRecord(ev[1], s));
   BLAUNCH(launch_accumulate_batch(B->dtype, B->d_acc_args, B->d_spec_base, B->d_out_base, B->d_items, B->n_items,
-                                  counter, spec, bout, B->grid, B->group, B->all_tables, B->cap, s));
+                                  counter, spec, bout, B->grid, B->units_per_band, B->all_tables, B->acc_shape, s));
   if (ev) BLAUNCH(hipEventRecord(ev[2], s));
   for (const ClassDev& c : B->classes)
     BLAUNCH(launch_ring_batch(B->dtype, true, B->d_rargs[adjoint ? 3 : 2], c.entries, c.count, c.lds, c.threads, c.mf, d_ys, bout,
@@ -509,7 +552,7 @@ extern "C" {
 
 arkcos_status_t arkcos_batch_plan(int32_t n, const arkcos_plan_t* plans, arkcos_batch_t* out) {
   try {
-    return build_batch(n, plans, out);
+    return build_batch(n, plans, false, out);
   } catch (const std::bad_alloc&) {
     return fail(ARKCOS_ERR_OUT_OF_MEMORY, "host allocation failed");
   } catch (...) {
@@ -517,12 +560,37 @@ arkcos_status_t arkcos_batch_plan(int32_t n, const arkcos_plan_t* plans, arkcos_
   }
 }
 
+arkcos_status_t arkcos_batch_plan_shared_input(int32_t n, const arkcos_plan_t* plans, arkcos_batch_t* out) {
+  try {
+    return build_batch(n, plans, true, out);
+  } catch (const std::bad_alloc&) {
+    return fail(ARKCOS_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(ARKCOS_ERR_INTERNAL, "unexpected exception in batch creation");
+  }
+}
+
+arkcos_status_t arkcos_batch_convolve_shared(arkcos_batch_t B, const void* x, void* const* y, void* ws,
+                                             hipStream_t stream) {
+  if (!B) return fail(ARKCOS_ERR_INVALID_VALUE, "null batch");
+  if (!B->shared) return fail(ARKCOS_ERR_INVALID_VALUE, "batch was not created with arkcos_batch_plan_shared_input");
+  if (!x) return fail(ARKCOS_ERR_INVALID_VALUE, "null input map");
+  try {
+    std::vector<const void*> xs(B->n, x);
+    return run_batch(B, xs.data(), y, 0, ws, stream);
+  } catch (const std::bad_alloc&) {
+    return fail(ARKCOS_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(ARKCOS_ERR_INTERNAL, "unexpected exception in batch call");
+  }
+}
+
 arkcos_status_t arkcos_batch_get_info(arkcos_batch_t B, arkcos_batch_info_t* info) {
   if (!B || !info) return fail(ARKCOS_ERR_INVALID_VALUE, "null argument");
   std::memset(info, 0, sizeof(*info));
   info->n_maps = B->n;
-  info->seg_units = B->seg_units;
-  info->group = B->group;
+  info->seg_units = B->units_per_band;
+  info->group = B->units_per_band;
   info->grid = B->grid;
   info->tuned = B->tuned;
   info->n_items = B->n_items;
@@ -540,6 +608,7 @@ arkcos_status_t arkcos_batch_workspace_size(arkcos_batch_t B, size_t* bytes) {
 arkcos_status_t arkcos_batch_convolve(arkcos_batch_t B, const void* const* x, void* const* y, int32_t adjoint,
                                       void* ws, hipStream_t stream) {
   if (!B) return fail(ARKCOS_ERR_INVALID_VALUE, "null batch");
+  if (B->shared) return fail(ARKCOS_ERR_INVALID_VALUE, "a shared-input batch is called with arkcos_batch_convolve_shared");
   if (adjoint != 0 && adjoint != 1) return fail(ARKCOS_ERR_INVALID_VALUE, "adjoint must be 0 or 1");
   try {
     return run_batch(B, x, y, adjoint, ws, stream);

@@ -41,17 +41,24 @@ static arkcos_status_t check_device(const arkcos_plan_s* P) {
   return ARKCOS_OK;
 }
 
+// Maps only: non-null, disjoint, aligned, and the plan's device current.
+arkcos_status_t check_plan_maps(const arkcos_plan_s* P, const void* in, const void* out) {
+  if (!in || !out) return fail(ARKCOS_ERR_INVALID_VALUE, "null map pointer");
+  const size_t bytes = (size_t)P->npix * elem_size(P);
+  if (overlaps(in, bytes, out, bytes)) return fail(ARKCOS_ERR_INVALID_VALUE, "input and output maps overlap");
+  if (reinterpret_cast<uintptr_t>(in) % elem_size(P) || reinterpret_cast<uintptr_t>(out) % elem_size(P))
+    return fail(ARKCOS_ERR_INVALID_VALUE, "misaligned map pointer");
+  return check_device(P);
+}
+
 static arkcos_status_t check_maps(const arkcos_plan_s* P, const void* in, const void* out, const void* ws) {
   if (!in || !out || !ws) return fail(ARKCOS_ERR_INVALID_VALUE, "null map or workspace pointer");
   const size_t bytes = (size_t)P->npix * elem_size(P);
-  if (overlaps(in, bytes, out, bytes)) return fail(ARKCOS_ERR_INVALID_VALUE, "input and output maps overlap");
   const size_t wsb = workspace_bytes(P);
   if (overlaps(in, bytes, ws, wsb) || overlaps(out, bytes, ws, wsb))
     return fail(ARKCOS_ERR_INVALID_VALUE, "workspace overlaps a map");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(ARKCOS_ERR_INVALID_VALUE, "workspace must be 256-byte aligned");
-  if (reinterpret_cast<uintptr_t>(in) % elem_size(P) || reinterpret_cast<uintptr_t>(out) % elem_size(P))
-    return fail(ARKCOS_ERR_INVALID_VALUE, "misaligned map pointer");
-  return check_device(P);
+  return check_plan_maps(P, in, out);
 }
 
 void workspace_split(const arkcos_plan_s* P, void* ws, void** spec, void** bout) {
@@ -118,6 +125,22 @@ arkcos_status_t arkcos_plan(const arkcos_geometry_t* geom, const arkcos_profile_
   }
 }
 
+arkcos_status_t arkcos_plan_for_error(const arkcos_geometry_t* geom, const arkcos_profile_t* profile,
+                                      const double* cl, int32_t lmax, double target_sigma2,
+                                      arkcos_dtype_t dtype, const arkcos_options_t* opts,
+                                      arkcos_plan_t* out, double* radius_rad) {
+  g_last_error.clear();
+  if (!out) return fail(ARKCOS_ERR_INVALID_VALUE, "null output handle");
+  double R = 0.0;
+  arkcos_status_t st = arkcos_choose_radius(profile, cl, lmax, target_sigma2, &R);
+  if (st != ARKCOS_OK) return st;
+  if (!(R > 0.0))
+    return fail(ARKCOS_ERR_NOT_SUPPORTED, "the truncation-error target holds without any kernel support (R = 0)");
+  st = arkcos_plan(geom, profile, R, dtype, opts, out);
+  if (st == ARKCOS_OK && radius_rad) *radius_rad = R;
+  return st;
+}
+
 arkcos_status_t arkcos_plan_destroy(arkcos_plan_t plan) {
   if (!plan) return fail(ARKCOS_ERR_INVALID_VALUE, "null plan");
   int cur = 0;
@@ -149,10 +172,11 @@ arkcos_status_t arkcos_plan_get_info(arkcos_plan_t P, arkcos_plan_info_t* info) 
   info->plan_bytes = P->plan_bytes;
   for (const auto& pr : P->h_pairs)
     if (pr.band >= 0 && pr.kind >= 0 && pr.kind < 4) ++info->pairs_by_kind[pr.kind];
-  info->acc_seg_units = P->acc.seg_units;
-  info->acc_group = P->acc.group;
-  info->acc_window = P->acc.cap;
-  info->acc_tuned = P->acc.tuned;
+  info->acc_seg_units = kBandUnits;
+  info->acc_group = kBandUnits;
+  info->acc_window = P->acc_shape.max_window;
+  info->acc_tuned = 0;
+  info->support_radius_rad = P->radius;
   return ARKCOS_OK;
 }
 

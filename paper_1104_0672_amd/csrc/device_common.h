@@ -65,9 +65,6 @@ template <typename R> __device__ __forceinline__ cx_t<R> chirp(int l, int n) {
 // is synchronised on entry and exit.  INV = true gives the unnormalised
 // inverse.  tw: exp(-2 pi i k / TN) for k < TN, TN a multiple of M.
 // ---------------------------------------------------------------------------
-template <typename R> struct FftLimits;
-template <> struct FftLimits<float> { static constexpr int kMaxM = 8192; };
-template <> struct FftLimits<double> { static constexpr int kMaxM = 4096; };
 
 __device__ __forceinline__ int lidx(int i) { return i + (i >> 5); }
 __host__ __device__ constexpr int lds_elems(int m) { return m + (m >> 5) + 1; }

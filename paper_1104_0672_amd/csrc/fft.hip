@@ -443,9 +443,14 @@ template <typename R> RingArgs<R> ring_args(arkcos_plan_s* P, bool out_side, int
   return a;
 }
 
-// Threads per block for a ring class whose longest FFT has length fft_len.
+// Threads per block for a ring class whose longest FFT has length fft_len:
+// at least 256, and enough for 16 points per thread (FP32 up to 16384 points
+// in 1024 threads, FP64 up to 8192 in 512: 135 KB of LDS either way).
 int fft_threads(arkcos_dtype_t dt, int32_t fft_len) {
-  return (dt == ARKCOS_F32 && fft_len > kFftCap<256>) ? 512 : 256;
+  (void)dt;
+  int nt = 256;
+  while (16 * nt < fft_len) nt *= 2;
+  return nt;
 }
 
 int32_t ct_fft_length(arkcos_dtype_t dt, int32_t fft_len, int64_t rings) {
@@ -476,9 +481,13 @@ hipError_t configure_fft_kernels(arkcos_plan_s* P) {
     if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 512, 8192>, b);
     if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 128, 2048>, b);
     if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 64, 1024>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 1024, 0>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 1024, 0>, b);
   } else {
     if (e == hipSuccess) e = allow_lds(r2c_kernel<double, 256, 0>, b);
     if (e == hipSuccess) e = allow_lds(c2r_kernel<double, 256, 0>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<double, 512, 0>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<double, 512, 0>, b);
   }
   return e;
 }
@@ -506,10 +515,14 @@ static void r2c_class(const FftClass& c, const RingArgs<R>& a, const void* x, vo
       r2c_kernel<R, 64, 1024><<<(unsigned)c.count, 64, c.lds, s>>>(a, c.d_rings, xi, so);
       return;
     }
-    if (c.threads == 512) {
-      r2c_kernel<R, 512, 0><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, xi, so);
+    if (c.threads == 1024) {
+      r2c_kernel<R, 1024, 0><<<(unsigned)c.count, 1024, c.lds, s>>>(a, c.d_rings, xi, so);
       return;
     }
+  }
+  if (c.threads == 512) {
+    r2c_kernel<R, 512, 0><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, xi, so);
+    return;
   }
   r2c_kernel<R, 256, 0><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, xi, so);
 }
@@ -535,10 +548,14 @@ static void c2r_class(const FftClass& c, const RingArgs<R>& a, const void* b, vo
       c2r_kernel<R, 64, 1024><<<(unsigned)c.count, 64, c.lds, s>>>(a, c.d_rings, bi, yo);
       return;
     }
-    if (c.threads == 512) {
-      c2r_kernel<R, 512, 0><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, bi, yo);
+    if (c.threads == 1024) {
+      c2r_kernel<R, 1024, 0><<<(unsigned)c.count, 1024, c.lds, s>>>(a, c.d_rings, bi, yo);
       return;
     }
+  }
+  if (c.threads == 512) {
+    c2r_kernel<R, 512, 0><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, bi, yo);
+    return;
   }
   c2r_kernel<R, 256, 0><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, bi, yo);
 }
@@ -556,11 +573,19 @@ hipError_t launch_r2c(arkcos_plan_s* P, const void* x, void* spec, int32_t adjoi
 
 size_t ring_args_size() { return sizeof(RingArgs<float>); }
 
-void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out) {
-  if (P->dtype == ARKCOS_F32)
-    *reinterpret_cast<RingArgs<float>*>(out) = ring_args<float>(P, out_side, adjoint, zero_pole);
-  else
-    *reinterpret_cast<RingArgs<double>*>(out) = ring_args<double>(P, out_side, adjoint, zero_pole);
+void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out,
+                    const int64_t* off, const int32_t* len) {
+  if (P->dtype == ARKCOS_F32) {
+    RingArgs<float> a = ring_args<float>(P, out_side, adjoint, zero_pole);
+    if (off) a.off = off;
+    if (len) a.len = len;
+    *reinterpret_cast<RingArgs<float>*>(out) = a;
+  } else {
+    RingArgs<double> a = ring_args<double>(P, out_side, adjoint, zero_pole);
+    if (off) a.off = off;
+    if (len) a.len = len;
+    *reinterpret_cast<RingArgs<double>*>(out) = a;
+  }
 }
 
 // Batched ring transforms: forward (R2C of maps[m] into ws + base[m]) or
@@ -596,10 +621,12 @@ hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, 
       return ring_batch<float, 128, 2048>(inverse, args, entries, count, lds, maps, ws, base, s);
     if (threads == 64 && mf == 1024)
       return ring_batch<float, 64, 1024>(inverse, args, entries, count, lds, maps, ws, base, s);
+    if (threads == 1024) return ring_batch<float, 1024, 0>(inverse, args, entries, count, lds, maps, ws, base, s);
     return threads == 512 ? ring_batch<float, 512, 0>(inverse, args, entries, count, lds, maps, ws, base, s)
                           : ring_batch<float, 256, 0>(inverse, args, entries, count, lds, maps, ws, base, s);
   }
-  return ring_batch<double, 256, 0>(inverse, args, entries, count, lds, maps, ws, base, s);
+  return threads == 512 ? ring_batch<double, 512, 0>(inverse, args, entries, count, lds, maps, ws, base, s)
+                        : ring_batch<double, 256, 0>(inverse, args, entries, count, lds, maps, ws, base, s);
 }
 
 // Step (a) into the output-ring layout (lengths out_len): the extended

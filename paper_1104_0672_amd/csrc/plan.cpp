@@ -58,27 +58,6 @@ bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 }  // namespace
 
-// Clamped cubic spline moments (second derivatives at the knots) for
-// equispaced knots with spacing h; end slopes zero.
-void spline_moments(const std::vector<double>& c, double h, std::vector<double>& M) {
-  const int n = (int)c.size();
-  std::vector<double> sub(n), diag(n), sup(n), rhs(n);
-  const double s = 6.0 / (h * h);
-  for (int k = 0; k < n; ++k) {
-    if (k == 0) { sub[k] = 0; diag[k] = 2; sup[k] = 1; rhs[k] = s * (c[1] - c[0]); }
-    else if (k == n - 1) { sub[k] = 1; diag[k] = 2; sup[k] = 0; rhs[k] = -s * (c[n - 1] - c[n - 2]); }
-    else { sub[k] = 1; diag[k] = 4; sup[k] = 1; rhs[k] = s * (c[k + 1] - 2 * c[k] + c[k - 1]); }
-  }
-  for (int k = 1; k < n; ++k) {
-    double f = sub[k] / diag[k - 1];
-    diag[k] -= f * sup[k - 1];
-    rhs[k] -= f * rhs[k - 1];
-  }
-  M.assign(n, 0.0);
-  M[n - 1] = rhs[n - 1] / diag[n - 1];
-  for (int k = n - 2; k >= 0; --k) M[k] = (rhs[k] - sup[k] * M[k + 1]) / diag[k];
-}
-
 #define HIPCHK(expr)                                                                      \
   do {                                                                                    \
     hipError_t _e = (expr);                                                               \
@@ -184,7 +163,10 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P) {
   }
   struct Free { void* a; void* b; ~Free() { if (a) hipFree(a); if (b) hipFree(b); } } fr{d_abs, d_band};
 
-  // kernel samples over each pair's full window, indexed by coefficient offsets
+  // kernel samples over each pair's full window, indexed by coefficient
+  // offsets: until the table choices below, a pair's off is its sample
+  // offset (the band kernel reads the samples through it)
+  for (int64_t q = 0; q < np; ++q) P->h_pairs[q].off = P->h_coef_off[q];
   HIPCHK(hipMemcpy(P->d_pairs, P->h_pairs.data(), np * sizeof(PairDev), hipMemcpyHostToDevice));
   HIPCHK(launch_kernel_rows(P, d_abs, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -333,49 +315,17 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P) {
   return ARKCOS_OK;
 }
 
-// Clamped-spline moments of the knot values src (n of them, spacing h),
-// solved on the device by the tridiagonal (Thomas) recurrence; the knots are
-// copied to knots first (src may equal knots).  One thread: n <= 64.
-__global__ void spline_update_kernel(const double* __restrict__ src, int n, double h, double* knots, double* mom) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double c[64], diag[64], rhs[64];
-  for (int k = 0; k < n; ++k) c[k] = src[k];
-  for (int k = 0; k < n; ++k) knots[k] = c[k];
-  const double s6 = 6.0 / (h * h);
-  for (int k = 0; k < n; ++k) {
-    if (k == 0) { diag[k] = 2; rhs[k] = s6 * (c[1] - c[0]); }
-    else if (k == n - 1) { diag[k] = 2; rhs[k] = -s6 * (c[n - 1] - c[n - 2]); }
-    else { diag[k] = 4; rhs[k] = s6 * (c[k + 1] - 2 * c[k] + c[k - 1]); }
-  }
-  // sub- and super-diagonals are 1 everywhere they exist
-  for (int k = 1; k < n; ++k) {
-    const double f = 1.0 / diag[k - 1];
-    diag[k] -= f;
-    rhs[k] -= f * rhs[k - 1];
-  }
-  double next = rhs[n - 1] / diag[n - 1];
-  mom[n - 1] = next;
-  for (int k = n - 2; k >= 0; --k) {
-    next = (rhs[k] - next) / diag[k];
-    mom[k] = next;
-  }
-}
-
 // New spline knots (device array of n_knots doubles) applied on stream s:
 // moments, kernel samples and K_ij(m) tables recomputed in place with the
 // layout of plan creation.  Enqueues kernels only (no allocation, no host
 // synchronisation), so it can be captured in a graph.
 hipError_t update_knots(arkcos_plan_s* P, const double* d_src, hipStream_t s) {
-  const int n = (int)P->knots.size();
-  spline_update_kernel<<<1, 64, 0, s>>>(d_src, n, P->theta_max / (n - 1), P->d_knots, P->d_spline_mom);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_spline_update(P, d_src, s);
   if (e != hipSuccess) return e;
   e = launch_kernel_rows(P, nullptr, s);
   if (e != hipSuccess) return e;
   return launch_table_list(P, P->d_tab_list, P->d_tab_coef, P->n_tab_list, s);
 }
-
-arkcos_status_t choose_acc_config(arkcos_plan_s* P);
 
 arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* prof, double R,
                            arkcos_dtype_t dtype, const arkcos_options_t* o, arkcos_plan_s** out) {
@@ -575,7 +525,10 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   P->n_pairs = (int64_t)P->h_pairs.size();
 
   // ------------------------------------------------------ FFT strategies
-  const int64_t maxM = dtype == ARKCOS_F32 ? 8192 : 4096;
+  // LDS FFTs of up to 16384 (FP32) or 8192 (FP64) complex points: 135 KB
+  // of the CU's 160 KB, one 1024- or 512-thread block per ring (nside 4096
+  // in FP32, 2048 in FP64)
+  const int64_t maxM = dtype == ARKCOS_F32 ? 16384 : 8192;
   const size_t csz = dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
   const size_t rsz = dtype == ARKCOS_F32 ? sizeof(float) : sizeof(double);
   std::vector<int32_t> fft_kind(nr), fft_m(nr);
@@ -843,11 +796,22 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   HIPCHK(upload(P, &P->rt.out_len, P->h_out_len));
   HIPCHK(upload(P, &P->d_units, P->h_units));
 
-  // segments of consecutive units and their (segment, mode tile) items
+  // bands of consecutive units, and work items: (band, first mode) tiles
+  build_bands(P, kBandUnits, P->h_bands, &P->acc_shape);
   {
-    arkcos_status_t st = choose_acc_config(P);
-    if (st != ARKCOS_OK) return st;
+    std::vector<WorkItem> its;
+    std::vector<double> cost;
+    accumulation_items(P, P->h_bands, its, cost);
+    // heaviest first, so that the launch does not end on a long item
+    std::vector<size_t> ord(its.size());
+    for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    P->h_items.clear();
+    for (size_t k : ord) P->h_items.push_back(its[k]);
   }
+  HIPCHK(upload(P, &P->d_items, P->h_items));
+  HIPCHK(upload(P, &P->d_bands, P->h_bands));
+  HIPCHK(configure_accumulate(P));
 
   // rings whose pixels can lie within R of a pole pixel (direct-sum columns)
   if (g->kind == 1) {
@@ -865,168 +829,62 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   return ARKCOS_OK;
 }
 
-// Work items of the accumulation: every (segment, mode tile) that some unit
-// of the segment reaches, with an estimate of its cost (table pairs, or the
-// recurrence length of the others, still inside their band at that tile).
-void accumulation_items(const arkcos_plan_s* P, const std::vector<SegDev>& segs, std::vector<WorkItem>& items,
+// Work items of the accumulation: each band's mode tiles in runs of
+// kTilesPerItem, with an estimate of their cost (recurrence length of the
+// pairs still inside their band, summed over the tiles).
+void accumulation_items(const arkcos_plan_s* P, const std::vector<BandDev>& bands, std::vector<WorkItem>& items,
                         std::vector<double>& cost) {
   items.clear();
   cost.clear();
-  for (int32_t s = 0; s < (int32_t)segs.size(); ++s) {
-    const SegDev& sg = segs[s];
-    if (sg.band < 0) continue;
-    for (int32_t t = 0; t <= sg.band / kSweepTile; ++t) {
-      const int32_t m0 = t * kSweepTile;
+  for (int32_t b = 0; b < (int32_t)bands.size(); ++b) {
+    const BandDev& bd = bands[b];
+    if (bd.band < 0) continue;
+    const int32_t ntile = bd.band / kAccTile + 1;
+    for (int32_t t0 = 0; t0 < ntile; t0 += kTilesPerItem) {
+      const int32_t nt = std::min(kTilesPerItem, ntile - t0);
       double c = 0.0;
-      for (int32_t u = sg.u0; u < sg.u0 + sg.nu; ++u) {
+      for (int32_t u = bd.u0; u < bd.u0 + bd.nu; ++u) {
         const UnitDev& U = P->h_units[u];
-        if (U.band < m0) continue;
-        c += 4.0;
         for (int32_t q = U.pbeg; q < U.pend; ++q) {
           const PairDev& pr = P->h_pairs[q];
-          if (pr.band < m0) continue;
-          c += pr.kind == KG_TABLE ? 1.0 : (double)((pr.ncoef + 7) / 8) * 4.0;
+          const int32_t live = std::min(nt, pr.band / kAccTile + 1 - t0);
+          if (live <= 0) continue;
+          c += live * (pr.kind == KG_TABLE ? 3.0 : (double)((pr.ncoef + 3) / 4 * 4) + 4.0);
         }
       }
-      items.push_back(WorkItem{s, t, 1, 0});
-      cost.push_back(c);
+      items.push_back(WorkItem{b, t0, nt, 0});
+      cost.push_back(c + 8.0 * nt);
     }
   }
 }
 
-// Segments of seg_units consecutive units, swept `group` units at a time;
-// *cap receives the ring slots the LDS window needs: the input rings of two
-// consecutive groups (the current one and the one whose rows are loaded
-// while it is summed).
-void build_segments(const arkcos_plan_s* P, int32_t seg_units, int32_t group, std::vector<SegDev>& segs,
-                    int32_t* cap) {
-  segs.clear();
-  int32_t c = 1;
-  const int64_t nunits = P->n_units;
-  for (int64_t u0 = 0; u0 < nunits; u0 += seg_units) {
-    SegDev S{};
-    S.u0 = (int32_t)u0;
-    S.nu = (int32_t)std::min<int64_t>(seg_units, nunits - u0);
-    S.jlo = P->h_units[u0].jlo;
-    S.band = -1;
-    for (int64_t u = u0; u < u0 + S.nu; ++u) S.band = std::max(S.band, P->h_units[u].band);
-    for (int64_t g = u0; g < u0 + S.nu; g += group) {
-      const int64_t last = std::min<int64_t>(g + 2 * group, u0 + S.nu) - 1;
-      c = std::max(c, P->h_units[last].jhi - P->h_units[g].jlo + 1);
+// Groups consecutive units into bands of units_per_band, with the input-ring
+// window of each band and the largest window.
+void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<BandDev>& bands, AccShape* shape) {
+  bands.clear();
+  *shape = AccShape{};
+  const int64_t nunits = P->n_units, nr = P->nrings;
+  for (int64_t u0 = 0; u0 < nunits; u0 += units_per_band) {
+    BandDev B{};
+    B.u0 = (int32_t)u0;
+    B.nu = (int32_t)std::min<int64_t>(units_per_band, nunits - u0);
+    B.jlo = (int32_t)nr;
+    B.jhi = -1;
+    B.band = -1;
+    B.pbeg = P->h_units[u0].pbeg;
+    B.npair = P->h_units[u0 + B.nu - 1].pend - B.pbeg;
+    for (int64_t u = u0; u < u0 + B.nu; ++u) {
+      const UnitDev& U = P->h_units[u];
+      if (U.pend > U.pbeg) {
+        B.jlo = std::min(B.jlo, P->h_pairs[U.pbeg].j);
+        B.jhi = std::max(B.jhi, P->h_pairs[U.pend - 1].j);
+      }
+      B.band = std::max(B.band, U.band);
     }
-    segs.push_back(S);
+    if (B.jhi >= B.jlo) shape->max_window = std::max(shape->max_window, B.jhi - B.jlo + 1);
+    shape->max_band_pairs = std::max(shape->max_band_pairs, B.npair);
+    bands.push_back(B);
   }
-  *cap = c;
-}
-
-namespace {
-
-// Largest LDS window the accumulation uses (bytes); wider windows make the
-// kernel read the spectra straight from memory instead (cap = 0).
-constexpr size_t kMaxWindowBytes = 96 * 1024;
-
-hipError_t make_acc_config(arkcos_plan_s* P, int32_t seg_units, int32_t group, AccConfig& c,
-                           std::vector<void*>& owned) {
-  std::vector<SegDev> segs;
-  int32_t cap = 0;
-  build_segments(P, seg_units, group, segs, &cap);
-  if (acc_lds_bytes(P->dtype, cap) > kMaxWindowBytes) cap = 0;
-  std::vector<WorkItem> its;
-  std::vector<double> cost;
-  accumulation_items(P, segs, its, cost);
-  // heaviest first, so that the launch does not end on a long item
-  std::vector<size_t> ord(its.size());
-  for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
-  std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-  std::vector<WorkItem> sorted;
-  for (size_t k : ord) sorted.push_back(its[k]);
-  c = AccConfig{};
-  c.seg_units = seg_units;
-  c.group = group;
-  c.cap = cap;
-  c.n_items = (int32_t)sorted.size();
-  void *ds = nullptr, *di = nullptr;
-  hipError_t e = hipMalloc(&ds, std::max<size_t>(segs.size(), 1) * sizeof(SegDev));
-  if (e != hipSuccess) return e;
-  owned.push_back(ds);
-  e = hipMalloc(&di, std::max<size_t>(sorted.size(), 1) * sizeof(WorkItem));
-  if (e != hipSuccess) return e;
-  owned.push_back(di);
-  if (!segs.empty()) e = hipMemcpy(ds, segs.data(), segs.size() * sizeof(SegDev), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !sorted.empty())
-    e = hipMemcpy(di, sorted.data(), sorted.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
-  c.d_segs = (SegDev*)ds;
-  c.d_items = (WorkItem*)di;
-  return e;
-}
-
-}  // namespace
-
-// The accumulation's segment length and group size.  Large plans time each
-// candidate on a scratch workspace (the kernel's control flow does not depend
-// on the data) and keep the fastest; small plans take 64 units in groups of
-// 4.  ARKCOS_ACC_CONFIG="S,G" forces a choice.  The result does not depend on
-// the choice: every unit sums its pairs in the same order.
-arkcos_status_t choose_acc_config(arkcos_plan_s* P) {
-  std::vector<std::pair<int32_t, int32_t>> cand;
-  if (const char* e = getenv("ARKCOS_ACC_CONFIG"); e && *e) {
-    int a = 0, b = 0;
-    if (sscanf(e, "%d,%d", &a, &b) == 2 && a > 0 && (b == 4 || b == 8)) cand.push_back({a, b});
-  }
-  if (cand.empty()) {
-    if (P->npix >= (int64_t(1) << 20))
-      cand = {{32, 4}, {64, 4}, {128, 4}, {32, 8}, {64, 8}, {128, 8}};
-    else
-      cand = {{64, 4}};
-  }
-  std::vector<void*> owned;
-  struct Free {
-    std::vector<void*>* v;
-    ~Free() { for (void* a : *v) hipFree(a); }
-  } fr{&owned};
-  if (cand.size() == 1) {
-    HIPCHK(make_acc_config(P, cand[0].first, cand[0].second, P->acc, owned));
-    for (void* a : owned) P->allocations.push_back(a);
-    owned.clear();
-    return ARKCOS_OK;
-  }
-  void* ws = nullptr;
-  const size_t wsb = workspace_bytes(P);
-  HIPCHK(hipMalloc(&ws, wsb));
-  owned.push_back(ws);
-  HIPCHK(hipMemset(ws, 0, wsb));
-  void *spec = nullptr, *bout = nullptr;
-  workspace_split(P, ws, &spec, &bout);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  struct Ev {
-    hipEvent_t a, b;
-    ~Ev() { hipEventDestroy(a); hipEventDestroy(b); }
-  } ev{e0, e1};
-  float best = 1e30f;
-  size_t best_k = 0;
-  std::vector<AccConfig> cfg(cand.size());
-  std::vector<std::vector<void*>> mem(cand.size());
-  for (size_t k = 0; k < cand.size(); ++k) {
-    HIPCHK(make_acc_config(P, cand[k].first, cand[k].second, cfg[k], mem[k]));
-    HIPCHK(launch_accumulate_config(P, cfg[k], spec, bout, nullptr));
-    HIPCHK(hipEventRecord(e0, nullptr));
-    for (int r = 0; r < 3; ++r) HIPCHK(launch_accumulate_config(P, cfg[k], spec, bout, nullptr));
-    HIPCHK(hipEventRecord(e1, nullptr));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
-      best_k = k;
-    }
-  }
-  for (size_t k = 0; k < cand.size(); ++k)
-    for (void* a : mem[k]) (k == best_k ? P->allocations : owned).push_back(a);
-  P->acc = cfg[best_k];
-  P->acc.tuned = 1;
-  return ARKCOS_OK;
 }
 
 int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count) {

@@ -222,6 +222,40 @@ __global__ void __launch_bounds__(NT) bluestein_filter_kernel(
   for (int r = threadIdx.x; r <= n / 2; r += blockDim.x) o[M + n + r] = cconj(expipi<R>(r, 2 * n));
 }
 
+// Clamped-spline moments of the knot values src (n of them, spacing h),
+// solved on the device by the tridiagonal (Thomas) recurrence; the knots are
+// copied to knots first (src may equal knots).  One thread: n <= 64.
+__global__ void spline_update_kernel(const double* __restrict__ src, int n, double h, double* knots, double* mom) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double c[64], diag[64], rhs[64];
+  for (int k = 0; k < n; ++k) c[k] = src[k];
+  for (int k = 0; k < n; ++k) knots[k] = c[k];
+  const double s6 = 6.0 / (h * h);
+  for (int k = 0; k < n; ++k) {
+    if (k == 0) { diag[k] = 2; rhs[k] = s6 * (c[1] - c[0]); }
+    else if (k == n - 1) { diag[k] = 2; rhs[k] = -s6 * (c[n - 1] - c[n - 2]); }
+    else { diag[k] = 4; rhs[k] = s6 * (c[k + 1] - 2 * c[k] + c[k - 1]); }
+  }
+  // sub- and super-diagonals are 1 everywhere they exist
+  for (int k = 1; k < n; ++k) {
+    const double f = 1.0 / diag[k - 1];
+    diag[k] -= f;
+    rhs[k] -= f * rhs[k - 1];
+  }
+  double next = rhs[n - 1] / diag[n - 1];
+  mom[n - 1] = next;
+  for (int k = n - 2; k >= 0; --k) {
+    next = (rhs[k] - next) / diag[k];
+    mom[k] = next;
+  }
+}
+
+hipError_t launch_spline_update(arkcos_plan_s* P, const double* d_src, hipStream_t s) {
+  const int n = (int)P->knots.size();
+  spline_update_kernel<<<1, 64, 0, s>>>(d_src, n, P->theta_max / (n - 1), P->d_knots, P->d_spline_mom);
+  return hipGetLastError();
+}
+
 static ProfileDev make_profile(arkcos_plan_s* P) {
   ProfileDev pd{};
   pd.kind = P->prof_kind;
@@ -288,7 +322,14 @@ hipError_t launch_bluestein_filters(arkcos_plan_s* P, const int32_t* d_ring_list
   const int lds = (int)((size_t)lds_elems(P->max_bl_m) * (P->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2)));
   const int nt = fft_threads(P->dtype, P->max_bl_m);
   hipError_t e;
-  if (P->dtype == ARKCOS_F32 && nt == 512) {
+  if (P->dtype == ARKCOS_F32 && nt == 1024) {
+    e = hipFuncSetAttribute((const void*)bluestein_filter_kernel<float, 1024>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    bluestein_filter_kernel<float, 1024><<<count, 1024, lds, s>>>(
+        d_ring_list, P->rt.n, P->rt.fft_m, P->rt.bl_off, (const float2*)P->d_twiddle, P->twiddle_n,
+        (float2*)P->d_bl);
+  } else if (P->dtype == ARKCOS_F32 && nt == 512) {
     e = hipFuncSetAttribute((const void*)bluestein_filter_kernel<float, 512>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
@@ -302,6 +343,13 @@ hipError_t launch_bluestein_filters(arkcos_plan_s* P, const int32_t* d_ring_list
     bluestein_filter_kernel<float, 256><<<count, 256, lds, s>>>(
         d_ring_list, P->rt.n, P->rt.fft_m, P->rt.bl_off, (const float2*)P->d_twiddle, P->twiddle_n,
         (float2*)P->d_bl);
+  } else if (nt == 512) {
+    e = hipFuncSetAttribute((const void*)bluestein_filter_kernel<double, 512>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    bluestein_filter_kernel<double, 512><<<count, 512, lds, s>>>(
+        d_ring_list, P->rt.n, P->rt.fft_m, P->rt.bl_off, (const double2*)P->d_twiddle, P->twiddle_n,
+        (double2*)P->d_bl);
   } else {
     e = hipFuncSetAttribute((const void*)bluestein_filter_kernel<double, 256>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);

@@ -14,6 +14,29 @@
 #include <vector>
 
 namespace arkcos {
+
+// Clamped cubic spline moments (second derivatives at the knots) for
+// equispaced knots with spacing h; end slopes zero (host code shared with
+// the plan builder).
+void spline_moments(const std::vector<double>& c, double h, std::vector<double>& M) {
+  const int n = (int)c.size();
+  std::vector<double> sub(n), diag(n), sup(n), rhs(n);
+  const double s = 6.0 / (h * h);
+  for (int k = 0; k < n; ++k) {
+    if (k == 0) { sub[k] = 0; diag[k] = 2; sup[k] = 1; rhs[k] = s * (c[1] - c[0]); }
+    else if (k == n - 1) { sub[k] = 1; diag[k] = 2; sup[k] = 0; rhs[k] = -s * (c[n - 1] - c[n - 2]); }
+    else { sub[k] = 1; diag[k] = 4; sup[k] = 1; rhs[k] = s * (c[k + 1] - 2 * c[k] + c[k - 1]); }
+  }
+  for (int k = 1; k < n; ++k) {
+    double f = sub[k] / diag[k - 1];
+    diag[k] -= f * sup[k - 1];
+    rhs[k] -= f * rhs[k - 1];
+  }
+  M.assign(n, 0.0);
+  M[n - 1] = rhs[n - 1] / diag[n - 1];
+  for (int k = n - 2; k >= 0; --k) M[k] = (rhs[k] - sup[k] * M[k + 1]) / diag[k];
+}
+
 namespace {
 
 constexpr int kNodes = 16;

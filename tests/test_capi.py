@@ -89,3 +89,27 @@ def test_default_options(lib):
     lib.arkcos_default_options(ctypes.byref(o))
     assert (o.oversample, o.kgen, o.fix_pole_pixels, o.band_tol, o.mode, o.own_grid, o.kernel_eval,
             o.table_nodes, tuple(o.reserved)) == (0, 0, 1, -1.0, 0, 0, 0, 0, (0, 0, 0, 0))
+
+
+def test_device_code_is_built_for_gfx950_only(lib):
+    """Every object of the library that carries device code carries it for
+    gfx950 and for no other target: a kernel in a source compiled without the
+    target would have no code object on the MI355X."""
+    build = os.path.join(ROOT, "paper_1104_0672_amd", "_build")
+    objs = sorted(f for f in os.listdir(build) if f.endswith(".o"))
+    assert objs
+    with_device = 0
+    for f in objs:
+        path = os.path.join(build, f)
+        sections = subprocess.run(["readelf", "-S", path], capture_output=True, text=True).stdout
+        if ".hip_fatbin" not in sections:
+            continue
+        dump = os.path.join(build, f + ".fatbin.tmp")
+        subprocess.run(["objcopy", "-O", "binary", "--only-section=.hip_fatbin", path, dump], check=True)
+        data = open(dump, "rb").read()
+        os.remove(dump)
+        targets = set(re.findall(rb"amdgcn-amd-amdhsa--(gfx[0-9a-z]+)", data))
+        if targets:
+            with_device += 1
+            assert targets == {b"gfx950"}, (f, targets)
+    assert with_device >= 6  # the .hip sources

@@ -67,11 +67,14 @@ def test_fix_pole_pixels_off_matches_reference():
 
 
 def test_unsupported_sizes_are_rejected():
+    """Ring FFTs run in one workgroup's LDS up to 16384 (FP32) or 8192 (FP64)
+    complex points: the polar rings' Bluestein transforms stop nside 8192 in
+    FP32 and nside 4096 in FP64."""
     from paper_1104_0672_amd import ArkcosError, Plan
     with pytest.raises(ArkcosError, match="NOT_SUPPORTED"):
-        Plan("healpix", 0.01, nside=4096, fwhm=0.002, dtype="f32")
+        Plan("healpix", 0.002, nside=8192, fwhm=0.0005, dtype="f32")
     with pytest.raises(ArkcosError, match="NOT_SUPPORTED"):
-        Plan("healpix", 0.01, nside=2048, fwhm=0.002, dtype="f64")
+        Plan("healpix", 0.004, nside=4096, fwhm=0.001, dtype="f64")
 
 
 def test_aliasing_and_argument_errors():

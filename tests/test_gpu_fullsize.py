@@ -165,7 +165,11 @@ def test_healpix1024_spline_gradient_all_knots_against_the_definition():
     print(f"  max |g32 - g64| / max|g_def| = {e_prec.max():.2e}", flush=True)
     assert e_prec.max() <= 2e-5
     assert e_meth[:62].max() <= 3e-3 and e_meth[62:].max() <= 3e-2
-    # central differences of the oracle's loss on the sampled rows
+    # central differences of the oracle's loss on the sampled rows.  The loss
+    # is quadratic in the knots, so they are exact up to rounding; the two
+    # losses are O(rows) and differ by O(h g), so their difference is taken
+    # row by row and summed exactly (fsum): rounding then stays near
+    # sqrt(rows) eps / h, far below 1e-7 of the largest gradient
     cref = oracle.direct(w.grid, w.profile, w.radius, x, idx=idx)
     h = 1e-3
     for k in (0, 7, 31, 62, 63):
@@ -173,12 +177,11 @@ def test_healpix1024_spline_gradient_all_knots_against_the_definition():
         e[k] = 1.0
         pk = W.Profile("spline", theta_max=w.profile.theta_max, knots=tuple(e))
         ck = oracle.direct(w.grid, pk, w.radius, x, idx=idx)
-        lp = 0.5 * np.sum((cref + h * ck - t[idx]) ** 2)
-        lm = 0.5 * np.sum((cref - h * ck - t[idx]) ** 2)
-        fd = (lp - lm) / (2 * h)
+        dl = 0.5 * ((cref + h * ck - t[idx]) ** 2 - (cref - h * ck - t[idx]) ** 2)
+        fd = math.fsum(dl) / (2 * h)
         print(f"  knot {k}: central difference {fd:.6e}, definition {g_def[k]:.6e}, GPU FP32 {g32[k]:.6e}",
               flush=True)
-        assert abs(fd - g_def[k]) <= 1e-9 * scale
+        assert abs(fd - g_def[k]) <= 1e-7 * scale
         assert abs(g32[k] - fd) <= (e_meth[k] + 2e-5) * scale * 1.01
 
 

@@ -118,9 +118,9 @@ def make_input(w: Workload) -> np.ndarray:
         idx, amp = point_sources(npix, 200, w.seed, loguniform=False)
         np.add.at(x, idx, amp)
         return x
-    if w.name.startswith("healpix2048"):
+    if w.name.startswith("healpix2048") or w.name.startswith("healpix4096"):
         x = white_noise(npix, w.seed, scale=1e-4)
-        idx, amp = point_sources(npix, 2000, w.seed, loguniform=True)
+        idx, amp = point_sources(npix, 2000 if w.grid.nside == 2048 else 8000, w.seed, loguniform=True)
         np.add.at(x, idx, amp)
         return x
     return white_noise(npix, w.seed)
@@ -150,6 +150,14 @@ def healpix2048() -> Workload:
     1e-4 white noise plus 2000 log-uniform point sources."""
     return Workload("healpix2048_5arcmin", Grid("healpix", nside=2048), gaussian(5.0),
                     20.0 * ARCMIN, "f32", 3)
+
+
+def healpix4096() -> Workload:
+    """HEALPix nside 4096 (201,326,592 pixels), FP32, the same 5' Gaussian
+    cut at 20' as the nside-2048 workload (a higher-resolution channel, the
+    scale the paper's Sect. 5 looks ahead to), with the same input recipe."""
+    return Workload("healpix4096_5arcmin", Grid("healpix", nside=4096), gaussian(5.0),
+                    20.0 * ARCMIN, "f32", 6)
 
 
 def healpix1024_spline(n_knots: int = 64) -> Workload:

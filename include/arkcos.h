@@ -198,6 +198,20 @@ arkcos_status_t arkcos_workspace_size(arkcos_plan_t plan, size_t* bytes);
 arkcos_status_t arkcos_convolve(arkcos_plan_t plan, const void* x, void* y, void* ws,
                                 hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): y = C x exactly as
+ * arkcos_convolve computes it (same kernels, same order, the same bits), with
+ * the workspace taken from a fixed device array inside the library
+ * (arkcos_noalloc_scratch_bytes() bytes, 64 MiB, per device, held until the
+ * process ends) instead of a caller's buffer.  No allocation of any kind.
+ * Plans whose arkcos_workspace_size exceeds the array are rejected with
+ * ARKCOS_ERR_NOT_SUPPORTED before any work is enqueued.  Every call on one
+ * device shares that device's array: calls that may overlap in time on one
+ * device race (serialise them, e.g. on one stream).  x, y as for
+ * arkcos_convolve. */
+arkcos_status_t arkcos_convolve_noalloc(arkcos_plan_t plan, const void* x, void* y, hipStream_t stream);
+size_t arkcos_noalloc_scratch_bytes(void);
+
 /* xbar = C^T r, the exact transpose of arkcos_convolve as a linear map: the
  * same ring pipeline with the roles of the ring pairs swapped, K_ji and the
  * pixel weights, i.e. xbar = w * C(r / w); the direct-sum pole rows transpose

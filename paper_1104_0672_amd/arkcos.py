@@ -67,7 +67,8 @@ EXPORTED = ["arkcos_default_options", "arkcos_plan", "arkcos_plan_destroy", "ark
             "arkcos_batch_convolve", "arkcos_batch_timing", "arkcos_batch_stage_times", "arkcos_batch_destroy",
             "arkcos_plan_timing", "arkcos_stage_times", "arkcos_status_string", "arkcos_last_error",
             "arkcos_truncation_variance", "arkcos_choose_radius", "arkcos_plan_for_error",
-            "arkcos_batch_plan_shared_input", "arkcos_batch_convolve_shared"]
+            "arkcos_batch_plan_shared_input", "arkcos_batch_convolve_shared",
+            "arkcos_convolve_noalloc", "arkcos_noalloc_scratch_bytes"]
 
 _lib = None
 
@@ -95,6 +96,9 @@ def load_library(path: str = LIB_PATH):
     lib.arkcos_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.arkcos_convolve.argtypes = [vp, vp, vp, vp, vp]
     lib.arkcos_convolve_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    lib.arkcos_convolve_noalloc.argtypes = [vp, vp, vp, vp]
+    lib.arkcos_noalloc_scratch_bytes.argtypes = []
+    lib.arkcos_noalloc_scratch_bytes.restype = ctypes.c_size_t
     lib.arkcos_kernel_grad.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint32, vp]
     lib.arkcos_set_knots.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.arkcos_set_knots_async.argtypes = [vp, vp, vp]
@@ -118,6 +122,8 @@ def load_library(path: str = LIB_PATH):
     lib.arkcos_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         f = getattr(lib, name)
+        if name == "arkcos_noalloc_scratch_bytes":
+            continue
         if f.restype is ctypes.c_int or name in ("arkcos_plan", "arkcos_plan_destroy", "arkcos_plan_for_error"):
             f.restype = st
     _lib = lib
@@ -260,6 +266,17 @@ class Plan:
                                                  ctypes.c_void_p(xb.data_ptr()), self._ws_ptr(ws),
                                                  _stream_ptr(stream)), "arkcos_convolve_adjoint")
         return xb
+
+    def convolve_noalloc(self, x: torch.Tensor, out: torch.Tensor, stream=None):
+        """y = C x with the library's fixed device scratch as the workspace
+        (arkcos_convolve_noalloc: nothing is allocated; calls on one device
+        must not overlap)."""
+        x = self._map(x, "x")
+        out = self._map(out, "out")
+        _check(self._lib.arkcos_convolve_noalloc(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                                 ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+               "arkcos_convolve_noalloc")
+        return out
 
     def kernel_grad(self, x: torch.Tensor, r: torch.Tensor, out: Optional[torch.Tensor] = None,
                     ws=None, reuse_spectra: bool = False, stream=None):

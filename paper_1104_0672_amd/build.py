@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libarkcos.so")
 
-SOURCES = ["plan_kernels.hip", "fft.hip", "accum.hip", "pole.hip", "grad.hip", "batch.hip",
+SOURCES = ["plan_kernels.hip", "fft.hip", "accum.hip", "pole.hip", "grad.hip", "batch.hip", "noalloc.hip",
            "plan.cpp", "capi.cpp", "truncation.cpp"]
 
 ARCH = os.environ.get("ARKCOS_OFFLOAD_ARCH", "gfx950")

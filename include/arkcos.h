@@ -150,8 +150,9 @@ typedef struct {
                                [0] Clenshaw recurrence on the centred grid,
                                [1] Clenshaw on the half-shifted own grid,
                                [2] precomputed table, [3] Reinsch's recurrence */
-  int32_t acc_seg_units;    /* accumulation: output units (rings with their mirrors) per work item */
-  int32_t acc_group;        /* wavefronts per accumulation workgroup (one per unit) */
+  int32_t acc_seg_units;    /* accumulation: output units (rings with their mirrors) per work
+                               item, one wavefront each: 8 or 16 */
+  int32_t acc_group;        /* mode tiles (256 modes each) per work item */
   int32_t acc_window;       /* widest input-ring window of a work item's units */
   int32_t acc_tuned;        /* 1: shape chosen by timing at plan creation, 0: fixed */
   double support_radius_rad; /* R of the plan (given, or chosen by arkcos_plan_for_error) */

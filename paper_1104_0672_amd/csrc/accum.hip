@@ -474,13 +474,13 @@ __device__ __forceinline__ BandDev load_band(const BandDev* g) {
 // TAB_ONLY: every pair of the plan has a table of K_ij(m) (no recurrence
 // code, fewer registers, more waves: the FP32 form is held to 80 VGPRs, so
 // that three blocks share a CU instead of two).
-template <typename R, bool TAB_ONLY>
-__global__ void __launch_bounds__(kAccThreads)
+template <typename R, int NW, bool TAB_ONLY>
+__global__ void __launch_bounds__(64 * NW)
     __attribute__((amdgpu_waves_per_eu((TAB_ONLY && sizeof(R) == 4) ? 6 : 1))) accumulate_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec,
                                                                  cx_t<R>* __restrict__ bout, AccLayout lay) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WorkItem it = a.items[blockIdx.x];
-  accumulate_band<R, kBandUnits, TAB_ONLY>(a, a.bands[it.band], it.t0, it.nt, spec, bout, smem, lay);
+  accumulate_band<R, NW, TAB_ONLY>(a, a.bands[it.band], it.t0, it.nt, spec, bout, smem, lay);
 }
 
 // Batched form: one persistent launch drains a queue of (map, band, tiles)
@@ -572,6 +572,9 @@ static hipError_t batch_launch_nw(int32_t units_per_band, const void* maps, cons
                                   const int64_t* out_base, const BatchItem* items, int32_t n_items, int32_t* counter,
                                   const void* spec, void* bout, int32_t grid, size_t lds, AccLayout lay,
                                   hipStream_t s) {
+  if (units_per_band == 16)
+    return batch_launch<R, 16, TAB_ONLY>(maps, spec_base, out_base, items, n_items, counter, spec, bout, grid, lds,
+                                         lay, s);
   return units_per_band == 4 ? batch_launch<R, 4, TAB_ONLY>(maps, spec_base, out_base, items, n_items, counter, spec,
                                                             bout, grid, lds, lay, s)
                              : batch_launch<R, 8, TAB_ONLY>(maps, spec_base, out_base, items, n_items, counter, spec,
@@ -603,34 +606,57 @@ template <typename K> static hipError_t allow_acc_lds(K* k, size_t bytes) {
   return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t configure_accumulate(arkcos_plan_s* P) {
-  const size_t lds = acc_lds_bytes(P->dtype, P->acc_shape);
+hipError_t configure_accumulate_shape(const arkcos_plan_s* P, const AccShape& shape) {
+  const size_t lds = acc_lds_bytes(P->dtype, shape);
   hipError_t e;
   if (P->dtype == ARKCOS_F32) {
-    e = allow_acc_lds(accumulate_kernel<float, false>, lds);
-    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<float, true>, lds);
+    e = allow_acc_lds(accumulate_kernel<float, 8, false>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<float, 8, true>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<float, 16, false>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<float, 16, true>, lds);
   } else {
-    e = allow_acc_lds(accumulate_kernel<double, false>, lds);
-    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<double, true>, lds);
+    e = allow_acc_lds(accumulate_kernel<double, 8, false>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<double, 8, true>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<double, 16, false>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<double, 16, true>, lds);
   }
   return e;
 }
 
-hipError_t launch_accumulate(arkcos_plan_s* P, const void* spec, void* bout, hipStream_t s) {
-  if (P->h_items.empty()) return hipSuccess;
-  const size_t lds = acc_lds_bytes(P->dtype, P->acc_shape);
-  const AccLayout lay = acc_layout(P->dtype, P->acc_shape);
-  const unsigned grid = (unsigned)P->h_items.size();
-  const bool tab = P->all_tables;
+hipError_t configure_accumulate(arkcos_plan_s* P) { return configure_accumulate_shape(P, P->acc_shape); }
+
+template <typename R, int NW>
+static void launch_nw(const arkcos_plan_s* P, const AccArgs<R>& a, unsigned grid, size_t lds, AccLayout lay,
+                      const void* spec, void* bout, hipStream_t s) {
+  auto k = P->all_tables ? accumulate_kernel<R, NW, true> : accumulate_kernel<R, NW, false>;
+  k<<<grid, 64 * NW, lds, s>>>(a, (const cx_t<R>*)spec, (cx_t<R>*)bout, lay);
+}
+
+// One launch of the plan's accumulation with the given bands, items and
+// shape (the plan's own, or a candidate timed at plan creation).
+hipError_t launch_accumulate_shape(const arkcos_plan_s* P, const BandDev* bands, const WorkItem* items,
+                                   int32_t n_items, int32_t units, const AccShape& shape, const void* spec,
+                                   void* bout, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  const size_t lds = acc_lds_bytes(P->dtype, shape);
+  const AccLayout lay = acc_layout(P->dtype, shape);
   if (P->dtype == ARKCOS_F32) {
-    auto k = tab ? accumulate_kernel<float, true> : accumulate_kernel<float, false>;
-    k<<<grid, kAccThreads, lds, s>>>(make_acc_args<float>(P, P->d_bands), (const float2*)spec, (float2*)bout, lay);
+    AccArgs<float> a = make_acc_args<float>(P, bands);
+    a.items = items;
+    if (units == 16) launch_nw<float, 16>(P, a, (unsigned)n_items, lds, lay, spec, bout, s);
+    else launch_nw<float, 8>(P, a, (unsigned)n_items, lds, lay, spec, bout, s);
   } else {
-    auto k = tab ? accumulate_kernel<double, true> : accumulate_kernel<double, false>;
-    k<<<grid, kAccThreads, lds, s>>>(make_acc_args<double>(P, P->d_bands), (const double2*)spec, (double2*)bout,
-                                     lay);
+    AccArgs<double> a = make_acc_args<double>(P, bands);
+    a.items = items;
+    if (units == 16) launch_nw<double, 16>(P, a, (unsigned)n_items, lds, lay, spec, bout, s);
+    else launch_nw<double, 8>(P, a, (unsigned)n_items, lds, lay, spec, bout, s);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_accumulate(arkcos_plan_s* P, const void* spec, void* bout, hipStream_t s) {
+  return launch_accumulate_shape(P, P->d_bands, P->d_items, (int32_t)P->h_items.size(), P->acc_units, P->acc_shape,
+                                 spec, bout, s);
 }
 
 }  // namespace arkcos

@@ -174,6 +174,9 @@ struct arkcos_plan_s {
   arkcos::WorkItem* d_items = nullptr;
   arkcos::BandDev* d_bands = nullptr;
   arkcos::AccShape acc_shape;  // LDS needs of the accumulation bands
+  int32_t acc_units = arkcos::kBandUnits;      // units per band (wavefronts per block): 8 or 16
+  int32_t acc_tiles = arkcos::kTilesPerItem;   // mode tiles per work item
+  int32_t acc_tuned = 0;                       // 1: band shape chosen by timing at plan creation
   std::vector<arkcos::BandDev> h_bands;
   bool all_tables = false;     // every pair reads K_ij(m) from a table
   void* d_coef = nullptr;       // recurrence coefficients, plan dtype
@@ -238,6 +241,10 @@ hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const in
                                    int32_t* counter, const void* spec, void* bout, int32_t grid,
                                    int32_t units_per_band, bool all_tables, const AccShape& shape, hipStream_t s);
 hipError_t configure_accumulate(arkcos_plan_s* P);
+hipError_t configure_accumulate_shape(const arkcos_plan_s* P, const AccShape& shape);
+hipError_t launch_accumulate_shape(const arkcos_plan_s* P, const BandDev* bands, const WorkItem* items,
+                                   int32_t n_items, int32_t units, const AccShape& shape, const void* spec,
+                                   void* bout, hipStream_t s);
 size_t ring_args_size();
 void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out,
                     const int64_t* off = nullptr, const int32_t* len = nullptr);
@@ -261,7 +268,8 @@ void fill_pole_map(arkcos_plan_s* P, void* out);
 hipError_t launch_pole_batch(arkcos_dtype_t dt, const void* maps, const int2* entries, int32_t count, int32_t adjoint,
                              const void* xs, const void* ys, hipStream_t s);
 void build_bands(const arkcos_plan_s* P, int32_t units_per_band, std::vector<BandDev>& bands, AccShape* shape);
-void accumulation_items(const arkcos_plan_s* P, const std::vector<BandDev>& bands, std::vector<WorkItem>& items,
+void accumulation_items(const arkcos_plan_s* P, const std::vector<BandDev>& bands, int32_t tiles_per_item,
+                        std::vector<WorkItem>& items,
                         std::vector<double>& cost);
 int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count);
 void workspace_split(const arkcos_plan_s* P, void* ws, void** spec, void** bout);

@@ -133,7 +133,7 @@ hipError_t build_queue(arkcos_batch_s* B, const std::vector<int32_t>& maps, int3
     fill_acc_args(P, (const BandDev*)d, Q.acc_args.data() + asz * mi, B->d_union_off, B->d_union_len);
     std::vector<WorkItem> its;
     std::vector<double> cost;
-    accumulation_items(P, bands, its, cost);
+    accumulation_items(P, bands, kTilesPerItem, its, cost);
     for (size_t k = 0; k < its.size(); ++k)
       costed.push_back({cost[k], BatchItem{(int32_t)mi, its[k].band, its[k].t0, its[k].nt}});
   }
@@ -250,7 +250,7 @@ arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out) 
   BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
   float best = 1e30f;
   int32_t bu = kBandUnits, bb = 2;
-  for (int32_t upb : {4, 8}) {
+  for (int32_t upb : {4, 8, 16}) {
     Queue Q;
     std::vector<void*> owned;
     hipError_t e = build_queue(B, sub, upb, Q, owned);

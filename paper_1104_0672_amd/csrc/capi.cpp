@@ -172,10 +172,10 @@ arkcos_status_t arkcos_plan_get_info(arkcos_plan_t P, arkcos_plan_info_t* info) 
   info->plan_bytes = P->plan_bytes;
   for (const auto& pr : P->h_pairs)
     if (pr.band >= 0 && pr.kind >= 0 && pr.kind < 4) ++info->pairs_by_kind[pr.kind];
-  info->acc_seg_units = kBandUnits;
-  info->acc_group = kBandUnits;
+  info->acc_seg_units = P->acc_units;
+  info->acc_group = P->acc_tiles;
   info->acc_window = P->acc_shape.max_window;
-  info->acc_tuned = 0;
+  info->acc_tuned = P->acc_tuned;
   info->support_radius_rad = P->radius;
   return ARKCOS_OK;
 }

@@ -327,6 +327,103 @@ hipError_t update_knots(arkcos_plan_s* P, const double* d_src, hipStream_t s) {
   return launch_table_list(P, P->d_tab_list, P->d_tab_coef, P->n_tab_list, s);
 }
 
+// Bands of units_per_band units and their items (mode tiles in runs of
+// tiles), heaviest first so that a launch does not end on a long item.
+static void make_bands_items(const arkcos_plan_s* P, int32_t units, int32_t tiles, std::vector<BandDev>& bands,
+                             AccShape* shape, std::vector<WorkItem>& items) {
+  build_bands(P, units, bands, shape);
+  std::vector<WorkItem> its;
+  std::vector<double> cost;
+  accumulation_items(P, bands, tiles, its, cost);
+  std::vector<size_t> ord(its.size());
+  for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+  items.clear();
+  for (size_t k : ord) items.push_back(its[k]);
+}
+
+// The accumulation's band shape: units per band (8 or 16 wavefronts per
+// block; wider bands re-read the window's spectra less often but hold fewer
+// waves per CU) and mode tiles per item.  Plans of a million pixels or more
+// time every candidate on a scratch workspace (the kernel's control flow
+// does not depend on the data) and keep the fastest; smaller plans take 8
+// units and 4 tiles.  ARKCOS_ACC_SHAPE="U,T" forces a choice.  The result
+// does not depend on the shape: every unit sums its pairs in the same order.
+arkcos_status_t choose_accumulation_shape(arkcos_plan_s* P) {
+  std::vector<std::pair<int32_t, int32_t>> cand;
+  if (const char* e = getenv("ARKCOS_ACC_SHAPE"); e && *e) {
+    int u = 0, t = 0;
+    if (sscanf(e, "%d,%d", &u, &t) == 2 && (u == 8 || u == 16) && t >= 1 && t <= 16) cand.push_back({u, t});
+  }
+  if (cand.empty()) {
+    // (16-unit bands only in FP32: the FP64 recurrence form would spill)
+    if (P->npix >= (int64_t(1) << 20) && P->dtype == ARKCOS_F32)
+      cand = {{8, 4}, {16, 4}, {8, 2}, {16, 2}, {8, 8}, {16, 8}};
+    else if (P->npix >= (int64_t(1) << 20))
+      cand = {{8, 4}, {8, 2}, {8, 8}};
+    else
+      cand = {{kBandUnits, kTilesPerItem}};
+  }
+  P->acc_tuned = 0;
+  if (cand.size() == 1) {
+    P->acc_units = cand[0].first;
+    P->acc_tiles = cand[0].second;
+    make_bands_items(P, P->acc_units, P->acc_tiles, P->h_bands, &P->acc_shape, P->h_items);
+    return ARKCOS_OK;
+  }
+  void *ws = nullptr, *d_b = nullptr, *d_i = nullptr;
+  struct Free {
+    void** a[3];
+    ~Free() { for (void** p : a) if (*p) hipFree(*p); }
+  } fr{{&ws, &d_b, &d_i}};
+  const size_t wsb = workspace_bytes(P);
+  HIPCHK(hipMalloc(&ws, wsb));
+  HIPCHK(hipMemset(ws, 0, wsb));
+  void *spec = nullptr, *bout = nullptr;
+  workspace_split(P, ws, &spec, &bout);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { hipEventDestroy(a); hipEventDestroy(b); }
+  } ev{e0, e1};
+  float best = 1e30f;
+  size_t best_k = 0;
+  for (size_t k = 0; k < cand.size(); ++k) {
+    std::vector<BandDev> bands;
+    std::vector<WorkItem> items;
+    AccShape sh;
+    make_bands_items(P, cand[k].first, cand[k].second, bands, &sh, items);
+    if (d_b) HIPCHK(hipFree(d_b));
+    if (d_i) HIPCHK(hipFree(d_i));
+    d_b = d_i = nullptr;
+    HIPCHK(hipMalloc(&d_b, std::max<size_t>(bands.size(), 1) * sizeof(BandDev)));
+    HIPCHK(hipMalloc(&d_i, std::max<size_t>(items.size(), 1) * sizeof(WorkItem)));
+    if (!bands.empty()) HIPCHK(hipMemcpy(d_b, bands.data(), bands.size() * sizeof(BandDev), hipMemcpyHostToDevice));
+    if (!items.empty()) HIPCHK(hipMemcpy(d_i, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    HIPCHK(configure_accumulate_shape(P, sh));
+    const int32_t ni = (int32_t)items.size();
+    HIPCHK(launch_accumulate_shape(P, (BandDev*)d_b, (WorkItem*)d_i, ni, cand[k].first, sh, spec, bout, nullptr));
+    HIPCHK(hipEventRecord(e0, nullptr));
+    for (int r = 0; r < 3; ++r)
+      HIPCHK(launch_accumulate_shape(P, (BandDev*)d_b, (WorkItem*)d_i, ni, cand[k].first, sh, spec, bout, nullptr));
+    HIPCHK(hipEventRecord(e1, nullptr));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_k = k;
+    }
+  }
+  P->acc_units = cand[best_k].first;
+  P->acc_tiles = cand[best_k].second;
+  P->acc_tuned = 1;
+  make_bands_items(P, P->acc_units, P->acc_tiles, P->h_bands, &P->acc_shape, P->h_items);
+  return ARKCOS_OK;
+}
+
 arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* prof, double R,
                            arkcos_dtype_t dtype, const arkcos_options_t* o, arkcos_plan_s** out) {
   // ---------------------------------------------------------- validation
@@ -797,17 +894,9 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   HIPCHK(upload(P, &P->d_units, P->h_units));
 
   // bands of consecutive units, and work items: (band, first mode) tiles
-  build_bands(P, kBandUnits, P->h_bands, &P->acc_shape);
   {
-    std::vector<WorkItem> its;
-    std::vector<double> cost;
-    accumulation_items(P, P->h_bands, its, cost);
-    // heaviest first, so that the launch does not end on a long item
-    std::vector<size_t> ord(its.size());
-    for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
-    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-    P->h_items.clear();
-    for (size_t k : ord) P->h_items.push_back(its[k]);
+    arkcos_status_t st = choose_accumulation_shape(P);
+    if (st != ARKCOS_OK) return st;
   }
   HIPCHK(upload(P, &P->d_items, P->h_items));
   HIPCHK(upload(P, &P->d_bands, P->h_bands));
@@ -830,18 +919,18 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
 }
 
 // Work items of the accumulation: each band's mode tiles in runs of
-// kTilesPerItem, with an estimate of their cost (recurrence length of the
+// tiles_per_item, with an estimate of their cost (recurrence length of the
 // pairs still inside their band, summed over the tiles).
-void accumulation_items(const arkcos_plan_s* P, const std::vector<BandDev>& bands, std::vector<WorkItem>& items,
-                        std::vector<double>& cost) {
+void accumulation_items(const arkcos_plan_s* P, const std::vector<BandDev>& bands, int32_t tiles_per_item,
+                        std::vector<WorkItem>& items, std::vector<double>& cost) {
   items.clear();
   cost.clear();
   for (int32_t b = 0; b < (int32_t)bands.size(); ++b) {
     const BandDev& bd = bands[b];
     if (bd.band < 0) continue;
     const int32_t ntile = bd.band / kAccTile + 1;
-    for (int32_t t0 = 0; t0 < ntile; t0 += kTilesPerItem) {
-      const int32_t nt = std::min(kTilesPerItem, ntile - t0);
+    for (int32_t t0 = 0; t0 < ntile; t0 += tiles_per_item) {
+      const int32_t nt = std::min(tiles_per_item, ntile - t0);
       double c = 0.0;
       for (int32_t u = bd.u0; u < bd.u0 + bd.nu; ++u) {
         const UnitDev& U = P->h_units[u];

@@ -349,7 +349,10 @@ def bench_spline(steps: int, dev):
     y = torch.empty_like(x)
     ws = plan.workspace()
     out = {"workload": w.name, "npix": plan.npix, "oversample": int(plan.info.oversample),
-           "plan_seconds": round(plan_s, 2)}
+           "plan_seconds": round(plan_s, 2), "table_fft_rows": int(plan.info.table_fft_rows),
+           "grad_fft_rows": int(plan.info.grad_fft_rows)}
+    log(f"bench: spline plan {plan_s:.2f} s, rows by FFT: tables {plan.info.table_fft_rows}, "
+        f"gradient {plan.info.grad_fft_rows}")
     for name, fn in (("forward", lambda: plan.convolve(x, out=y, ws=ws)),
                      ("knot_gradient", lambda: plan.kernel_grad(x, r, ws=ws))):
         fn()
@@ -361,6 +364,43 @@ def bench_spline(steps: int, dev):
         ms = 1e3 * (time.perf_counter() - t0) / steps
         out[name] = {"ms": round(ms, 3), "pixels_per_s": plan.npix / (ms * 1e-3)}
         log(f"bench: spline {name} {ms:.3f} ms")
+    # a knot update on the stream (new samples and K_ij(m) tables), and one
+    # training step through the autograd function: forward, loss 1/2 |y - t|^2,
+    # backward (transpose for d/dx and the knot gradient), a plain gradient
+    # step on the knots (so every step applies new knots)
+    from paper_1104_0672_amd import convolve
+    knots = torch.tensor(w.profile.knots, dtype=torch.float64, device=dev)
+    plan.set_knots_async(knots)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.set_knots_async(knots)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    out["set_knots"] = {"ms": round(ms, 3)}
+    log(f"bench: spline set_knots {ms:.3f} ms")
+    kp = knots.clone().requires_grad_(True)
+    xg = x.clone().requires_grad_(True)
+    tgt = r
+
+    def train_step():
+        y_ = convolve(xg, plan, kp)
+        loss = 0.5 * ((y_ - tgt) ** 2).sum()
+        gx, gk = torch.autograd.grad(loss, (xg, kp))
+        with torch.no_grad():
+            kp.sub_(1e-9 * gk)
+        return gx
+
+    train_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        train_step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    out["training_step"] = {"ms": round(ms, 3), "pixels_per_s": plan.npix / (ms * 1e-3),
+                            "what": "forward + backward (d/dx and d/dknots) + knot update, autograd"}
+    log(f"bench: spline training step {ms:.3f} ms")
     del plan, ws
     torch.cuda.empty_cache()
     return out

@@ -156,6 +156,10 @@ typedef struct {
   int32_t acc_window;       /* widest input-ring window of a work item's units */
   int32_t acc_tuned;        /* 1: shape chosen by timing at plan creation, 0: fixed */
   double support_radius_rad; /* R of the plan (given, or chosen by arkcos_plan_for_error) */
+  int32_t table_fft_rows;   /* spline plans: K_ij(m) tables computed by FFTs of the
+                               kernel samples (wide rows on power-of-two grids) */
+  int32_t grad_fft_rows;    /* spline plans: kernel rows whose knot-gradient
+                               correlation is transformed by FFTs */
 } arkcos_plan_info_t;
 
 /* Fill *opts with the defaults (oversample 0, kgen 0, fix_pole_pixels 1,

@@ -51,7 +51,8 @@ class PlanInfo(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t),
                 ("plan_bytes", ctypes.c_size_t), ("pairs_by_kind", ctypes.c_int64 * 4),
                 ("acc_seg_units", ctypes.c_int32), ("acc_group", ctypes.c_int32), ("acc_window", ctypes.c_int32),
-                ("acc_tuned", ctypes.c_int32), ("support_radius_rad", ctypes.c_double)]
+                ("acc_tuned", ctypes.c_int32), ("support_radius_rad", ctypes.c_double),
+                ("table_fft_rows", ctypes.c_int32), ("grad_fft_rows", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):

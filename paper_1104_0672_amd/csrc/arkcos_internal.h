@@ -23,7 +23,8 @@ constexpr int kAccTile = 256;          // modes per accumulation tile (four per 
 constexpr int kAccThreads = 64 * kBandUnits;  // one wavefront per unit
 
 // FFT strategy of one ring length.
-enum FftKind : int32_t { FFT_DIRECT = 0, FFT_POW2 = 1, FFT_BLUESTEIN = 2 };
+// FFT_MIXED: n = 2^a 3^b 5^c 7^d, not a power of two: mixed-radix passes.
+enum FftKind : int32_t { FFT_DIRECT = 0, FFT_POW2 = 1, FFT_BLUESTEIN = 2, FFT_MIXED = 3 };
 
 // K_ij(m) source of one ring pair.
 //  KG_CENTRED  : nodes 2 pi d / G, recurrence on cos(m nu)
@@ -81,6 +82,21 @@ constexpr double kGradItemWork = 16777216.0;  // samples x modes of a wide-row i
 constexpr int kGradZBytes = 32768;    // LDS for a wide-row item's correlation: its modes come in chunks of this
 constexpr int kGradBlocksPerCU = 3;   // gradient blocks resident per CU (LDS and registers)
 
+// A wide kernel row (more than kGradMaxCoef samples, centred nodes) on a
+// power-of-two grid of G longitudes, taken by FFTs instead of sums over
+// samples x modes (spline plans: the knot gradient's correlation Y(d) and the
+// K_ij(m) tables): S = G / (2 P) real sub-sequences of 2 P points (every
+// S-th mode or sample), each one LDS FFT of P complex points.
+struct RowFft {
+  int32_t unit, pair, P, pad;
+};
+constexpr int64_t kFftRowMinGrid = 512;  // smaller grids: the direct sums
+constexpr int64_t kGradYBytes = int64_t(256) << 20;  // Y buffer of the FFT rows: chunks of at most this
+// P of the FFT path for pair q with nc samples, or 0 for the direct sums
+int32_t fft_row_points(const arkcos_plan_s* P, int64_t q, int64_t nc);
+// block size (threads) of an FFT row of P points: 16 points per thread
+constexpr int fft_row_threads(int32_t P) { return P <= 4096 ? 256 : (P <= 8192 ? 512 : 1024); }
+
 // One accumulation work item: band `band`, mode tiles [t0, t0 + nt) of
 // kAccTile modes each.
 struct WorkItem {
@@ -123,7 +139,8 @@ struct FftClass {
   int32_t count = 0;
   int32_t lds = 0;
   int32_t threads = 256;  // block size: 512 when an FFT is longer than 4096 points
-  int32_t mf = 0;         // the FFT length of every ring of the class, if they share one
+  int32_t mf = 0;         // the FFT length of every ring of the class, if they share one;
+                          // -1: a class of mixed-radix rings (FFT_MIXED)
 };
 
 }  // namespace arkcos
@@ -163,6 +180,7 @@ struct arkcos_plan_s {
   std::vector<arkcos::FftClass> fft_classes;
   std::vector<int32_t> h_ring_lds;       // LDS bytes of each ring's transform
   std::vector<int32_t> h_fft_len;        // its complex FFT length (0: plain DFT)
+  std::vector<int32_t> h_fft_kind;       // its FftKind
   std::vector<int32_t> h_spec_len, h_out_len;
   std::vector<int64_t> h_spec_off, h_out_off;
 
@@ -200,10 +218,22 @@ struct arkcos_plan_s {
   int32_t* d_ncoef_window = nullptr;  // kernel samples inside each pair's window
   double* d_basis_mom = nullptr;    // spline basis moments S[a][k], n_knots^2
   std::vector<arkcos::GradItem> h_grad_items;  // knot-gradient work items, in unit / pair / sample order
+  // wide rows by FFT (spline plans), grouped by block size [256, 512, 1024]:
+  // gradient rows (with the offset of each row's Y(d) in its chunk's buffer,
+  // the chunk boundaries, and the blocks and slots of the interval sums),
+  // and table rows
+  arkcos::RowFft* d_gfft = nullptr;
+  int64_t* d_gfft_yoff = nullptr;
+  std::vector<int32_t> h_gfft_chunk;  // rows [chunk[c], chunk[c + 1]) share the Y buffer in turn
+  int64_t grad_y_elems = 0;           // Y buffer: the largest chunk's samples
+  int32_t n_gfft[3] = {0, 0, 0}, n_gfft_slots = 0;
+  arkcos::RowFft* d_tfft = nullptr;
+  int32_t n_tfft[3] = {0, 0, 0};
   arkcos::GradItem* d_grad_items = nullptr;
   int32_t* d_grad_run = nullptr;    // n_grad_runs + 1 item offsets: the items of each gradient block
   int32_t n_grad_runs = 0;
   int32_t grad_zcache_bytes = 0;    // LDS of a gradient block for a wide row's correlation
+  int32_t grad_fold = 0;            // 1: the gradient reads spectra through their modes 0 .. N/2
   int32_t* d_pole_rings = nullptr;  // rings within reach of a pole pixel
   int32_t n_pole_rings = 0;
   size_t plan_bytes = 0;
@@ -227,6 +257,8 @@ hipError_t launch_spline_update(arkcos_plan_s* P, const double* d_src, hipStream
 hipError_t launch_band(arkcos_plan_s* P, double threshold, int32_t* band_out, hipStream_t s);
 hipError_t launch_table_list(arkcos_plan_s* P, const int32_t* d_list, const int64_t* d_coef_off,
                              int32_t count, hipStream_t s);
+// the K_ij(m) tables of the FFT table rows (spline plans)
+hipError_t launch_table_fft(arkcos_plan_s* P, hipStream_t s);
 hipError_t configure_fft_kernels(arkcos_plan_s* P);
 // batched form
 size_t acc_args_size();
@@ -274,6 +306,7 @@ void accumulation_items(const arkcos_plan_s* P, const std::vector<BandDev>& band
 int32_t* pole_ring_list(arkcos_plan_s* P, int32_t* count);
 void workspace_split(const arkcos_plan_s* P, void* ws, void** spec, void** bout);
 double* grad_slots(const arkcos_plan_s* P, void* ws);
+void* grad_y(const arkcos_plan_s* P, void* ws);  // Y(d) buffer of the FFT rows
 hipError_t launch_r2c_layout(arkcos_plan_s* P, const void* x, void* spec, bool out_layout, int32_t zero_pole,
                              hipStream_t s);
 size_t workspace_bytes(const arkcos_plan_s* P);

@@ -285,6 +285,7 @@ hipError_t make_classes(arkcos_batch_s* B, const std::vector<int2>& entries, std
     // a compile-time FFT length: one class per length
     const int32_t ct = ct_fft_length(B->dtype, P->h_fft_len[e.y], per_len[P->h_fft_len[e.y]]);
     if (ct > 0) b = (int64_t(1) << 40) + ct;
+    if (P->h_fft_kind[e.y] == FFT_MIXED) b |= int64_t(1) << 39;  // mixed-radix rings: classes of their own
     cls[b].push_back(e);
   }
   for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
@@ -299,6 +300,7 @@ hipError_t make_classes(arkcos_batch_s* B, const std::vector<int2>& entries, std
     c.lds = mx;
     // one compile-time FFT length for the whole class: compile-time transforms
     c.mf = (lo == len) ? ct_fft_length(B->dtype, len, per_len[len]) : 0;
+    if (it->first & (int64_t(1) << 39)) c.mf = -1;
     c.threads = c.mf > 0 ? c.mf / 16 : fft_threads(B->dtype, len);
     hipError_t e = bupload(B, &c.entries, it->second);
     if (e != hipSuccess) return e;

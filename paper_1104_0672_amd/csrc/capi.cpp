@@ -177,6 +177,8 @@ arkcos_status_t arkcos_plan_get_info(arkcos_plan_t P, arkcos_plan_info_t* info) 
   info->acc_window = P->acc_shape.max_window;
   info->acc_tuned = P->acc_tuned;
   info->support_radius_rad = P->radius;
+  info->table_fft_rows = P->n_tfft[0] + P->n_tfft[1] + P->n_tfft[2];
+  info->grad_fft_rows = P->n_gfft[0] + P->n_gfft[1] + P->n_gfft[2];
   return ARKCOS_OK;
 }
 

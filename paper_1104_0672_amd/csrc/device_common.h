@@ -477,6 +477,169 @@ __device__ __forceinline__ void bluestein_ct(cx_t<R>* buf, int n, const cx_t<R>*
   if constexpr (!REGOUT) __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Mixed-radix FFT in LDS for lengths n = 2^a 3^b 5^c 7^d (n <= 16 NT): a
+// Stockham pass per factor (radix 16, 8, 4, 2 for the power of two, then 3,
+// 5 and 7), each butterfly's twiddles exp(-/+ 2 pi i k r / (Ns R)) formed
+// from one exactly reduced sincospi value by products, the butterflies' R
+// points in registers and written back in place after a barrier (the whole
+// pass's inputs are read first).  Same padded layout and conventions as
+// lds_fft: synchronised on entry and exit, INV = unnormalised inverse.
+// ---------------------------------------------------------------------------
+
+// DFT of odd radix R in registers: y_k = sum_r v_r W_R^{rk} from the pairs
+// a_r = v_r + v_{R-r}, b_r = v_r - v_{R-r} (exact cosines and sines of 2 pi
+// r k / R).
+template <typename C, bool INV, int RAD> __device__ __forceinline__ void dft_odd(C* v) {
+  using T = decltype(C{}.x);
+  static_assert(RAD == 3 || RAD == 5 || RAD == 7, "odd radix");
+  constexpr int H = (RAD - 1) / 2;
+  // cos / sin of 2 pi q / RAD, q = 1 .. H
+  const T cs3[1] = {T(-0.5)}, sn3[1] = {T(0.86602540378443864676)};
+  const T cs5[2] = {T(0.30901699437494742410), T(-0.80901699437494742410)};
+  const T sn5[2] = {T(0.95105651629515357212), T(0.58778525229247312917)};
+  const T cs7[3] = {T(0.62348980185873353053), T(-0.22252093395631440429), T(-0.90096886790241912624)};
+  const T sn7[3] = {T(0.78183148246802980871), T(0.97492791218182360702), T(0.43388373911755812048)};
+  const T* cs = RAD == 3 ? cs3 : (RAD == 5 ? cs5 : cs7);
+  const T* sn = RAD == 3 ? sn3 : (RAD == 5 ? sn5 : sn7);
+  C a[H], b[H];
+#pragma unroll
+  for (int r = 1; r <= H; ++r) {
+    a[r - 1] = cadd(v[r], v[RAD - r]);
+    b[r - 1] = csub(v[r], v[RAD - r]);
+  }
+  C y[RAD];
+  C s0 = v[0];
+#pragma unroll
+  for (int r = 0; r < H; ++r) s0 = cadd(s0, a[r]);
+  y[0] = s0;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    C re = v[0], im = cmake<C>(T(0), T(0));
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+      const int q = (r * k) % RAD;                   // W^{rk} = cos(2 pi q / R) - i sin(2 pi q / R)
+      const int qq = q <= H ? q : RAD - q;
+      const T c = cs[qq - 1], sg = q <= H ? sn[qq - 1] : -sn[qq - 1];
+      re = cadd(re, cscale(a[r - 1], c));
+      im = cadd(im, cscale(b[r - 1], sg));
+    }
+    // forward: y_k = re - i im, y_{R-k} = re + i im (inverse: the opposite)
+    const C mi = cmake<C>(im.y, -im.x);               // -i im
+    y[k] = INV ? csub(re, mi) : cadd(re, mi);
+    y[RAD - k] = INV ? cadd(re, mi) : csub(re, mi);
+  }
+#pragma unroll
+  for (int k = 0; k < RAD; ++k) v[k] = y[k];
+}
+
+template <typename C, bool INV, int RAD> __device__ __forceinline__ void dft_any(C* v) {
+  if constexpr (RAD == 3 || RAD == 5 || RAD == 7) dft_odd<C, INV, RAD>(v);
+  else dft_reg<C, INV, RAD>(v);
+}
+
+// One mixed-radix Stockham pass of radix RAD over the n points (n / RAD
+// butterflies, j = threadIdx.x + b NT), the product of the radices of the
+// earlier passes being Ns.
+template <typename R, bool INV, int RAD, int NT>
+__device__ __forceinline__ void mixed_pass(cx_t<R>* buf, int n, int Ns) {
+  using C = cx_t<R>;
+  constexpr int MAXB = (16 * NT / RAD + NT - 1) / NT;
+  const int Q = n / RAD;
+  C v[MAXB][RAD];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = threadIdx.x + b * NT;
+    if (j < Q) {
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[b][r] = buf[lidx(j + r * Q)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = threadIdx.x + b * NT;
+    if (j < Q) {
+      const int k = j % Ns;
+      if (Ns > 1) {
+        // w = exp(-2 pi i k / (Ns RAD)) = exp(i pi 2 (Ns RAD - k) / (Ns RAD))
+        C w = expipi<R>(2 * (Ns * RAD - k), Ns * RAD);
+        if (INV) w = cconj(w);
+        C p = w;
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          v[b][r] = cmul(v[b][r], p);
+          p = cmul(p, w);
+        }
+      }
+      dft_any<C, INV, RAD>(v[b]);
+      const int o = (j - k) * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf[lidx(o + r * Ns)] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// The passes of n = 2^a 3^b 5^c 7^d: radix 16 while 16 divides the rest,
+// then 8, 4 or 2 once, then the odd factors.
+template <typename R, bool INV, int NT>
+__device__ void mixed_fft(cx_t<R>* buf, int n) {
+  int rest = n, Ns = 1;
+  while ((rest & 15) == 0) {
+    mixed_pass<R, INV, 16, NT>(buf, n, Ns);
+    Ns *= 16;
+    rest >>= 4;
+  }
+  if ((rest & 7) == 0) {
+    mixed_pass<R, INV, 8, NT>(buf, n, Ns);
+    Ns *= 8;
+    rest >>= 3;
+  } else if ((rest & 3) == 0) {
+    mixed_pass<R, INV, 4, NT>(buf, n, Ns);
+    Ns *= 4;
+    rest >>= 2;
+  } else if ((rest & 1) == 0) {
+    mixed_pass<R, INV, 2, NT>(buf, n, Ns);
+    Ns *= 2;
+    rest >>= 1;
+  }
+  while (rest % 3 == 0) {
+    mixed_pass<R, INV, 3, NT>(buf, n, Ns);
+    Ns *= 3;
+    rest /= 3;
+  }
+  while (rest % 5 == 0) {
+    mixed_pass<R, INV, 5, NT>(buf, n, Ns);
+    Ns *= 5;
+    rest /= 5;
+  }
+  while (rest % 7 == 0) {
+    mixed_pass<R, INV, 7, NT>(buf, n, Ns);
+    Ns *= 7;
+    rest /= 7;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wide kernel rows by FFT.  A real sequence x_q, q < 2P, packed as
+// z_l = x_2l + i x_2l+1 (l < P) and transformed in place by an LDS FFT of P
+// points gives the 2P-point transform of x at any k in [0, 2P):
+//   X(k) = E(k) + wk O(k),  E = (Z(k) + conj Z(-k)) / 2,  O = (Z(k) - conj Z(-k)) / 2i,
+// with wk = exp(-i pi k / P) for the forward transform and exp(+i pi k / P)
+// for the inverse (Z, E, O of period P).  buf: padded layout (lidx).
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ cx_t<R> real_from_packed(const cx_t<R>* buf, int P, int k, cx_t<R> wk) {
+  using C = cx_t<R>;
+  const int k1 = k & (P - 1), k2 = (P - k1) & (P - 1);
+  const C z1 = buf[lidx(k1)], z2 = cconj(buf[lidx(k2)]);
+  const C e = cscale(cadd(z1, z2), R(0.5));
+  const C d = csub(z1, z2);
+  const C o = cmake<C>(R(0.5) * d.y, R(-0.5) * d.x);  // d / 2i
+  return cadd(e, cmul(wk, o));
+}
+
 // Loads and stores through the global address space.  Pointers read from
 // memory (per-map argument blocks of the batched kernels) are otherwise
 // generic, and generic (flat) accesses count against the LDS wait counter

@@ -16,9 +16,10 @@
 //
 // A real ring of even length N is transformed as a complex sequence of length
 // N/2 (even samples in the real part, odd samples in the imaginary part) with
-// the usual split; the complex DFT is a power-of-two LDS FFT or, for other
-// lengths, Bluestein's chirp convolution through a power-of-two FFT.  Rings of
-// up to 64 pixels use a plain DFT.  One block transforms one ring.
+// the usual split; the complex DFT is a power-of-two LDS FFT, a mixed-radix
+// one (radices 2-16, 3, 5, 7) for lengths with no other prime factors, or,
+// for the rest, Bluestein's chirp convolution through a power-of-two FFT.
+// Rings of up to 64 pixels use a plain DFT.  One block transforms one ring.
 #include "arkcos_internal.h"
 #include "device_common.h"
 
@@ -143,7 +144,8 @@ __device__ __forceinline__ void r2c_ring(const RingArgs<R>& a, const int j, cons
         if (l < n) buf[lidx(l)] = cscale(z[e], scale);
       }
       __syncthreads();
-      if (kind == FFT_POW2) lds_fft<R, false, NT>(buf, n, a.tw, a.TN);
+      if constexpr (MF < 0) mixed_fft<R, false, NT>(buf, n);  // the mixed-radix classes hold only FFT_MIXED rings
+      else if (kind == FFT_POW2) lds_fft<R, false, NT>(buf, n, a.tw, a.TN);
       else bluestein<R, false, NT>(buf, n, M, a.bl + a.bl_off[j], a.tw, a.TN);
     }
     constexpr int kPairBatch = PairBatch<R>::value;
@@ -368,7 +370,8 @@ __device__ __forceinline__ void c2r_ring(const RingArgs<R>& a, const int i, cons
     }
     return;
   }
-  if (kind == FFT_POW2) lds_fft<R, true, NT>(buf, n, a.tw, a.TN);
+  if constexpr (MF < 0) mixed_fft<R, true, NT>(buf, n);
+  else if (kind == FFT_POW2) lds_fft<R, true, NT>(buf, n, a.tw, a.TN);
   else bluestein<R, true, NT>(buf, n, M, a.bl + a.bl_off[i], a.tw, a.TN);
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -483,11 +486,21 @@ hipError_t configure_fft_kernels(arkcos_plan_s* P) {
     if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 64, 1024>, b);
     if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 1024, 0>, b);
     if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 1024, 0>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 256, -1>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 512, -1>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<float, 1024, -1>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 256, -1>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 512, -1>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<float, 1024, -1>, b);
   } else {
     if (e == hipSuccess) e = allow_lds(r2c_kernel<double, 256, 0>, b);
     if (e == hipSuccess) e = allow_lds(c2r_kernel<double, 256, 0>, b);
     if (e == hipSuccess) e = allow_lds(r2c_kernel<double, 512, 0>, b);
     if (e == hipSuccess) e = allow_lds(c2r_kernel<double, 512, 0>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<double, 256, -1>, b);
+    if (e == hipSuccess) e = allow_lds(r2c_kernel<double, 512, -1>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<double, 256, -1>, b);
+    if (e == hipSuccess) e = allow_lds(c2r_kernel<double, 512, -1>, b);
   }
   return e;
 }
@@ -498,6 +511,19 @@ template <typename R>
 static void r2c_class(const FftClass& c, const RingArgs<R>& a, const void* x, void* spec, hipStream_t s) {
   const R* xi = (const R*)x;
   cx_t<R>* so = (cx_t<R>*)spec;
+  if (c.mf < 0) {  // mixed-radix rings
+    if constexpr (sizeof(R) == 4) {
+      if (c.threads == 1024) {
+        r2c_kernel<R, 1024, -1><<<(unsigned)c.count, 1024, c.lds, s>>>(a, c.d_rings, xi, so);
+        return;
+      }
+    }
+    if (c.threads == 512)
+      r2c_kernel<R, 512, -1><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, xi, so);
+    else
+      r2c_kernel<R, 256, -1><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, xi, so);
+    return;
+  }
   if constexpr (sizeof(R) == 4) {
     if (c.threads == 512 && c.mf == 8192) {
       r2c_kernel<R, 512, 8192><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, xi, so);
@@ -531,6 +557,19 @@ template <typename R>
 static void c2r_class(const FftClass& c, const RingArgs<R>& a, const void* b, void* y, hipStream_t s) {
   const cx_t<R>* bi = (const cx_t<R>*)b;
   R* yo = (R*)y;
+  if (c.mf < 0) {  // mixed-radix rings
+    if constexpr (sizeof(R) == 4) {
+      if (c.threads == 1024) {
+        c2r_kernel<R, 1024, -1><<<(unsigned)c.count, 1024, c.lds, s>>>(a, c.d_rings, bi, yo);
+        return;
+      }
+    }
+    if (c.threads == 512)
+      c2r_kernel<R, 512, -1><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, bi, yo);
+    else
+      c2r_kernel<R, 256, -1><<<(unsigned)c.count, 256, c.lds, s>>>(a, c.d_rings, bi, yo);
+    return;
+  }
   if constexpr (sizeof(R) == 4) {
     if (c.threads == 512 && c.mf == 8192) {
       c2r_kernel<R, 512, 8192><<<(unsigned)c.count, 512, c.lds, s>>>(a, c.d_rings, bi, yo);
@@ -612,6 +651,15 @@ hipError_t launch_ring_batch(arkcos_dtype_t dt, bool inverse, const void* args, 
                              int32_t lds, int32_t threads, int32_t mf, const void* maps, void* ws,
                              const int64_t* base, hipStream_t s) {
   if (count == 0) return hipSuccess;
+  if (mf < 0) {  // mixed-radix rings
+    if (dt == ARKCOS_F32) {
+      if (threads == 1024) return ring_batch<float, 1024, -1>(inverse, args, entries, count, lds, maps, ws, base, s);
+      return threads == 512 ? ring_batch<float, 512, -1>(inverse, args, entries, count, lds, maps, ws, base, s)
+                            : ring_batch<float, 256, -1>(inverse, args, entries, count, lds, maps, ws, base, s);
+    }
+    return threads == 512 ? ring_batch<double, 512, -1>(inverse, args, entries, count, lds, maps, ws, base, s)
+                          : ring_batch<double, 256, -1>(inverse, args, entries, count, lds, maps, ws, base, s);
+  }
   if (dt == ARKCOS_F32) {
     if (threads == 512 && mf == 8192)
       return ring_batch<float, 512, 8192>(inverse, args, entries, count, lds, maps, ws, base, s);

@@ -47,6 +47,67 @@ struct GradArgs {
   double* slots;         // [slot][4 * (nk - 1)]
   int64_t TN;            // length of the twiddle table
   int32_t zcache_bytes;  // LDS for a wide row's correlation
+  int32_t fold;          // 1: read the extended spectra through their stored modes 0 .. N/2
+};
+
+// A~(m) of a ring of N pixels (N even) from the modes 0 .. N/2 that head its
+// extended spectrum: A~(qN + r) = s^q A~(r) for r <= N/2 and
+// A~(qN + N - k) = s^(q+1) conj(A~(k)), s = -1 for rings whose first pixel is
+// offset by half a pixel, 1 otherwise.  A row's correlation then reads a few
+// KB per ring, which stay in cache across the rows of a unit, instead of the
+// whole extension.
+template <typename C>
+__device__ __forceinline__ C ext_mode(const C* __restrict__ base, uint32_t N, bool shifted, uint32_t m) {
+  const uint32_t q = m / N, r = m - q * N;
+  const bool up = 2 * r > N;
+  const C v = base[up ? N - r : r];
+  const bool neg = shifted && ((q + (up ? 1u : 0u)) & 1u);
+  const decltype(v.x) sg = neg ? -1 : 1;
+  return cmake<C>(sg * v.x, (up ? -sg : sg) * v.y);
+}
+
+// X_ij(m) + X_i'j'(m), X = Re[conj(R~_i(m)) A~_j(m)], for output ring i
+// (mirror i') and input ring j (mirror j'); a mirror ring has the pixel
+// count and offset of its ring.
+template <typename R> struct PairX {
+  using C = cx_t<R>;
+  const C *ai, *ri, *am, *rm;
+  uint32_t Ni, Nj;
+  bool shi, shj, mirror, fold;
+  __device__ __forceinline__ PairX(const GradArgs& g, const C* aspec, const C* rspec, const UnitDev& u, int j) {
+    const int jm = g.nrings - 1 - j;
+    ai = aspec + g.spec_off[j];
+    am = aspec + g.spec_off[jm];
+    ri = rspec + g.out_off[u.i];
+    mirror = u.im >= 0;
+    rm = mirror ? rspec + g.out_off[u.im] : ri;
+    Ni = (uint32_t)g.n[u.i];
+    Nj = (uint32_t)g.n[j];
+    shi = g.phase_den[u.i] != 0;
+    shj = g.phase_den[j] != 0;
+    fold = g.fold != 0;
+  }
+  __device__ __forceinline__ double operator()(uint32_t m) const {
+    C a0, r0, a1, r1;
+    if (fold) {
+      a0 = ext_mode(ai, Nj, shj, m);
+      r0 = ext_mode(ri, Ni, shi, m);
+      if (mirror) {
+        a1 = ext_mode(am, Nj, shj, m);
+        r1 = ext_mode(rm, Ni, shi, m);
+      }
+    } else {
+      a0 = ai[m];
+      r0 = ri[m];
+      if (mirror) {
+        a1 = am[m];
+        r1 = rm[m];
+      }
+    }
+    double X = (double)r0.x * a0.x + (double)r0.y * a0.y;
+    if (mirror) X += (double)r1.x * a1.x + (double)r1.y * a1.y;
+    return X;
+  }
 };
 
 constexpr int kGradSpl = kGradPass / 64;  // wide rows: samples per lane in a pass
@@ -223,18 +284,10 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
       if (pr.band < 0 || (item.pair < 0) != (nc <= kGradMaxCoef)) continue;
       const int j = pr.j, jm = g.nrings - 1 - j;
       const int64_t pl = (int64_t)pr.grid;
-      const C* ai = aspec + g.spec_off[j];
-      const C* ri = rspec + g.out_off[u.i];
-      const C* am = aspec + g.spec_off[jm];
-      const C* rm = mirror ? rspec + g.out_off[u.im] : ri;
+      const PairX<R> px(g, aspec, rspec, u, j);
       const double scale = g.w[j] / (double)pl;
       auto xcorr = [&](int m) -> double {  // eps_m h(m) (X_ij(m) + X_i'j'(m))
-        const C a0 = ai[m], r0 = ri[m];
-        double X = (double)r0.x * a0.x + (double)r0.y * a0.y;
-        if (mirror) {
-          const C a1 = am[m], r1 = rm[m];
-          X += (double)r1.x * a1.x + (double)r1.y * a1.y;
-        }
+        const double X = px((uint32_t)m);
         double wm = m == 0 ? 1.0 : 2.0;
         if (m == pr.nyq) wm *= 0.5;
         return X * wm;
@@ -383,6 +436,189 @@ __global__ void __launch_bounds__(kGradThreads) grad_items_kernel(GradArgs g, co
   for (int e = tid; e < nint4; e += blockDim.x) out[e] = U[e];
 }
 
+// Interval sums held by one wavefront: lane l keeps entries l + 64 j (j < 4)
+// of the 4 (nk - 1) <= 252 sums in registers.  wave_interval_add adds the
+// pieces of 64 consecutive samples (lane k: sample k, invalid lanes give
+// nothing): their interval indices do not decrease with the lane, so a
+// segmented scan over lanes of equal index leaves each interval's total in
+// its last lane, and the (few) totals are added into the owning lanes one
+// interval at a time.  The order of every addition is fixed.
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ void wave_interval_add(double (&Ur)[4], const GradArgs& g, bool valid, double t,
+                                                  double wgt) {
+  const int lane = threadIdx.x & 63;
+  int a = g.nk;  // past every interval: outside the support or no sample
+  double pc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (valid && !(t > g.radius || t > g.theta_max + kSupportTol)) {
+    a = (int)floor(t / g.h);
+    a = a < 0 ? 0 : (a > g.nk - 2 ? g.nk - 2 : a);
+    const double u = t / g.h - a, v = 1.0 - u, h2 = g.h * g.h / 6.0;
+    pc[0] = wgt * v;
+    pc[1] = wgt * u;
+    pc[2] = wgt * h2 * (v * v * v - v);
+    pc[3] = wgt * h2 * (u * u * u - u);
+  }
+  if (__ballot(a < g.nk) == 0) return;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int au = __shfl_up(a, off, 64);
+    double up[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) up[c] = __shfl_up(pc[c], off, 64);
+    if (lane >= off && au == a) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) pc[c] += up[c];
+    }
+  }
+  const int an = __shfl_down(a, 1, 64);
+  uint64_t ends = __ballot(a < g.nk && (lane == 63 || an != a));
+  while (ends) {
+    const int e = __builtin_ctzll(ends);
+    ends &= ends - 1;
+    const int ae = __builtin_amdgcn_readlane(a, e);
+    const double s0 = readlane_f64(pc[0], e), s1 = readlane_f64(pc[1], e);
+    const double s2 = readlane_f64(pc[2], e), s3 = readlane_f64(pc[3], e);
+    const int k0 = 4 * ae, j = k0 >> 6;  // entries k0 .. k0 + 3: lanes (k0 & 63) + c of register j
+    if ((lane >> 2) == ((k0 & 63) >> 2)) {
+      const int c = lane & 3;
+      const double v = c == 0 ? s0 : (c == 1 ? s1 : (c == 2 ? s2 : s3));
+      if (j == 0) Ur[0] += v;
+      else if (j == 1) Ur[1] += v;
+      else if (j == 2) Ur[2] += v;
+      else Ur[3] += v;
+    }
+  }
+}
+
+// The LDS FFT as a call: inlined into the row kernel, the compiler's
+// schedule of it holds about twice the registers (a 1024-thread block then
+// spills).
+template <typename R, bool INV, int NT>
+__device__ __noinline__ void lds_fft_outlined(cx_t<R>* buf, int M, const cx_t<R>* __restrict__ tw, int TN) {
+  lds_fft<R, INV, NT>(buf, M, tw, TN);
+}
+
+// Wide rows by FFT: Y(d) = sum_{m <= band} Z(m) cos(2 pi m d / G) with
+// Z(m) = eps_m h(m) (X_ij(m) + X_i'j'(m)) on a power-of-two grid G.  With
+// S = G / (2 P), the modes split into S real sub-sequences z_q = Z(S q + s)
+// of 2 P points, and
+//   Y(d) = Re sum_s exp(2 pi i s d / G) Y_s(d mod 2P),
+// Y_s the inverse 2P-point transform of z (one packed P-point LDS FFT).  One
+// block per row writes Y(d), d < nc, to the row's place in the chunk's buffer
+// (thread k owns the samples k + NT i in every pass).
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT) grad_row_fft_kernel(GradArgs g, const RowFft* __restrict__ rows,
+                                                          const int64_t* __restrict__ yoff,
+                                                          const cx_t<R>* __restrict__ aspec,
+                                                          const cx_t<R>* __restrict__ rspec,
+                                                          const cx_t<R>* __restrict__ tw, R* __restrict__ Y) {
+  using C = cx_t<R>;
+  extern __shared__ __align__(16) unsigned char gsm[];
+  C* buf = reinterpret_cast<C*>(gsm);
+  const int tid = threadIdx.x;
+  const RowFft row = rows[blockIdx.x];
+  const UnitDev u = g.units[row.unit];
+  const bool mirror = u.im >= 0;
+  const int q = row.pair, Pn = row.P;
+  const PairDev pr = g.pairs[q];
+  const int64_t G = pr.grid;
+  const int S = (int)(G / (2 * (int64_t)Pn));
+  const int nc = g.ncoef_window[q], band = pr.band;
+  const int j = pr.j;
+  const PairX<R> px(g, aspec, rspec, u, j);
+  R* Yr = Y + yoff[blockIdx.x];
+  auto xcorr = [&](int64_t m) -> R {  // eps_m h(m) (X_ij(m) + X_i'j'(m)), zero past the band
+    if (m > band) return R(0);
+    const double X = px((uint32_t)m);
+    double wm = m == 0 ? 1.0 : 2.0;
+    if (m == pr.nyq) wm *= 0.5;
+    return (R)(X * wm);
+  };
+  const int64_t kstep = g.TN / (2 * (int64_t)Pn), gstep = g.TN / G;
+  for (int s = 0; s < S; ++s) {
+    for (int l = tid; l < Pn; l += NT) {
+      const int64_t m0 = (int64_t)S * (2 * l) + s;
+      buf[lidx(l)] = cmake<C>(xcorr(m0), xcorr(m0 + S));
+    }
+    __syncthreads();
+    lds_fft_outlined<R, true, NT>(buf, Pn, tw, (int)g.TN);
+    for (int d = tid; d < nc; d += NT) {
+      const int k = d & (2 * Pn - 1);
+      const C X = real_from_packed<R>(buf, Pn, k, cconj(tw[k * kstep]));
+      const C ph = cconj(tw[(((int64_t)s * d) & (G - 1)) * gstep]);  // exp(2 pi i s d / G)
+      const R v = ph.x * X.x - ph.y * X.y;
+      Yr[d] = s == 0 ? v : Yr[d] + v;
+    }
+    __syncthreads();  // buf is rewritten by the next pass
+  }
+}
+
+template <typename R, int NT>
+static hipError_t grad_row_fft_launch(const GradArgs& g, const RowFft* rows, const int64_t* yoff, int32_t count,
+                                      const void* spec, const void* bout, const void* twd, void* Y, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const size_t lds = (size_t)lds_elems(16 * NT) * sizeof(cx_t<R>);
+  hipError_t e = hipFuncSetAttribute((const void*)grad_row_fft_kernel<R, NT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  grad_row_fft_kernel<R, NT><<<count, NT, lds, s>>>(g, rows, yoff, (const cx_t<R>*)spec, (const cx_t<R>*)bout,
+                                                    (const cx_t<R>*)twd, (R*)Y);
+  return hipGetLastError();
+}
+
+// The FFT rows' Y(d) into the interval sums: persistent blocks take the
+// rows b, b + grid, ... of a chunk in order; wave w of a block takes the
+// samples 64 (4 k + w) .. + 63 (k = 0, 1, ...) of a row into its register
+// sums; at the end the waves' sums are added in wave order and written to
+// (first chunk) or added into (later chunks) the block's slot.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) grad_row_scatter_kernel(GradArgs g, const RowFft* __restrict__ rows,
+                                                                  int32_t nrows, const int64_t* __restrict__ yoff,
+                                                                  const R* __restrict__ Y, int32_t slot0,
+                                                                  int32_t accumulate) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double part[NW * 256];
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double Ur[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int ri = blockIdx.x; ri < nrows; ri += gridDim.x) {
+    const RowFft row = rows[ri];
+    const UnitDev u = g.units[row.unit];
+    const int q = row.pair;
+    const PairDev pr = g.pairs[q];
+    const int64_t G = pr.grid;
+    const int nc = g.ncoef_window[q], j = pr.j;
+    const double scale = g.w[j] / (double)G;
+    const double thi = g.theta[u.i], thj = g.theta[j], si = g.sint[u.i], sj = g.sint[j];
+    const R* Yr = Y + yoff[ri];
+    for (int d0 = 64 * wv; d0 < nc; d0 += 64 * NW) {
+      const int d = d0 + lane;
+      double t = 0.0, wgt = 0.0;
+      if (d < nc) {
+        t = grad_distance(thi, thj, si, sj, 2 * (int64_t)d, G);
+        const double cd = (d == 0 || 2 * (int64_t)d == G) ? 1.0 : 2.0;
+        wgt = cd * scale * (double)Yr[d];
+      }
+      wave_interval_add(Ur, g, d < nc, t, wgt);
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) part[wv * 256 + lane + 64 * jj] = Ur[jj];
+  __syncthreads();
+  const int nint4 = 4 * (g.nk - 1);
+  double* out = g.slots + (size_t)(slot0 + blockIdx.x) * nint4;
+  for (int e = tid; e < nint4; e += kBlock) {
+    double v = 0.0;
+    for (int w = 0; w < NW; ++w) v += part[w * 256 + e];
+    out[e] = accumulate ? out[e] + v : v;
+  }
+}
+
 // Direct-sum pole rows: one block per pole pixel p, slot slot0 + b.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) grad_pole_kernel(GradArgs g, const int32_t* __restrict__ rings,
@@ -490,6 +726,7 @@ arkcos_status_t run_kernel_grad(arkcos_plan_s* P, const void* x, const void* r, 
   g.slots = slots;
   g.TN = P->twiddle_n;
   g.zcache_bytes = P->grad_zcache_bytes;
+  g.fold = P->grad_fold;
   const int32_t nruns = P->n_grad_runs;
   const size_t lds = (size_t)P->grad_zcache_bytes;
   if (P->dtype == ARKCOS_F32) {
@@ -508,18 +745,61 @@ arkcos_status_t run_kernel_grad(arkcos_plan_s* P, const void* x, const void* r, 
                                                                  (const double2*)P->d_twiddle);
   }
   if (e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string("gradient kernels: ") + hipGetErrorString(e));
-  int32_t nslots = nruns;
+  // the wide rows taken by FFTs, a chunk at a time: Y(d) of the chunk's rows
+  // (one launch per block size), then their interval sums into the slots
+  // after the runs'
+  if (P->n_gfft_slots > 0) {
+    void* Y = grad_y(P, ws);
+    const int32_t cls_end[3] = {P->n_gfft[0], P->n_gfft[0] + P->n_gfft[1],
+                                P->n_gfft[0] + P->n_gfft[1] + P->n_gfft[2]};
+    for (size_t c = 0; c + 1 < P->h_gfft_chunk.size() && e == hipSuccess; ++c) {
+      const int32_t r0 = P->h_gfft_chunk[c], r1 = P->h_gfft_chunk[c + 1];
+      auto part = [&](int k, int32_t& b) {  // rows of block-size class k in [r0, r1)
+        const int32_t lo = std::max(r0, k == 0 ? 0 : cls_end[k - 1]), hi = std::min(r1, cls_end[k]);
+        b = lo;
+        return hi - lo;
+      };
+      int32_t b0 = 0, b1 = 0, b2 = 0;
+      const int32_t n0 = part(0, b0), n1 = part(1, b1), n2 = part(2, b2);
+      const RowFft* rows = P->d_gfft;
+      const int64_t* yo = P->d_gfft_yoff;
+      if (P->dtype == ARKCOS_F32) {
+        e = grad_row_fft_launch<float, 256>(g, rows + b0, yo + b0, n0, spec, bout, P->d_twiddle, Y, s);
+        if (e == hipSuccess)
+          e = grad_row_fft_launch<float, 512>(g, rows + b1, yo + b1, n1, spec, bout, P->d_twiddle, Y, s);
+        if (e == hipSuccess)
+          e = grad_row_fft_launch<float, 1024>(g, rows + b2, yo + b2, n2, spec, bout, P->d_twiddle, Y, s);
+        if (e == hipSuccess) {
+          grad_row_scatter_kernel<float><<<P->n_gfft_slots, kBlock, 0, s>>>(g, rows + r0, r1 - r0, yo + r0,
+                                                                             (const float*)Y, nruns, c > 0);
+          e = hipGetLastError();
+        }
+      } else {
+        e = grad_row_fft_launch<double, 256>(g, rows + b0, yo + b0, n0, spec, bout, P->d_twiddle, Y, s);
+        if (e == hipSuccess)
+          e = grad_row_fft_launch<double, 512>(g, rows + b1, yo + b1, n1, spec, bout, P->d_twiddle, Y, s);
+        if (e == hipSuccess) {
+          grad_row_scatter_kernel<double><<<P->n_gfft_slots, kBlock, 0, s>>>(g, rows + r0, r1 - r0, yo + r0,
+                                                                              (const double*)Y, nruns, c > 0);
+          e = hipGetLastError();
+        }
+      }
+    }
+    if (e != hipSuccess) return fail(ARKCOS_ERR_DEVICE, std::string("gradient kernels: ") + hipGetErrorString(e));
+  }
+  const int32_t nmain = nruns + P->n_gfft_slots;
+  int32_t nslots = nmain;
   if (fix) {
     int32_t count = 0;
     int32_t* list = pole_ring_list(P, &count);
     if (P->dtype == ARKCOS_F32)
-      grad_pole_kernel<float><<<8, kBlock, 0, s>>>(g, list, count, (const float*)x, (const float*)r, nruns);
+      grad_pole_kernel<float><<<8, kBlock, 0, s>>>(g, list, count, (const float*)x, (const float*)r, nmain);
     else
-      grad_pole_kernel<double><<<8, kBlock, 0, s>>>(g, list, count, (const double*)x, (const double*)r, nruns);
+      grad_pole_kernel<double><<<8, kBlock, 0, s>>>(g, list, count, (const double*)x, (const double*)r, nmain);
     nslots += 8;
   }
-  // (the workspace holds n_grad_runs + 8 slots and then the sums)
-  double* sums = slots + (size_t)(nruns + 8) * (size_t)(4 * (g.nk - 1));
+  // (the workspace holds n_grad_runs + n_gfft_slots + 8 slots and then the sums)
+  double* sums = slots + (size_t)(nmain + 8) * (size_t)(4 * (g.nk - 1));
   grad_sum_kernel<<<(unsigned)(4 * (g.nk - 1)), kBlock, 0, s>>>(slots, nslots, 4 * (g.nk - 1), sums);
   grad_final_kernel<<<1, kBlock, 0, s>>>(sums, g.nk, P->d_basis_mom, grad);
   e = hipGetLastError();

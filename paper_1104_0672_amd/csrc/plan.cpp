@@ -66,6 +66,36 @@ bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
                   std::string(#expr) + ": " + hipGetErrorString(_e));                     \
   } while (0)
 
+// P of the FFT path for the kernel row of pair q with nc samples (spline
+// plans; 0: the direct sums).  The row's grid G must be a power of two of at
+// least kFftRowMinGrid longitudes dividing the twiddle table's length, its
+// nodes centred, and the FFTs (S = G /
+// (2 P) sub-transforms of P points, P at most 16384 in FP32 and 8192 in FP64,
+// the largest that one workgroup's LDS holds) cheaper than the sums over
+// samples x modes.
+int32_t fft_row_points(const arkcos_plan_s* P, int64_t q, int64_t nc) {
+  const PairDev& pr = P->h_pairs[q];
+  if (P->prof_kind != 1 || P->h_pair_shift[q] || pr.band < 0 || nc <= kGradMaxCoef) return 0;
+  const int64_t G = pr.grid;
+  if (!is_pow2(G) || G < kFftRowMinGrid || P->twiddle_n % G != 0) return 0;
+  const int64_t pcap = P->dtype == ARKCOS_F32 ? 16384 : 8192;
+  const int64_t Pn = std::min<int64_t>(G / 2, pcap);
+  const int64_t S = G / (2 * Pn);
+  const double direct = (double)nc * (double)(pr.band + 1);
+  const double fft = 4.0 * (double)S * (double)Pn * std::log2((double)Pn) + 2.0 * (double)G;
+  return direct > fft ? (int32_t)Pn : 0;
+}
+
+// Rows grouped by block size (fft_row_threads), biggest first within each.
+static void group_fft_rows(std::vector<RowFft>& rows, int32_t counts[3]) {
+  auto cls = [](int32_t Pn) { return Pn <= 4096 ? 0 : (Pn <= 8192 ? 1 : 2); };
+  std::stable_sort(rows.begin(), rows.end(), [&](const RowFft& a, const RowFft& b) {
+    return cls(a.P) != cls(b.P) ? cls(a.P) < cls(b.P) : a.P > b.P;
+  });
+  for (int c = 0; c < 3; ++c) counts[c] = 0;
+  for (const RowFft& r : rows) ++counts[cls(r.P)];
+}
+
 // Uploads the spline knots and their moments (spline plans only).
 arkcos_status_t upload_knots(arkcos_plan_s* P) {
   if (P->prof_kind != 1) return ARKCOS_OK;
@@ -86,6 +116,7 @@ arkcos_status_t upload_knots(arkcos_plan_s* P) {
 arkcos_status_t build_grad_items(arkcos_plan_s* P) {
   std::vector<GradItem> items;
   std::vector<double> cost;
+  std::vector<RowFft> fft_rows;
   int64_t zmax = 0;
   const int64_t rsz = P->dtype == ARKCOS_F32 ? 4 : 8;
   const int64_t chunk = kGradZBytes / rsz;
@@ -105,6 +136,10 @@ arkcos_status_t build_grad_items(arkcos_plan_s* P) {
       const PairDev& pr = P->h_pairs[q];
       const int64_t nc = P->h_ncoef_window[q];
       if (pr.band < 0 || nc <= kGradMaxCoef) continue;
+      if (const int32_t Pn = fft_row_points(P, q, nc); Pn > 0) {
+        fft_rows.push_back(RowFft{(int32_t)u, q, Pn, 0});
+        continue;
+      }
       const int64_t nm = pr.band + 1;
       for (int64_t m0 = 0; m0 < nm; m0 += chunk) {
         const int64_t len = std::min(chunk, nm - m0);
@@ -135,6 +170,30 @@ arkcos_status_t build_grad_items(arkcos_plan_s* P) {
   }
   P->h_grad_items = items;
   P->n_grad_runs = (int32_t)nruns;
+  // FFT rows: Y(d) of each row at an offset in its chunk's buffer (chunks
+  // of at most kGradYBytes), and the persistent blocks of the interval sums,
+  // each with its own slot
+  group_fft_rows(fft_rows, P->n_gfft);
+  {
+    std::vector<int64_t> yoff(fft_rows.size());
+    P->h_gfft_chunk.assign(1, 0);
+    P->grad_y_elems = 0;
+    int64_t used = 0;
+    for (size_t k = 0; k < fft_rows.size(); ++k) {
+      const int64_t nc = P->h_ncoef_window[fft_rows[k].pair];
+      if (used > 0 && (used + nc) * rsz > kGradYBytes) {
+        P->h_gfft_chunk.push_back((int32_t)k);
+        used = 0;
+      }
+      yoff[k] = used;
+      used += nc;
+      P->grad_y_elems = std::max(P->grad_y_elems, used);
+    }
+    P->h_gfft_chunk.push_back((int32_t)fft_rows.size());
+    HIPCHK(upload(P, &P->d_gfft_yoff, yoff));
+  }
+  P->n_gfft_slots = std::min<int32_t>((int32_t)fft_rows.size(), 4 * cus);
+  HIPCHK(upload(P, &P->d_gfft, fft_rows));
   // a wide-row item's correlation (one mode chunk) is staged in LDS
   P->grad_zcache_bytes = (int32_t)((std::max<int64_t>(zmax, 1) * rsz + 15) / 16 * 16);
   HIPCHK(upload(P, &P->d_grad_items, items));
@@ -254,6 +313,7 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P) {
   int64_t table_total = 0, ntab = 0;
   std::vector<int32_t> tab_list;
   std::vector<int64_t> tab_coef;
+  std::vector<RowFft> tab_fft;  // wide spline rows whose tables come from FFTs
   P->h_tab_owner.assign(np, -1);
   for (int64_t q = 0; q < np; ++q) {
     PairDev& pr = P->h_pairs[q];
@@ -277,8 +337,12 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P) {
       pr.kind = KG_TABLE;
       pr.off = table_total;
       table_total += table_span(pr.band);
-      tab_list.push_back((int32_t)q);
-      tab_coef.push_back(P->h_coef_off[q]);
+      if (const int32_t Pn = fft_row_points(P, q, pr.ncoef); Pn > 0) {
+        tab_fft.push_back(RowFft{-1, (int32_t)q, Pn, 0});
+      } else {
+        tab_list.push_back((int32_t)q);
+        tab_coef.push_back(P->h_coef_off[q]);
+      }
       ++ntab;
     } else {
       pr.kind = P->h_pair_shift[q] ? KG_SHIFTED : (pr.ncoef > kClenshawMaxCoef ? KG_REINSCH : KG_CENTRED);
@@ -310,7 +374,10 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P) {
   P->n_tab_list = (int32_t)tab_list.size();
   HIPCHK(upload(P, &P->d_tab_list, tab_list));
   HIPCHK(upload(P, &P->d_tab_coef, tab_coef));
+  group_fft_rows(tab_fft, P->n_tfft);
+  HIPCHK(upload(P, &P->d_tfft, tab_fft));
   HIPCHK(launch_table_list(P, P->d_tab_list, P->d_tab_coef, P->n_tab_list, s));
+  HIPCHK(launch_table_fft(P, s));
   HIPCHK(hipStreamSynchronize(s));
   return ARKCOS_OK;
 }
@@ -324,7 +391,9 @@ hipError_t update_knots(arkcos_plan_s* P, const double* d_src, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = launch_kernel_rows(P, nullptr, s);
   if (e != hipSuccess) return e;
-  return launch_table_list(P, P->d_tab_list, P->d_tab_coef, P->n_tab_list, s);
+  e = launch_table_list(P, P->d_tab_list, P->d_tab_coef, P->n_tab_list, s);
+  if (e != hipSuccess) return e;
+  return launch_table_fft(P, s);
 }
 
 // Bands of units_per_band units and their items (mode tiles in runs of
@@ -635,6 +704,40 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   std::vector<size_t> ring_lds(nr, 0);
   int64_t twn = 4;
   size_t lds = 0;
+  // Rings whose half length has no prime factor above 7 take the
+  // mixed-radix transform when they fill launches of their own: at least
+  // kMixedMinRings of them share a launch class (LDS bucket), or every
+  // non-power-of-two ring of the plan qualifies (ECP grids, HEALPix belts of
+  // such a length).  Scattered lengths (HEALPix polar rings: two rings per
+  // length) stay with Bluestein, whose launches they share; in classes of
+  // their own they ran as small, tail-bound launches (nside 2048 forward
+  // 0.81 -> 0.89 ms).
+  auto smooth7 = [](int64_t v) {
+    for (int64_t f : {2, 3, 5, 7})
+      while (v % f == 0) v /= f;
+    return v == 1;
+  };
+  auto mixed_ok = [&](int64_t N) {
+    const int64_t n = N / 2;
+    return N > kDirectMax && !is_pow2(n) && smooth7(n) && n <= maxM;
+  };
+  auto lds_bucket = [&](int64_t n) {
+    size_t b = 32768;
+    while (b < (size_t)lds_elems((int)n) * csz) b <<= 1;
+    return b;
+  };
+  std::map<size_t, int64_t> mixed_per_bucket;
+  int64_t n_mixed_ok = 0, n_not_pow2 = 0;
+  for (int64_t k = 0; k < nr; ++k) {
+    const int64_t N = P->h_n[k];
+    if (N > kDirectMax && !is_pow2(N / 2)) ++n_not_pow2;
+    if (mixed_ok(N)) {
+      ++mixed_per_bucket[lds_bucket(N / 2)];
+      ++n_mixed_ok;
+    }
+  }
+  constexpr int64_t kMixedMinRings = 1024;
+  const bool all_mixed = n_mixed_ok == n_not_pow2;
   for (int64_t k = 0; k < nr; ++k) {
     const int64_t N = P->h_n[k];
     if (N <= kDirectMax) {
@@ -645,7 +748,13 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       continue;
     }
     const int64_t n = N / 2;
-    if (is_pow2(n)) {
+    if (mixed_ok(N) && (all_mixed || mixed_per_bucket[lds_bucket(n)] >= kMixedMinRings)) {
+      // a mixed-radix transform of the ring's own length (no Bluestein)
+      fft_kind[k] = FFT_MIXED;
+      fft_m[k] = (int32_t)n;
+      ring_lds[k] = (size_t)lds_elems((int)n) * csz;
+      lds = std::max(lds, ring_lds[k]);
+    } else if (is_pow2(n)) {
       if (n > maxM) return fail(ARKCOS_ERR_NOT_SUPPORTED, "ring FFT longer than the LDS limit");
       fft_kind[k] = FFT_POW2;
       fft_m[k] = (int32_t)n;
@@ -681,6 +790,7 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   P->max_fft_lds = (int32_t)((lds + 15) / 16 * 16);
   P->h_ring_lds.resize(nr);
   P->h_fft_len = fft_m;
+  P->h_fft_kind = fft_kind;
   for (int64_t k = 0; k < nr; ++k) P->h_ring_lds[k] = (int32_t)((ring_lds[k] + 15) / 16 * 16);
   {
     // launch classes by LDS size: power-of-two buckets from 32 KiB, so that
@@ -702,6 +812,7 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       while (b < ring_lds[k]) b <<= 1;
       const int32_t ct = ct_fft_length(dtype, fft_m[k], per_len[fft_m[k]]);
       if (ct > 0) b = (size_t(1) << 40) + (size_t)ct;
+      if (fft_kind[k] == FFT_MIXED) b |= size_t(1) << 39;  // mixed-radix rings: classes of their own
       pairs_of[b].push_back({(int32_t)k, nr - 1 - k != k ? (int32_t)(nr - 1 - k) : -1});
     }
     std::map<size_t, std::vector<int32_t>> cls;
@@ -726,6 +837,7 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
       }
       c.lds = (int32_t)((mx + 15) / 16 * 16);
       c.mf = (lo == len) ? ct_fft_length(dtype, len, per_len[len]) : 0;
+      if (it->first & (size_t(1) << 39)) c.mf = -1;
       c.threads = c.mf > 0 ? c.mf / 16 : fft_threads(dtype, len);
       HIPCHK(upload(P, &c.d_rings, it->second));
       P->fft_classes.push_back(c);
@@ -892,6 +1004,19 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   HIPCHK(upload(P, &P->rt.out_off, P->h_out_off));
   HIPCHK(upload(P, &P->rt.out_len, P->h_out_len));
   HIPCHK(upload(P, &P->d_units, P->h_units));
+  // the knot gradient may read a ring's extended spectrum through its
+  // stored modes 0 .. N/2 (every read mode m <= band lies below the
+  // spectrum's length, and so does its folded index): rings of even length,
+  // a mirror ring with the pixel count and offset of its ring
+  if (P->prof_kind == 1) {
+    bool fold = true;
+    for (int64_t k = 0; k < nr && fold; ++k) {
+      const int64_t km = nr - 1 - k;
+      fold = P->h_n[k] % 2 == 0 && P->h_n[km] == P->h_n[k] &&
+             (P->h_phase_den[km] != 0) == (P->h_phase_den[k] != 0);
+    }
+    P->grad_fold = fold ? 1 : 0;
+  }
 
   // bands of consecutive units, and work items: (band, first mode) tiles
   {
@@ -987,14 +1112,24 @@ static size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
 static size_t grad_slot_bytes(const arkcos_plan_s* P) {
   if (P->prof_kind != 1) return 0;
-  // one slot per run, eight for the pole rows, one for their sum
-  return al256((size_t)(P->n_grad_runs + 9) * 4 * (P->knots.size() - 1) * sizeof(double));
+  // one slot per run and per FFT-row block, eight for the pole rows, one for their sum
+  return al256((size_t)(P->n_grad_runs + P->n_gfft_slots + 9) * 4 * (P->knots.size() - 1) * sizeof(double));
+}
+
+// the FFT rows' Y(d) (one chunk at a time), after the slots
+static size_t grad_y_bytes(const arkcos_plan_s* P) {
+  if (P->prof_kind != 1 || P->grad_y_elems == 0) return 0;
+  return al256((size_t)P->grad_y_elems * (P->dtype == ARKCOS_F32 ? sizeof(float) : sizeof(double)));
 }
 
 size_t workspace_bytes(const arkcos_plan_s* P) {
   const size_t csz = P->dtype == ARKCOS_F32 ? sizeof(float2) : sizeof(double2);
   return al256(std::max<int64_t>(P->spec_total, 1) * csz) + al256(std::max<int64_t>(P->out_total, 1) * csz) +
-         grad_slot_bytes(P);
+         grad_slot_bytes(P) + grad_y_bytes(P);
+}
+
+void* grad_y(const arkcos_plan_s* P, void* ws) {
+  return reinterpret_cast<char*>(grad_slots(P, ws)) + grad_slot_bytes(P);
 }
 
 double* grad_slots(const arkcos_plan_s* P, void* ws) {

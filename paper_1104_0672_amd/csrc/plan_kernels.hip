@@ -194,6 +194,85 @@ __global__ void __launch_bounds__(kBlock) table_kernel(
         m <= pr.band ? (R)k_of_m_fp64(coef64 + coef_off[t], pr.ncoef, m, pair_shift[q], pl, pr.nyq) : R(0);
 }
 
+// Tables of the FFT rows (spline plans): K(m) = h(m) sum_{d < n} a_d cos(2 pi m d / G)
+// for m <= band (h = 1/2 at the Nyquist mode), zero to the end of the last
+// tile.  With S = G / (2 P), the samples split into S real sub-sequences
+// x_q = a_{S q + s} of 2 P points, and
+//   K(m) = Re sum_s exp(-2 pi i s m / G) X_s(m mod 2P),
+// X_s the forward 2P-point transform of x (one packed P-point LDS FFT).  One
+// block per row; each thread keeps its modes over the passes, so the
+// table's partial sums need no synchronisation.
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT) table_fft_kernel(const PairDev* __restrict__ pairs,
+                                                       const RowFft* __restrict__ rows,
+                                                       const int64_t* __restrict__ coef_off,
+                                                       const double* __restrict__ coef64,
+                                                       const cx_t<R>* __restrict__ tw, int64_t TN,
+                                                       R* __restrict__ table) {
+  using C = cx_t<R>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* buf = reinterpret_cast<C*>(smem);
+  const RowFft row = rows[blockIdx.x];
+  const int q = row.pair, Pn = row.P;
+  const PairDev pr = pairs[q];
+  const int64_t G = pr.grid;
+  const int S = (int)(G / (2 * (int64_t)Pn));
+  const int nc = pr.ncoef, band = pr.band;
+  const double* a = coef64 + coef_off[q];
+  R* T = table + pr.off;
+  const int64_t kstep = TN / (2 * (int64_t)Pn), gstep = TN / G;
+  for (int s = 0; s < S; ++s) {
+    for (int l = threadIdx.x; l < Pn; l += NT) {
+      const int64_t d0 = (int64_t)S * (2 * l) + s, d1 = d0 + S;
+      buf[lidx(l)] = cmake<C>(d0 < nc ? (R)a[d0] : R(0), d1 < nc ? (R)a[d1] : R(0));
+    }
+    __syncthreads();
+    lds_fft<R, false, NT>(buf, Pn, tw, (int)TN);
+    for (int m = threadIdx.x; m <= band; m += NT) {
+      const int k = m & (2 * Pn - 1);
+      const C X = real_from_packed<R>(buf, Pn, k, tw[k * kstep]);
+      const C ph = tw[(((int64_t)s * m) & (G - 1)) * gstep];  // exp(-2 pi i s m / G)
+      const R v = ph.x * X.x - ph.y * X.y;
+      T[m] = s == 0 ? v : T[m] + v;
+    }
+    __syncthreads();  // buf is rewritten by the next pass
+  }
+  const int end = table_span(band);
+  for (int m = threadIdx.x; m < end; m += NT) {
+    if (m > band) T[m] = R(0);
+    else if (m == pr.nyq) T[m] *= R(0.5);
+  }
+}
+
+template <typename R, int NT>
+static hipError_t table_fft_launch(arkcos_plan_s* P, const RowFft* rows, int32_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  int32_t pmax = NT * 16;
+  const size_t lds = (size_t)lds_elems(pmax) * sizeof(cx_t<R>);
+  hipError_t e = hipFuncSetAttribute((const void*)table_fft_kernel<R, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  table_fft_kernel<R, NT><<<count, NT, lds, s>>>(P->d_pairs, rows, P->d_coef_off, P->d_coef64,
+                                                 (const cx_t<R>*)P->d_twiddle, P->twiddle_n, (R*)P->d_table);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_fft(arkcos_plan_s* P, hipStream_t s) {
+  const RowFft* r0 = P->d_tfft;
+  const RowFft* r1 = r0 + P->n_tfft[0];
+  const RowFft* r2 = r1 + P->n_tfft[1];
+  hipError_t e;
+  if (P->dtype == ARKCOS_F32) {
+    e = table_fft_launch<float, 256>(P, r0, P->n_tfft[0], s);
+    if (e == hipSuccess) e = table_fft_launch<float, 512>(P, r1, P->n_tfft[1], s);
+    if (e == hipSuccess) e = table_fft_launch<float, 1024>(P, r2, P->n_tfft[2], s);
+  } else {
+    e = table_fft_launch<double, 256>(P, r0, P->n_tfft[0], s);
+    if (e == hipSuccess) e = table_fft_launch<double, 512>(P, r1, P->n_tfft[1], s);
+  }
+  return e;
+}
+
 // Bluestein filter of length n: FFT_M of b_l = exp(+i pi l^2 / n) placed at l
 // and M - l for 0 <= l < n, followed by the chirp exp(-i pi l^2 / n), l < n,
 // and the ring's half-angle phases w_r = exp(-i pi r / (2 n)), r <= n / 2

@@ -181,6 +181,9 @@ def test_knot_gradient_wide_rows_64_knots(dtype, tol):
     assert th[0] < w.profile.theta_max  # the pole lies inside ring 0's support: full-ring rows
     _say(f"case knot gradient wide rows {w.name} {dtype} p=16")
     plan = Plan.from_workload(w, oversample=16)
+    # the rows on the 2048-longitude grid go through the FFT forms
+    _say(f"  rows by FFT: tables {plan.info.table_fft_rows}, gradient {plan.info.grad_fft_rows}")
+    assert plan.info.grad_fft_rows > 0 and plan.info.table_fft_rows > 0
     rng = np.random.default_rng(12)
     x, t = rng.standard_normal(w.grid.npix), rng.standard_normal(w.grid.npix)
     y = plan.convolve(_tt(x, dtype)).double().cpu().numpy()
@@ -192,10 +195,17 @@ def test_knot_gradient_wide_rows_64_knots(dtype, tol):
     assert err <= tol
 
 
-def test_set_knots_async_equals_host_update():
+@pytest.mark.parametrize("nside,p", [(16, None), (32, 16)])
+def test_set_knots_async_equals_host_update(nside, p):
+    """Knot updates on the device and from the host give the same map, equal
+    to the FP64 hybrid reference with the new knots.  At nside 32 with
+    oversample 16 the wide rows' tables come from FFTs of the samples."""
     from paper_1104_0672_amd import Plan
-    w = _spline_workload(16, 12, "f64", 21)
-    pa, pb = Plan.from_workload(w), Plan.from_workload(w)
+    w = _spline_workload(nside, 12, "f64", 21)
+    _say(f"case set_knots {w.name} p={p}")
+    pa, pb = Plan.from_workload(w, oversample=p or 0), Plan.from_workload(w, oversample=p or 0)
+    if p == 16:
+        assert pa.info.table_fft_rows > 0
     c2 = np.asarray(w.profile.knots) * 1.3 + 0.05 * np.random.default_rng(22).standard_normal(12)
     x = _tt(np.random.default_rng(23).standard_normal(w.grid.npix), "f64")
     pa.set_knots(c2)

@@ -93,6 +93,22 @@ def test_ecp_ragged_shapes_fp64(ntheta, nphi):
     assert _frac(y, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("nphi", [96, 120, 420, 1000, 1260, 3072])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-6)])
+def test_ecp_mixed_radix_ring_lengths(nphi, dtype, tol):
+    """Rings whose half length has no prime factor above 7 take the
+    mixed-radix transform (radices 2-16, 3, 5, 7; e.g. 210 = 2 3 5 7): exact
+    against the direct sum on ECP grids, where the method is exact."""
+    g = W.Grid("ecp", ntheta=12, nphi=nphi)
+    prof = W.Profile("gaussian", fwhm=2.5 * math.pi / 12)
+    w = W.Workload(f"ecp12x{nphi}", g, prof, 3 * prof.fwhm, dtype, 13)
+    _say(f"case ecp 12x{nphi} {dtype}")
+    x = W.make_input(w)
+    _, y = _run(w, x)
+    ref = oracle.direct(g, prof, w.radius, x)
+    assert _frac(y, ref) <= tol
+
+
 @pytest.mark.parametrize("nside,p", [(4, 2), (16, 1), (16, 2), (40, 2), (24, 4)])
 def test_healpix_fp64_matches_step_by_step_method(nside, p):
     w = W.scaled_healpix(nside, fwhm_arcmin=2.5 * 60 * math.degrees(math.sqrt(math.pi / 3) / nside),

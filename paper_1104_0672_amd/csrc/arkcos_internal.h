@@ -233,7 +233,6 @@ struct arkcos_plan_s {
   int32_t* d_grad_run = nullptr;    // n_grad_runs + 1 item offsets: the items of each gradient block
   int32_t n_grad_runs = 0;
   int32_t grad_zcache_bytes = 0;    // LDS of a gradient block for a wide row's correlation
-  int32_t grad_fold = 0;            // 1: the gradient reads spectra through their modes 0 .. N/2
   int32_t* d_pole_rings = nullptr;  // rings within reach of a pole pixel
   int32_t n_pole_rings = 0;
   size_t plan_bytes = 0;

@@ -677,4 +677,32 @@ template <typename T> __device__ __forceinline__ T uniform(T v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// A~(m) of a ring of N pixels (N even) from the modes 0 .. N/2 that head its
+// extended spectrum (a mode m folds to an index no larger than m):
+// A~(qN + r) = s^q A~(r) for r <= N/2 and A~(qN + N - k) = s^(q+1) conj(A~(k)),
+// s = -1 for rings whose first pixel is offset by half a pixel, 1 otherwise.
+// The knot gradient reads spectra this way: a row's correlation then touches
+// a few KB per ring, which stay in cache across the rows of a unit, instead
+// of the whole extension.
+// inv = 1/N in FP32: the quotient m / N (m < 2^24) from the float product is
+// off by at most one, then corrected.
+template <typename C>
+__device__ __forceinline__ C ext_mode(const C* __restrict__ base, uint32_t N, float inv, bool shifted, uint32_t m) {
+  int qi = (int)((float)m * inv);
+  int ri = (int)m - qi * (int)N;
+  if (ri < 0) {
+    ri += (int)N;
+    --qi;
+  } else if (ri >= (int)N) {
+    ri -= (int)N;
+    ++qi;
+  }
+  const uint32_t q = (uint32_t)qi, r = (uint32_t)ri;
+  const bool up = 2 * r > N;
+  const C v = base[up ? N - r : r];
+  const bool neg = shifted && ((q + (up ? 1u : 0u)) & 1u);
+  const decltype(v.x) sg = neg ? -1 : 1;
+  return cmake<C>(sg * v.x, (up ? -sg : sg) * v.y);
+}
+
 }  // namespace arkcos

@@ -47,24 +47,7 @@ struct GradArgs {
   double* slots;         // [slot][4 * (nk - 1)]
   int64_t TN;            // length of the twiddle table
   int32_t zcache_bytes;  // LDS for a wide row's correlation
-  int32_t fold;          // 1: read the extended spectra through their stored modes 0 .. N/2
 };
-
-// A~(m) of a ring of N pixels (N even) from the modes 0 .. N/2 that head its
-// extended spectrum: A~(qN + r) = s^q A~(r) for r <= N/2 and
-// A~(qN + N - k) = s^(q+1) conj(A~(k)), s = -1 for rings whose first pixel is
-// offset by half a pixel, 1 otherwise.  A row's correlation then reads a few
-// KB per ring, which stay in cache across the rows of a unit, instead of the
-// whole extension.
-template <typename C>
-__device__ __forceinline__ C ext_mode(const C* __restrict__ base, uint32_t N, bool shifted, uint32_t m) {
-  const uint32_t q = m / N, r = m - q * N;
-  const bool up = 2 * r > N;
-  const C v = base[up ? N - r : r];
-  const bool neg = shifted && ((q + (up ? 1u : 0u)) & 1u);
-  const decltype(v.x) sg = neg ? -1 : 1;
-  return cmake<C>(sg * v.x, (up ? -sg : sg) * v.y);
-}
 
 // X_ij(m) + X_i'j'(m), X = Re[conj(R~_i(m)) A~_j(m)], for output ring i
 // (mirror i') and input ring j (mirror j'); a mirror ring has the pixel
@@ -73,7 +56,8 @@ template <typename R> struct PairX {
   using C = cx_t<R>;
   const C *ai, *ri, *am, *rm;
   uint32_t Ni, Nj;
-  bool shi, shj, mirror, fold;
+  float invi, invj;
+  bool shi, shj, mirror;
   __device__ __forceinline__ PairX(const GradArgs& g, const C* aspec, const C* rspec, const UnitDev& u, int j) {
     const int jm = g.nrings - 1 - j;
     ai = aspec + g.spec_off[j];
@@ -85,24 +69,15 @@ template <typename R> struct PairX {
     Nj = (uint32_t)g.n[j];
     shi = g.phase_den[u.i] != 0;
     shj = g.phase_den[j] != 0;
-    fold = g.fold != 0;
+    invi = 1.0f / (float)Ni;
+    invj = 1.0f / (float)Nj;
   }
   __device__ __forceinline__ double operator()(uint32_t m) const {
-    C a0, r0, a1, r1;
-    if (fold) {
-      a0 = ext_mode(ai, Nj, shj, m);
-      r0 = ext_mode(ri, Ni, shi, m);
-      if (mirror) {
-        a1 = ext_mode(am, Nj, shj, m);
-        r1 = ext_mode(rm, Ni, shi, m);
-      }
-    } else {
-      a0 = ai[m];
-      r0 = ri[m];
-      if (mirror) {
-        a1 = am[m];
-        r1 = rm[m];
-      }
+    C a1, r1;
+    const C a0 = ext_mode(ai, Nj, invj, shj, m), r0 = ext_mode(ri, Ni, invi, shi, m);
+    if (mirror) {
+      a1 = ext_mode(am, Nj, invj, shj, m);
+      r1 = ext_mode(rm, Ni, invi, shi, m);
     }
     double X = (double)r0.x * a0.x + (double)r0.y * a0.y;
     if (mirror) X += (double)r1.x * a1.x + (double)r1.y * a1.y;
@@ -726,7 +701,6 @@ arkcos_status_t run_kernel_grad(arkcos_plan_s* P, const void* x, const void* r, 
   g.slots = slots;
   g.TN = P->twiddle_n;
   g.zcache_bytes = P->grad_zcache_bytes;
-  g.fold = P->grad_fold;
   const int32_t nruns = P->n_grad_runs;
   const size_t lds = (size_t)P->grad_zcache_bytes;
   if (P->dtype == ARKCOS_F32) {

@@ -1004,19 +1004,6 @@ arkcos_status_t build_plan(const arkcos_geometry_t* g, const arkcos_profile_t* p
   HIPCHK(upload(P, &P->rt.out_off, P->h_out_off));
   HIPCHK(upload(P, &P->rt.out_len, P->h_out_len));
   HIPCHK(upload(P, &P->d_units, P->h_units));
-  // the knot gradient may read a ring's extended spectrum through its
-  // stored modes 0 .. N/2 (every read mode m <= band lies below the
-  // spectrum's length, and so does its folded index): rings of even length,
-  // a mirror ring with the pixel count and offset of its ring
-  if (P->prof_kind == 1) {
-    bool fold = true;
-    for (int64_t k = 0; k < nr && fold; ++k) {
-      const int64_t km = nr - 1 - k;
-      fold = P->h_n[k] % 2 == 0 && P->h_n[km] == P->h_n[k] &&
-             (P->h_phase_den[km] != 0) == (P->h_phase_den[k] != 0);
-    }
-    P->grad_fold = fold ? 1 : 0;
-  }
 
   // bands of consecutive units, and work items: (band, first mode) tiles
   {

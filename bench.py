@@ -106,7 +106,8 @@ def summarize_traffic(fetch_csv: str, write_csv: str, calib_mib: int, out_path: 
     """Per-stage HBM bytes per forward step from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by the ratio of
     the known size of the copy-calibration dispatches to what the same counter
-    reads for them."""
+    reads for them.  Only dispatches from the first ring transform on count:
+    the plan's shape tuner launches the accumulation before it."""
     import collections
     calib_bytes = calib_mib * 2**20
     res = {}
@@ -114,13 +115,17 @@ def summarize_traffic(fetch_csv: str, write_csv: str, calib_mib: int, out_path: 
         per = collections.defaultdict(float)
         steps = 0
         cal = []
-        for r in _counter_rows(path):
-            if r["Counter_Name"] != counter:
-                continue
+        rows = sorted((r for r in _counter_rows(path) if r["Counter_Name"] == counter),
+                      key=lambda r: int(r["Dispatch_Id"]))
+        started = False
+        for r in rows:
             name = _short(r["Kernel_Name"])
             kib = float(r["Counter_Value"])
             if name == "__amd_rocclr_copyBuffer" and kib * 1024 > 0.5 * calib_bytes:
                 cal.append(kib * 1024)
+                continue
+            started = started or name == KERNEL_NAMES["ring_r2c"]
+            if not started:
                 continue
             per[name] += kib * 1024
             if name == "accumulate_kernel":
@@ -185,12 +190,24 @@ def summarize_counters(csv_path: str, cmd: str, title: str):
     instructions x 4 cycles / (1024 SIMDs x 2.4 GHz x dispatch duration under
     the profiler)."""
     import collections
-    rows = _counter_rows(csv_path)
+    rows = sorted(_counter_rows(csv_path), key=lambda r: int(r["Dispatch_Id"]))
     per = collections.defaultdict(lambda: collections.defaultdict(float))
     durs = collections.defaultdict(dict)
+    # accumulation dispatches of the shape tuners (plan and batch creation)
+    # are left out: a counted one follows a ring transform
+    name_of = {}
     for r in rows:
         n = _short(r["Kernel_Name"])
-        if not (n in KERNEL_NAMES.values() or "grad" in n or "batch" in n):
+        if n in KERNEL_NAMES.values() or "grad" in n or "batch" in n:
+            name_of.setdefault(int(r["Dispatch_Id"]), n)
+    skip, prev = set(), ""
+    for d in sorted(name_of):
+        if name_of[d].startswith("accumulate") and not prev.startswith("r2c"):
+            skip.add(d)
+        prev = name_of[d]
+    for r in rows:
+        n = _short(r["Kernel_Name"])
+        if not (n in KERNEL_NAMES.values() or "grad" in n or "batch" in n) or int(r["Dispatch_Id"]) in skip:
             continue
         key = (n, int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"])), int(r["Workgroup_Size"]))
         per[key][r["Counter_Name"]] += float(r["Counter_Value"])

@@ -685,9 +685,15 @@ template <typename T> __device__ __forceinline__ T uniform(T v) {
 // a few KB per ring, which stay in cache across the rows of a unit, instead
 // of the whole extension.
 // inv = 1/N in FP32: the quotient m / N (m < 2^24) from the float product is
-// off by at most one, then corrected.
-template <typename C>
-__device__ __forceinline__ C ext_mode(const C* __restrict__ base, uint32_t N, float inv, bool shifted, uint32_t m) {
+// off by at most one, then corrected.  ext_index gives the stored mode k and
+// the signs of the real and imaginary parts, A~(m) = (sre A(k).x, sim A(k).y);
+// a ring and its mirror share them.
+struct ExtIdx {
+  uint32_t k;
+  float sre, sim;
+};
+
+__device__ __forceinline__ ExtIdx ext_index(uint32_t N, float inv, bool shifted, uint32_t m) {
   int qi = (int)((float)m * inv);
   int ri = (int)m - qi * (int)N;
   if (ri < 0) {
@@ -699,10 +705,20 @@ __device__ __forceinline__ C ext_mode(const C* __restrict__ base, uint32_t N, fl
   }
   const uint32_t q = (uint32_t)qi, r = (uint32_t)ri;
   const bool up = 2 * r > N;
-  const C v = base[up ? N - r : r];
   const bool neg = shifted && ((q + (up ? 1u : 0u)) & 1u);
-  const decltype(v.x) sg = neg ? -1 : 1;
-  return cmake<C>(sg * v.x, (up ? -sg : sg) * v.y);
+  const float sg = neg ? -1.f : 1.f;
+  return ExtIdx{up ? N - r : r, sg, up ? -sg : sg};
+}
+
+template <typename C> __device__ __forceinline__ C ext_at(const C* __restrict__ base, const ExtIdx& e) {
+  using T = decltype(base->x);
+  const C v = base[e.k];
+  return cmake<C>(T(e.sre) * v.x, T(e.sim) * v.y);
+}
+
+template <typename C>
+__device__ __forceinline__ C ext_mode(const C* __restrict__ base, uint32_t N, float inv, bool shifted, uint32_t m) {
+  return ext_at(base, ext_index(N, inv, shifted, m));
 }
 
 }  // namespace arkcos

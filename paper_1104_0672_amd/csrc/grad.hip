@@ -72,17 +72,18 @@ template <typename R> struct PairX {
     invi = 1.0f / (float)Ni;
     invj = 1.0f / (float)Nj;
   }
-  __device__ __forceinline__ double operator()(uint32_t m) const {
-    C a1, r1;
-    const C a0 = ext_mode(ai, Nj, invj, shj, m), r0 = ext_mode(ri, Ni, invi, shi, m);
+  // in precision T (the row FFTs take it in the plan's precision)
+  template <typename T> __device__ __forceinline__ T eval(uint32_t m) const {
+    const ExtIdx ej = ext_index(Nj, invj, shj, m), ei = ext_index(Ni, invi, shi, m);
+    const C a0 = ext_at(ai, ej), r0 = ext_at(ri, ei);
+    T X = (T)r0.x * (T)a0.x + (T)r0.y * (T)a0.y;
     if (mirror) {
-      a1 = ext_mode(am, Nj, invj, shj, m);
-      r1 = ext_mode(rm, Ni, invi, shi, m);
+      const C a1 = ext_at(am, ej), r1 = ext_at(rm, ei);
+      X += (T)r1.x * (T)a1.x + (T)r1.y * (T)a1.y;
     }
-    double X = (double)r0.x * a0.x + (double)r0.y * a0.y;
-    if (mirror) X += (double)r1.x * a1.x + (double)r1.y * a1.y;
     return X;
   }
+  __device__ __forceinline__ double operator()(uint32_t m) const { return eval<double>(m); }
 };
 
 constexpr int kGradSpl = kGradPass / 64;  // wide rows: samples per lane in a pass
@@ -510,10 +511,10 @@ __global__ void __launch_bounds__(NT) grad_row_fft_kernel(GradArgs g, const RowF
   R* Yr = Y + yoff[blockIdx.x];
   auto xcorr = [&](int64_t m) -> R {  // eps_m h(m) (X_ij(m) + X_i'j'(m)), zero past the band
     if (m > band) return R(0);
-    const double X = px((uint32_t)m);
-    double wm = m == 0 ? 1.0 : 2.0;
-    if (m == pr.nyq) wm *= 0.5;
-    return (R)(X * wm);
+    const R X = px.template eval<R>((uint32_t)m);
+    R wm = m == 0 ? R(1) : R(2);
+    if (m == pr.nyq) wm *= R(0.5);
+    return X * wm;
   };
   const int64_t kstep = g.TN / (2 * (int64_t)Pn), gstep = g.TN / G;
   for (int s = 0; s < S; ++s) {

@@ -175,13 +175,17 @@ arkcos_status_t build_grad_items(arkcos_plan_s* P) {
   // each with its own slot
   group_fft_rows(fft_rows, P->n_gfft);
   {
+    // (ARKCOS_GRAD_CHUNK_BYTES sets a smaller chunk budget, so that tests
+    // reach the chunked path on small plans)
+    int64_t budget = kGradYBytes;
+    if (const char* e = getenv("ARKCOS_GRAD_CHUNK_BYTES"); e && *e) budget = std::max<int64_t>(atoll(e), 1);
     std::vector<int64_t> yoff(fft_rows.size());
     P->h_gfft_chunk.assign(1, 0);
     P->grad_y_elems = 0;
     int64_t used = 0;
     for (size_t k = 0; k < fft_rows.size(); ++k) {
       const int64_t nc = P->h_ncoef_window[fft_rows[k].pair];
-      if (used > 0 && (used + nc) * rsz > kGradYBytes) {
+      if (used > 0 && (used + nc) * rsz > budget) {
         P->h_gfft_chunk.push_back((int32_t)k);
         used = 0;
       }

@@ -195,6 +195,36 @@ def test_knot_gradient_wide_rows_64_knots(dtype, tol):
     assert err <= tol
 
 
+def test_knot_gradient_fft_rows_in_chunks():
+    """The FFT rows' Y(d) go through the workspace a chunk of rows at a time
+    (at most 256 MiB each); a tiny budget makes every chunk a few rows, so the
+    chunked path (slots written by the first chunk, added to by the others)
+    is compared with the one-chunk plan and with the FP64 reference."""
+    import os
+    from paper_1104_0672_amd import Plan
+    w = _spline_workload(32, 64, "f64", 31)
+    _say(f"case knot gradient in chunks {w.name} f64 p=16")
+    ref_plan = Plan.from_workload(w, oversample=16)
+    os.environ["ARKCOS_GRAD_CHUNK_BYTES"] = "16384"
+    try:
+        chunked = Plan.from_workload(w, oversample=16)
+    finally:
+        del os.environ["ARKCOS_GRAD_CHUNK_BYTES"]
+    assert chunked.info.grad_fft_rows > 0
+    assert chunked.workspace_bytes < ref_plan.workspace_bytes
+    rng = np.random.default_rng(32)
+    x, t = rng.standard_normal(w.grid.npix), rng.standard_normal(w.grid.npix)
+    xd = _tt(x, "f64")
+    r = ref_plan.convolve(xd).cpu().numpy() - t
+    g1 = ref_plan.kernel_grad(xd, _tt(r, "f64")).cpu().numpy()
+    g2 = chunked.kernel_grad(xd, _tt(r, "f64")).cpu().numpy()
+    d = np.abs(g2 - g1).max() / np.abs(g1).max()
+    ref = oracle.hybrid_knot_grad(w.grid, w.profile, w.radius, x, r, oversample=16)
+    e = np.abs(g2 - ref).max() / np.abs(ref).max()
+    _say(f"  chunked vs one chunk {d:.2e}, vs FP64 reference {e:.2e}")
+    assert d <= 1e-12 and e <= 1e-10
+
+
 @pytest.mark.parametrize("nside,p", [(16, None), (32, 16)])
 def test_set_knots_async_equals_host_update(nside, p):
     """Knot updates on the device and from the host give the same map, equal

@@ -113,3 +113,29 @@ def test_device_code_is_built_for_gfx950_only(lib):
             with_device += 1
             assert targets == {b"gfx950"}, (f, targets)
     assert with_device >= 6  # the .hip sources
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (a C program built against include/arkcos.h prints them)."""
+    from paper_1104_0672_amd import arkcos as ak
+    pairs = [(ak.Geometry, "arkcos_geometry_t"), (ak.ProfileC, "arkcos_profile_t"),
+             (ak.Options, "arkcos_options_t"), (ak.PlanInfo, "arkcos_plan_info_t"),
+             (ak.BatchInfo, "arkcos_batch_info_t")]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "arkcos.h"', "int main(void) {"]
+    expect = []
+    for cls, cname in pairs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(cls))
+        for name, _ in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {name}));')
+            expect.append(getattr(cls, name).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    exe = tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    # (the header takes hipStream_t from the HIP runtime header)
+    cpp = subprocess.run(["/opt/rocm/bin/hipconfig", "--cpp_config"], capture_output=True, text=True).stdout.split()
+    subprocess.run(["gcc", "-std=c11", *cpp, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == expect

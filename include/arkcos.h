@@ -160,6 +160,10 @@ typedef struct {
                                kernel samples (wide rows on power-of-two grids) */
   int32_t grad_fft_rows;    /* spline plans: kernel rows whose knot-gradient
                                correlation is transformed by FFTs */
+  int32_t acc_units_per_wave; /* accumulation: output units per wavefront (1; 2 or 3
+                               for FP32 plans whose pairs all have tables, with
+                               acc_seg_units = 8 x this) */
+  int32_t reserved2;        /* 0 */
 } arkcos_plan_info_t;
 
 /* Fill *opts with the defaults (oversample 0, kgen 0, fix_pole_pixels 1,

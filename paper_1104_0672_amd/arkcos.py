@@ -52,7 +52,8 @@ class PlanInfo(ctypes.Structure):
                 ("plan_bytes", ctypes.c_size_t), ("pairs_by_kind", ctypes.c_int64 * 4),
                 ("acc_seg_units", ctypes.c_int32), ("acc_group", ctypes.c_int32), ("acc_window", ctypes.c_int32),
                 ("acc_tuned", ctypes.c_int32), ("support_radius_rad", ctypes.c_double),
-                ("table_fft_rows", ctypes.c_int32), ("grad_fft_rows", ctypes.c_int32)]
+                ("table_fft_rows", ctypes.c_int32), ("grad_fft_rows", ctypes.c_int32),
+                ("acc_units_per_wave", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):

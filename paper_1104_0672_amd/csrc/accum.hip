@@ -457,6 +457,181 @@ __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandD
   }
 }
 
+// Table-only plans, U units per wavefront: the band holds U NW units and
+// wave w takes the units w + NW x (x < U), so the window of input rings a
+// band stages (its units' supports, some 36 rings wider than the band at
+// nside 2048 / 5') serves U times as many units per block.  Per stage a wave
+// streams the table tiles of its first unit's pairs in the staged chunk, then
+// those of its next, each exactly as the one-unit form does (the same order
+// of the sum over a unit's pairs).  Every wave must call this; it
+// synchronises the block.
+template <typename R, int NW, int U>
+__device__ __forceinline__ void accumulate_band_tabu(const AccArgs<R>& a, const BandDev& bd, const int t0,
+                                                     const int nt, const cx_t<R>* __restrict__ spec,
+                                                     cx_t<R>* __restrict__ bout, unsigned char* smem,
+                                                     const AccLayout lay) {
+  using C = cx_t<R>;
+  constexpr int CH = AccLds<R>::kRings;
+  constexpr int RPW = (2 * CH + NW - 1) / NW;
+  constexpr int MPL = kModesPerLane;
+  C* sa = reinterpret_cast<C*>(smem);
+  RowRef* rows = reinterpret_cast<RowRef*>(smem + lay.rows_off);
+  PairLds* dsc = reinterpret_cast<PairLds*>(smem + lay.pairs_off);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int win = max(bd.jhi - bd.jlo + 1, 0);
+  const int cbase = win > 0 ? bd.jlo / CH * CH : 0;
+  const int nch = win > 0 ? (bd.jhi + 1 - cbase + CH - 1) / CH : 1;
+  for (int r = threadIdx.x; r < 2 * win; r += NW * 64) {
+    int j = bd.jlo + (r >> 1);
+    if (r & 1) j = a.nrings - 1 - j;
+    rows[r].off = gload(a.spec_off + j);
+    rows[r].len = gload(a.spec_len + j);
+  }
+  UnitDev u[U];
+  bool act[U], mirror[U];
+  int npair[U];
+  PairLds* mine[U];
+#pragma unroll
+  for (int x = 0; x < U; ++x) {
+    const int ux = w + NW * x;
+    act[x] = ux < bd.nu;
+    u[x] = UnitDev{};
+    if (act[x]) {
+      u[x].i = gload(&a.units[bd.u0 + ux].i);
+      u[x].im = gload(&a.units[bd.u0 + ux].im);
+      u[x].pbeg = gload(&a.units[bd.u0 + ux].pbeg);
+      u[x].pend = gload(&a.units[bd.u0 + ux].pend);
+      u[x].band = gload(&a.units[bd.u0 + ux].band);
+    }
+    mirror[x] = u[x].im >= 0;
+    npair[x] = act[x] ? u[x].pend - u[x].pbeg : 0;
+    mine[x] = dsc + (act[x] ? u[x].pbeg - bd.pbeg : 0);
+    // every pair has a table: the descriptors in input-ring order
+    for (int b = 0; b < npair[x]; b += 64) {
+      const int q = b + lane;
+      if (q < npair[x]) {
+        const PairDev* g = a.pairs + u[x].pbeg + q;
+        PairLds d;
+        d.meta = (uint32_t)(gload(&g->j) - bd.jlo) | ((uint32_t)KG_TABLE << 24);
+        d.band = gload(&g->band);
+        d.ncoef = 0;
+        d.off = (uint32_t)gload(&g->off);
+        mine[x][q] = d;
+      }
+    }
+  }
+  __syncthreads();  // row table and descriptors ready
+
+  const int nst = nt * nch;
+  C pre[RPW][MPL];
+  auto issue = [&](int s) {
+    const int t = s / nch, c = s - t * nch;
+    const int m = (t0 + t) * kAccTile + lane;
+    const int cs = cbase + c * CH;
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int r = w + NW * k;
+      const int j = cs + (r >> 1);
+#pragma unroll
+      for (int e = 0; e < MPL; ++e) pre[k][e] = cmake<C>(R(0), R(0));
+      if (r < 2 * CH && j >= bd.jlo && j <= bd.jhi) {
+        const RowRef rr = rows[2 * (j - bd.jlo) + (r & 1)];
+#pragma unroll
+        for (int e = 0; e < MPL; ++e)
+          if (m + 64 * e < rr.len) pre[k][e] = gload(spec + rr.off + m + 64 * e);
+      }
+    }
+  };
+  issue(0);
+  C acc0[U][MPL], acc1[U][MPL];
+  int qt[U];
+#pragma unroll
+  for (int x = 0; x < U; ++x) qt[x] = 0;
+  for (int s = 0; s < nst; ++s) {
+    const int t = s / nch, c = s - t * nch;
+    const int m0 = (t0 + t) * kAccTile;
+    const int c0 = cbase + c * CH - bd.jlo, c1 = c0 + CH;
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int r = w + NW * k;
+      if (r < 2 * CH) {
+#pragma unroll
+        for (int e = 0; e < MPL; ++e) sa[r * kAccTile + 64 * e + lane] = pre[k][e];
+      }
+    }
+    __syncthreads();
+    if (s + 1 < nst) issue(s + 1);
+#pragma unroll
+    for (int x = 0; x < U; ++x) {
+      const bool busy = act[x] && m0 <= u[x].band;
+      if (c == 0) {
+#pragma unroll
+        for (int e = 0; e < MPL; ++e) {
+          acc0[x][e] = cmake<C>(R(0), R(0));
+          acc1[x][e] = acc0[x][e];
+        }
+        qt[x] = 0;
+      }
+      if (busy) {
+        // up to CH pairs of this unit in the staged chunk: descriptors read
+        // together (the area has CH spare entries), then every live tile
+        // loaded, then accumulated
+        PairU d[CH];
+#pragma unroll
+        for (int y = 0; y < CH; ++y) d[y] = uniform_pair(mine[x][qt[x] + y]);
+        int g = 0;
+        uint32_t live = 0;
+#pragma unroll
+        for (int y = 0; y < CH; ++y)
+          if (g == y && qt[x] + y < npair[x] && pl_row(d[y].meta) < c1) {
+            g = y + 1;
+            if (d[y].band >= m0) live |= 1u << y;
+          }
+        R kv[CH][MPL];
+#pragma unroll
+        for (int y = 0; y < CH; ++y)
+          if ((live >> y) & 1u) {
+            const R* tb = a.table + d[y].off + m0;
+#pragma unroll
+            for (int e = 0; e < MPL; ++e) kv[y][e] = gload(tb + 64 * e + lane);
+          }
+#pragma unroll
+        for (int y = 0; y < CH; ++y)
+          if ((live >> y) & 1u) {
+            const C* s0 = sa + 2 * (pl_row(d[y].meta) - c0) * kAccTile + lane;
+#pragma unroll
+            for (int e = 0; e < MPL; ++e) {
+              const C v = s0[64 * e];
+              acc0[x][e] = cmake<C>(fma(kv[y][e], v.x, acc0[x][e].x), fma(kv[y][e], v.y, acc0[x][e].y));
+            }
+            if (mirror[x]) {
+#pragma unroll
+              for (int e = 0; e < MPL; ++e) {
+                const C v = s0[kAccTile + 64 * e];
+                acc1[x][e] = cmake<C>(fma(kv[y][e], v.x, acc1[x][e].x), fma(kv[y][e], v.y, acc1[x][e].y));
+              }
+            }
+          }
+        qt[x] += g;
+      }
+      if (busy && c == nch - 1) {
+        const int64_t o0 = gload(a.out_off + u[x].i);
+        const int64_t o1 = mirror[x] ? gload(a.out_off + u[x].im) : 0;
+#pragma unroll
+        for (int e = 0; e < MPL; ++e) {
+          const int m = m0 + 64 * e + lane;
+          if (m <= u[x].band) {
+            gstore(bout + o0 + m, acc0[x][e]);
+            if (mirror[x]) gstore(bout + o1 + m, acc1[x][e]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // A band descriptor read with wave-uniform (scalar) values.
 __device__ __forceinline__ BandDev load_band(const BandDev* g) {
   BandDev b;
@@ -481,6 +656,15 @@ __global__ void __launch_bounds__(64 * NW)
   extern __shared__ __align__(16) unsigned char smem[];
   const WorkItem it = a.items[blockIdx.x];
   accumulate_band<R, NW, TAB_ONLY>(a, a.bands[it.band], it.t0, it.nt, spec, bout, smem, lay);
+}
+
+// Table-only plans with U units per wavefront (bands of U NW units).
+template <typename R, int NW, int U>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4)))
+    accumulate_u_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec, cx_t<R>* __restrict__ bout, AccLayout lay) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const WorkItem it = a.items[blockIdx.x];
+  accumulate_band_tabu<R, NW, U>(a, a.bands[it.band], it.t0, it.nt, spec, bout, smem, lay);
 }
 
 // Batched form: one persistent launch drains a queue of (map, band, tiles)
@@ -614,6 +798,8 @@ hipError_t configure_accumulate_shape(const arkcos_plan_s* P, const AccShape& sh
     if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<float, 8, true>, lds);
     if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<float, 16, false>, lds);
     if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<float, 16, true>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_u_kernel<float, 8, 2>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_u_kernel<float, 8, 3>, lds);
   } else {
     e = allow_acc_lds(accumulate_kernel<double, 8, false>, lds);
     if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<double, 8, true>, lds);
@@ -636,14 +822,21 @@ static void launch_nw(const arkcos_plan_s* P, const AccArgs<R>& a, unsigned grid
 // shape (the plan's own, or a candidate timed at plan creation).
 hipError_t launch_accumulate_shape(const arkcos_plan_s* P, const BandDev* bands, const WorkItem* items,
                                    int32_t n_items, int32_t units, const AccShape& shape, const void* spec,
-                                   void* bout, hipStream_t s) {
+                                   void* bout, hipStream_t s, int32_t units_per_wave) {
   if (n_items == 0) return hipSuccess;
   const size_t lds = acc_lds_bytes(P->dtype, shape);
   const AccLayout lay = acc_layout(P->dtype, shape);
   if (P->dtype == ARKCOS_F32) {
     AccArgs<float> a = make_acc_args<float>(P, bands);
     a.items = items;
-    if (units == 16) launch_nw<float, 16>(P, a, (unsigned)n_items, lds, lay, spec, bout, s);
+    if (units_per_wave > 1 && P->all_tables && units == 8 * units_per_wave) {
+      if (units_per_wave == 2)
+        accumulate_u_kernel<float, 8, 2><<<(unsigned)n_items, 512, lds, s>>>(a, (const float2*)spec, (float2*)bout, lay);
+      else
+        accumulate_u_kernel<float, 8, 3><<<(unsigned)n_items, 512, lds, s>>>(a, (const float2*)spec, (float2*)bout, lay);
+    } else if (units == 16) {
+      launch_nw<float, 16>(P, a, (unsigned)n_items, lds, lay, spec, bout, s);
+    }
     else launch_nw<float, 8>(P, a, (unsigned)n_items, lds, lay, spec, bout, s);
   } else {
     AccArgs<double> a = make_acc_args<double>(P, bands);
@@ -656,7 +849,7 @@ hipError_t launch_accumulate_shape(const arkcos_plan_s* P, const BandDev* bands,
 
 hipError_t launch_accumulate(arkcos_plan_s* P, const void* spec, void* bout, hipStream_t s) {
   return launch_accumulate_shape(P, P->d_bands, P->d_items, (int32_t)P->h_items.size(), P->acc_units, P->acc_shape,
-                                 spec, bout, s);
+                                 spec, bout, s, P->acc_upw);
 }
 
 }  // namespace arkcos

@@ -195,6 +195,7 @@ struct arkcos_plan_s {
   int32_t acc_units = arkcos::kBandUnits;      // units per band (wavefronts per block): 8 or 16
   int32_t acc_tiles = arkcos::kTilesPerItem;   // mode tiles per work item
   int32_t acc_tuned = 0;                       // 1: band shape chosen by timing at plan creation
+  int32_t acc_upw = 1;                         // units per wavefront (2: 16-unit bands in 8-wave blocks)
   std::vector<arkcos::BandDev> h_bands;
   bool all_tables = false;     // every pair reads K_ij(m) from a table
   void* d_coef = nullptr;       // recurrence coefficients, plan dtype
@@ -275,7 +276,7 @@ hipError_t configure_accumulate(arkcos_plan_s* P);
 hipError_t configure_accumulate_shape(const arkcos_plan_s* P, const AccShape& shape);
 hipError_t launch_accumulate_shape(const arkcos_plan_s* P, const BandDev* bands, const WorkItem* items,
                                    int32_t n_items, int32_t units, const AccShape& shape, const void* spec,
-                                   void* bout, hipStream_t s);
+                                   void* bout, hipStream_t s, int32_t units_per_wave = 1);
 size_t ring_args_size();
 void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out,
                     const int64_t* off = nullptr, const int32_t* len = nullptr);

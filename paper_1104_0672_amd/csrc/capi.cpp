@@ -179,6 +179,7 @@ arkcos_status_t arkcos_plan_get_info(arkcos_plan_t P, arkcos_plan_info_t* info) 
   info->support_radius_rad = P->radius;
   info->table_fft_rows = P->n_tfft[0] + P->n_tfft[1] + P->n_tfft[2];
   info->grad_fft_rows = P->n_gfft[0] + P->n_gfft[1] + P->n_gfft[2];
+  info->acc_units_per_wave = P->acc_upw;
   return ARKCOS_OK;
 }
 

@@ -423,24 +423,33 @@ static void make_bands_items(const arkcos_plan_s* P, int32_t units, int32_t tile
 // units and 4 tiles.  ARKCOS_ACC_SHAPE="U,T" forces a choice.  The result
 // does not depend on the shape: every unit sums its pairs in the same order.
 arkcos_status_t choose_accumulation_shape(arkcos_plan_s* P) {
-  std::vector<std::pair<int32_t, int32_t>> cand;
+  struct Cand {
+    int32_t units, tiles, upw;  // units per band, mode tiles per item, units per wavefront
+  };
+  std::vector<Cand> cand;
   if (const char* e = getenv("ARKCOS_ACC_SHAPE"); e && *e) {
-    int u = 0, t = 0;
-    if (sscanf(e, "%d,%d", &u, &t) == 2 && (u == 8 || u == 16) && t >= 1 && t <= 16) cand.push_back({u, t});
+    int u = 0, t = 0, w = 1;
+    const int got = sscanf(e, "%d,%d,%d", &u, &t, &w);
+    const bool per_wave = got == 3 && w >= 2 && w <= 3 && u == 8 * w && P->all_tables && P->dtype == ARKCOS_F32;
+    if (got >= 2 && (u == 8 || u == 16 || per_wave) && t >= 1 && t <= 16) cand.push_back({u, t, per_wave ? w : 1});
   }
   if (cand.empty()) {
-    // (16-unit bands only in FP32: the FP64 recurrence form would spill)
-    if (P->npix >= (int64_t(1) << 20) && P->dtype == ARKCOS_F32)
-      cand = {{8, 4}, {16, 4}, {8, 2}, {16, 2}, {8, 8}, {16, 8}};
-    else if (P->npix >= (int64_t(1) << 20))
-      cand = {{8, 4}, {8, 2}, {8, 8}};
-    else
-      cand = {{kBandUnits, kTilesPerItem}};
+    // (16-unit bands only in FP32: the FP64 recurrence form would spill;
+    // two units per wavefront only for table-only FP32 plans)
+    if (P->npix >= (int64_t(1) << 20) && P->dtype == ARKCOS_F32) {
+      cand = {{8, 4, 1}, {16, 4, 1}, {8, 2, 1}, {16, 2, 1}, {8, 8, 1}, {16, 8, 1}};
+      if (P->all_tables) cand.insert(cand.end(), {{16, 4, 2}, {16, 2, 2}, {24, 2, 3}});
+    } else if (P->npix >= (int64_t(1) << 20)) {
+      cand = {{8, 4, 1}, {8, 2, 1}, {8, 8, 1}};
+    } else {
+      cand = {{kBandUnits, kTilesPerItem, 1}};
+    }
   }
   P->acc_tuned = 0;
   if (cand.size() == 1) {
-    P->acc_units = cand[0].first;
-    P->acc_tiles = cand[0].second;
+    P->acc_units = cand[0].units;
+    P->acc_tiles = cand[0].tiles;
+    P->acc_upw = cand[0].upw;
     make_bands_items(P, P->acc_units, P->acc_tiles, P->h_bands, &P->acc_shape, P->h_items);
     return ARKCOS_OK;
   }
@@ -467,7 +476,7 @@ arkcos_status_t choose_accumulation_shape(arkcos_plan_s* P) {
     std::vector<BandDev> bands;
     std::vector<WorkItem> items;
     AccShape sh;
-    make_bands_items(P, cand[k].first, cand[k].second, bands, &sh, items);
+    make_bands_items(P, cand[k].units, cand[k].tiles, bands, &sh, items);
     if (d_b) HIPCHK(hipFree(d_b));
     if (d_i) HIPCHK(hipFree(d_i));
     d_b = d_i = nullptr;
@@ -477,21 +486,27 @@ arkcos_status_t choose_accumulation_shape(arkcos_plan_s* P) {
     if (!items.empty()) HIPCHK(hipMemcpy(d_i, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
     HIPCHK(configure_accumulate_shape(P, sh));
     const int32_t ni = (int32_t)items.size();
-    HIPCHK(launch_accumulate_shape(P, (BandDev*)d_b, (WorkItem*)d_i, ni, cand[k].first, sh, spec, bout, nullptr));
+    HIPCHK(launch_accumulate_shape(P, (BandDev*)d_b, (WorkItem*)d_i, ni, cand[k].units, sh, spec, bout, nullptr,
+                                   cand[k].upw));
     HIPCHK(hipEventRecord(e0, nullptr));
     for (int r = 0; r < 3; ++r)
-      HIPCHK(launch_accumulate_shape(P, (BandDev*)d_b, (WorkItem*)d_i, ni, cand[k].first, sh, spec, bout, nullptr));
+      HIPCHK(launch_accumulate_shape(P, (BandDev*)d_b, (WorkItem*)d_i, ni, cand[k].units, sh, spec, bout, nullptr,
+                                     cand[k].upw));
     HIPCHK(hipEventRecord(e1, nullptr));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (const char* e = getenv("ARKCOS_ACC_TIMES"); e && *e == '1')
+      fprintf(stderr, "arkcos plan: accumulation candidate %d units, %d tiles, %d per wave: %.4f ms\n",
+              cand[k].units, cand[k].tiles, cand[k].upw, ms / 3.0f);
     if (ms < best) {
       best = ms;
       best_k = k;
     }
   }
-  P->acc_units = cand[best_k].first;
-  P->acc_tiles = cand[best_k].second;
+  P->acc_units = cand[best_k].units;
+  P->acc_tiles = cand[best_k].tiles;
+  P->acc_upw = cand[best_k].upw;
   P->acc_tuned = 1;
   make_bands_items(P, P->acc_units, P->acc_tiles, P->h_bands, &P->acc_shape, P->h_items);
   return ARKCOS_OK;

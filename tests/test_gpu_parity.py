@@ -161,6 +161,35 @@ def test_healpix256_30arcmin_full_map():
     assert err <= 1e-4
 
 
+def test_accumulation_shapes_are_bitwise_equal():
+    """Every accumulation shape (units per band, mode tiles per item, units
+    per wavefront) sums each unit's pairs in the same order, so the forward
+    and transposed maps are the same to the bit; the first shape's forward is
+    also checked against the direct sum."""
+    import os
+    w = W.healpix256()
+    _say(f"case accumulation shapes {w.name}")
+    x = W.make_input(w)
+    outs = []
+    for shape in ("8,4", "8,2", "16,4", "16,4,2", "16,2,2", "24,2,3"):
+        os.environ["ARKCOS_ACC_SHAPE"] = shape
+        try:
+            plan = _plan(w)
+        finally:
+            del os.environ["ARKCOS_ACC_SHAPE"]
+        info = plan.info
+        want_upw = int(shape.split(",")[2]) if shape.count(",") == 2 else 1
+        _say(f"  shape {shape}: {info.acc_seg_units} units, {info.acc_group} tiles, "
+             f"{info.acc_units_per_wave} per wave")
+        assert info.acc_units_per_wave == want_upw and info.acc_seg_units == int(shape.split(",")[0])
+        xt = _tt(x, w)
+        outs.append((plan.convolve(xt).cpu(), plan.adjoint(xt).cpu()))
+    for k in range(1, len(outs)):
+        assert torch.equal(outs[k][0], outs[0][0]) and torch.equal(outs[k][1], outs[0][1])
+    ref = oracle.direct(w.grid, w.profile, w.radius, x)
+    assert _frac(outs[0][0].numpy().astype(np.float64), ref) <= 1e-4
+
+
 def test_fp64_adjoint_dot_product_and_transpose():
     for w in (W.ecp_64x128(), W.scaled_healpix(16, 200.0, 3.0, dtype="f64")):
         _say(f"case adjoint {w.name}")

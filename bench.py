@@ -291,7 +291,8 @@ def bench_batch(n_maps: int, steps: int, dev):
     plan_s = time.perf_counter() - t0
     info = batch.info
     npix = int(info.npix_total)
-    log(f"bench: batch plans {plan_s:.1f} s, {info.n_items} items, {info.seg_units} units per band, "
+    log(f"bench: batch plans {plan_s:.1f} s, {info.n_items} items, {info.seg_units} units per band "
+        f"({info.units_per_wave} per wave), "
         f"grid {info.grid}, {npix / 1e9:.2f} Gpix, workspace {info.workspace_bytes / 2**30:.1f} GiB")
     xs = []
     for w in wl:
@@ -301,7 +302,8 @@ def bench_batch(n_maps: int, steps: int, dev):
     ys = [torch.empty_like(x) for x in xs]
     ws = batch.workspace()
     out = {"n_maps": n_maps, "npix_total": npix, "plan_seconds": round(plan_s, 2),
-           "seg_units": int(info.seg_units), "group": int(info.group), "grid": int(info.grid), "items": int(info.n_items)}
+           "seg_units": int(info.seg_units), "group": int(info.group), "units_per_wave": int(info.units_per_wave),
+           "grid": int(info.grid), "items": int(info.n_items)}
     total_alg = 3 * 2 * 4 * npix
     for name, adj in (("forward", False), ("adjoint", True)):
         batch.convolve(xs, outs=ys, adjoint=adj, ws=ws)

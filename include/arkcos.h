@@ -257,10 +257,11 @@ arkcos_status_t arkcos_set_knots_async(arkcos_plan_t plan, const double* knot_va
 typedef struct {
   int32_t n_maps;
   int32_t seg_units;        /* output units (rings with mirrors) per work item, autotuned */
-  int32_t group;            /* units summed at a time (wavefronts per workgroup), autotuned */
+  int32_t group;            /* wavefronts per workgroup of the accumulation, autotuned */
   int32_t grid;             /* workgroups of the persistent accumulation launch, autotuned */
   int32_t tuned;            /* 1: measured now, 2: read from the autotune cache */
-  int32_t reserved;
+  int32_t units_per_wave;   /* output units per wavefront (1, or 2 for table-only FP32
+                               batches: group = seg_units / 2) */
   int64_t n_items;          /* work items in the queue */
   int64_t npix_total;
   size_t workspace_bytes;

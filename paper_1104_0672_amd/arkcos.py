@@ -58,7 +58,7 @@ class PlanInfo(ctypes.Structure):
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("n_maps", ctypes.c_int32), ("seg_units", ctypes.c_int32), ("group", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("tuned", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("tuned", ctypes.c_int32), ("units_per_wave", ctypes.c_int32),
                 ("n_items", ctypes.c_int64), ("npix_total", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t)]
 
 

@@ -690,6 +690,27 @@ __global__ void __launch_bounds__(64 * NW) accumulate_batch_kernel(
   }
 }
 
+// The batched form with U units per wavefront (table-only batches).
+template <typename R, int NW, int U>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) accumulate_batch_u_kernel(
+    const AccArgs<R>* __restrict__ maps, const int64_t* __restrict__ spec_base,
+    const int64_t* __restrict__ out_base, const BatchItem* __restrict__ items, int32_t n_items,
+    int32_t* __restrict__ counter, const cx_t<R>* __restrict__ spec, cx_t<R>* __restrict__ bout, AccLayout lay) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int cur;
+  for (;;) {
+    __syncthreads();  // the previous item is done with `cur` and the LDS tiles
+    if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(cur);
+    if (it >= n_items) break;
+    const BatchItem bi = items[it];
+    const AccArgs<R> a = maps[bi.map];
+    accumulate_band_tabu<R, NW, U>(a, load_band(a.bands + bi.band), bi.t0, bi.nt, spec + spec_base[bi.map],
+                                   bout + out_base[bi.map], smem, lay);
+  }
+}
+
 __global__ void reset_counter_kernel(int32_t* counter) {
   if (threadIdx.x == 0) counter[0] = 0;
 }
@@ -768,10 +789,20 @@ static hipError_t batch_launch_nw(int32_t units_per_band, const void* maps, cons
 hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const int64_t* spec_base,
                                    const int64_t* out_base, const BatchItem* items, int32_t n_items,
                                    int32_t* counter, const void* spec, void* bout, int32_t grid,
-                                   int32_t units_per_band, bool all_tables, const AccShape& shape, hipStream_t s) {
+                                   int32_t units_per_band, bool all_tables, const AccShape& shape, hipStream_t s,
+                                   int32_t units_per_wave) {
   reset_counter_kernel<<<1, 64, 0, s>>>(counter);
   const size_t lds = acc_lds_bytes(dt, shape);
   const AccLayout lay = acc_layout(dt, shape);
+  if (dt == ARKCOS_F32 && all_tables && units_per_wave == 2 && units_per_band == 16) {
+    hipError_t e = hipFuncSetAttribute((const void*)accumulate_batch_u_kernel<float, 8, 2>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    accumulate_batch_u_kernel<float, 8, 2><<<grid, 512, lds, s>>>((const AccArgs<float>*)maps, spec_base, out_base,
+                                                                  items, n_items, counter, (const float2*)spec,
+                                                                  (float2*)bout, lay);
+    return hipGetLastError();
+  }
   if (dt == ARKCOS_F32)
     return all_tables ? batch_launch_nw<float, true>(units_per_band, maps, spec_base, out_base, items, n_items,
                                                      counter, spec, bout, grid, lds, lay, s)

@@ -50,6 +50,7 @@ struct arkcos_batch_s {
   int32_t n = 0;
   std::vector<arkcos_plan_s*> plans;
   int32_t units_per_band = kBandUnits, grid = 0, tuned = 0;
+  int32_t units_per_wave = 1;  // 2: table-only FP32 batches, bands of 16 units in 8-wave blocks
   bool all_tables = false;  // every plan reads all its K_ij(m) from tables
   AccShape acc_shape;
   int64_t spec_total = 0, out_total = 0, npix_total = 0;
@@ -161,33 +162,38 @@ std::string tune_key(const arkcos_batch_s* B) {
   return k.str();
 }
 
-bool read_cache(const std::string& key, int32_t* upb, int32_t* bpc) {
+// Cache lines: key, units per band, blocks per CU, units per wavefront.
+bool read_cache(const std::string& key, int32_t* upb, int32_t* bpc, int32_t* upw) {
   const char* path = getenv("ARKCOS_AUTOTUNE_CACHE");
   if (!path || !*path) return false;
   std::ifstream f(path);
-  std::string k;
-  int32_t a, b;
-  while (f >> k >> a >> b)
-    if (k == key) {
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream in(line);
+    std::string k;
+    int32_t a = 0, b = 0, c = 0;
+    if ((in >> k >> a >> b >> c) && k == key) {
       *upb = a;
       *bpc = b;
+      *upw = c;
       return true;
     }
+  }
   return false;
 }
 
-void write_cache(const std::string& key, int32_t upb, int32_t bpc) {
+void write_cache(const std::string& key, int32_t upb, int32_t bpc, int32_t upw) {
   const char* path = getenv("ARKCOS_AUTOTUNE_CACHE");
   if (!path || !*path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << " " << upb << " " << bpc << "\n";
+  f << key << " " << upb << " " << bpc << " " << upw << "\n";
 }
 
 // Times the accumulation of one queue on the subset's workspace (zero
 // spectra); returns milliseconds per launch.
 hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64_t>& sb,
                       const std::vector<int64_t>& ob, void* spec, void* bout, int32_t* counter, int32_t upb,
-                      int32_t grid, float* ms) {
+                      int32_t grid, float* ms, int32_t upw) {
   void *dargs = nullptr, *ditems = nullptr, *dsb = nullptr, *dob = nullptr;
   hipError_t e = hipMalloc(&dargs, Q.acc_args.size());
   if (e == hipSuccess) e = hipMalloc(&ditems, std::max<size_t>(Q.items.size(), 1) * sizeof(BatchItem));
@@ -206,7 +212,7 @@ hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64
     if (e == hipSuccess)
       e = launch_accumulate_batch(B->dtype, dargs, (const int64_t*)dsb, (const int64_t*)dob, (const BatchItem*)ditems,
                                   (int32_t)Q.items.size(), counter, spec, bout, grid, upb, B->all_tables, Q.shape,
-                                  nullptr);
+                                  nullptr, upw);
   }
   if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -222,7 +228,7 @@ hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64
   return e;
 }
 
-arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out) {
+arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out, int32_t* upw_out) {
   // subset: up to four maps per ring count
   std::map<int64_t, int> seen;
   std::vector<int32_t> sub;
@@ -249,18 +255,23 @@ arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out) 
   int cus = 0;
   BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
   float best = 1e30f;
-  int32_t bu = kBandUnits, bb = 2;
-  for (int32_t upb : {4, 8, 16}) {
+  int32_t bu = kBandUnits, bb = 2, bw = 1;
+  // (units per band, units per wavefront): two units per wavefront only for
+  // table-only FP32 batches
+  std::vector<std::pair<int32_t, int32_t>> shapes = {{4, 1}, {8, 1}, {16, 1}};
+  if (B->all_tables && B->dtype == ARKCOS_F32) shapes.push_back({16, 2});
+  for (const auto& [upb, upw] : shapes) {
     Queue Q;
     std::vector<void*> owned;
     hipError_t e = build_queue(B, sub, upb, Q, owned);
     for (int32_t bpc : {1, 2, 4}) {
       float ms = 0.f;
-      if (e == hipSuccess) e = time_queue(B, Q, sb, ob, spec, bout, (int32_t*)ctr, upb, cus * bpc, &ms);
+      if (e == hipSuccess) e = time_queue(B, Q, sb, ob, spec, bout, (int32_t*)ctr, upb, cus * bpc, &ms, upw);
       if (e == hipSuccess && ms < best) {
         best = ms;
         bu = upb;
         bb = bpc;
+        bw = upw;
       }
     }
     for (void* p : owned) hipFree(p);
@@ -268,6 +279,7 @@ arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out) 
   }
   *upb_out = bu;
   *bpc_out = bb;
+  *upw_out = bw;
   return ARKCOS_OK;
 }
 
@@ -421,16 +433,18 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, bool shared, 
   }
 
   // band size and grid: cached, else measured
-  int32_t upb = kBandUnits, bpc = 2;
+  int32_t upb = kBandUnits, bpc = 2, upw = 1;
   const std::string key = tune_key(B);
-  if (read_cache(key, &upb, &bpc)) {
+  if (read_cache(key, &upb, &bpc, &upw) &&
+      (upw == 1 || (upw == 2 && upb == 16 && B->all_tables && B->dtype == ARKCOS_F32))) {
     B->tuned = 2;
   } else {
-    arkcos_status_t st = autotune(B, &upb, &bpc);
+    arkcos_status_t st = autotune(B, &upb, &bpc, &upw);
     if (st != ARKCOS_OK) return st;
-    write_cache(key, upb, bpc);
+    write_cache(key, upb, bpc, upw);
     B->tuned = 1;
   }
+  B->units_per_wave = upw;
   int cus = 0;
   BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   B->units_per_band = upb;
@@ -534,7 +548,8 @@ arkcos_status_t run_batch(arkcos_batch_s* B, const void* const* x, void* const* 
                               B->d_spec_base, s));
   if (ev) BLAUNCH(hipEventRecord(ev[1], s));
   BLAUNCH(launch_accumulate_batch(B->dtype, B->d_acc_args, B->d_spec_base, B->d_out_base, B->d_items, B->n_items,
-                                  counter, spec, bout, B->grid, B->units_per_band, B->all_tables, B->acc_shape, s));
+                                  counter, spec, bout, B->grid, B->units_per_band, B->all_tables, B->acc_shape, s,
+                                  B->units_per_wave));
   if (ev) BLAUNCH(hipEventRecord(ev[2], s));
   for (const ClassDev& c : B->classes)
     BLAUNCH(launch_ring_batch(B->dtype, true, B->d_rargs[adjoint ? 3 : 2], c.entries, c.count, c.lds, c.threads, c.mf, d_ys, bout,
@@ -592,7 +607,8 @@ arkcos_status_t arkcos_batch_get_info(arkcos_batch_t B, arkcos_batch_info_t* inf
   std::memset(info, 0, sizeof(*info));
   info->n_maps = B->n;
   info->seg_units = B->units_per_band;
-  info->group = B->units_per_band;
+  info->group = B->units_per_band / B->units_per_wave;
+  info->units_per_wave = B->units_per_wave;
   info->grid = B->grid;
   info->tuned = B->tuned;
   info->n_items = B->n_items;

@@ -465,13 +465,13 @@ __device__ __forceinline__ void accumulate_band(const AccArgs<R>& a, const BandD
 // those of its next, each exactly as the one-unit form does (the same order
 // of the sum over a unit's pairs).  Every wave must call this; it
 // synchronises the block.
-template <typename R, int NW, int U>
+template <typename R, int NW, int U, int CHR = AccLds<R>::kRings>
 __device__ __forceinline__ void accumulate_band_tabu(const AccArgs<R>& a, const BandDev& bd, const int t0,
                                                      const int nt, const cx_t<R>* __restrict__ spec,
                                                      cx_t<R>* __restrict__ bout, unsigned char* smem,
                                                      const AccLayout lay) {
   using C = cx_t<R>;
-  constexpr int CH = AccLds<R>::kRings;
+  constexpr int CH = CHR;
   constexpr int RPW = (2 * CH + NW - 1) / NW;
   constexpr int MPL = kModesPerLane;
   C* sa = reinterpret_cast<C*>(smem);
@@ -573,31 +573,32 @@ __device__ __forceinline__ void accumulate_band_tabu(const AccArgs<R>& a, const 
         }
         qt[x] = 0;
       }
-      if (busy) {
-        // up to CH pairs of this unit in the staged chunk: descriptors read
-        // together (the area has CH spare entries), then every live tile
-        // loaded, then accumulated
-        PairU d[CH];
+      // this unit's pairs in the staged chunk, in groups of up to GS: the
+      // group's descriptors read together (the area has 8 spare entries),
+      // then every live tile loaded, then accumulated
+      constexpr int GS = CH < 8 ? CH : 8;
+      for (int grp = 0; busy && grp < CH / GS; ++grp) {
+        PairU d[GS];
 #pragma unroll
-        for (int y = 0; y < CH; ++y) d[y] = uniform_pair(mine[x][qt[x] + y]);
+        for (int y = 0; y < GS; ++y) d[y] = uniform_pair(mine[x][qt[x] + y]);
         int g = 0;
         uint32_t live = 0;
 #pragma unroll
-        for (int y = 0; y < CH; ++y)
+        for (int y = 0; y < GS; ++y)
           if (g == y && qt[x] + y < npair[x] && pl_row(d[y].meta) < c1) {
             g = y + 1;
             if (d[y].band >= m0) live |= 1u << y;
           }
-        R kv[CH][MPL];
+        R kv[GS][MPL];
 #pragma unroll
-        for (int y = 0; y < CH; ++y)
+        for (int y = 0; y < GS; ++y)
           if ((live >> y) & 1u) {
             const R* tb = a.table + d[y].off + m0;
 #pragma unroll
             for (int e = 0; e < MPL; ++e) kv[y][e] = gload(tb + 64 * e + lane);
           }
 #pragma unroll
-        for (int y = 0; y < CH; ++y)
+        for (int y = 0; y < GS; ++y)
           if ((live >> y) & 1u) {
             const C* s0 = sa + 2 * (pl_row(d[y].meta) - c0) * kAccTile + lane;
 #pragma unroll
@@ -614,6 +615,7 @@ __device__ __forceinline__ void accumulate_band_tabu(const AccArgs<R>& a, const 
             }
           }
         qt[x] += g;
+        if (g < GS) break;
       }
       if (busy && c == nch - 1) {
         const int64_t o0 = gload(a.out_off + u[x].i);
@@ -658,13 +660,14 @@ __global__ void __launch_bounds__(64 * NW)
   accumulate_band<R, NW, TAB_ONLY>(a, a.bands[it.band], it.t0, it.nt, spec, bout, smem, lay);
 }
 
-// Table-only plans with U units per wavefront (bands of U NW units).
-template <typename R, int NW, int U>
+// Table-only plans with U units per wavefront (bands of U NW units), CHR
+// input rings staged at a time.
+template <typename R, int NW, int U, int CHR = AccLds<R>::kRings>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4)))
     accumulate_u_kernel(AccArgs<R> a, const cx_t<R>* __restrict__ spec, cx_t<R>* __restrict__ bout, AccLayout lay) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WorkItem it = a.items[blockIdx.x];
-  accumulate_band_tabu<R, NW, U>(a, a.bands[it.band], it.t0, it.nt, spec, bout, smem, lay);
+  accumulate_band_tabu<R, NW, U, CHR>(a, a.bands[it.band], it.t0, it.nt, spec, bout, smem, lay);
 }
 
 // Batched form: one persistent launch drains a queue of (map, band, tiles)
@@ -741,22 +744,23 @@ void fill_acc_args(arkcos_plan_s* P, const BandDev* bands, void* out, const int6
 // LDS of one accumulation block: the staged spectra (2 CH rows of kAccTile
 // complex values), the row table of the whole window, the band's pair
 // descriptors.
-static AccLayout acc_layout(arkcos_dtype_t dt, const AccShape& sh) {
+static AccLayout acc_layout(arkcos_dtype_t dt, const AccShape& sh, int32_t staged_rings = 0) {
   const int32_t win = std::max(sh.max_window, 1);
   size_t tile;
   if (dt == ARKCOS_F32)
-    tile = 2 * (size_t)AccLds<float>::kRings * kAccTile * sizeof(float2);
+    tile = 2 * (size_t)(staged_rings ? staged_rings : AccLds<float>::kRings) * kAccTile * sizeof(float2);
   else
-    tile = 2 * (size_t)AccLds<double>::kRings * kAccTile * sizeof(double2);
+    tile = 2 * (size_t)(staged_rings ? staged_rings : AccLds<double>::kRings) * kAccTile * sizeof(double2);
   AccLayout l;
   l.rows_off = (int32_t)tile;
   l.pairs_off = (int32_t)(tile + 2 * (size_t)win * sizeof(RowRef));
   return l;
 }
 
-size_t acc_lds_bytes(arkcos_dtype_t dt, const AccShape& sh) {
-  // CH spare descriptors: a group of table pairs reads CH descriptors at once
-  return (size_t)acc_layout(dt, sh).pairs_off + (size_t)(std::max(sh.max_band_pairs, 1) + 8) * sizeof(PairLds);
+size_t acc_lds_bytes(arkcos_dtype_t dt, const AccShape& sh, int32_t staged_rings) {
+  // 8 spare descriptors: a group of table pairs reads up to 8 descriptors at once
+  return (size_t)acc_layout(dt, sh, staged_rings).pairs_off +
+         (size_t)(std::max(sh.max_band_pairs, 1) + 8) * sizeof(PairLds);
 }
 
 template <typename R, int NW, bool TAB_ONLY>
@@ -831,6 +835,7 @@ hipError_t configure_accumulate_shape(const arkcos_plan_s* P, const AccShape& sh
     if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<float, 16, true>, lds);
     if (e == hipSuccess) e = allow_acc_lds(accumulate_u_kernel<float, 8, 2>, lds);
     if (e == hipSuccess) e = allow_acc_lds(accumulate_u_kernel<float, 8, 3>, lds);
+    if (e == hipSuccess) e = allow_acc_lds(accumulate_u_kernel<float, 8, 2, 16>, acc_lds_bytes(P->dtype, shape, 16));
   } else {
     e = allow_acc_lds(accumulate_kernel<double, 8, false>, lds);
     if (e == hipSuccess) e = allow_acc_lds(accumulate_kernel<double, 8, true>, lds);
@@ -853,14 +858,17 @@ static void launch_nw(const arkcos_plan_s* P, const AccArgs<R>& a, unsigned grid
 // shape (the plan's own, or a candidate timed at plan creation).
 hipError_t launch_accumulate_shape(const arkcos_plan_s* P, const BandDev* bands, const WorkItem* items,
                                    int32_t n_items, int32_t units, const AccShape& shape, const void* spec,
-                                   void* bout, hipStream_t s, int32_t units_per_wave) {
+                                   void* bout, hipStream_t s, int32_t units_per_wave, int32_t staged_rings) {
   if (n_items == 0) return hipSuccess;
   const size_t lds = acc_lds_bytes(P->dtype, shape);
   const AccLayout lay = acc_layout(P->dtype, shape);
   if (P->dtype == ARKCOS_F32) {
     AccArgs<float> a = make_acc_args<float>(P, bands);
     a.items = items;
-    if (units_per_wave > 1 && P->all_tables && units == 8 * units_per_wave) {
+    if (units_per_wave == 2 && staged_rings == 16 && P->all_tables && units == 16) {
+      accumulate_u_kernel<float, 8, 2, 16><<<(unsigned)n_items, 512, acc_lds_bytes(P->dtype, shape, 16), s>>>(
+          a, (const float2*)spec, (float2*)bout, acc_layout(P->dtype, shape, 16));
+    } else if (units_per_wave > 1 && P->all_tables && units == 8 * units_per_wave) {
       if (units_per_wave == 2)
         accumulate_u_kernel<float, 8, 2><<<(unsigned)n_items, 512, lds, s>>>(a, (const float2*)spec, (float2*)bout, lay);
       else
@@ -880,7 +888,7 @@ hipError_t launch_accumulate_shape(const arkcos_plan_s* P, const BandDev* bands,
 
 hipError_t launch_accumulate(arkcos_plan_s* P, const void* spec, void* bout, hipStream_t s) {
   return launch_accumulate_shape(P, P->d_bands, P->d_items, (int32_t)P->h_items.size(), P->acc_units, P->acc_shape,
-                                 spec, bout, s, P->acc_upw);
+                                 spec, bout, s, P->acc_upw, P->acc_ch);
 }
 
 }  // namespace arkcos

@@ -196,6 +196,7 @@ struct arkcos_plan_s {
   int32_t acc_tiles = arkcos::kTilesPerItem;   // mode tiles per work item
   int32_t acc_tuned = 0;                       // 1: band shape chosen by timing at plan creation
   int32_t acc_upw = 1;                         // units per wavefront (2: 16-unit bands in 8-wave blocks)
+  int32_t acc_ch = 0;                          // input rings staged at a time (0: the dtype's default)
   std::vector<arkcos::BandDev> h_bands;
   bool all_tables = false;     // every pair reads K_ij(m) from a table
   void* d_coef = nullptr;       // recurrence coefficients, plan dtype
@@ -267,7 +268,7 @@ size_t acc_args_size();
 // least every mode the plan's pairs read).
 void fill_acc_args(arkcos_plan_s* P, const BandDev* bands, void* out, const int64_t* spec_off = nullptr,
                    const int32_t* spec_len = nullptr);
-size_t acc_lds_bytes(arkcos_dtype_t dt, const AccShape& shape);
+size_t acc_lds_bytes(arkcos_dtype_t dt, const AccShape& shape, int32_t staged_rings = 0);
 hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const int64_t* spec_base,
                                    const int64_t* out_base, const BatchItem* items, int32_t n_items,
                                    int32_t* counter, const void* spec, void* bout, int32_t grid,
@@ -277,7 +278,7 @@ hipError_t configure_accumulate(arkcos_plan_s* P);
 hipError_t configure_accumulate_shape(const arkcos_plan_s* P, const AccShape& shape);
 hipError_t launch_accumulate_shape(const arkcos_plan_s* P, const BandDev* bands, const WorkItem* items,
                                    int32_t n_items, int32_t units, const AccShape& shape, const void* spec,
-                                   void* bout, hipStream_t s, int32_t units_per_wave = 1);
+                                   void* bout, hipStream_t s, int32_t units_per_wave = 1, int32_t staged_rings = 0);
 size_t ring_args_size();
 void fill_ring_args(arkcos_plan_s* P, bool out_side, int32_t adjoint, int32_t zero_pole, void* out,
                     const int64_t* off = nullptr, const int32_t* len = nullptr);

@@ -425,6 +425,7 @@ static void make_bands_items(const arkcos_plan_s* P, int32_t units, int32_t tile
 arkcos_status_t choose_accumulation_shape(arkcos_plan_s* P) {
   struct Cand {
     int32_t units, tiles, upw;  // units per band, mode tiles per item, units per wavefront
+    int32_t ch = 0;             // input rings staged at a time (0: the default)
   };
   std::vector<Cand> cand;
   if (const char* e = getenv("ARKCOS_ACC_SHAPE"); e && *e) {
@@ -438,7 +439,8 @@ arkcos_status_t choose_accumulation_shape(arkcos_plan_s* P) {
     // two units per wavefront only for table-only FP32 plans)
     if (P->npix >= (int64_t(1) << 20) && P->dtype == ARKCOS_F32) {
       cand = {{8, 4, 1}, {16, 4, 1}, {8, 2, 1}, {16, 2, 1}, {8, 8, 1}, {16, 8, 1}};
-      if (P->all_tables) cand.insert(cand.end(), {{16, 4, 2}, {16, 2, 2}, {24, 2, 3}});
+      if (P->all_tables)
+        cand.insert(cand.end(), {{16, 4, 2}, {16, 2, 2}, {24, 2, 3}, {16, 4, 2, 16}, {16, 2, 2, 16}});
     } else if (P->npix >= (int64_t(1) << 20)) {
       cand = {{8, 4, 1}, {8, 2, 1}, {8, 8, 1}};
     } else {
@@ -450,6 +452,7 @@ arkcos_status_t choose_accumulation_shape(arkcos_plan_s* P) {
     P->acc_units = cand[0].units;
     P->acc_tiles = cand[0].tiles;
     P->acc_upw = cand[0].upw;
+    P->acc_ch = cand[0].ch;
     make_bands_items(P, P->acc_units, P->acc_tiles, P->h_bands, &P->acc_shape, P->h_items);
     return ARKCOS_OK;
   }
@@ -487,18 +490,18 @@ arkcos_status_t choose_accumulation_shape(arkcos_plan_s* P) {
     HIPCHK(configure_accumulate_shape(P, sh));
     const int32_t ni = (int32_t)items.size();
     HIPCHK(launch_accumulate_shape(P, (BandDev*)d_b, (WorkItem*)d_i, ni, cand[k].units, sh, spec, bout, nullptr,
-                                   cand[k].upw));
+                                   cand[k].upw, cand[k].ch));
     HIPCHK(hipEventRecord(e0, nullptr));
     for (int r = 0; r < 3; ++r)
       HIPCHK(launch_accumulate_shape(P, (BandDev*)d_b, (WorkItem*)d_i, ni, cand[k].units, sh, spec, bout, nullptr,
-                                     cand[k].upw));
+                                     cand[k].upw, cand[k].ch));
     HIPCHK(hipEventRecord(e1, nullptr));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     if (const char* e = getenv("ARKCOS_ACC_TIMES"); e && *e == '1')
-      fprintf(stderr, "arkcos plan: accumulation candidate %d units, %d tiles, %d per wave: %.4f ms\n",
-              cand[k].units, cand[k].tiles, cand[k].upw, ms / 3.0f);
+      fprintf(stderr, "arkcos plan: accumulation candidate %d units, %d tiles, %d per wave, %d rings staged: %.4f ms\n",
+              cand[k].units, cand[k].tiles, cand[k].upw, cand[k].ch, ms / 3.0f);
     if (ms < best) {
       best = ms;
       best_k = k;
@@ -507,6 +510,7 @@ arkcos_status_t choose_accumulation_shape(arkcos_plan_s* P) {
   P->acc_units = cand[best_k].units;
   P->acc_tiles = cand[best_k].tiles;
   P->acc_upw = cand[best_k].upw;
+  P->acc_ch = cand[best_k].ch;
   P->acc_tuned = 1;
   make_bands_items(P, P->acc_units, P->acc_tiles, P->h_bands, &P->acc_shape, P->h_items);
   return ARKCOS_OK;

@@ -694,7 +694,7 @@ __global__ void __launch_bounds__(64 * NW) accumulate_batch_kernel(
 }
 
 // The batched form with U units per wavefront (table-only batches).
-template <typename R, int NW, int U>
+template <typename R, int NW, int U, int CHR = AccLds<R>::kRings>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) accumulate_batch_u_kernel(
     const AccArgs<R>* __restrict__ maps, const int64_t* __restrict__ spec_base,
     const int64_t* __restrict__ out_base, const BatchItem* __restrict__ items, int32_t n_items,
@@ -709,8 +709,8 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4)
     if (it >= n_items) break;
     const BatchItem bi = items[it];
     const AccArgs<R> a = maps[bi.map];
-    accumulate_band_tabu<R, NW, U>(a, load_band(a.bands + bi.band), bi.t0, bi.nt, spec + spec_base[bi.map],
-                                   bout + out_base[bi.map], smem, lay);
+    accumulate_band_tabu<R, NW, U, CHR>(a, load_band(a.bands + bi.band), bi.t0, bi.nt, spec + spec_base[bi.map],
+                                        bout + out_base[bi.map], smem, lay);
   }
 }
 
@@ -794,10 +794,20 @@ hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const in
                                    const int64_t* out_base, const BatchItem* items, int32_t n_items,
                                    int32_t* counter, const void* spec, void* bout, int32_t grid,
                                    int32_t units_per_band, bool all_tables, const AccShape& shape, hipStream_t s,
-                                   int32_t units_per_wave) {
+                                   int32_t units_per_wave, int32_t staged_rings) {
   reset_counter_kernel<<<1, 64, 0, s>>>(counter);
   const size_t lds = acc_lds_bytes(dt, shape);
   const AccLayout lay = acc_layout(dt, shape);
+  if (dt == ARKCOS_F32 && all_tables && units_per_wave == 2 && units_per_band == 16 && staged_rings == 16) {
+    const size_t lds16 = acc_lds_bytes(dt, shape, 16);
+    hipError_t e = hipFuncSetAttribute((const void*)accumulate_batch_u_kernel<float, 8, 2, 16>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds16);
+    if (e != hipSuccess) return e;
+    accumulate_batch_u_kernel<float, 8, 2, 16><<<grid, 512, lds16, s>>>(
+        (const AccArgs<float>*)maps, spec_base, out_base, items, n_items, counter, (const float2*)spec, (float2*)bout,
+        acc_layout(dt, shape, 16));
+    return hipGetLastError();
+  }
   if (dt == ARKCOS_F32 && all_tables && units_per_wave == 2 && units_per_band == 16) {
     hipError_t e = hipFuncSetAttribute((const void*)accumulate_batch_u_kernel<float, 8, 2>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

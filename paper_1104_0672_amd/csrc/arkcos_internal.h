@@ -273,7 +273,7 @@ hipError_t launch_accumulate_batch(arkcos_dtype_t dt, const void* maps, const in
                                    const int64_t* out_base, const BatchItem* items, int32_t n_items,
                                    int32_t* counter, const void* spec, void* bout, int32_t grid,
                                    int32_t units_per_band, bool all_tables, const AccShape& shape, hipStream_t s,
-                                   int32_t units_per_wave = 1);
+                                   int32_t units_per_wave = 1, int32_t staged_rings = 0);
 hipError_t configure_accumulate(arkcos_plan_s* P);
 hipError_t configure_accumulate_shape(const arkcos_plan_s* P, const AccShape& shape);
 hipError_t launch_accumulate_shape(const arkcos_plan_s* P, const BandDev* bands, const WorkItem* items,

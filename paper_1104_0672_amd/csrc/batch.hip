@@ -51,6 +51,7 @@ struct arkcos_batch_s {
   std::vector<arkcos_plan_s*> plans;
   int32_t units_per_band = kBandUnits, grid = 0, tuned = 0;
   int32_t units_per_wave = 1;  // 2: table-only FP32 batches, bands of 16 units in 8-wave blocks
+  int32_t staged_rings = 0;    // input rings the accumulation stages at a time (0: the default)
   bool all_tables = false;  // every plan reads all its K_ij(m) from tables
   AccShape acc_shape;
   int64_t spec_total = 0, out_total = 0, npix_total = 0;
@@ -162,8 +163,9 @@ std::string tune_key(const arkcos_batch_s* B) {
   return k.str();
 }
 
-// Cache lines: key, units per band, blocks per CU, units per wavefront.
-bool read_cache(const std::string& key, int32_t* upb, int32_t* bpc, int32_t* upw) {
+// Cache lines: key, units per band, blocks per CU, units per wavefront,
+// staged rings.
+bool read_cache(const std::string& key, int32_t* upb, int32_t* bpc, int32_t* upw, int32_t* ch) {
   const char* path = getenv("ARKCOS_AUTOTUNE_CACHE");
   if (!path || !*path) return false;
   std::ifstream f(path);
@@ -171,29 +173,30 @@ bool read_cache(const std::string& key, int32_t* upb, int32_t* bpc, int32_t* upw
   while (std::getline(f, line)) {
     std::istringstream in(line);
     std::string k;
-    int32_t a = 0, b = 0, c = 0;
-    if ((in >> k >> a >> b >> c) && k == key) {
+    int32_t a = 0, b = 0, c = 0, d = 0;
+    if ((in >> k >> a >> b >> c >> d) && k == key) {
       *upb = a;
       *bpc = b;
       *upw = c;
+      *ch = d;
       return true;
     }
   }
   return false;
 }
 
-void write_cache(const std::string& key, int32_t upb, int32_t bpc, int32_t upw) {
+void write_cache(const std::string& key, int32_t upb, int32_t bpc, int32_t upw, int32_t ch) {
   const char* path = getenv("ARKCOS_AUTOTUNE_CACHE");
   if (!path || !*path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << " " << upb << " " << bpc << " " << upw << "\n";
+  f << key << " " << upb << " " << bpc << " " << upw << " " << ch << "\n";
 }
 
 // Times the accumulation of one queue on the subset's workspace (zero
 // spectra); returns milliseconds per launch.
 hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64_t>& sb,
                       const std::vector<int64_t>& ob, void* spec, void* bout, int32_t* counter, int32_t upb,
-                      int32_t grid, float* ms, int32_t upw) {
+                      int32_t grid, float* ms, int32_t upw, int32_t ch) {
   void *dargs = nullptr, *ditems = nullptr, *dsb = nullptr, *dob = nullptr;
   hipError_t e = hipMalloc(&dargs, Q.acc_args.size());
   if (e == hipSuccess) e = hipMalloc(&ditems, std::max<size_t>(Q.items.size(), 1) * sizeof(BatchItem));
@@ -212,7 +215,7 @@ hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64
     if (e == hipSuccess)
       e = launch_accumulate_batch(B->dtype, dargs, (const int64_t*)dsb, (const int64_t*)dob, (const BatchItem*)ditems,
                                   (int32_t)Q.items.size(), counter, spec, bout, grid, upb, B->all_tables, Q.shape,
-                                  nullptr, upw);
+                                  nullptr, upw, ch);
   }
   if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -228,7 +231,8 @@ hipError_t time_queue(arkcos_batch_s* B, const Queue& Q, const std::vector<int64
   return e;
 }
 
-arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out, int32_t* upw_out) {
+arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out, int32_t* upw_out,
+                         int32_t* ch_out) {
   // subset: up to four maps per ring count
   std::map<int64_t, int> seen;
   std::vector<int32_t> sub;
@@ -255,23 +259,31 @@ arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out, 
   int cus = 0;
   BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
   float best = 1e30f;
-  int32_t bu = kBandUnits, bb = 2, bw = 1;
-  // (units per band, units per wavefront): two units per wavefront only for
-  // table-only FP32 batches
-  std::vector<std::pair<int32_t, int32_t>> shapes = {{4, 1}, {8, 1}, {16, 1}};
-  if (B->all_tables && B->dtype == ARKCOS_F32) shapes.push_back({16, 2});
-  for (const auto& [upb, upw] : shapes) {
+  int32_t bu = kBandUnits, bb = 2, bw = 1, bc = 0;
+  // (units per band, units per wavefront, staged rings): two units per
+  // wavefront only for table-only FP32 batches
+  struct Shape {
+    int32_t upb, upw, ch;
+  };
+  std::vector<Shape> shapes = {{4, 1, 0}, {8, 1, 0}, {16, 1, 0}};
+  // (staging 16 rings at a time, {16, 2, 16}, measured no faster on the 256-map
+  // batch and slower on ten kernels over one input map: not a candidate)
+  if (B->all_tables && B->dtype == ARKCOS_F32) shapes.push_back({16, 2, 0});
+  for (const Shape& sh : shapes) {
+    const int32_t upb = sh.upb;
     Queue Q;
     std::vector<void*> owned;
     hipError_t e = build_queue(B, sub, upb, Q, owned);
     for (int32_t bpc : {1, 2, 4}) {
       float ms = 0.f;
-      if (e == hipSuccess) e = time_queue(B, Q, sb, ob, spec, bout, (int32_t*)ctr, upb, cus * bpc, &ms, upw);
+      if (e == hipSuccess)
+        e = time_queue(B, Q, sb, ob, spec, bout, (int32_t*)ctr, upb, cus * bpc, &ms, sh.upw, sh.ch);
       if (e == hipSuccess && ms < best) {
         best = ms;
         bu = upb;
         bb = bpc;
-        bw = upw;
+        bw = sh.upw;
+        bc = sh.ch;
       }
     }
     for (void* p : owned) hipFree(p);
@@ -280,6 +292,7 @@ arkcos_status_t autotune(arkcos_batch_s* B, int32_t* upb_out, int32_t* bpc_out, 
   *upb_out = bu;
   *bpc_out = bb;
   *upw_out = bw;
+  *ch_out = bc;
   return ARKCOS_OK;
 }
 
@@ -433,18 +446,19 @@ arkcos_status_t build_batch(int32_t n, const arkcos_plan_t* plans, bool shared, 
   }
 
   // band size and grid: cached, else measured
-  int32_t upb = kBandUnits, bpc = 2, upw = 1;
+  int32_t upb = kBandUnits, bpc = 2, upw = 1, ch = 0;
   const std::string key = tune_key(B);
-  if (read_cache(key, &upb, &bpc, &upw) &&
+  if (read_cache(key, &upb, &bpc, &upw, &ch) && (ch == 0 || ch == 16) &&
       (upw == 1 || (upw == 2 && upb == 16 && B->all_tables && B->dtype == ARKCOS_F32))) {
     B->tuned = 2;
   } else {
-    arkcos_status_t st = autotune(B, &upb, &bpc, &upw);
+    arkcos_status_t st = autotune(B, &upb, &bpc, &upw, &ch);
     if (st != ARKCOS_OK) return st;
-    write_cache(key, upb, bpc, upw);
+    write_cache(key, upb, bpc, upw, ch);
     B->tuned = 1;
   }
   B->units_per_wave = upw;
+  B->staged_rings = upw == 2 ? ch : 0;
   int cus = 0;
   BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   B->units_per_band = upb;
@@ -549,7 +563,7 @@ arkcos_status_t run_batch(arkcos_batch_s* B, const void* const* x, void* const* 
   if (ev) BLAUNCH(hipEventRecord(ev[1], s));
   BLAUNCH(launch_accumulate_batch(B->dtype, B->d_acc_args, B->d_spec_base, B->d_out_base, B->d_items, B->n_items,
                                   counter, spec, bout, B->grid, B->units_per_band, B->all_tables, B->acc_shape, s,
-                                  B->units_per_wave));
+                                  B->units_per_wave, B->staged_rings));
   if (ev) BLAUNCH(hipEventRecord(ev[2], s));
   for (const ClassDev& c : B->classes)
     BLAUNCH(launch_ring_batch(B->dtype, true, B->d_rargs[adjoint ? 3 : 2], c.entries, c.count, c.lds, c.threads, c.mf, d_ys, bout,

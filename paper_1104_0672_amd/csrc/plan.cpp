@@ -429,10 +429,11 @@ arkcos_status_t choose_accumulation_shape(arkcos_plan_s* P) {
   };
   std::vector<Cand> cand;
   if (const char* e = getenv("ARKCOS_ACC_SHAPE"); e && *e) {
-    int u = 0, t = 0, w = 1;
-    const int got = sscanf(e, "%d,%d,%d", &u, &t, &w);
-    const bool per_wave = got == 3 && w >= 2 && w <= 3 && u == 8 * w && P->all_tables && P->dtype == ARKCOS_F32;
-    if (got >= 2 && (u == 8 || u == 16 || per_wave) && t >= 1 && t <= 16) cand.push_back({u, t, per_wave ? w : 1});
+    int u = 0, t = 0, w = 1, ch = 0;
+    const int got = sscanf(e, "%d,%d,%d,%d", &u, &t, &w, &ch);
+    const bool per_wave = got >= 3 && w >= 2 && w <= 3 && u == 8 * w && P->all_tables && P->dtype == ARKCOS_F32;
+    if (got >= 2 && (u == 8 || u == 16 || per_wave) && t >= 1 && t <= 16)
+      cand.push_back({u, t, per_wave ? w : 1, (per_wave && w == 2 && got == 4 && ch == 16) ? 16 : 0});
   }
   if (cand.empty()) {
     // (16-unit bands only in FP32: the FP64 recurrence form would spill;

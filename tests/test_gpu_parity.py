@@ -171,14 +171,14 @@ def test_accumulation_shapes_are_bitwise_equal():
     _say(f"case accumulation shapes {w.name}")
     x = W.make_input(w)
     outs = []
-    for shape in ("8,4", "8,2", "16,4", "16,4,2", "16,2,2", "24,2,3"):
+    for shape in ("8,4", "8,2", "16,4", "16,4,2", "16,2,2", "24,2,3", "16,4,2,16"):
         os.environ["ARKCOS_ACC_SHAPE"] = shape
         try:
             plan = _plan(w)
         finally:
             del os.environ["ARKCOS_ACC_SHAPE"]
         info = plan.info
-        want_upw = int(shape.split(",")[2]) if shape.count(",") == 2 else 1
+        want_upw = int(shape.split(",")[2]) if shape.count(",") >= 2 else 1
         _say(f"  shape {shape}: {info.acc_seg_units} units, {info.acc_group} tiles, "
              f"{info.acc_units_per_wave} per wave")
         assert info.acc_units_per_wave == want_upw and info.acc_seg_units == int(shape.split(",")[0])

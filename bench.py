@@ -34,6 +34,17 @@ FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4
 STAGES = ["ring_r2c", "accumulate", "fold_c2r", "pole_fix"]
 KERNEL_NAMES = {"ring_r2c": "r2c_kernel", "accumulate": "accumulate_kernel", "fold_c2r": "c2r_kernel",
                 "pole_fix": "pole_forward_kernel"}
+# the accumulation stage runs one of these (the plan's tuned shape: one unit
+# per wavefront, or two or three)
+STAGE_KERNELS = {"accumulate": ("accumulate_kernel", "accumulate_u_kernel")}
+
+
+def stage_of(kernel: str):
+    """The forward stage a kernel (short name) belongs to, or None."""
+    for stage, name in KERNEL_NAMES.items():
+        if kernel == name or kernel in STAGE_KERNELS.get(stage, ()):
+            return stage
+    return None
 KERNEL_SOURCES = {"ring_r2c": ["fft.hip", "device_common.h"], "accumulate": ["accum.hip", "device_common.h"],
                   "fold_c2r": ["fft.hip", "device_common.h"], "pole_fix": ["pole.hip"]}
 
@@ -127,8 +138,9 @@ def summarize_traffic(fetch_csv: str, write_csv: str, calib_mib: int, out_path: 
             started = started or name == KERNEL_NAMES["ring_r2c"]
             if not started:
                 continue
-            per[name] += kib * 1024
-            if name == "accumulate_kernel":
+            st = stage_of(name)
+            per[KERNEL_NAMES[st] if st else name] += kib * 1024
+            if st == "accumulate":
                 steps += 1
         if not cal or not steps:
             raise SystemExit(f"{path}: no calibration copy or no accumulate dispatch found")
@@ -170,7 +182,7 @@ def summarize_kernels(trace_dir: str, cmd: str, title: str):
     agg = collections.defaultdict(list)
     for r in trace:
         n = _short(r["Kernel_Name"])
-        if n in KERNEL_NAMES.values() or "batch" in n or "grad" in n or "adjoint" in n:
+        if stage_of(n) or "batch" in n or "grad" in n or "adjoint" in n:
             key = (n, int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"])), int(r["Workgroup_Size_X"]),
                    int(r["LDS_Block_Size"]))
             agg[key].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
@@ -198,7 +210,7 @@ def summarize_counters(csv_path: str, cmd: str, title: str):
     name_of = {}
     for r in rows:
         n = _short(r["Kernel_Name"])
-        if n in KERNEL_NAMES.values() or "grad" in n or "batch" in n:
+        if stage_of(n) or "grad" in n or "batch" in n:
             name_of.setdefault(int(r["Dispatch_Id"]), n)
     skip, prev = set(), ""
     for d in sorted(name_of):
@@ -207,7 +219,7 @@ def summarize_counters(csv_path: str, cmd: str, title: str):
         prev = name_of[d]
     for r in rows:
         n = _short(r["Kernel_Name"])
-        if not (n in KERNEL_NAMES.values() or "grad" in n or "batch" in n) or int(r["Dispatch_Id"]) in skip:
+        if not (stage_of(n) or "grad" in n or "batch" in n) or int(r["Dispatch_Id"]) in skip:
             continue
         key = (n, int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"])), int(r["Workgroup_Size"]))
         per[key][r["Counter_Name"]] += float(r["Counter_Value"])
@@ -550,7 +562,9 @@ def main():
     achieved = bytes_per_launch / dur_s / 1e9
     traffic = measured_traffic(stage)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL_NAMES[stage],
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": ("accumulate_u_kernel" if stage == "accumulate" and plan.info.acc_units_per_wave > 1
+                           else KERNEL_NAMES[stage]),
                 "kernel_ms": round(stage_ms[dom], 4), "algorithmic_bytes_per_launch": bytes_per_launch}
     total_alg = 3 * 2 * elem * plan.npix
     forms = {"plain": {"pixels_per_s": value, "ms": ms_per_step,

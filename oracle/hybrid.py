@@ -34,7 +34,7 @@ ring's spectrum beyond its own Nyquist mode instead of repeating it, and
 step (d) keeps only the output ring's modes |m| <= N_i / 2 instead of folding
 the higher ones onto them.
 
-Readings taken where the paper is silent (each listed in the design doc):
+Readings taken where the paper is silent:
 
 * Kernel grids: pairs of equal-length rings sample the kernel at their true
   pixel offsets on a grid of their own length (exact); other pairs sample it

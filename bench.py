@@ -519,7 +519,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the single-map path "
-              "shards by latitude band across GPUs, which this build does not run.", file=sys.stderr)
+              "would shard by latitude band across GPUs, which is a design only: nothing here runs on more "
+              "than one GPU.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

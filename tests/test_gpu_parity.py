@@ -190,6 +190,34 @@ def test_accumulation_shapes_are_bitwise_equal():
     assert _frac(outs[0][0].numpy().astype(np.float64), ref) <= 1e-4
 
 
+@pytest.mark.parametrize("nside,fwhm_arcmin", [(16, 200.0), (64, 60.0), (512, 10.0)])
+def test_accumulation_shapes_bitwise_equal_across_sizes(nside, fwhm_arcmin):
+    """The multi-unit shapes on other sizes (ragged last bands, windows
+    reaching the poles, short maps): bitwise equal to one unit per wave."""
+    import os
+    fw = math.radians(fwhm_arcmin / 60.0)
+    w = W.Workload(f"healpix{nside}_{fwhm_arcmin:g}", W.Grid("healpix", nside=nside),
+                   W.Profile("gaussian", fwhm=fw), 3.0 * fw, "f32", nside)
+    _say(f"case accumulation shapes {w.name}")
+    x = W.white_noise(w.grid.npix, nside)
+    outs = []
+    for shape in ("8,4", "16,2,2,16", "24,2,3", "16,4,2"):
+        os.environ["ARKCOS_ACC_SHAPE"] = shape
+        try:
+            plan = _plan(w)
+        finally:
+            del os.environ["ARKCOS_ACC_SHAPE"]
+        kinds = list(plan.info.pairs_by_kind)
+        all_tab = kinds[0] + kinds[1] + kinds[3] == 0
+        want = int(shape.split(",")[2]) if shape.count(",") >= 2 and all_tab else 1
+        assert plan.info.acc_units_per_wave == want
+        xt = _tt(x, w)
+        outs.append((plan.convolve(xt).cpu(), plan.adjoint(xt).cpu()))
+        _say(f"  shape {shape}: {plan.info.acc_seg_units} units, {plan.info.acc_units_per_wave} per wave")
+    for k in range(1, len(outs)):
+        assert torch.equal(outs[k][0], outs[0][0]) and torch.equal(outs[k][1], outs[0][1])
+
+
 def test_fp64_adjoint_dot_product_and_transpose():
     for w in (W.ecp_64x128(), W.scaled_healpix(16, 200.0, 3.0, dtype="f64")):
         _say(f"case adjoint {w.name}")

@@ -186,8 +186,9 @@ def test_healpix1024_spline_gradient_all_knots_against_the_definition():
 
 
 def test_healpix1024_spline_gradient_central_differences():
-    """Full-map gradient of the FP32 plan against central differences of the
-    same method in FP64 (the loss is quadratic in the knots: exact)."""
+    """Full-map gradient of the FP32 plan, and of the FP64 plan, against
+    central differences of the same method in FP64 (the loss is quadratic in
+    the knots: exact up to rounding)."""
     from paper_1104_0672_amd import Plan
     w = W.healpix1024_spline()
     npix = w.grid.npix
@@ -202,16 +203,30 @@ def test_healpix1024_spline_gradient_central_differences():
     g = p32.kernel_grad(x32, r.float()).cpu().numpy()
     c = np.asarray(w.profile.knots)
     h = 1e-3
+    fds = {}
     for k in (0, 7, 31, 63):
         e = np.zeros_like(c)
         e[k] = h
         p64.set_knots(c + e)
-        lp = 0.5 * float(((p64.convolve(x64) - t64) ** 2).sum())
+        yp = p64.convolve(x64)
         p64.set_knots(c - e)
-        lm = 0.5 * float(((p64.convolve(x64) - t64) ** 2).sum())
-        fd = (lp - lm) / (2 * h)
+        ym = p64.convolve(x64)
+        # L(+) - L(-) summed per pixel as (yp - ym)(yp + ym - 2t) / 2: no
+        # cancellation between the two losses' large sums
+        fd = float((0.5 * (yp - ym) * (yp + ym - 2.0 * t64)).sum()) / (2 * h)
+        fds[k] = fd
         print(f"  knot {k}: gradient {g[k]:.6e}, central difference {fd:.6e}", flush=True)
-        assert abs(fd - g[k]) <= 1e-4 * np.abs(g).max()
+        assert abs(fd - g[k]) <= 2e-5 * np.abs(g).max()
+    # the FP64 plan's own gradient (its wide rows by 8192-point FFTs in
+    # 512-thread blocks) against the same differences, which are exact for
+    # the quadratic loss up to rounding
+    p64.set_knots(c)
+    r64 = p64.convolve(x64) - t64
+    g64 = p64.kernel_grad(x64, r64).cpu().numpy()
+    assert p64.info.grad_fft_rows > 0
+    for k, fd in fds.items():
+        print(f"  knot {k}: FP64 gradient {g64[k]:.9e}, central difference {fd:.9e}", flush=True)
+        assert abs(fd - g64[k]) <= 1e-9 * np.abs(g64).max()
 
 
 def test_batch256_sampled_maps():

@@ -581,14 +581,17 @@ __device__ __forceinline__ void accumulate_band_tabu(const AccArgs<R>& a, const 
         PairU d[GS];
 #pragma unroll
         for (int y = 0; y < GS; ++y) d[y] = uniform_pair(mine[x][qt[x] + y]);
-        int g = 0;
-        uint32_t live = 0;
-#pragma unroll
-        for (int y = 0; y < GS; ++y)
-          if (g == y && qt[x] + y < npair[x] && pl_row(d[y].meta) < c1) {
-            g = y + 1;
-            if (d[y].band >= m0) live |= 1u << y;
-          }
+        // the group's pairs in the chunk (a prefix: pairs are in input-ring
+        // order) and those whose band reaches the tile, by one ballot each
+        // over lanes 0 .. GS-1 instead of a scalar test per pair
+        bool in_chunk = false, reach = false;
+        if (lane < GS && qt[x] + lane < npair[x]) {
+          const PairLds dl = mine[x][qt[x] + lane];
+          in_chunk = pl_row(dl.meta) < c1;
+          reach = in_chunk && dl.band >= m0;
+        }
+        const int g = __builtin_amdgcn_readfirstlane(__popcll(__ballot(in_chunk)));
+        const uint32_t live = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)__ballot(reach));
         R kv[GS][MPL];
 #pragma unroll
         for (int y = 0; y < GS; ++y)

@@ -88,12 +88,16 @@ constexpr int kGradBlocksPerCU = 3;   // gradient blocks resident per CU (LDS an
 // K_ij(m) tables): S = G / (2 P) real sub-sequences of 2 P points (every
 // S-th mode or sample), each one LDS FFT of P complex points.
 struct RowFft {
-  int32_t unit, pair, P, pad;
+  int32_t unit, pair, P;
+  int32_t half;  // gradient rows: 1 for the half-length cosine sum (P = G / 4, one pass)
 };
 constexpr int64_t kFftRowMinGrid = 512;  // smaller grids: the direct sums
+constexpr int64_t kHalfMaxSamplesF32 = 1024;  // FP32 gradient rows of the half-length cosine sum: samples
 constexpr int64_t kGradYBytes = int64_t(256) << 20;  // Y buffer of the FFT rows: chunks of at most this
 // P of the FFT path for pair q with nc samples, or 0 for the direct sums
 int32_t fft_row_points(const arkcos_plan_s* P, int64_t q, int64_t nc);
+// the largest P of an FFT row (one workgroup's LDS)
+int64_t fft_row_max_points(const arkcos_plan_s* P);
 // block size (threads) of an FFT row of P points: 16 points per thread
 constexpr int fft_row_threads(int32_t P) { return P <= 4096 ? 256 : (P <= 8192 ? 512 : 1024); }
 

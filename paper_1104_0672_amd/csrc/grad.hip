@@ -517,6 +517,72 @@ __global__ void __launch_bounds__(NT) grad_row_fft_kernel(GradArgs g, const RowF
     return X * wm;
   };
   const int64_t kstep = g.TN / (2 * (int64_t)Pn), gstep = g.TN / G;
+  if (row.half) {
+    // The half-length cosine sum (N = G / 2, Pn = N / 2).  The modes m < G
+    // fold onto 0..N (cos(2 pi m d / G) is even about N):
+    //   f_0 = 2 Z(0), f_N = 2 Z(N), f_m = Z(m) + Z(G - m) (0 < m < N),
+    //   Y(d) = f_0 / 2 + (-1)^d f_N / 2 + sum_{0 < m < N} f_m cos(pi m d / N).
+    // With y_j = (f_j + f_{N-j}) / 2 - sin(pi j / N) (f_j - f_{N-j}) (j < N)
+    // and X the N-point inverse transform of y (one packed Pn-point FFT),
+    //   Y(2k) = Re X(k),   Y(2k + 1) = Y(1) + sum_{0 < k' <= k} Im X(k'),
+    //   Y(1) = (f_0 - f_N) / 2 + sum_{0 < m < N} f_m cos(pi m / N)
+    // (summed while y is built): the sine-weighted differences cancel in
+    // Re X and leave the first differences of the odd samples in Im X.  Half
+    // the transform of the S-pass form; the odd samples by a block scan in a
+    // fixed order.
+    constexpr int NW = NT / 64;
+    __shared__ R wsum[NW];
+    const int lane = tid & 63, wv = tid >> 6, N = 2 * Pn;
+    R* br = reinterpret_cast<R*>(buf);
+    auto put = [&](int jj, R v) { br[2 * lidx(jj >> 1) + (jj & 1)] = v; };
+    R f1 = R(0);
+    for (int jj = tid; jj <= Pn; jj += NT) {
+      if (jj == 0) {
+        const R z0 = xcorr(0), zn = xcorr(N);
+        put(0, z0 + zn);
+        f1 += z0 - zn;
+      } else if (jj == Pn) {
+        put(Pn, xcorr(Pn) + xcorr(G - Pn));  // sin = 1, cos = 0
+      } else {
+        const C t = tw[(int64_t)jj * gstep];  // exp(-i pi jj / N)
+        const R fa = xcorr(jj) + xcorr(G - jj), fb = xcorr(N - jj) + xcorr(N + jj);
+        const R h = R(0.5) * (fa + fb), dl = -t.y * (fa - fb);
+        put(jj, h - dl);
+        put(N - jj, h + dl);
+        f1 += t.x * (fa - fb);
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) f1 += __shfl_xor(f1, o, 64);
+    if (lane == 0) wsum[wv] = f1;
+    __syncthreads();
+    R carry = R(0);  // Y(1)
+    for (int w = 0; w < NW; ++w) carry += wsum[w];
+    lds_fft_outlined<R, true, NT>(buf, Pn, tw, (int)g.TN);  // its barriers also order the wsum reads
+    const int ke = (nc + 1) / 2, ko = nc / 2;  // even and odd samples below nc
+    for (int k0 = 0; k0 < ke; k0 += NT) {
+      const int k = k0 + tid;
+      C X = cmake<C>(R(0), R(0));
+      if (k < ke) X = real_from_packed<R>(buf, Pn, k, cconj(tw[(int64_t)k * kstep]));
+      R v = (k >= 1 && k < ko) ? X.y : R(0);
+      for (int o = 1; o < 64; o <<= 1) {
+        const R u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+      }
+      if (lane == 63) wsum[wv] = v;
+      __syncthreads();
+      R pre = R(0), tot = R(0);
+      for (int w = 0; w < NW; ++w) {
+        const R sw = wsum[w];
+        if (w < wv) pre += sw;
+        tot += sw;
+      }
+      if (k < ke) Yr[2 * k] = X.x;
+      if (k < ko) Yr[2 * k + 1] = carry + pre + v;
+      carry += tot;
+      __syncthreads();  // wsum is rewritten by the next round
+    }
+    return;
+  }
   for (int s = 0; s < S; ++s) {
     for (int l = tid; l < Pn; l += NT) {
       const int64_t m0 = (int64_t)S * (2 * l) + s;

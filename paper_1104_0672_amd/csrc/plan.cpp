@@ -73,12 +73,14 @@ bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 // (2 P) sub-transforms of P points, P at most 16384 in FP32 and 8192 in FP64,
 // the largest that one workgroup's LDS holds) cheaper than the sums over
 // samples x modes.
+int64_t fft_row_max_points(const arkcos_plan_s* P) { return P->dtype == ARKCOS_F32 ? 16384 : 8192; }
+
 int32_t fft_row_points(const arkcos_plan_s* P, int64_t q, int64_t nc) {
   const PairDev& pr = P->h_pairs[q];
   if (P->prof_kind != 1 || P->h_pair_shift[q] || pr.band < 0 || nc <= kGradMaxCoef) return 0;
   const int64_t G = pr.grid;
   if (!is_pow2(G) || G < kFftRowMinGrid || P->twiddle_n % G != 0) return 0;
-  const int64_t pcap = P->dtype == ARKCOS_F32 ? 16384 : 8192;
+  const int64_t pcap = fft_row_max_points(P);
   const int64_t Pn = std::min<int64_t>(G / 2, pcap);
   const int64_t S = G / (2 * Pn);
   const double direct = (double)nc * (double)(pr.band + 1);
@@ -118,6 +120,10 @@ arkcos_status_t build_grad_items(arkcos_plan_s* P) {
   std::vector<double> cost;
   std::vector<RowFft> fft_rows;
   int64_t zmax = 0;
+  // (ARKCOS_GRAD_HALF=0 keeps every FFT row on the S-pass form, so that
+  // tests compare the two)
+  const char* he = getenv("ARKCOS_GRAD_HALF");
+  const bool half_off = he && *he == '0';
   const int64_t rsz = P->dtype == ARKCOS_F32 ? 4 : 8;
   const int64_t chunk = kGradZBytes / rsz;
   for (int64_t u = 0; u < P->n_units; ++u) {
@@ -137,7 +143,17 @@ arkcos_status_t build_grad_items(arkcos_plan_s* P) {
       const int64_t nc = P->h_ncoef_window[q];
       if (pr.band < 0 || nc <= kGradMaxCoef) continue;
       if (const int32_t Pn = fft_row_points(P, q, nc); Pn > 0) {
-        fft_rows.push_back(RowFft{(int32_t)u, q, Pn, 0});
+        // the half-length cosine sum (one pass of G / 4 points) wherever it
+        // fits one workgroup, else S passes of Pn points.  Its odd samples
+        // are a running sum of first differences, whose rounding errors add
+        // up along the row: FP32 rows take it only up to kHalfMaxSamplesF32
+        // samples (within about six times the S-pass rounding there).
+        const int64_t G = pr.grid;
+        const bool short_enough = P->dtype == ARKCOS_F64 || nc <= kHalfMaxSamplesF32;
+        if (!half_off && short_enough && G / 4 <= fft_row_max_points(P) && nc <= G / 2 + 1)
+          fft_rows.push_back(RowFft{(int32_t)u, q, (int32_t)(G / 4), 1});
+        else
+          fft_rows.push_back(RowFft{(int32_t)u, q, Pn, 0});
         continue;
       }
       const int64_t nm = pr.band + 1;

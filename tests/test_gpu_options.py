@@ -225,6 +225,38 @@ def test_knot_gradient_fft_rows_in_chunks():
     assert d <= 1e-12 and e <= 1e-10
 
 
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-10), ("f32", 2e-5)])
+def test_knot_gradient_half_length_rows(dt, tol):
+    """The FFT rows' cosine sums by the half-length form (one packed G/4-point
+    transform, the odd samples by a scan of first differences) against the
+    S-pass form of the same plan (ARKCOS_GRAD_HALF=0) and against the FP64
+    reference; 2048-longitude rows, so both forms run."""
+    import os
+    from paper_1104_0672_amd import Plan
+    w = _spline_workload(32, 64, dt, 33)
+    _say(f"case knot gradient half-length rows {w.name} {dt} p=16")
+    half = Plan.from_workload(w, oversample=16)
+    os.environ["ARKCOS_GRAD_HALF"] = "0"
+    try:
+        spass = Plan.from_workload(w, oversample=16)
+    finally:
+        del os.environ["ARKCOS_GRAD_HALF"]
+    assert half.info.grad_fft_rows > 0 and half.info.grad_fft_rows == spass.info.grad_fft_rows
+    rng = np.random.default_rng(34)
+    x, t = rng.standard_normal(w.grid.npix), rng.standard_normal(w.grid.npix)
+    xd = _tt(x, dt)
+    r = half.convolve(xd).double().cpu().numpy() - t
+    g1 = half.kernel_grad(xd, _tt(r, dt)).cpu().numpy()
+    g2 = spass.kernel_grad(xd, _tt(r, dt)).cpu().numpy()
+    d = np.abs(g1 - g2).max() / np.abs(g2).max()
+    ref = oracle.hybrid_knot_grad(w.grid, w.profile, w.radius, x, r, oversample=16)
+    e1 = np.abs(g1 - ref).max() / np.abs(ref).max()
+    e2 = np.abs(g2 - ref).max() / np.abs(ref).max()
+    _say(f"  half vs S-pass {d:.2e}; vs FP64 reference: half {e1:.2e}, S-pass {e2:.2e}")
+    assert d > 0.0  # the two forms round differently: both ran
+    assert e1 <= tol and e2 <= tol and d <= tol
+
+
 @pytest.mark.parametrize("nside,p", [(16, None), (32, 16)])
 def test_set_knots_async_equals_host_update(nside, p):
     """Knot updates on the device and from the host give the same map, equal

@@ -47,18 +47,56 @@ def stage_of(kernel: str):
     return None
 KERNEL_SOURCES = {"ring_r2c": ["fft.hip", "device_common.h"], "accumulate": ["accum.hip", "device_common.h"],
                   "fold_c2r": ["fft.hip", "device_common.h"], "pole_fix": ["pole.hip"]}
+# the batched form's kernels per stage (their sources: the stage's and the
+# batch planner's)
+BATCH_KERNELS = {"ring_r2c": ("r2c_batch_kernel",), "accumulate": ("accumulate_batch_kernel", "accumulate_batch_u_kernel"),
+                 "fold_c2r": ("c2r_batch_kernel",), "pole_fix": ("pole_batch_kernel",)}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash(stage: str) -> str:
+def kernel_source_hash(stage: str, batched: bool = False) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES[stage]:
+    for f in KERNEL_SOURCES[stage] + (["batch.hip"] if batched else []):
         with open(os.path.join(ROOT, "paper_1104_0672_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def batch_stage_of(kernel: str):
+    for stage, names in BATCH_KERNELS.items():
+        if kernel in names:
+            return stage
+    return None
+
+
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "counters_valu.json")
+
+
+def batched_valu_issue():
+    """VALU issue fraction of each stage of the batched form, from the
+    committed SQ counter summary (a 64-map batch; VALU wave instructions x 4
+    cycles over 1024 SIMDs x 2.4 GHz x the stage's profiled time, summed over
+    its launch shapes), if it was taken on the current kernel sources."""
+    if not os.path.exists(COUNTERS_JSON):
+        return None
+    with open(COUNTERS_JSON) as fh:
+        data = json.load(fh)
+    out = {}
+    for stage in BATCH_KERNELS:
+        valu = us = 0.0
+        for ent in data.get("kernels", []):
+            if batch_stage_of(ent["kernel"]) != stage:
+                continue
+            if ent.get("source_sha") != kernel_source_hash(stage, batched=True):
+                return None
+            valu += ent["valu_wave_insts"] * ent["dispatches"]
+            us += ent["us"] * ent["dispatches"]
+        if us > 0:
+            out[stage] = round(valu * 4 / (1024 * 2.4e9 * us * 1e-6), 3)
+    return {"stages": out, "source": "profiles/counters_valu.json"} if out else None
 
 
 def algorithmic_bytes(stage: str, plan, elem: int) -> int:
@@ -230,6 +268,7 @@ def summarize_counters(csv_path: str, cmd: str, title: str):
              "summed over the device); VALU issue = VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x duration):", "",
              "| kernel | workgroups | threads | dispatches | us (profiled) | VALU | SALU | LDS | VMEM rd | VMEM wr | VALU issue |",
              "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    ents = []
     for key in sorted(per):
         nd = len(durs[key])
         us = sum(durs[key].values()) / nd / 1e3
@@ -238,7 +277,15 @@ def summarize_counters(csv_path: str, cmd: str, title: str):
         frac = valu * 4 / (1024 * 2.4e9 * us * 1e-6) if us > 0 else 0.0
         cells = " | ".join(f"{c.get(k, 0.0) / 1e6:.2f} M" for k in names)
         lines.append(f"| `{key[0]}` | {key[1]} | {key[2]} | {nd} | {us:.1f} | {cells} | {frac:.2f} |")
+        st, bst = stage_of(key[0]), batch_stage_of(key[0])
+        sha = kernel_source_hash(bst, batched=True) if bst else (kernel_source_hash(st) if st else None)
+        ents.append({"kernel": key[0], "workgroups": key[1], "threads": key[2], "dispatches": nd,
+                     "us": round(us, 2), "valu_wave_insts": round(valu), "valu_issue": round(frac, 3),
+                     "source_sha": sha})
     print("\n".join(lines))
+    with open(COUNTERS_JSON, "w") as fh:
+        json.dump({"title": title, "command": cmd, "kernels": ents}, fh, indent=1)
+        fh.write("\n")
 
 
 def cpu_baseline(w, x, budget_s: float):
@@ -354,6 +401,10 @@ def bench_batch(n_maps: int, steps: int, dev):
     out["graph_forward"] = {"pixels_per_s": npix * steps / wall, "ms": ms,
                             "hbm_roofline_frac_24B_per_px": round(total_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"bench: batch forward as a replayed hipGraph {ms:.2f} ms, {npix * steps / wall:.3e} px/s")
+    out["valu_issue"] = batched_valu_issue()
+    if out["valu_issue"]:
+        log("bench: batch VALU issue per stage (committed SQ counters, 64-map batch): "
+            + ", ".join(f"{k}={v}" for k, v in out["valu_issue"]["stages"].items()))
     del graph, xs, ys, ws, batch, plans
     torch.cuda.empty_cache()
     return out

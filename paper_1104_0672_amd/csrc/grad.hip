@@ -480,12 +480,13 @@ __device__ __noinline__ void lds_fft_outlined(cx_t<R>* buf, int M, const cx_t<R>
   lds_fft<R, INV, NT>(buf, M, tw, TN);
 }
 
-// Wide rows by FFT: Y(d) = sum_{m <= band} Z(m) cos(2 pi m d / G) with
-// Z(m) = eps_m h(m) (X_ij(m) + X_i'j'(m)) on a power-of-two grid G.  With
-// S = G / (2 P), the modes split into S real sub-sequences z_q = Z(S q + s)
-// of 2 P points, and
+// Wide rows by FFT: Y(d) = sum_{m <= band, m < G} Z(m) cos(2 pi m d / G) with
+// Z(m) = eps_m h(m) (X_ij(m) + X_i'j'(m)) on a power-of-two grid G, in one of
+// two forms (RowFft::half).  The S-pass form: with S = G / (2 P), the modes
+// split into S real sub-sequences z_q = Z(S q + s) of 2 P points, and
 //   Y(d) = Re sum_s exp(2 pi i s d / G) Y_s(d mod 2P),
-// Y_s the inverse 2P-point transform of z (one packed P-point LDS FFT).  One
+// Y_s the inverse 2P-point transform of z (one packed P-point LDS FFT).  The
+// half-length form (P = G / 4, one pass) is described where it is taken.  One
 // block per row writes Y(d), d < nc, to the row's place in the chunk's buffer
 // (thread k owns the samples k + NT i in every pass).
 template <typename R, int NT>

@@ -117,7 +117,8 @@ constexpr int kFoldThreads = 256;    // threads sharing the period sums of a sho
 // entries of a pair's K_ij(m) table: modes 0..band, zero-padded to whole
 // mode tiles so that a tile is read without bounds checks
 __host__ __device__ constexpr int32_t table_span(int32_t band) { return (band / kAccTile + 1) * kAccTile; }
-constexpr int64_t kAutoTableBytes = int64_t(1) << 30;  // automatic choice: tables for every pair up to this size
+constexpr int64_t kAutoTableBytes = int64_t(1) << 30;  // automatic choice: tables for every pair up to this size,
+constexpr double kAutoTableShare = 0.8;  // or when the wide rows' tables are at least this share of all
 
 // A band of up to kBandUnits consecutive units: the input rings they need.
 struct BandDev {

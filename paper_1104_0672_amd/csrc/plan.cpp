@@ -318,17 +318,23 @@ arkcos_status_t build_kernel_tables(arkcos_plan_s* P) {
            P->h_w[P->h_pair_i[q]] == P->h_w[pr.j];
   };
   // table selection and offsets: automatic choice = tables for every pair if
-  // they fit in kAutoTableBytes (the accumulation then only streams them),
-  // otherwise tables only for rows too wide for the recurrence
+  // they fit in kAutoTableBytes (the accumulation then only streams them), or
+  // if the rows too wide for the recurrence, whose tables are built anyway,
+  // already hold at least kAutoTableShare of them; otherwise tables only for
+  // those wide rows
   bool all_auto = false;
   if (P->opts.kgen == 0) {
-    int64_t entries = 0;
+    int64_t entries = 0, wide = 0;
     for (int64_t q = 0; q < np; ++q) {
       if (band[q] < 0) continue;
       const int64_t t = transpose(q);
-      if (!(t >= 0 && t < q && compatible(t, q))) entries += table_span(band[q]);
+      if (!(t >= 0 && t < q && compatible(t, q))) {
+        entries += table_span(band[q]);
+        if (P->h_pairs[q].ncoef > kOtfMaxCoef) wide += table_span(band[q]);
+      }
     }
-    all_auto = entries * (int64_t)(P->dtype == ARKCOS_F32 ? 4 : 8) <= kAutoTableBytes;
+    all_auto = entries * (int64_t)(P->dtype == ARKCOS_F32 ? 4 : 8) <= kAutoTableBytes ||
+               (double)wide >= kAutoTableShare * (double)entries;
   }
   int64_t table_total = 0, ntab = 0;
   std::vector<int32_t> tab_list;

@@ -90,6 +90,24 @@ def test_healpix2048_5arcmin_full_map():
     assert e_all <= 1e-4
 
 
+def test_healpix1024_spline_takes_every_pair_by_table():
+    """The automatic kernel source (kgen 0) of the spline workload: its wide
+    rows need tables in any case and hold over 80 % of all the entries, so
+    every pair is tabled (the table-only accumulation), equal to the forced
+    choice (kgen 2) in tables and in the result."""
+    from paper_1104_0672_amd import Plan
+    w = W.healpix1024_spline()
+    auto, forced = Plan.from_workload(w), Plan.from_workload(w, kgen=2)
+    ka, kf = list(auto.info.pairs_by_kind), list(forced.info.pairs_by_kind)
+    print(f"case {w.name}: pairs by kind auto {ka} forced {kf}; table entries {auto.info.table_entries} / "
+          f"{forced.info.table_entries}; units per wave {auto.info.acc_units_per_wave}", flush=True)
+    assert ka[0] == ka[1] == ka[3] == 0 and ka == kf
+    assert auto.info.table_entries == forced.info.table_entries
+    x = torch.tensor(np.random.default_rng(5).standard_normal(w.grid.npix), dtype=torch.float32, device="cuda")
+    ya, yf = auto.convolve(x), forced.convolve(x)
+    assert torch.equal(ya, yf)
+
+
 def test_healpix1024_spline_forward_adjoint_gradient():
     from paper_1104_0672_amd import Plan
     w = W.healpix1024_spline()

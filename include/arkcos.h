@@ -173,7 +173,14 @@ void arkcos_default_options(arkcos_options_t* opts);
 /* Build a plan on the current device: ring and pair tables, the FP64 kernel
  * samples of every ring pair (step b), bands and optional K_ij(m) tables.
  * support_radius_rad: R in (0, pi).  opts may be NULL (defaults).  Blocks the
- * host until the device tables are ready.  *out is set only on success. */
+ * host until the device tables are ready.  *out is set only on success.
+ * Environment (tuning and test switches; none changes a result beyond
+ * rounding): ARKCOS_ACC_SHAPE="U,T[,W[,C]]" fixes the accumulation's shape
+ * (units per band, mode tiles per item, units per wavefront, staged rings)
+ * instead of timing the candidates, ARKCOS_ACC_TIMES=1 prints the candidates'
+ * times, ARKCOS_GRAD_CHUNK_BYTES sets the knot gradient's Y-buffer chunk,
+ * ARKCOS_GRAD_HALF=0 keeps every FFT row of the knot gradient on the S-pass
+ * form, ARKCOS_PLAN_STATS=1 prints the plan's (pair, mode) counts. */
 arkcos_status_t arkcos_plan(const arkcos_geometry_t* geom, const arkcos_profile_t* profile,
                             double support_radius_rad, arkcos_dtype_t dtype,
                             const arkcos_options_t* opts, arkcos_plan_t* out);

@@ -442,7 +442,7 @@ static void make_bands_items(const arkcos_plan_s* P, int32_t units, int32_t tile
 // waves per CU) and mode tiles per item.  Plans of a million pixels or more
 // time every candidate on a scratch workspace (the kernel's control flow
 // does not depend on the data) and keep the fastest; smaller plans take 8
-// units and 4 tiles.  ARKCOS_ACC_SHAPE="U,T" forces a choice.  The result
+// units and 4 tiles.  ARKCOS_ACC_SHAPE="U,T[,W[,C]]" forces a choice.  The result
 // does not depend on the shape: every unit sums its pairs in the same order.
 arkcos_status_t choose_accumulation_shape(arkcos_plan_s* P) {
   struct Cand {

@@ -98,8 +98,10 @@ typedef struct {
                                width (p = next power of two >= 4.3 pixel / FWHM) */
   int32_t kgen;             /* how K_ij(m) is produced per call: 0 = automatic
                                (precomputed tables for every pair if they take at
-                               most 1 GiB, otherwise the recurrence from the kernel
-                               samples for narrow pairs and tables for wide ones),
+                               most 1 GiB or if the wide pairs' tables, needed in
+                               any case, hold at least 80 % of the entries,
+                               otherwise the recurrence from the kernel samples
+                               for narrow pairs and tables for wide ones),
                                1 = recurrence for every pair (wide rows still use
                                tables), 2 = precomputed table for every pair */
   int32_t fix_pole_pixels;  /* HEALPix: recompute the 8 pixels of the first and last

@@ -205,22 +205,23 @@ def summarize_traffic(fetch_csv: str, write_csv: str, calib_mib: int, out_path: 
     print(json.dumps(out, indent=1))
 
 
-def summarize_kernels(trace_dir: str, cmd: str, title: str):
+def summarize_kernels(trace_dir: str, cmd: str, title: str, only: str = "", top: int = 0):
     """Markdown summary of a rocprofv3 --kernel-trace --stats run: the stats
-    table plus per-launch-shape averages of the convolution kernels."""
+    table (its first `top` rows if top > 0) plus per-launch-shape averages of
+    the convolution kernels (those whose name holds `only`, if given)."""
     import collections
     stats = _counter_rows(os.path.join(trace_dir, "run_kernel_stats.csv"))
     trace = _counter_rows(os.path.join(trace_dir, "run_kernel_trace.csv"))
     lines = [f"# {title}", "", "Command (from the repository root, one MI355X):", "", "```", cmd, "```", "",
              "All dispatches of the run (plan build, warmup and timed steps), from `run_kernel_stats.csv`:", "",
              "| kernel | calls | total us | average us | % |", "|---|---:|---:|---:|---:|"]
-    for s in stats:
+    for s in (stats[:top] if top > 0 else stats):
         lines.append(f"| `{_short(s['Name'])}` | {s['Calls']} | {float(s['TotalDurationNs']) / 1e3:.1f} | "
                      f"{float(s['AverageNs']) / 1e3:.1f} | {float(s['Percentage']):.1f} |")
     agg = collections.defaultdict(list)
     for r in trace:
         n = _short(r["Kernel_Name"])
-        if stage_of(n) or "batch" in n or "grad" in n or "adjoint" in n:
+        if (stage_of(n) or "batch" in n or "grad" in n or "adjoint" in n) and only in n:
             key = (n, int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"])), int(r["Workgroup_Size_X"]),
                    int(r["LDS_Block_Size"]))
             agg[key].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
@@ -557,13 +558,16 @@ def main():
                     help="offline: print a markdown summary of an SQ instruction-counter run")
     ap.add_argument("--summary-command", default="", help="command line recorded in a summary")
     ap.add_argument("--summary-title", default="")
+    ap.add_argument("--summary-only", default="", help="kernel summary: launch shapes of these kernels only")
+    ap.add_argument("--summary-top", type=int, default=0, help="kernel summary: first rows of the stats table")
     args = ap.parse_args()
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic, args.copy_calibration_mib,
                           os.path.join(ROOT, "profiles", "traffic_healpix2048_5arcmin.json"), args.summary_command)
         return
     if args.summarize_kernels:
-        summarize_kernels(args.summarize_kernels, args.summary_command, args.summary_title)
+        summarize_kernels(args.summarize_kernels, args.summary_command, args.summary_title,
+                          args.summary_only, args.summary_top)
         return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, args.summary_command, args.summary_title)
